@@ -1,0 +1,161 @@
+/*
+ * mf.h -- C ABI of libmf: Foata-level multifrontal LU of FEM systems on one MI355X (gfx950).
+ *
+ * The problem is stated as in the paper: a set of element matrices plus mesh connectivity
+ * (the fronts at the leaves of the elimination tree are the element matrices, Sec. 2.4), and a
+ * right-hand side (the multifrontal driver of Table 2 takes the FEM input and the load vector).
+ *
+ * Conventions shared by every entry point
+ *   - Every call returns int: MF_OK (0) on success, a negative MF_E* code on failure.  After a
+ *     failure, mf_last_error() returns a thread-local, NUL-terminated message.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP device memory on the
+ *     current device (e.g. from torch tensors).  The caller owns every buffer it passes; the
+ *     plan copies what it keeps.  All matrices are row-major, FP64 unless stated otherwise.
+ *   - Device work is enqueued on `hip_stream` (a hipStream_t, NULL = the null stream).
+ *   - A plan must not be used from two threads at the same time.
+ *   - Batches: n_mesh > 1 meshes are solved together.  Nodes and elements are concatenated in
+ *     mesh order; global node id = mesh node id + sum of n_nodes of the preceding meshes, and
+ *     the same for elements.
+ */
+#ifndef MF_H
+#define MF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MF_OK = 0,
+  MF_EINVAL = -1,       /* invalid argument (sizes, ids, pointers, unsupported combination) */
+  MF_ENOMEM = -2,       /* host or device allocation failed */
+  MF_EZERO_PIVOT = -3,  /* zero or non-finite pivot during factorization (no pivoting) */
+  MF_EHIP = -4,         /* a HIP runtime call failed (message names it) */
+  MF_ENOCONV = -5,      /* iterative refinement did not reach the tolerance */
+  MF_ESTATE = -6        /* call out of order, e.g. solve before a successful factor */
+};
+
+/* Arithmetic of the Schur-complement update C22 -= L21 U12 (Sec. 2.2) on the tiled path.  The
+ * pivot-block LU, the triangular solves and everything else always run in FP64. */
+enum { MF_FP64 = 0, MF_SCHUR_FP32 = 1, MF_SCHUR_BF16 = 2 };
+
+typedef struct mf_plan mf_plan;   /* opaque: host analysis, device plan, factor storage */
+
+/* One structured or unstructured mesh of tensor-product elements.
+ *   dim       2 or 3
+ *   npe       nodes per element, must equal 2^dim (Q1 elements)
+ *   n_nodes   nodes of this mesh; ids 0..n_nodes-1, every node used by some element
+ *   n_elem    elements of this mesh (>= 1)
+ *   conn      host [n_elem][npe] node ids, local node a = c_x + 2 c_y (+ 4 c_z)
+ *   elem_ijk  host [n_elem][dim] integer element coordinates, pairwise distinct; they drive the
+ *             nested-dissection bisection of the elimination tree                        */
+typedef struct {
+  int32_t dim, npe;
+  int64_t n_nodes, n_elem;
+  const int32_t *conn;
+  const int32_t *elem_ijk;
+} mf_mesh;
+
+typedef struct {
+  int64_t n;                 /* unknowns (sum of n_nodes) */
+  int64_t n_elem;            /* elements (sum of n_elem) */
+  int64_t n_fronts;          /* fronts (2 n_elem - n_mesh) */
+  int64_t sum_m;             /* sum of front widths: length of front_idx */
+  int64_t sum_mk;            /* sum of m*k: length of the L (and of the U) export buffer */
+  int64_t store_doubles;     /* device factor storage, doubles (sum of m^2) */
+  int32_t n_mesh, dim, npe;
+  int32_t height;            /* Foata classes are 0..height */
+  int32_t max_m, max_k;
+  double factor_flops;       /* sum over pivots of (r-1) + 2 (r-1)^2, r = m - p */
+  double solve_flops_per_rhs;/* sum over pivots of 1 + 4 (r-1) (forward + backward) */
+  double sum_cb2;            /* extend-add entries: sum over fronts of (m-k)^2 */
+} mf_info;
+
+/* Builds the elimination tree of the batch (host work only; no GPU needed).
+ * Tree (Sec. 2.4, Table 3): recursive coordinate bisection of each mesh's element index box --
+ * split the axis with the most elements (ties: lowest axis) at lo + floor(len/2), lower half
+ * first -- down to single elements; fronts numbered in post-order, mesh after mesh.
+ * Pivots of a front are the nodes whose elements all lie in it and in neither child (the front
+ * that owns them alone, Table 2); its contribution block (CB) is the rest of its children's
+ * CBs (a leaf: of its element's nodes).  Index list: pivots ascending, then CB ascending
+ * (pivots first, Sec. 3.2).  Foata class (Sec. 3.3) = height above the leaves.
+ * meshes: host array of n_mesh descriptors (read only during the call).
+ * out: receives a new plan; release it with mf_destroy.
+ * Errors: MF_EINVAL (bad sizes, ids out of range, duplicate elem_ijk, unused node), MF_ENOMEM. */
+int mf_analyse(int32_t n_mesh, const mf_mesh *meshes, mf_plan **out);
+
+/* Sizes and operation counts of an analysed plan. */
+int mf_plan_info(const mf_plan *plan, mf_info *out);
+
+/* Copies the tree to host buffers sized from mf_info (any pointer may be NULL to skip it):
+ *   parent[n_fronts] (-1 at a root), level[n_fronts], front_ptr[n_fronts+1] (offsets into
+ *   front_idx), front_idx[sum_m] (global node ids), npiv[n_fronts],
+ *   leaf_elem[n_fronts] (global element id of a leaf, -1 for internal fronts). */
+int mf_plan_export_tree(const mf_plan *plan, int32_t *parent, int32_t *level, int64_t *front_ptr,
+                        int32_t *front_idx, int32_t *npiv, int64_t *leaf_elem);
+
+/* Schedule tuning of an analysed plan (the autotuner's knob; defaults are used otherwise).
+ *   small_max_m  fronts of width <= small_max_m are assembled, eliminated and stored by one
+ *                workgroup with the front resident in LDS; wider fronts take the tiled path
+ *                (assembly, panel LU of nb pivots at a time, MFMA Schur GEMM).  It is clipped
+ *                to what fits in one workgroup's LDS on the device.  0 keeps the current value.
+ *   nb           panel width of the tiled path: 16, 32 or 64.  0 keeps the current value.
+ * Invalidates a previous factorization.  Errors: MF_EINVAL. */
+int mf_set_tuning(mf_plan *plan, int32_t small_max_m, int32_t nb);
+
+/* Numerical factorization (Table 2 over Foata classes, Sec. 3.3): for every class in order, all
+ * its fronts extend-add their children's contribution blocks (a leaf takes its element
+ * matrix), partially LU-eliminate their k pivots with the pivot row scaled by the pivot
+ * (U unit upper, L carrying the pivots), and apply the Schur update to their CB.
+ * elem_mats: device [n_elem][npe][npe] FP64.  precision: MF_FP64 / MF_SCHUR_FP32 / MF_SCHUR_BF16.
+ * Synchronizes `hip_stream` to read back the pivot status.
+ * Errors: MF_EZERO_PIVOT (the plan then holds no valid factor; see mf_last_error for the front
+ * and pivot), MF_EINVAL, MF_ENOMEM, MF_EHIP. */
+int mf_factor(mf_plan *plan, const double *elem_mats, int32_t precision, void *hip_stream);
+
+/* Solves A x = b (transpose = 0) or A^T x = b (transpose = 1) with the stored factors:
+ * forward substitution leaves -> root, backward substitution root -> leaves (Sec. 1.1).
+ * b, x: device [n][nrhs] FP64 (may alias).  Asynchronous on hip_stream.
+ * Errors: MF_ESTATE (no valid factor), MF_EINVAL, MF_ENOMEM, MF_EHIP. */
+int mf_solve(const mf_plan *plan, const double *b, double *x, int32_t nrhs, int32_t transpose,
+             void *hip_stream);
+
+/* r = b - A x with A applied element by element (A = sum_e P_e^T K_e P_e), FP64.
+ * elem_mats device [n_elem][npe][npe]; x, b, r device [n][nrhs].  Asynchronous. */
+int mf_residual(const mf_plan *plan, const double *elem_mats, const double *x, const double *b,
+                double *r, int32_t nrhs, void *hip_stream);
+
+/* Iterative refinement in FP64: x = solve(b); repeat r = b - A x, x += solve(r) until
+ * max_r ||r_r||_2 / ||b_r||_2 <= tol or max_it corrections were applied.
+ * elem_mats, b, x as above; its (host, may be NULL) receives the number of corrections and
+ * relres (host, may be NULL) the final relative residual.  Synchronizes hip_stream once per
+ * iteration.  Errors: MF_ENOCONV (tolerance not met; x holds the last iterate), MF_ESTATE,
+ * MF_EINVAL, MF_ENOMEM, MF_EHIP. */
+int mf_refine(const mf_plan *plan, const double *elem_mats, const double *b, double *x,
+              int32_t nrhs, double tol, int32_t max_it, int32_t *its, double *relres,
+              void *hip_stream);
+
+/* Adjoint element gradient: gK[e][a][b] = -sum_r lam[conn_e[a]][r] * u[conn_e[b]][r], the
+ * derivative of a loss through A = sum_e P_e^T K_e P_e given lam = A^{-T} dL/du.
+ * lam, u device [n][nrhs]; gK device [n_elem][npe][npe].  Asynchronous. */
+int mf_elem_grad(const mf_plan *plan, const double *lam, const double *u, int32_t nrhs,
+                 double *gK, void *hip_stream);
+
+/* Copies the factors to host buffers sized from mf_info, front after front in id order:
+ *   L: for each front an m x k row-major block, L[i][p] for i >= p (pivots on the diagonal),
+ *      zeros above;
+ *   U: for each front a k x m row-major block, U[p][p] = 1, U[p][j] for j > p, zeros left.
+ * Synchronous.  Errors: MF_ESTATE (no valid factor), MF_EINVAL, MF_EHIP. */
+int mf_export_factors(const mf_plan *plan, double *L, double *U);
+
+/* Releases the plan and all its device memory (NULL is ignored). */
+void mf_destroy(mf_plan *plan);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *mf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MF_H */

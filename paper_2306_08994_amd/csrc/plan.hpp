@@ -1,0 +1,83 @@
+// plan.hpp -- host-side plan of the multifrontal solver: elimination tree, front index lists,
+// extend-add maps, storage offsets and the per-class launch schedule.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace mf {
+
+// Per-front record shared by host and device (plain data, 48 bytes).
+struct FrontDesc {
+  int64_t store;   // offset (doubles) of the front's m x m row-major storage
+  int64_t idx;     // offset into front_idx / inv_l / inv_r (prefix sum of m)
+  int64_t cbrow;   // offset (rows) into a solve's contribution-block buffer (prefix sum of m-k)
+  int32_t m, k;    // width and number of pivots
+  int32_t left, right;  // child fronts, -1 for a leaf
+  int32_t elem;    // element of a leaf, -1 otherwise
+  int32_t level;   // Foata class
+};
+static_assert(sizeof(FrontDesc) == 48, "FrontDesc layout");
+
+// One tile of a batched GEMM update  C[i0:i1, j0:j1] -= A[i0:i1, q0:q1] * B[q0:q1, j0:j1],
+// where A, B and C are all views of the same front storage (row-major, leading dimension m).
+struct GemmTask {
+  int32_t front;
+  int32_t i0, i1, j0, j1;
+  int32_t q0, q1;
+  int32_t pad;
+};
+static_assert(sizeof(GemmTask) == 32, "GemmTask layout");
+
+// Work of one panel step of the tiled (HBM-resident) path inside one class.
+struct PanelStep {
+  std::vector<int32_t> fronts;     // fronts that still have pivots at this step
+  std::vector<int32_t> p0;         // first pivot of the panel per front
+  std::vector<GemmTask> update;    // trailing update restricted to the fully-summed region
+  int64_t trsm_items = 0;          // max over fronts of (rows + columns) of the two panels
+};
+
+struct LevelSchedule {
+  std::vector<int32_t> small;      // fronts factored entirely in LDS
+  int32_t small_max_m = 0;
+  std::vector<int32_t> large;      // fronts assembled and factored in HBM
+  int32_t large_max_m = 0;
+  std::vector<PanelStep> steps;
+  std::vector<GemmTask> schur;     // C22 -= L21 U12 tiles of the large fronts
+  std::vector<int32_t> all;        // every front of the class (solve)
+  int32_t max_m = 0;
+};
+
+struct HostPlan {
+  int32_t n_mesh = 0, dim = 0, npe = 0;
+  int64_t n = 0, n_elem = 0, F = 0;
+  std::vector<int32_t> conn;       // [n_elem][npe] global node ids
+  std::vector<int32_t> parent, level, npiv, width;
+  std::vector<int64_t> leaf_elem;
+  std::vector<int64_t> front_ptr;  // [F+1]
+  std::vector<int32_t> front_idx;  // [sum m]
+  std::vector<int32_t> inv_l, inv_r;  // [sum m] child CB position (leaf: local node in inv_l)
+  std::vector<FrontDesc> desc;
+  int32_t height = 0, max_m = 0, max_k = 0;
+  int64_t store_doubles = 0, sum_c = 0, sum_mk = 0;
+  double factor_flops = 0, solve_flops = 0, sum_cb2 = 0;
+  std::vector<LevelSchedule> levels;
+};
+
+// Tunables of the schedule (chosen by the autotuner or defaults).
+struct Tuning {
+  int32_t small_max_m = 128;   // fronts up to this width are factored in LDS
+  int32_t nb = 32;             // panel width of the tiled path
+  int32_t tile = 64;           // GEMM output tile edge
+};
+
+// Builds the tree and front structure; returns an error message or "" on success.
+std::string analyse(int32_t n_mesh, const int32_t *dims, const int32_t *npes,
+                    const int64_t *n_nodes, const int64_t *n_elem,
+                    const int32_t *const *conns, const int32_t *const *ijks, HostPlan &out);
+
+// (Re)builds the per-class schedule for the given tuning.
+void build_schedule(HostPlan &p, const Tuning &t);
+
+}  // namespace mf

@@ -1,0 +1,163 @@
+"""Python face of libmf: argument marshalling only.  Every step of the factor and solve runs in
+the HIP kernels behind the C ABI; torch provides device memory and the current stream."""
+from __future__ import annotations
+
+import ctypes
+from typing import Sequence
+
+import numpy as np
+
+from . import _lib
+from ._lib import MFError, check  # noqa: F401
+
+PRECISIONS = {"fp64": _lib.MF_FP64, "fp32": _lib.MF_SCHUR_FP32, "bf16": _lib.MF_SCHUR_BF16}
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_ptr(t, name, shape=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """Analysed elimination tree of one mesh or a batch of meshes (see mf_analyse).
+
+    ``meshes``: objects with ``conn`` (E, npe) and ``ijk`` (E, dim) integer arrays, ``dim`` and
+    ``n_nodes`` (``fixtures.Mesh`` satisfies this)."""
+
+    def __init__(self, meshes: Sequence):
+        lib = _lib.load()
+        self._keep = []
+        arr = (_lib.MfMesh * len(meshes))()
+        for i, m in enumerate(meshes):
+            conn = np.ascontiguousarray(m.conn, dtype=np.int32)
+            ijk = np.ascontiguousarray(m.ijk, dtype=np.int32)
+            self._keep += [conn, ijk]
+            arr[i].dim = int(m.dim)
+            arr[i].npe = int(conn.shape[1])
+            arr[i].n_nodes = int(m.n_nodes)
+            arr[i].n_elem = int(conn.shape[0])
+            arr[i].conn = conn.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+            arr[i].elem_ijk = ijk.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        h = ctypes.c_void_p()
+        check(lib.mf_analyse(len(meshes), arr, ctypes.byref(h)))
+        self._h = h
+        self._keep = []
+        inf = _lib.MfInfo()
+        check(lib.mf_plan_info(self._h, ctypes.byref(inf)))
+        self.info = {k: getattr(inf, k) for k, _ in _lib.MfInfo._fields_}
+        self.n = int(inf.n)
+        self.n_elem = int(inf.n_elem)
+        self.npe = int(inf.npe)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.load().mf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- structure ---------------------------------------------------------------------------
+    def export_tree(self) -> dict:
+        F = int(self.info["n_fronts"])
+        out = {"parent": np.empty(F, np.int32), "level": np.empty(F, np.int32),
+               "front_ptr": np.empty(F + 1, np.int64),
+               "front_idx": np.empty(int(self.info["sum_m"]), np.int32),
+               "npiv": np.empty(F, np.int32), "leaf_elem": np.empty(F, np.int64)}
+        ptr = lambda a: ctypes.c_void_p(a.ctypes.data)
+        check(_lib.load().mf_plan_export_tree(self._h, ptr(out["parent"]), ptr(out["level"]),
+                                              ptr(out["front_ptr"]), ptr(out["front_idx"]),
+                                              ptr(out["npiv"]), ptr(out["leaf_elem"])))
+        return out
+
+    def set_tuning(self, small_max_m: int = 0, nb: int = 0):
+        check(_lib.load().mf_set_tuning(self._h, int(small_max_m), int(nb)))
+
+    # -- numerics ----------------------------------------------------------------------------
+    def factor(self, K, precision: str = "fp64"):
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+        p = _dev_ptr(K, "K", (self.n_elem, self.npe, self.npe))
+        check(_lib.load().mf_factor(self._h, p, PRECISIONS[precision], _stream()))
+
+    def solve(self, b, transpose: bool = False, out=None):
+        import torch
+        b2 = b if b.dim() == 2 else b.reshape(-1, 1)
+        nrhs = int(b2.shape[1])
+        pb = _dev_ptr(b2, "b", (self.n, nrhs))
+        x = torch.empty_like(b2) if out is None else out.reshape(self.n, nrhs)
+        px = _dev_ptr(x, "x", (self.n, nrhs))
+        check(_lib.load().mf_solve(self._h, pb, px, nrhs, int(bool(transpose)), _stream()))
+        return x.reshape(b.shape)
+
+    def residual(self, K, x, b):
+        import torch
+        b2 = b if b.dim() == 2 else b.reshape(-1, 1)
+        nrhs = int(b2.shape[1])
+        r = torch.empty_like(b2)
+        check(_lib.load().mf_residual(self._h, _dev_ptr(K, "K", (self.n_elem, self.npe, self.npe)),
+                                      _dev_ptr(x.reshape(self.n, nrhs), "x"), _dev_ptr(b2, "b"),
+                                      _dev_ptr(r, "r"), nrhs, _stream()))
+        return r.reshape(b.shape)
+
+    def refine(self, K, b, tol: float = 1e-12, max_it: int = 30, x=None):
+        """Solve with FP64 iterative refinement; returns (x, corrections, relres)."""
+        import torch
+        b2 = b if b.dim() == 2 else b.reshape(-1, 1)
+        nrhs = int(b2.shape[1])
+        x = torch.empty_like(b2) if x is None else x.reshape(self.n, nrhs)
+        its = ctypes.c_int32(0)
+        rr = ctypes.c_double(0.0)
+        check(_lib.load().mf_refine(self._h, _dev_ptr(K, "K", (self.n_elem, self.npe, self.npe)),
+                                    _dev_ptr(b2, "b", (self.n, nrhs)), _dev_ptr(x, "x"), nrhs,
+                                    float(tol), int(max_it), ctypes.byref(its), ctypes.byref(rr),
+                                    _stream()))
+        return x.reshape(b.shape), int(its.value), float(rr.value)
+
+    def elem_grad(self, lam, u):
+        import torch
+        lam2 = lam if lam.dim() == 2 else lam.reshape(-1, 1)
+        nrhs = int(lam2.shape[1])
+        gK = torch.empty((self.n_elem, self.npe, self.npe), dtype=torch.float64, device=lam.device)
+        check(_lib.load().mf_elem_grad(self._h, _dev_ptr(lam2, "lam", (self.n, nrhs)),
+                                       _dev_ptr(u.reshape(self.n, nrhs), "u"), nrhs,
+                                       _dev_ptr(gK, "gK"), _stream()))
+        return gK
+
+    def export_factors(self):
+        """Per-front (L (m x k), U (k x m)) numpy arrays, fronts in id order."""
+        tot = int(self.info["sum_mk"])
+        L = np.empty(max(tot, 1))
+        U = np.empty(max(tot, 1))
+        check(_lib.load().mf_export_factors(self._h, ctypes.c_void_p(L.ctypes.data),
+                                            ctypes.c_void_p(U.ctypes.data)))
+        t = self.export_tree()
+        ms = np.diff(t["front_ptr"])
+        ks = t["npiv"]
+        Ls, Us, off = [], [], 0
+        for m, k in zip(ms, ks):
+            m, k = int(m), int(k)
+            Ls.append(L[off:off + m * k].reshape(m, k))
+            Us.append(U[off:off + m * k].reshape(k, m))
+            off += m * k
+        return Ls, Us
+
+
+def analyse(meshes) -> Plan:
+    return Plan(meshes)

@@ -1,0 +1,183 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, element by element.
+
+Sizes are chosen so the oracle finishes in seconds while the fronts still span several GEMM
+tiles, several panels and ragged tails; the tiled path is forced on small meshes by lowering
+the LDS threshold.  Full-size workloads are checked in test_gpu_fullsize.py."""
+import numpy as np
+import pytest
+
+from fixtures import config_problem, structured_q1
+from fixtures.mesh import reaction_diffusion
+from tests import gpu_common as G
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(problem, small_max_m=0, nb=0):
+    import torch
+    from paper_2306_08994_amd import Plan
+    dev = G.torch_dev()
+    plan = Plan(problem.meshes)
+    if small_max_m or nb:
+        plan.set_tuning(small_max_m, nb)
+    K = torch.from_numpy(problem.K).to(dev)
+    b = torch.from_numpy(problem.b).to(dev)
+    return plan, K, b
+
+
+def _rd(shape, seed=0, nrhs=2, sigma=1.0):
+    return reaction_diffusion("t", shape, np.random.default_rng(seed), "lognormal", sigma, nrhs)
+
+
+SMALL = [(1, 1), (2, 1), (4, 4), (5, 3), (16, 16), (2, 2, 2), (3, 4, 2), (5, 5, 5)]
+
+
+@pytest.mark.parametrize("shape", SMALL)
+def test_factor_lds_path(shape):
+    p = _rd(shape)
+    tree, conn, fac = G.oracle_factor(p)
+    plan, K, b = _setup(p)
+    plan.factor(K)
+    Ls, Us = plan.export_factors()
+    assert G.factor_violation(Ls, Us, fac) <= G.TOL_FACTOR
+
+
+TILED = [((64, 48), 8, 16), ((96, 80), 24, 32), ((70, 53), 40, 64), ((10, 9, 8), 16, 32),
+         ((12, 12, 12), 40, 16), ((14, 11, 9), 24, 64), ((12, 12, 12), 100, 32)]
+
+
+@pytest.mark.parametrize("shape,smax,nb", TILED)
+def test_factor_tiled_path(shape, smax, nb):
+    p = _rd(shape, seed=1)
+    tree, conn, fac = G.oracle_factor(p)
+    plan, K, b = _setup(p, smax, nb)
+    plan.factor(K)
+    Ls, Us = plan.export_factors()
+    ms = np.diff(tree.front_ptr)
+    assert ms.max() > 64 and (ms > smax).sum() > 0   # several tiles on the tiled path
+    assert G.factor_violation(Ls, Us, fac) <= G.TOL_FACTOR
+
+
+@pytest.mark.parametrize("shape,smax,nrhs", [((4, 4), 0, 1), ((16, 16), 0, 3), ((24, 20), 8, 8),
+                                             ((5, 4, 3), 0, 2), ((8, 8, 8), 40, 5)])
+def test_solve_parity(shape, smax, nrhs):
+    import torch
+    p = _rd(shape, seed=2, nrhs=nrhs)
+    tree, conn, fac = G.oracle_factor(p)
+    plan, K, b = _setup(p, smax)
+    plan.factor(K)
+    for trans in (False, True):
+        x = plan.solve(b, transpose=trans).cpu().numpy()
+        xo = G.oracle_solve(tree, fac, p.b, trans)
+        assert G.rel_err(x, xo) <= G.TOL_SOLVE, trans
+    x = plan.solve(b).cpu().numpy()
+    assert G.relres(p, conn, x) <= G.TOL_RELRES
+    # in-place (b and x alias)
+    bb = b.clone()
+    plan.solve(bb, out=bb)
+    torch.testing.assert_close(bb, torch.from_numpy(x).to(bb.device), rtol=0, atol=0)
+
+
+def test_residual_and_elem_grad_kernels():
+    import torch
+    from oracle import adjoint as oadj
+    from oracle import residual as ores
+    p = _rd((7, 6), seed=3, nrhs=3)
+    plan, K, b = _setup(p)
+    conn = np.concatenate([m.conn for m in p.meshes]).astype(np.int64)
+    x = np.random.default_rng(4).normal(size=b.shape)
+    xt = torch.from_numpy(x).to(b.device)
+    r = plan.residual(K, xt, b).cpu().numpy()
+    np.testing.assert_allclose(r, ores.residual(p.K, conn, x, p.b), rtol=1e-13, atol=1e-13)
+    lam = np.random.default_rng(5).normal(size=b.shape)
+    gK = plan.elem_grad(torch.from_numpy(lam).to(b.device), xt).cpu().numpy()
+    np.testing.assert_allclose(gK, oadj.elem_grad(conn, lam, x), rtol=1e-13, atol=1e-13)
+
+
+def test_batched_equals_unbatched():
+    import torch
+    from paper_2306_08994_amd import Plan
+    p = config_problem(4, n_mesh=5, side_range=(3, 14))
+    tree, conn, fac = G.oracle_factor(p)
+    plan, K, b = _setup(p)
+    plan.factor(K)
+    Ls, Us = plan.export_factors()
+    assert G.factor_violation(Ls, Us, fac) <= G.TOL_FACTOR
+    xb = plan.solve(b).cpu().numpy()
+    assert G.relres(p, conn, xb) <= G.TOL_RELRES
+    # mesh by mesh
+    noff, eoff, foff = p.node_offsets, p.elem_offsets, 0
+    for i, mesh in enumerate(p.meshes):
+        pl = Plan([mesh])
+        Ki = K[eoff[i]:eoff[i + 1]].contiguous()
+        pl.factor(Ki)
+        Li, Ui = pl.export_factors()
+        for f in range(len(Li)):
+            np.testing.assert_array_equal(Li[f], Ls[foff + f])
+            np.testing.assert_array_equal(Ui[f], Us[foff + f])
+        foff += len(Li)
+        xi = pl.solve(b[noff[i]:noff[i + 1]].contiguous()).cpu().numpy()
+        np.testing.assert_array_equal(xi, xb[noff[i]:noff[i + 1]])
+
+
+def test_nonsymmetric_tiled():
+    p = config_problem(4, n_mesh=2, side_range=(20, 30))
+    tree, conn, fac = G.oracle_factor(p)
+    plan, K, b = _setup(p, 24, 16)
+    plan.factor(K)
+    Ls, Us = plan.export_factors()
+    assert G.factor_violation(Ls, Us, fac) <= G.TOL_FACTOR
+    x = plan.solve(b).cpu().numpy()
+    assert G.rel_err(x, G.oracle_solve(tree, fac, p.b)) <= G.TOL_SOLVE
+    xt = plan.solve(b, transpose=True).cpu().numpy()
+    assert G.rel_err(xt, G.oracle_solve(tree, fac, p.b, True)) <= G.TOL_SOLVE
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_mixed_precision_refines_to_fp64(prec):
+    p = _rd((10, 9, 8), seed=6, nrhs=2)
+    tree, conn, fac = G.oracle_factor(p)
+    xo = G.oracle_solve(tree, fac, p.b)
+    plan, K, b = _setup(p, 40, 32)
+    plan.factor(K, prec)
+    Ls, Us = plan.export_factors()
+    err_factor = G.factor_violation(Ls, Us, fac)
+    assert err_factor > 1e-14          # the Schur update really ran in reduced precision
+    x, its, rr = plan.refine(K, b, tol=1e-12, max_it=40)
+    assert rr <= 1e-12
+    xn = x.cpu().numpy()
+    assert G.relres(p, conn, xn) <= 1e-12
+    assert G.rel_err(xn, xo) <= 1e-9
+    print(f"{prec}: factor deviation {err_factor:.2e}, {its} corrections, relres {rr:.2e}")
+
+
+def test_error_paths():
+    import torch
+    from paper_2306_08994_amd import MFError, Plan
+    from paper_2306_08994_amd import _lib
+    p = _rd((3, 3))
+    plan, K, b = _setup(p)
+    with pytest.raises(MFError) as ei:
+        plan.solve(b)
+    assert ei.value.code == _lib.MF_ESTATE
+    Kbad = K.clone()
+    Kbad[0, 0, 0] = 0.0             # the domain corner is a leaf pivot
+    with pytest.raises(MFError) as ei:
+        plan.factor(Kbad)
+    assert ei.value.code == _lib.MF_EZERO_PIVOT
+    with pytest.raises(MFError) as ei:
+        plan.solve(b)
+    assert ei.value.code == _lib.MF_ESTATE
+    Knan = K.clone()
+    Knan[4, 1, 1] = float("nan")
+    with pytest.raises(MFError):
+        plan.factor(Knan)
+    plan.factor(K)                  # recovers
+    x = plan.solve(b)
+    with pytest.raises(MFError) as ei:
+        plan.refine(K, b, tol=0.0, max_it=0)
+    assert ei.value.code == _lib.MF_ENOCONV
+    with pytest.raises(TypeError):
+        plan.factor(K.cpu())
+    with pytest.raises(TypeError):
+        plan.factor(K.float())
