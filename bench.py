@@ -1,20 +1,184 @@
 #!/usr/bin/env python3
 """Benchmark of the multifrontal factor + solve on one MI355X.
 
-Workload (a step): the 2D Q1 reaction-diffusion system on a 256 x 256 element grid (66,049
-unknowns), element coefficients lognormal(0, 1), 8 right-hand sides N(0, 1), seed 2: one FP64
-factorization (extend-add, panel LU, Schur update over the 17 Foata classes) followed by the
-solve and its FP64 residual check / refinement to a relative residual <= 1e-12.
+Workload of one step: the 2D Q1 reaction-diffusion system on a 256 x 256 element grid (66,049
+unknowns, 131,071 fronts, 17 Foata classes), element coefficients lognormal(0, 1), 8
+right-hand sides N(0, 1), seed 2.  A step is one FP64 factorization (extend-add, partial LU,
+Schur update, class by class) followed by the solve (forward and backward sweeps) and the FP64
+residual check, with refinement corrections applied only if the relative residual exceeds
+1e-12.  Inputs are resident in HBM before the timed region.
+
+value = algorithmic factor+solve GFLOP/s = (factor flops + nrhs * solve flops per RHS) / step
+time, with the operation counts of the method itself (division, multiplication and
+subtraction tasks), not dense n^3.
+
+Extra fields: per-kernel event timing of the same step (roofline of the dominant kernel),
+the batched and mixed-precision variants, and the CPU oracle on the host (cpu_baseline).
 Prints one JSON line.
 """
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_PEAK_TFS = 78.6           # MI355X dense FP64 (vector and matrix)
+FP32_PEAK_TFS = 157.3
+BF16_PEAK_TFS = 2500.0
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def time_steps(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    _sync()
+    t0 = time.perf_counter()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    out = None
+    for _ in range(steps):
+        out = fn()
+    ev1.record()
+    _sync()
+    wall = (time.perf_counter() - t0) / steps
+    return wall, ev0.elapsed_time(ev1) / 1e3 / steps, out
+
+
+def roofline_of(report):
+    """Dominant kernel (largest summed event time) and its achieved fraction of peak."""
+    ks = report["kernels"]
+    top = max(ks, key=lambda k: k["ms"])
+    sec = top["ms"] / 1e3
+    if top["name"].startswith("gemm"):
+        ach = top["flops"] / sec / 1e12
+        return top, {"bound": "mfma", "achieved": ach, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+                     "frac": ach / FP64_PEAK_TFS, "traffic": None}
+    ach = top["bytes"] / sec / 1e9
+    return top, {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": ach / HBM_PEAK_GBS, "traffic": None}
+
+
+CPU_SNIPPET = r"""
+import json, sys, time
+sys.path.insert(0, %(root)r)
+import numpy as np
+from fixtures import config_problem
+from oracle.tree import build_tree, front_flops
+from oracle.factor import factor, global_connectivity
+from oracle.solve import solve
+from oracle.residual import relres
+p = config_problem(2)
+tree = build_tree(p.meshes)
+conn = global_connectivity(p)
+fac_f, sol_f, _ = front_flops(tree)
+times = []
+for _ in range(%(runs)d):
+    t0 = time.perf_counter()
+    fac = factor(tree, p.K, conn)
+    x = solve(tree, fac, p.b)
+    times.append(time.perf_counter() - t0)
+t = sorted(times)[len(times) // 2]
+print(json.dumps({"sec": t, "flops": fac_f + p.nrhs * sol_f, "relres": relres(p.K, conn, x, p.b)}))
+"""
+
+
+def cpu_baseline(runs=3):
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    code = CPU_SNIPPET % {"root": ROOT, "runs": runs}
+    res = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                         timeout=600)
+    if res.returncode != 0:
+        return {"error": res.stderr[-400:]}
+    r = json.loads(res.stdout.strip().splitlines()[-1])
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": r["flops"] / r["sec"] / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+            "sample": f"the full step workload (256x256 Q1, 8 RHS): oracle factor + solve, median of "
+                      f"{runs} runs, single thread (OMP/OPENBLAS/MKL_NUM_THREADS=1)",
+            "ms_per_system": r["sec"] * 1e3, "relres": r["relres"], "host_cpu": model,
+            "host_nproc": os.cpu_count()}
+
+
+def variant_mixed(steps, warmup):
+    """3D Q1 32^3 (35,937 unknowns): FP64 vs FP32- and BF16-Schur factorizations, each refined
+    in FP64 to a relative residual <= 1e-12; error against the FP64 solution reported."""
+    import torch
+    from fixtures import config_problem
+    from paper_2306_08994_amd import Plan
+    p = config_problem(3)
+    plan = Plan(p.meshes)
+    K = torch.from_numpy(p.K).cuda()
+    b = torch.from_numpy(p.b).cuda()
+    x = torch.empty_like(b)
+    flops = plan.info["factor_flops"] + p.nrhs * plan.info["solve_flops_per_rhs"]
+    out = {"workload": "3D Q1 32x32x32 reaction-diffusion, k~lognormal(0,1), 1 RHS",
+           "n": plan.n, "max_front": plan.info["max_m"]}
+    ref = None
+    for prec in ("fp64", "fp32", "bf16"):
+        def step():
+            plan.factor(K, prec)
+            return plan.refine(K, b, tol=1e-12, max_it=60, x=x)
+        wall, dev, (xs, its, rr) = time_steps(step, steps, warmup)
+        xs = xs.clone()
+        if ref is None:
+            ref = xs
+        err = float(torch.linalg.norm(xs - ref) / torch.linalg.norm(ref))
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.factor(K, prec)
+        _sync()
+        tf = (time.perf_counter() - t0) / steps
+        out[prec] = {"ms_per_system": wall * 1e3, "ms_factor": tf * 1e3,
+                     "gflops": flops / wall / 1e9, "refine_corrections": its, "relres": rr,
+                     "err_vs_fp64": err}
+    return out
+
+
+def variant_batched(steps, warmup):
+    """256 independent 2D advection-diffusion meshes (sides 32..128) in one batch: every class
+    of all meshes in one launch sequence; FP64 and FP32-Schur, refined to 1e-12."""
+    import torch
+    from fixtures import config_problem
+    from paper_2306_08994_amd import Plan
+    p = config_problem(4)
+    plan = Plan(p.meshes)
+    K = torch.from_numpy(p.K).cuda()
+    b = torch.from_numpy(p.b).cuda()
+    x = torch.empty_like(b)
+    flops = plan.info["factor_flops"] + p.nrhs * plan.info["solve_flops_per_rhs"]
+    out = {"workload": "256 2D Q1 advection-diffusion meshes, sides U{32..128}, 1 RHS",
+           "n": plan.n, "systems": len(p.meshes), "fronts": plan.info["n_fronts"]}
+    ref = None
+    for prec in ("fp64", "fp32"):
+        def step():
+            plan.factor(K, prec)
+            return plan.refine(K, b, tol=1e-12, max_it=30, x=x)
+        wall, dev, (xs, its, rr) = time_steps(step, steps, warmup)
+        xs = xs.clone()
+        if ref is None:
+            ref = xs
+        err = float(torch.linalg.norm(xs - ref) / torch.linalg.norm(ref))
+        out[prec] = {"ms_per_batch": wall * 1e3, "ms_per_system": wall * 1e3 / len(p.meshes),
+                     "gflops": flops / wall / 1e9, "refine_corrections": its, "relres": rr,
+                     "err_vs_fp64": err}
+    return out
 
 
 def main():
@@ -23,12 +187,13 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU subtree mapping is a design, not part of this build)", file=sys.stderr)
+              "(the multi-GPU subtree mapping is described in the design, not built)",
+              file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
     from fixtures import config_problem
@@ -41,49 +206,54 @@ def main():
     t_analyse = time.perf_counter() - t0
     K = torch.from_numpy(p.K).to(dev)
     b = torch.from_numpy(p.b).to(dev)
+    x = torch.empty_like(b)
     info = plan.info
     nrhs = p.nrhs
 
     def step():
         plan.factor(K)
-        return plan.refine(K, b, tol=1e-12, max_it=5)
+        return plan.refine(K, b, tol=1e-12, max_it=5, x=x)
 
-    for _ in range(args.warmup):
-        x, its, rr = step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        x, its, rr = step()
-    torch.cuda.synchronize()
-    t_step = (time.perf_counter() - t0) / args.steps
-    # phase split
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan.factor(K)
-    torch.cuda.synchronize()
-    t_fac = (time.perf_counter() - t0) / args.steps
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        xs = plan.solve(b)
-    torch.cuda.synchronize()
-    t_sol = (time.perf_counter() - t0) / args.steps
+    t_step, t_dev, (_, its, rr) = time_steps(step, args.steps, args.warmup)
+    t_fac, _, _ = time_steps(lambda: plan.factor(K), args.steps, 1)
+    t_sol, _, _ = time_steps(lambda: plan.solve(b, out=x), args.steps, 1)
     flops = info["factor_flops"] + nrhs * info["solve_flops_per_rhs"]
+
+    # per-kernel event timing over the same steps (graphs off while profiling)
+    plan.profile(True)
+    for _ in range(args.steps):
+        step()
+    _sync()
+    rep = plan.profile_report()
+    plan.profile(False)
+    top, roof = roofline_of(rep)
+
     out = {
-        "metric": "factor+solve GFLOP/s (FP64, relres<=1e-12)",
+        "metric": "factor+solve GFLOP/s at relres<=1e-12 (FP64 multifrontal, 256x256 Q1, 8 RHS)",
         "value": flops / t_step / 1e9,
         "unit": "GFLOP/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": t_step * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "2D Q1 256x256 reaction-diffusion, k~lognormal(0,1), 8 RHS, FP64",
+        "config": {"workload": "2D Q1 256x256 reaction-diffusion, k~lognormal(0,1), 8 RHS, FP64, seed 2",
                    "n": info["n"], "fronts": info["n_fronts"], "classes": info["height"] + 1,
-                   "nrhs": nrhs},
+                   "nrhs": nrhs, "global_batch": 1, "parallelism": "single GPU"},
         "ms_per_system": t_step * 1e3,
         "ms_factor": t_fac * 1e3, "ms_solve": t_sol * 1e3, "ms_analyse_host": t_analyse * 1e3,
         "relres": rr, "refine_corrections": its,
+        "roofline": dict(roof, kernel=top["name"],
+                         avg_launch_us=top["ms"] * 1e3 / top["launches"],
+                         bytes_per_launch=top["bytes"] / top["launches"],
+                         flops_per_launch=top["flops"] / top["launches"]),
+        "kernels": rep["kernels"],
     }
+    if not args.no_variants:
+        vs = max(3, args.steps // 4)
+        out["mixed_precision_3d"] = variant_mixed(vs, 2)
+        out["batched_256_meshes"] = variant_batched(vs, 2)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))
 
 

@@ -149,6 +149,18 @@ int mf_elem_grad(const mf_plan *plan, const double *lam, const double *u, int32_
  * Synchronous.  Errors: MF_ESTATE (no valid factor), MF_EINVAL, MF_EHIP. */
 int mf_export_factors(const mf_plan *plan, double *L, double *U);
 
+/* Per-launch timing (tracing).  enable = 1 clears the counters and starts bracketing every
+ * kernel launch the plan issues with HIP events on the launch stream (captured graphs are not
+ * used while it is on); enable = 0 stops it.  Errors: MF_EINVAL. */
+int mf_profile(mf_plan *plan, int32_t enable);
+
+/* Writes a NUL-terminated JSON summary of the timed launches into buf (cap bytes, may be
+ * NULL): {"kernels": [{"name", "launches", "ms" (summed event time), "bytes", "flops"}]},
+ * where bytes and flops are the algorithmic HBM traffic and operation count of those launches.
+ * needed (may be NULL) receives the size required.  Waits for the recorded events.
+ * Errors: MF_EINVAL, MF_EHIP. */
+int mf_profile_report(mf_plan *plan, char *buf, int64_t cap, int64_t *needed);
+
 /* Releases the plan and all its device memory (NULL is ignored). */
 void mf_destroy(mf_plan *plan);
 

@@ -7,4 +7,13 @@ library; the first Plan does, and raises if it has not been built.
 """
 from .solver import MFError, Plan, analyse  # noqa: F401
 
-__all__ = ["Plan", "analyse", "MFError"]
+
+def __getattr__(name):
+    # the autograd wrapper needs torch; import it on first use only
+    if name in ("MFSolve", "mf_solve"):
+        from . import autograd
+        return getattr(autograd, name)
+    raise AttributeError(name)
+
+
+__all__ = ["Plan", "analyse", "MFError", "MFSolve", "mf_solve"]

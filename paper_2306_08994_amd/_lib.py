@@ -14,8 +14,8 @@ ERROR_NAMES = {MF_EINVAL: "MF_EINVAL", MF_ENOMEM: "MF_ENOMEM", MF_EZERO_PIVOT: "
                MF_EHIP: "MF_EHIP", MF_ENOCONV: "MF_ENOCONV", MF_ESTATE: "MF_ESTATE"}
 
 EXPORTED = ["mf_analyse", "mf_plan_info", "mf_plan_export_tree", "mf_set_tuning", "mf_factor", "mf_solve",
-            "mf_residual", "mf_refine", "mf_elem_grad", "mf_export_factors", "mf_destroy",
-            "mf_last_error"]
+            "mf_residual", "mf_refine", "mf_elem_grad", "mf_export_factors", "mf_profile",
+            "mf_profile_report", "mf_destroy", "mf_last_error"]
 
 
 class MfMesh(ctypes.Structure):
@@ -62,6 +62,8 @@ def load():
                                 POINTER(c_int32), dp, c_void_p]),
         "mf_elem_grad": (c_int32, [P, c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
         "mf_export_factors": (c_int32, [P, c_void_p, c_void_p]),
+        "mf_profile": (c_int32, [P, c_int32]),
+        "mf_profile_report": (c_int32, [P, c_char_p, c_int64, POINTER(c_int64)]),
         "mf_destroy": (None, [P]),
         "mf_last_error": (c_char_p, []),
     }

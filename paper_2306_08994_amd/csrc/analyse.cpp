@@ -240,6 +240,14 @@ std::string analyse(int32_t n_mesh, const int32_t *dims, const int32_t *npes,
           int32_t pos[2];
           for (int s = 0; s < 2; ++s) {
             const int32_t c = c2[s];
+            if (T.left[c] < 0 && kk[c] == 0) {
+              // pass-through leaf (no pivots): its contribution block is its element matrix, so
+              // the map points straight at the element's local node
+              pos[s] = -1;
+              for (int a = 0; a < npe; ++a)
+                if (conn[(int64_t)T.elem[c] * npe + a] == lst[i]) pos[s] = a;
+              continue;
+            }
             const int32_t *b0 = lidx.data() + lptr[c] + kk[c], *b1 = lidx.data() + lptr[c + 1];
             const int32_t *it = std::lower_bound(b0, b1, lst[i]);
             pos[s] = (it != b1 && *it == lst[i]) ? (int32_t)(it - b0) : -1;
@@ -284,10 +292,15 @@ void build_schedule(HostPlan &P, const Tuning &t) {
   P.levels.assign(P.height + 1, LevelSchedule());
   for (int64_t f = 0; f < P.F; ++f) {
     const FrontDesc &d = P.desc[f];
+    if (d.elem >= 0 && d.k == 0) continue;   // pass-through leaf: read directly by its parent
     LevelSchedule &L = P.levels[d.level];
     L.all.push_back((int32_t)f);
     L.max_m = std::max(L.max_m, d.m);
-    if (d.m <= t.small_max_m) {
+    L.max_k = std::max(L.max_k, d.k);
+    if (d.m <= std::min(t.tiny_max_m, t.small_max_m)) {
+      L.tiny.push_back((int32_t)f);
+      L.tiny_max_m = std::max(L.tiny_max_m, d.m);
+    } else if (d.m <= t.small_max_m) {
       L.small.push_back((int32_t)f);
       L.small_max_m = std::max(L.small_max_m, d.m);
     } else {

@@ -1,102 +1,9 @@
-// api.hip -- C ABI of libmf (declared in include/mf.h): device plan upload, the per-class launch
-// schedule of the factorization (Sec. 3.3: Foata classes run in order, fronts inside a class
-// run concurrently), the substitution sweeps, refinement and the adjoint helpers.
-#include <hip/hip_runtime.h>
+// api.hip -- C ABI of libmf (declared in include/mf.h).
+#include "api_core.hpp"
 
-#include <algorithm>
-#include <cmath>
-#include <cstdio>
-#include <cstring>
-#include <string>
-#include <vector>
-
-#include "../../include/mf.h"
-#include "kernels.hpp"
-#include "plan.hpp"
-
-namespace {
+namespace mfapi {
 
 thread_local std::string g_err;
-
-int fail(int code, const std::string &msg) {
-  g_err = msg;
-  return code;
-}
-
-#define HIPCHK(call)                                                                     \
-  do {                                                                                   \
-    hipError_t e_ = (call);                                                              \
-    if (e_ != hipSuccess)                                                                \
-      return fail(MF_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));           \
-  } while (0)
-
-struct StepDev {
-  int64_t fronts = 0, p0 = 0, n = 0;
-  int64_t update = 0, n_update = 0;
-  int64_t trsm_items = 0;
-};
-
-struct LevelDev {
-  int64_t small = 0, n_small = 0;
-  int32_t small_max_m = 0;
-  int64_t large = 0, n_large = 0;
-  int32_t large_max_m = 0;
-  int64_t all = 0, n_all = 0;
-  int32_t max_m = 0;
-  std::vector<StepDev> steps;
-  int64_t schur = 0, n_schur = 0;
-};
-
-template <typename T>
-void dfree(T *&p) {
-  if (p) (void)hipFree((void *)p);
-  p = nullptr;
-}
-
-}  // namespace
-
-struct mf_plan {
-  mf::HostPlan hp;
-  mf::Tuning tune;
-  int device = -1;
-  bool uploaded = false;
-  bool factored = false;
-  int max_shared = 65536;
-  mf::FrontDesc *d_desc = nullptr;
-  int32_t *d_front_idx = nullptr, *d_inv_l = nullptr, *d_inv_r = nullptr, *d_conn = nullptr;
-  int64_t *d_nptr = nullptr;
-  int32_t *d_nelem = nullptr;
-  int32_t *d_lists = nullptr;
-  mf::GemmTask *d_tasks = nullptr;
-  double *d_store = nullptr;
-  int *d_status = nullptr;
-  int *h_status = nullptr;
-  double *d_ycb = nullptr;
-  size_t ycb_cap = 0;
-  double *d_work = nullptr;
-  size_t work_cap = 0;
-  double *h_part = nullptr;
-  size_t part_cap = 0;
-  std::vector<LevelDev> lv;
-
-  ~mf_plan() {
-    dfree(d_desc);
-    dfree(d_front_idx);
-    dfree(d_inv_l);
-    dfree(d_inv_r);
-    dfree(d_conn);
-    dfree(d_nptr);
-    dfree(d_nelem);
-    dfree(d_lists);
-    dfree(d_tasks);
-    dfree(d_store);
-    dfree(d_status);
-    dfree(d_ycb);
-    dfree(d_work);
-    if (h_status) (void)hipHostFree(h_status);
-    if (h_part) (void)hipHostFree(h_part);
-  }
-};
 
 namespace {
 
@@ -109,6 +16,99 @@ int upload(T *&dst, const std::vector<T> &src) {
   return MF_OK;
 }
 
+// -- cost model -----------------------------------------------------------------------------
+double child_cb_entries(const mf::HostPlan &H, const mf::FrontDesc &d) {
+  if (d.elem >= 0) return (double)H.npe * H.npe;
+  double s = 0;
+  for (int32_t c : {d.left, d.right}) {
+    const mf::FrontDesc &x = H.desc[c];
+    s += (x.elem >= 0 && x.k == 0) ? (double)H.npe * H.npe : (double)(x.m - x.k) * (x.m - x.k);
+  }
+  return s;
+}
+
+double elim_flops(int32_t m, int32_t k) {
+  double f = 0;
+  for (int32_t p = 0; p < k; ++p) {
+    const double r = (double)(m - p);
+    f += (r - 1) + 2 * (r - 1) * (r - 1);
+  }
+  return f;
+}
+
+Cost front_factor_cost(const mf::HostPlan &H, int32_t f) {
+  const mf::FrontDesc &d = H.desc[f];
+  const double cb = child_cb_entries(H, d);
+  Cost c;
+  c.bytes = 8.0 * (cb + (double)d.m * d.m);
+  c.flops = elim_flops(d.m, d.k) + (d.elem >= 0 ? 0.0 : cb);
+  return c;
+}
+
+Cost gemm_cost(const std::vector<mf::GemmTask> &ts) {
+  Cost c;
+  for (const auto &t : ts) {
+    const double ni = t.i1 - t.i0, nj = t.j1 - t.j0, nq = t.q1 - t.q0;
+    c.flops += 2 * ni * nj * nq;
+    c.bytes += 8 * (2 * ni * nj + ni * nq + nq * nj);
+  }
+  return c;
+}
+
+void level_costs(const mf::HostPlan &H, const mf::LevelSchedule &S, LevelDev &D, int32_t nb) {
+  for (int32_t f : S.tiny) {
+    Cost c = front_factor_cost(H, f);
+    D.c_tiny.bytes += c.bytes;
+    D.c_tiny.flops += c.flops;
+  }
+  for (int32_t f : S.small) {
+    Cost c = front_factor_cost(H, f);
+    D.c_small.bytes += c.bytes;
+    D.c_small.flops += c.flops;
+  }
+  for (int32_t f : S.large) {
+    const mf::FrontDesc &d = H.desc[f];
+    const double cb = child_cb_entries(H, d);
+    D.c_assemble.bytes += 8.0 * (cb + (double)d.m * d.m);
+    D.c_assemble.flops += cb;
+  }
+  for (size_t s = 0; s < S.steps.size(); ++s) {
+    const mf::PanelStep &st = S.steps[s];
+    StepDev &sd = D.steps[s];
+    for (size_t i = 0; i < st.fronts.size(); ++i) {
+      const mf::FrontDesc &d = H.desc[st.fronts[i]];
+      const double pb = std::min(nb, d.k - st.p0[i]);
+      const double rest = d.m - st.p0[i] - pb;
+      sd.diag.bytes += 16 * pb * pb;
+      sd.diag.flops += elim_flops((int32_t)pb, (int32_t)pb);
+      sd.trsm.bytes += 8 * (pb * pb + 4 * rest * pb);
+      sd.trsm.flops += 2 * rest * pb * pb;
+    }
+    sd.upd = gemm_cost(st.update);
+  }
+  D.c_schur = gemm_cost(S.schur);
+  for (int32_t f : S.all) {
+    const mf::FrontDesc &d = H.desc[f];
+    const double m = d.m, k = d.k;
+    double ch = 0;
+    if (d.elem < 0)
+      for (int32_t c : {d.left, d.right}) {
+        const mf::FrontDesc &x = H.desc[c];
+        if (!(x.elem >= 0 && x.k == 0)) ch += x.m - x.k;
+      }
+    D.down_coef += 8 * (m * k - k * (k - 1) / 2);
+    D.down_rhs_bytes += 8 * (k + ch + (m - k) + k);
+    D.up_coef += 8 * (m * k - k * (k - 1) / 2);
+    D.up_rhs_bytes += 8 * (m + k);
+    for (int32_t p = 0; p < d.k; ++p) {
+      D.down_rhs_flops += 1 + 2 * (m - p - 1);
+      D.up_rhs_flops += 2 * (m - p - 1);
+    }
+  }
+}
+
+}  // namespace
+
 int ensure_uploaded(mf_plan *P) {
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
@@ -118,6 +118,7 @@ int ensure_uploaded(mf_plan *P) {
                                  " but the current device is " + std::to_string(dev));
     return MF_OK;
   }
+  P->drop_graphs();
   P->device = dev;
   HIPCHK(hipDeviceGetAttribute(&P->max_shared, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   mf::HostPlan &H = P->hp;
@@ -126,32 +127,35 @@ int ensure_uploaded(mf_plan *P) {
   while ((int64_t)(mm + 1) * ((mm + 1) | 1) * 8 <= P->max_shared) ++mm;
   P->tune.small_max_m = std::min<int32_t>(P->tune.small_max_m, mm);
   mf::build_schedule(H, P->tune);
-  // flatten the schedule
   std::vector<int32_t> lists;
   std::vector<mf::GemmTask> tasks;
   P->lv.assign(H.levels.size(), LevelDev());
+  auto put = [&](const std::vector<int32_t> &v) {
+    const int64_t off = (int64_t)lists.size();
+    lists.insert(lists.end(), v.begin(), v.end());
+    return off;
+  };
   for (size_t l = 0; l < H.levels.size(); ++l) {
     const mf::LevelSchedule &S = H.levels[l];
     LevelDev &D = P->lv[l];
-    D.small = (int64_t)lists.size();
+    D.tiny = put(S.tiny);
+    D.n_tiny = (int64_t)S.tiny.size();
+    D.tiny_max_m = S.tiny_max_m;
+    D.small = put(S.small);
     D.n_small = (int64_t)S.small.size();
     D.small_max_m = S.small_max_m;
-    lists.insert(lists.end(), S.small.begin(), S.small.end());
-    D.large = (int64_t)lists.size();
+    D.large = put(S.large);
     D.n_large = (int64_t)S.large.size();
     D.large_max_m = S.large_max_m;
-    lists.insert(lists.end(), S.large.begin(), S.large.end());
-    D.all = (int64_t)lists.size();
+    D.all = put(S.all);
     D.n_all = (int64_t)S.all.size();
     D.max_m = S.max_m;
-    lists.insert(lists.end(), S.all.begin(), S.all.end());
+    D.max_k = S.max_k;
     for (const mf::PanelStep &st : S.steps) {
       StepDev sd;
       sd.n = (int64_t)st.fronts.size();
-      sd.fronts = (int64_t)lists.size();
-      lists.insert(lists.end(), st.fronts.begin(), st.fronts.end());
-      sd.p0 = (int64_t)lists.size();
-      lists.insert(lists.end(), st.p0.begin(), st.p0.end());
+      sd.fronts = put(st.fronts);
+      sd.p0 = put(st.p0);
       sd.update = (int64_t)tasks.size();
       sd.n_update = (int64_t)st.update.size();
       tasks.insert(tasks.end(), st.update.begin(), st.update.end());
@@ -161,6 +165,7 @@ int ensure_uploaded(mf_plan *P) {
     D.schur = (int64_t)tasks.size();
     D.n_schur = (int64_t)S.schur.size();
     tasks.insert(tasks.end(), S.schur.begin(), S.schur.end());
+    level_costs(H, S, D, P->tune.nb);
   }
   // node -> (element, local node) pairs in ascending element order, for the residual
   std::vector<int64_t> nptr(H.n + 1, 0);
@@ -185,10 +190,13 @@ int ensure_uploaded(mf_plan *P) {
   if (!P->d_status) HIPCHK(hipMalloc((void **)&P->d_status, mf::kStatusWords * sizeof(int)));
   if (!P->h_status)
     HIPCHK(hipHostMalloc((void **)&P->h_status, mf::kStatusWords * sizeof(int), hipHostMallocDefault));
+  if (!P->cap_stream) HIPCHK(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
   // raise the dynamic-LDS limit of the kernels that size LDS per launch (best effort)
-  const void *dyn[] = {(const void *)mf::k_factor_small<256>, (const void *)mf::k_solve_down<false>,
-                       (const void *)mf::k_solve_down<true>, (const void *)mf::k_solve_up<false>,
-                       (const void *)mf::k_solve_up<true>};
+  const void *dyn[] = {(const void *)mf::k_factor_tiny, (const void *)mf::k_factor_small,
+                       (const void *)mf::k_solve_down_wave<false>, (const void *)mf::k_solve_down_wave<true>,
+                       (const void *)mf::k_solve_up_wave<false>, (const void *)mf::k_solve_up_wave<true>,
+                       (const void *)mf::k_solve_down_block<false>, (const void *)mf::k_solve_down_block<true>,
+                       (const void *)mf::k_solve_up_block<false>, (const void *)mf::k_solve_up_block<true>};
   for (const void *fn : dyn)
     (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, P->max_shared);
   (void)hipGetLastError();
@@ -196,8 +204,9 @@ int ensure_uploaded(mf_plan *P) {
   return MF_OK;
 }
 
-int grow(double *&buf, size_t &cap, size_t doubles) {
+int grow(mf_plan *P, double *&buf, size_t &cap, size_t doubles) {
   if (cap >= doubles && buf) return MF_OK;
+  P->drop_graphs();   // captured launches may hold the old pointer
   dfree(buf);
   cap = 0;
   if (hipMalloc((void **)&buf, std::max<size_t>(doubles, 1) * sizeof(double)) != hipSuccess)
@@ -206,57 +215,91 @@ int grow(double *&buf, size_t &cap, size_t doubles) {
   return MF_OK;
 }
 
+// -- launches -------------------------------------------------------------------------------
+struct Scope {
+  mf_plan *P;
+  hipStream_t s;
+  int kind;
+  Cost cost;
+  hipEvent_t a = nullptr;
+  Scope(mf_plan *P_, int kind_, Cost c, hipStream_t s_) : P(P_), s(s_), kind(kind_), cost(c) {
+    if (P->prof.on && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, s);
+  }
+  ~Scope() {
+    if (!a) return;
+    hipEvent_t b = nullptr;
+    if (hipEventCreate(&b) != hipSuccess) {
+      (void)hipEventDestroy(a);
+      return;
+    }
+    (void)hipEventRecord(b, s);
+    P->prof.recs.push_back(ProfRec{kind, a, b, cost});
+  }
+};
+
+#define LAUNCH(kind, cost, kern, grid, block, lds, stream, ...)                          \
+  do {                                                                                   \
+    ::mfapi::Scope sc_(P, kind, cost, stream);                                           \
+    hipLaunchKernelGGL(kern, grid, block, lds, stream, __VA_ARGS__);                     \
+  } while (0)
+
 int launch_factor(mf_plan *P, const double *K, int prec, hipStream_t s) {
   const mf::HostPlan &H = P->hp;
   hipLaunchKernelGGL(mf::k_clear_status, dim3(1), dim3(64), 0, s, P->d_status);
   for (size_t l = 0; l < P->lv.size(); ++l) {
     const LevelDev &D = P->lv[l];
+    if (D.n_tiny) {
+      const int m = D.tiny_max_m;
+      const int ldsw = m * (m | 1);
+      const int grid = (int)std::min<int64_t>((D.n_tiny + 3) / 4, 65535);
+      LAUNCH(K_TINY, D.c_tiny, mf::k_factor_tiny, dim3(grid), dim3(256), (size_t)4 * ldsw * 8, s,
+             P->d_desc, P->d_lists + D.tiny, (int)D.n_tiny, P->d_store, P->d_inv_l, P->d_inv_r, K,
+             H.npe, P->d_status, ldsw);
+    }
     if (D.n_small) {
       const int m = D.small_max_m;
       const size_t lds = (size_t)m * (m | 1) * sizeof(double);
       const int grid = (int)std::min<int64_t>(D.n_small, 16384);
-      hipLaunchKernelGGL(mf::k_factor_small<256>, dim3(grid), dim3(256), lds, s, P->d_desc,
-                         P->d_lists + D.small, (int)D.n_small, P->d_store, P->d_inv_l, P->d_inv_r,
-                         K, H.npe, P->d_status);
+      LAUNCH(K_SMALL, D.c_small, mf::k_factor_small, dim3(grid), dim3(256), lds, s, P->d_desc,
+             P->d_lists + D.small, (int)D.n_small, P->d_store, P->d_inv_l, P->d_inv_r, K, H.npe,
+             P->d_status);
     }
     if (D.n_large) {
-      hipLaunchKernelGGL(mf::k_assemble, dim3((D.large_max_m + 3) / 4, (unsigned)D.n_large),
-                         dim3(256), 0, s, P->d_desc, P->d_lists + D.large, P->d_store, P->d_inv_l,
-                         P->d_inv_r, K, H.npe);
+      LAUNCH(K_ASSEMBLE, D.c_assemble, mf::k_assemble,
+             dim3((D.large_max_m + 3) / 4, (unsigned)D.n_large), dim3(256), 0, s, P->d_desc,
+             P->d_lists + D.large, P->d_store, P->d_inv_l, P->d_inv_r, K, H.npe);
       for (const StepDev &st : D.steps) {
         const dim3 gd((unsigned)st.n), gt((unsigned)((st.trsm_items + 255) / 256), (unsigned)st.n);
         const int32_t *fr = P->d_lists + st.fronts, *p0 = P->d_lists + st.p0;
         switch (P->tune.nb) {
           case 16:
-            hipLaunchKernelGGL(mf::k_panel_diag<16>, gd, dim3(256), 0, s, P->d_desc, fr, p0, P->d_store, P->d_status);
+            LAUNCH(K_DIAG, st.diag, mf::k_panel_diag<16>, gd, dim3(256), 0, s, P->d_desc, fr, p0, P->d_store, P->d_status);
             if (st.trsm_items > 0)
-              hipLaunchKernelGGL(mf::k_panel_trsm<16>, gt, dim3(256), 0, s, P->d_desc, fr, p0, P->d_store);
+              LAUNCH(K_TRSM, st.trsm, mf::k_panel_trsm<16>, gt, dim3(256), 0, s, P->d_desc, fr, p0, P->d_store);
             break;
           case 64:
-            hipLaunchKernelGGL(mf::k_panel_diag<64>, gd, dim3(256), 0, s, P->d_desc, fr, p0, P->d_store, P->d_status);
+            LAUNCH(K_DIAG, st.diag, mf::k_panel_diag<64>, gd, dim3(256), 0, s, P->d_desc, fr, p0, P->d_store, P->d_status);
             if (st.trsm_items > 0)
-              hipLaunchKernelGGL(mf::k_panel_trsm<64>, gt, dim3(256), 0, s, P->d_desc, fr, p0, P->d_store);
+              LAUNCH(K_TRSM, st.trsm, mf::k_panel_trsm<64>, gt, dim3(256), 0, s, P->d_desc, fr, p0, P->d_store);
             break;
           default:
-            hipLaunchKernelGGL(mf::k_panel_diag<32>, gd, dim3(256), 0, s, P->d_desc, fr, p0, P->d_store, P->d_status);
+            LAUNCH(K_DIAG, st.diag, mf::k_panel_diag<32>, gd, dim3(256), 0, s, P->d_desc, fr, p0, P->d_store, P->d_status);
             if (st.trsm_items > 0)
-              hipLaunchKernelGGL(mf::k_panel_trsm<32>, gt, dim3(256), 0, s, P->d_desc, fr, p0, P->d_store);
+              LAUNCH(K_TRSM, st.trsm, mf::k_panel_trsm<32>, gt, dim3(256), 0, s, P->d_desc, fr, p0, P->d_store);
         }
         if (st.n_update)
-          hipLaunchKernelGGL(mf::k_gemm_update<0>, dim3((unsigned)st.n_update), dim3(256), 0, s,
-                             P->d_desc, P->d_tasks + st.update, P->d_store);
+          LAUNCH(K_GEMM_PANEL, st.upd, mf::k_gemm_update<0>, dim3((unsigned)st.n_update), dim3(256), 0,
+                 s, P->d_desc, P->d_tasks + st.update, P->d_store);
       }
       if (D.n_schur) {
         const mf::GemmTask *t = P->d_tasks + D.schur;
+        const dim3 g((unsigned)D.n_schur);
         if (prec == MF_SCHUR_FP32)
-          hipLaunchKernelGGL(mf::k_gemm_update<1>, dim3((unsigned)D.n_schur), dim3(256), 0, s,
-                             P->d_desc, t, P->d_store);
+          LAUNCH(K_GEMM_SCHUR, D.c_schur, mf::k_gemm_update<1>, g, dim3(256), 0, s, P->d_desc, t, P->d_store);
         else if (prec == MF_SCHUR_BF16)
-          hipLaunchKernelGGL(mf::k_gemm_update<2>, dim3((unsigned)D.n_schur), dim3(256), 0, s,
-                             P->d_desc, t, P->d_store);
+          LAUNCH(K_GEMM_SCHUR, D.c_schur, mf::k_gemm_update<2>, g, dim3(256), 0, s, P->d_desc, t, P->d_store);
         else
-          hipLaunchKernelGGL(mf::k_gemm_update<0>, dim3((unsigned)D.n_schur), dim3(256), 0, s,
-                             P->d_desc, t, P->d_store);
+          LAUNCH(K_GEMM_SCHUR, D.c_schur, mf::k_gemm_update<0>, g, dim3(256), 0, s, P->d_desc, t, P->d_store);
       }
     }
   }
@@ -264,48 +307,114 @@ int launch_factor(mf_plan *P, const double *K, int prec, hipStream_t s) {
   return MF_OK;
 }
 
-int chunk_for(const mf_plan *P, int32_t max_m, int32_t nrhs) {
+constexpr int kWaveSolveMaxM = 64;
+
+// Largest power-of-two column chunk (<= nrhs) whose LDS footprint fits.
+int chunk(const mf_plan *P, int32_t nrhs, int64_t fixed_doubles, int64_t per_col_doubles) {
   int nc = 1;
-  while (nc * 2 <= nrhs && (int64_t)max_m * nc * 2 * 8 <= P->max_shared) nc *= 2;
+  while (nc * 2 <= nrhs && (fixed_doubles + per_col_doubles * nc * 2) * 8 <= P->max_shared) nc *= 2;
   return nc;
 }
 
-int launch_solve(const mf_plan *P, const double *b, double *x, int32_t nrhs, bool trans,
-                 hipStream_t s) {
-  const int gridcap = 8192;
-  for (size_t l = 0; l < P->lv.size(); ++l) {
-    const LevelDev &D = P->lv[l];
-    if (!D.n_all) continue;
-    const int nc = chunk_for(P, D.max_m, nrhs);
-    const size_t lds = (size_t)D.max_m * nc * sizeof(double);
-    const int grid = (int)std::min<int64_t>(D.n_all, gridcap);
-    if (trans)
-      hipLaunchKernelGGL(mf::k_solve_down<true>, dim3(grid), dim3(256), lds, s, P->d_desc,
-                         P->d_lists + D.all, (int)D.n_all, P->d_store, P->d_front_idx, P->d_inv_l,
-                         P->d_inv_r, b, x, P->d_ycb, nrhs, nc);
-    else
-      hipLaunchKernelGGL(mf::k_solve_down<false>, dim3(grid), dim3(256), lds, s, P->d_desc,
-                         P->d_lists + D.all, (int)D.n_all, P->d_store, P->d_front_idx, P->d_inv_l,
-                         P->d_inv_r, b, x, P->d_ycb, nrhs, nc);
-  }
-  for (size_t l = P->lv.size(); l-- > 0;) {
-    const LevelDev &D = P->lv[l];
-    if (!D.n_all) continue;
-    const int nc = chunk_for(P, D.max_m, nrhs);
-    const size_t lds = (size_t)D.max_m * nc * sizeof(double);
-    const int grid = (int)std::min<int64_t>(D.n_all, gridcap);
-    if (trans)
-      hipLaunchKernelGGL(mf::k_solve_up<true>, dim3(grid), dim3(256), lds, s, P->d_desc,
-                         P->d_lists + D.all, (int)D.n_all, P->d_store, P->d_front_idx, x, nrhs, nc);
-    else
-      hipLaunchKernelGGL(mf::k_solve_up<false>, dim3(grid), dim3(256), lds, s, P->d_desc,
-                         P->d_lists + D.all, (int)D.n_all, P->d_store, P->d_front_idx, x, nrhs, nc);
+int launch_solve(mf_plan *P, const double *b, double *x, int32_t nrhs, bool trans, hipStream_t s) {
+  const int gridcap = 16384;
+  for (int pass = 0; pass < 2; ++pass) {
+    const bool down = pass == 0;
+    for (size_t step = 0; step < P->lv.size(); ++step) {
+      const size_t l = down ? step : P->lv.size() - 1 - step;
+      const LevelDev &D = P->lv[l];
+      if (!D.n_all) continue;
+      Cost c;
+      c.bytes = (down ? D.down_coef : D.up_coef) + nrhs * (down ? D.down_rhs_bytes : D.up_rhs_bytes);
+      c.flops = nrhs * (down ? D.down_rhs_flops : D.up_rhs_flops);
+      const int32_t *lst = P->d_lists + D.all;
+      const int n = (int)D.n_all;
+      const int mmax = std::max(1, D.max_m), kmax = std::max(1, D.max_k);
+      if (D.max_m <= kWaveSolveMaxM) {
+        // per wave: W (mmax x nc) + coefficients
+        const int cld = down ? (kmax | 1) : (mmax | 1);
+        const int64_t cdoubles = down ? (int64_t)mmax * cld : (int64_t)kmax * cld;
+        const int nc = chunk(P, nrhs, 4 * cdoubles, 4 * (int64_t)mmax);
+        const int ldsw = (int)(mmax * nc + cdoubles);
+        const size_t lds = (size_t)4 * ldsw * 8;
+        const int grid = (int)std::min<int64_t>((n + 3) / 4, gridcap);
+        if (down && trans)
+          LAUNCH(K_DOWN_WAVE, c, mf::k_solve_down_wave<true>, dim3(grid), dim3(256), lds, s, P->d_desc,
+                 lst, n, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, b, x, P->d_ycb, nrhs, nc,
+                 mmax, cld, ldsw);
+        else if (down)
+          LAUNCH(K_DOWN_WAVE, c, mf::k_solve_down_wave<false>, dim3(grid), dim3(256), lds, s, P->d_desc,
+                 lst, n, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, b, x, P->d_ycb, nrhs, nc,
+                 mmax, cld, ldsw);
+        else if (trans)
+          LAUNCH(K_UP_WAVE, c, mf::k_solve_up_wave<true>, dim3(grid), dim3(256), lds, s, P->d_desc, lst,
+                 n, P->d_store, P->d_front_idx, x, nrhs, nc, mmax, cld, ldsw);
+        else
+          LAUNCH(K_UP_WAVE, c, mf::k_solve_up_wave<false>, dim3(grid), dim3(256), lds, s, P->d_desc, lst,
+                 n, P->d_store, P->d_front_idx, x, nrhs, nc, mmax, cld, ldsw);
+      } else {
+        const int64_t fixed = (int64_t)mf::NBS * (mf::NBS + 1);
+        const int nc = chunk(P, nrhs, fixed, mmax + mf::NBS);
+        const size_t lds = (size_t)(fixed + (int64_t)(mmax + mf::NBS) * nc) * 8;
+        const int grid = std::min(n, gridcap);
+        if (down && trans)
+          LAUNCH(K_DOWN_BLOCK, c, mf::k_solve_down_block<true>, dim3(grid), dim3(256), lds, s, P->d_desc,
+                 lst, n, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, b, x, P->d_ycb, nrhs, nc, mmax);
+        else if (down)
+          LAUNCH(K_DOWN_BLOCK, c, mf::k_solve_down_block<false>, dim3(grid), dim3(256), lds, s, P->d_desc,
+                 lst, n, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, b, x, P->d_ycb, nrhs, nc, mmax);
+        else if (trans)
+          LAUNCH(K_UP_BLOCK, c, mf::k_solve_up_block<true>, dim3(grid), dim3(256), lds, s, P->d_desc, lst,
+                 n, P->d_store, P->d_front_idx, x, nrhs, nc, mmax);
+        else
+          LAUNCH(K_UP_BLOCK, c, mf::k_solve_up_block<false>, dim3(grid), dim3(256), lds, s, P->d_desc, lst,
+                 n, P->d_store, P->d_front_idx, x, nrhs, nc, mmax);
+      }
+    }
   }
   HIPCHK(hipGetLastError());
   return MF_OK;
 }
 
-// max over columns of ||a_c||_2 / ||ref_c||_2 (ref may be null: plain norms returned in out)
+// Runs `launch` on `s`, through a cached hipGraph when graphs are enabled and profiling is off.
+// The graph is captured on the plan's private stream (the caller's stream may be the null
+// stream, which cannot be captured) and replayed on `s`.
+template <typename F>
+int run_graphed(mf_plan *P, Graph *cache, int n_cache, int &next, const GraphKey &key,
+                hipStream_t s, F &&launch) {
+  if (!P->use_graphs || P->prof.on) return launch(s);
+  int slot = -1;
+  for (int i = 0; i < n_cache; ++i)
+    if (cache[i].exec && cache[i].key == key) slot = i;
+  if (slot < 0) {
+    slot = next;
+    next = (next + 1) % n_cache;
+  }
+  Graph &g = cache[slot];
+  if (!(g.exec && g.key == key)) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g = Graph();
+    HIPCHK(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
+    const int rc = launch(P->cap_stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(P->cap_stream, &graph);
+    if (rc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(MF_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    const hipError_t e2 = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e2 != hipSuccess) {
+      g.exec = nullptr;
+      return fail(MF_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+    }
+    g.key = key;
+  }
+  HIPCHK(hipGraphLaunch(g.exec, s));
+  return MF_OK;
+}
+
 int col_norms(mf_plan *P, const double *a, int64_t n, int32_t nrhs, hipStream_t s,
               std::vector<double> &out) {
   const int64_t rows_per = 4096;
@@ -318,8 +427,7 @@ int col_norms(mf_plan *P, const double *a, int64_t n, int32_t nrhs, hipStream_t 
     HIPCHK(hipHostMalloc((void **)&P->h_part, need * sizeof(double), hipHostMallocDefault));
     P->part_cap = need;
   }
-  // partials live at the tail of the work buffer
-  double *dpart = P->d_work + 2 * (size_t)n * nrhs;
+  double *dpart = P->d_work + 2 * (size_t)n * nrhs;   // tail of the refinement workspace
   hipLaunchKernelGGL(mf::k_colsq_partial, dim3((unsigned)blocks), dim3(256), 0, s, a, n, nrhs,
                      rows_per, dpart);
   HIPCHK(hipGetLastError());
@@ -332,7 +440,9 @@ int col_norms(mf_plan *P, const double *a, int64_t n, int32_t nrhs, hipStream_t 
   return MF_OK;
 }
 
-}  // namespace
+}  // namespace mfapi
+
+using namespace mfapi;
 
 extern "C" {
 
@@ -413,6 +523,7 @@ int mf_set_tuning(mf_plan *P, int32_t small_max_m, int32_t nb) {
   if (nb > 0) P->tune.nb = nb;
   P->uploaded = false;      // the schedule is rebuilt at the next device call
   P->factored = false;
+  P->drop_graphs();
   return MF_OK;
 }
 
@@ -424,7 +535,12 @@ int mf_factor(mf_plan *P, const double *elem_mats, int32_t precision, void *hip_
   if (rc) return rc;
   hipStream_t s = (hipStream_t)hip_stream;
   P->factored = false;
-  if ((rc = launch_factor(P, elem_mats, precision, s))) return rc;
+  GraphKey key;
+  key.p0 = elem_mats;
+  key.a = precision;
+  rc = run_graphed(P, P->g_factor, 2, P->g_factor_next, key, s,
+                   [&](hipStream_t st) { return launch_factor(P, elem_mats, precision, st); });
+  if (rc) return rc;
   HIPCHK(hipMemcpyAsync(P->h_status, P->d_status, mf::kStatusWords * sizeof(int),
                         hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -443,8 +559,15 @@ int mf_solve(const mf_plan *Pc, const double *b, double *x, int32_t nrhs, int32_
   if (transpose != 0 && transpose != 1) return fail(MF_EINVAL, "transpose must be 0 or 1");
   if (!P->factored) return fail(MF_ESTATE, "no valid factorization: call mf_factor first");
   int rc;
-  if ((rc = grow(P->d_ycb, P->ycb_cap, (size_t)std::max<int64_t>(1, P->hp.sum_c) * nrhs))) return rc;
-  return launch_solve(P, b, x, nrhs, transpose != 0, (hipStream_t)hip_stream);
+  if ((rc = grow(P, P->d_ycb, P->ycb_cap, (size_t)std::max<int64_t>(1, P->hp.sum_c) * nrhs)))
+    return rc;
+  GraphKey key;
+  key.p0 = b;
+  key.p1 = x;
+  key.a = nrhs;
+  key.b = transpose;
+  return run_graphed(P, P->g_solve, 4, P->g_solve_next, key, (hipStream_t)hip_stream,
+                     [&](hipStream_t st) { return launch_solve(P, b, x, nrhs, transpose != 0, st); });
 }
 
 int mf_residual(const mf_plan *P, const double *elem_mats, const double *x, const double *b,
@@ -474,7 +597,7 @@ int mf_refine(const mf_plan *Pc, const double *elem_mats, const double *b, doubl
   const size_t nn = (size_t)n * nrhs;
   const size_t parts = (size_t)std::max<int64_t>(1, (n + 4095) / 4096) * nrhs;
   int rc;
-  if ((rc = grow(P->d_work, P->work_cap, 2 * nn + parts))) return rc;
+  if ((rc = grow(P, P->d_work, P->work_cap, 2 * nn + parts))) return rc;
   double *r = P->d_work, *dx = P->d_work + nn;
   if ((rc = mf_solve(P, b, x, nrhs, 0, hip_stream))) return rc;
   std::vector<double> bn, rn;
@@ -540,6 +663,54 @@ int mf_export_factors(const mf_plan *P, double *L, double *U) {
         Uf[(int64_t)p * d.m + i] = i > p ? Fm[(int64_t)p * d.m + i] : (i == p ? 1.0 : 0.0);
       }
     off += (int64_t)d.m * d.k;
+  }
+  return MF_OK;
+}
+
+int mf_profile(mf_plan *P, int32_t enable) {
+  if (!P) return fail(MF_EINVAL, "null plan");
+  for (auto &r : P->prof.recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  P->prof = Profiler();
+  P->prof.on = enable != 0;
+  return MF_OK;
+}
+
+int mf_profile_report(mf_plan *P, char *buf, int64_t cap, int64_t *needed) {
+  if (!P) return fail(MF_EINVAL, "null plan");
+  Profiler &pr = P->prof;
+  for (auto &r : pr.recs) {
+    HIPCHK(hipEventSynchronize(r.b));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+    pr.ms[r.kind] += ms;
+    pr.bytes[r.kind] += r.cost.bytes;
+    pr.flops[r.kind] += r.cost.flops;
+    pr.launches[r.kind] += 1;
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  pr.recs.clear();
+  std::string js = "{\"kernels\": [";
+  bool first = true;
+  for (int k = 0; k < K_COUNT; ++k) {
+    if (!pr.launches[k]) continue;
+    char line[256];
+    std::snprintf(line, sizeof line,
+                  "%s{\"name\": \"%s\", \"launches\": %lld, \"ms\": %.6f, \"bytes\": %.6e, \"flops\": %.6e}",
+                  first ? "" : ", ", kKindName[k], (long long)pr.launches[k], pr.ms[k], pr.bytes[k],
+                  pr.flops[k]);
+    js += line;
+    first = false;
+  }
+  js += "]}";
+  if (needed) *needed = (int64_t)js.size() + 1;
+  if (buf && cap > 0) {
+    const size_t n = std::min<size_t>((size_t)cap - 1, js.size());
+    std::memcpy(buf, js.data(), n);
+    buf[n] = 0;
   }
   return MF_OK;
 }

@@ -1,0 +1,177 @@
+// api_core.hpp -- host side of libmf: the device plan (uploaded once per plan), algorithmic
+// cost model per launch, optional per-launch event timing, hipGraph capture of the per-class
+// launch sequences, and the launch schedules of the factor and the solve.
+//
+// Scheduling (Sec. 3.3): Foata classes are executed in order, and all fronts of one class are
+// independent tasks.  Each class is a handful of launches over the class's front lists (the
+// bag of tasks); stream order is the barrier between classes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mf.h"
+#include "common.hpp"
+#include "factor_kernels.hpp"
+#include "plan.hpp"
+#include "solve_kernels.hpp"
+
+namespace mfapi {
+
+extern thread_local std::string g_err;
+
+inline int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(call)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return ::mfapi::fail(MF_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));  \
+  } while (0)
+
+enum Kind {
+  K_TINY, K_SMALL, K_ASSEMBLE, K_DIAG, K_TRSM, K_GEMM_PANEL, K_GEMM_SCHUR,
+  K_DOWN_WAVE, K_DOWN_BLOCK, K_UP_WAVE, K_UP_BLOCK, K_RESIDUAL, K_OTHER, K_COUNT
+};
+static const char *const kKindName[K_COUNT] = {
+    "factor_tiny", "factor_small", "assemble", "panel_diag", "panel_trsm", "gemm_panel",
+    "gemm_schur", "solve_down_wave", "solve_down_block", "solve_up_wave", "solve_up_block",
+    "residual", "other"};
+
+// Algorithmic traffic and work of one launch (bytes that must cross HBM at least once, flops
+// of the method's own operation count).
+struct Cost {
+  double bytes = 0, flops = 0;
+};
+
+struct StepDev {
+  int64_t fronts = 0, p0 = 0, n = 0;
+  int64_t update = 0, n_update = 0;
+  int64_t trsm_items = 0;
+  Cost diag, trsm, upd;
+};
+
+struct LevelDev {
+  int64_t tiny = 0, n_tiny = 0;
+  int32_t tiny_max_m = 0;
+  int64_t small = 0, n_small = 0;
+  int32_t small_max_m = 0;
+  int64_t large = 0, n_large = 0;
+  int32_t large_max_m = 0;
+  int64_t all = 0, n_all = 0;
+  int32_t max_m = 0, max_k = 0;
+  std::vector<StepDev> steps;
+  int64_t schur = 0, n_schur = 0;
+  Cost c_tiny, c_small, c_assemble, c_schur;
+  // solves: fixed (coefficient) bytes, bytes and flops per right-hand side
+  double down_coef = 0, down_rhs_bytes = 0, down_rhs_flops = 0;
+  double up_coef = 0, up_rhs_bytes = 0, up_rhs_flops = 0;
+};
+
+struct ProfRec {
+  int kind;
+  hipEvent_t a, b;
+  Cost cost;
+};
+
+struct Profiler {
+  bool on = false;
+  std::vector<ProfRec> recs;
+  double ms[K_COUNT] = {0};
+  double bytes[K_COUNT] = {0};
+  double flops[K_COUNT] = {0};
+  int64_t launches[K_COUNT] = {0};
+};
+
+struct GraphKey {
+  const void *p0 = nullptr, *p1 = nullptr;
+  int32_t a = -1, b = -1;
+  bool operator==(const GraphKey &o) const { return p0 == o.p0 && p1 == o.p1 && a == o.a && b == o.b; }
+};
+
+struct Graph {
+  hipGraphExec_t exec = nullptr;
+  GraphKey key;
+};
+
+template <typename T>
+void dfree(T *&p) {
+  if (p) (void)hipFree((void *)p);
+  p = nullptr;
+}
+
+}  // namespace mfapi
+
+struct mf_plan {
+  mf::HostPlan hp;
+  mf::Tuning tune;
+  int device = -1;
+  bool uploaded = false;
+  bool factored = false;
+  bool use_graphs = true;
+  int max_shared = 65536;
+  mf::FrontDesc *d_desc = nullptr;
+  int32_t *d_front_idx = nullptr, *d_inv_l = nullptr, *d_inv_r = nullptr, *d_conn = nullptr;
+  int64_t *d_nptr = nullptr;
+  int32_t *d_nelem = nullptr;
+  int32_t *d_lists = nullptr;
+  mf::GemmTask *d_tasks = nullptr;
+  double *d_store = nullptr;
+  int *d_status = nullptr;
+  int *h_status = nullptr;
+  double *d_ycb = nullptr;
+  size_t ycb_cap = 0;
+  double *d_work = nullptr;
+  size_t work_cap = 0;
+  double *h_part = nullptr;
+  size_t part_cap = 0;
+  std::vector<mfapi::LevelDev> lv;
+  mfapi::Profiler prof;
+  hipStream_t cap_stream = nullptr;
+  mfapi::Graph g_factor[2], g_solve[4];   // small caches, least recently captured evicted
+  int g_factor_next = 0, g_solve_next = 0;
+
+  void drop_graphs() {
+    for (auto &g : g_factor) {
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+      g = mfapi::Graph();
+    }
+    for (auto &g : g_solve) {
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+      g = mfapi::Graph();
+    }
+  }
+
+  ~mf_plan() {
+    drop_graphs();
+    for (auto &r : prof.recs) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    mfapi::dfree(d_desc);
+    mfapi::dfree(d_front_idx);
+    mfapi::dfree(d_inv_l);
+    mfapi::dfree(d_inv_r);
+    mfapi::dfree(d_conn);
+    mfapi::dfree(d_nptr);
+    mfapi::dfree(d_nelem);
+    mfapi::dfree(d_lists);
+    mfapi::dfree(d_tasks);
+    mfapi::dfree(d_store);
+    mfapi::dfree(d_status);
+    mfapi::dfree(d_ycb);
+    mfapi::dfree(d_work);
+    if (h_status) (void)hipHostFree(h_status);
+    if (h_part) (void)hipHostFree(h_part);
+  }
+};

@@ -1,0 +1,100 @@
+// common.hpp -- device-side helpers shared by the factor and solve kernels.
+//
+// Storage: every front f owns an m x m row-major FP64 block at store + desc[f].store.  After the
+// front is factored it holds, in place,
+//   L (pivots on the diagonal)  at rows p..m-1 of columns p < k,
+//   U (unit diagonal, implicit) at columns p+1..m-1 of rows p < k,
+//   the Schur complement (contribution block, CB) in rows and columns k..m-1,
+// i.e. the result of the division / multiplication / subtraction tasks of Table 2 applied to
+// the assembled front.  A parent reads its children's CBs straight from their storage.
+// A leaf without pivots is never stored: its CB is its element matrix, and the parent's
+// extend-add map addresses the element matrix directly.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <type_traits>
+
+#include "plan.hpp"
+
+namespace mf {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+constexpr int kStatusWords = 4;   // [0] error flag, [1] front, [2] pivot
+
+__device__ inline void record_bad_pivot(int *st, int f, int p) {
+  if (atomicCAS(st, 0, 1) == 0) {
+    st[1] = f;
+    st[2] = p;
+  }
+}
+
+__device__ inline bool good_pivot(double v) { return v != 0.0 && __builtin_isfinite(v); }
+
+// Orders the LDS traffic of one wave: every LDS access the wave issued before is complete and
+// visible to the accesses it issues after (a wave executes in lockstep, so no s_barrier).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline bool passthrough(const FrontDesc &c) { return c.elem >= 0 && c.k == 0; }
+
+__global__ void k_clear_status(int *st) {
+  if (threadIdx.x < kStatusWords) st[threadIdx.x] = 0;
+}
+
+// Sources of the extend-add of one front: its element matrix (a leaf), or its two children's
+// contribution blocks (left first, then right), each with its leading dimension.
+struct GatherCtx {
+  const double *ke;   // element matrix of a leaf front, else null
+  const double *ca, *cb;
+  int la, lb, npe;
+};
+
+__device__ inline GatherCtx gather_ctx(const FrontDesc *__restrict__ fd, const FrontDesc &d,
+                                       const double *__restrict__ store,
+                                       const double *__restrict__ K, int npe) {
+  GatherCtx g;
+  g.npe = npe;
+  g.ke = nullptr;
+  g.ca = g.cb = nullptr;
+  g.la = g.lb = 0;
+  if (d.elem >= 0) {
+    g.ke = K + (int64_t)d.elem * npe * npe;
+    return g;
+  }
+  const FrontDesc a = fd[d.left], b = fd[d.right];
+  if (passthrough(a)) {
+    g.ca = K + (int64_t)a.elem * npe * npe;
+    g.la = npe;
+  } else {
+    g.ca = store + a.store + (int64_t)a.k * a.m + a.k;
+    g.la = a.m;
+  }
+  if (passthrough(b)) {
+    g.cb = K + (int64_t)b.elem * npe * npe;
+    g.lb = npe;
+  } else {
+    g.cb = store + b.store + (int64_t)b.k * b.m + b.k;
+    g.lb = b.m;
+  }
+  return g;
+}
+
+// Entry (i, j) of the assembled front from the maps of rows i and j: for a leaf, li/lj are
+// local element nodes; otherwise li/lj (ri/rj) index the left (right) child's CB, -1 = absent.
+__device__ inline double gather_entry(const GatherCtx &g, int li, int lj, int ri, int rj) {
+  if (g.ke) return g.ke[li * g.npe + lj];
+  double v = 0.0;
+  if ((li | lj) >= 0) v += g.ca[(int64_t)li * g.la + lj];
+  if ((ri | rj) >= 0) v += g.cb[(int64_t)ri * g.lb + rj];
+  return v;
+}
+
+}  // namespace mf

@@ -1,0 +1,336 @@
+// factor_kernels.hpp -- gfx950 kernels of the multifrontal factorization.
+//
+// Per Foata class, every front is assembled (extend-add of its children's contribution blocks,
+// or its element matrix for a leaf) and partially eliminated: for each pivot p the division
+// tasks scale row p by the pivot, then every (i, j) > p receives its multiplication and
+// subtraction F[i][j] -= F[i][p] U[p][j] (Table 2).  Three routes by front width:
+//   tiny   one wave per front, front in LDS, wave-level ordering only;
+//   small  one workgroup per front, front in LDS;
+//   tiled  front in HBM: extend-add, then panels of NB pivots (diagonal-block LU, the two
+//          triangular panel solves, trailing update of the fully summed rows and columns), then
+//          the Schur update C22 -= L21 U12 as one MFMA GEMM.
+#pragma once
+
+#include "common.hpp"
+
+namespace mf {
+
+// ---------------------------------------------------------------------------------------------
+// tiny: one wave per front, four fronts per workgroup, grid-stride over the class's list.
+// ---------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_factor_tiny(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ list, int nlist,
+              double *__restrict__ store, const int32_t *__restrict__ inv_l,
+              const int32_t *__restrict__ inv_r, const double *__restrict__ K, int npe,
+              int *__restrict__ status, int ldsw) {
+  extern __shared__ double sm[];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double *sh = sm + wv * ldsw;
+  for (int li = blockIdx.x * 4 + wv; li < nlist; li += gridDim.x * 4) {
+    const int f = list[li];
+    const FrontDesc d = fd[f];
+    const int m = d.m, k = d.k, ld = m | 1;
+    const int32_t *il = inv_l + d.idx;
+    const int32_t *ir = inv_r + d.idx;
+    const GatherCtx g = gather_ctx(fd, d, store, K, npe);
+    for (int t = lane; t < m * m; t += 64) {
+      const int i = t / m, j = t - (t / m) * m;
+      sh[i * ld + j] = gather_entry(g, il[i], il[j], ir[i], ir[j]);
+    }
+    wave_sync();
+    for (int p = 0; p < k; ++p) {
+      const double piv = sh[p * ld + p];
+      if (!good_pivot(piv)) {
+        if (lane == 0) record_bad_pivot(status, f, p);
+        break;
+      }
+      for (int j = p + 1 + lane; j < m; j += 64) sh[p * ld + j] = sh[p * ld + j] / piv;
+      wave_sync();
+      const int r = m - p - 1;
+      for (int t = lane; t < r * r; t += 64) {
+        const int i = p + 1 + t / r, j = p + 1 + (t - (t / r) * r);
+        sh[i * ld + j] -= sh[i * ld + p] * sh[p * ld + j];
+      }
+      wave_sync();
+    }
+    double *out = store + d.store;
+    for (int t = lane; t < m * m; t += 64) {
+      const int i = t / m, j = t - (t / m) * m;
+      out[t] = sh[i * ld + j];
+    }
+    wave_sync();
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// small: one workgroup per front, the whole front resident in LDS.
+// ---------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_factor_small(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ list, int nlist,
+               double *__restrict__ store, const int32_t *__restrict__ inv_l,
+               const int32_t *__restrict__ inv_r, const double *__restrict__ K, int npe,
+               int *__restrict__ status) {
+  extern __shared__ double sh[];
+  const int tid = threadIdx.x;
+  for (int li = blockIdx.x; li < nlist; li += gridDim.x) {
+    const int f = list[li];
+    const FrontDesc d = fd[f];
+    const int m = d.m, k = d.k, ld = m | 1;
+    const int32_t *il = inv_l + d.idx;
+    const int32_t *ir = inv_r + d.idx;
+    const GatherCtx g = gather_ctx(fd, d, store, K, npe);
+    for (int t = tid; t < m * m; t += 256) {
+      const int i = t / m, j = t - (t / m) * m;
+      sh[i * ld + j] = gather_entry(g, il[i], il[j], ir[i], ir[j]);
+    }
+    __syncthreads();
+    for (int p = 0; p < k; ++p) {
+      const double piv = sh[p * ld + p];
+      if (!good_pivot(piv)) {
+        if (tid == 0) record_bad_pivot(status, f, p);
+        break;
+      }
+      for (int j = p + 1 + tid; j < m; j += 256) sh[p * ld + j] = sh[p * ld + j] / piv;
+      __syncthreads();
+      const int r = m - p - 1;
+      for (int t = tid; t < r * r; t += 256) {
+        const int i = p + 1 + t / r, j = p + 1 + (t - (t / r) * r);
+        sh[i * ld + j] -= sh[i * ld + p] * sh[p * ld + j];
+      }
+      __syncthreads();
+    }
+    double *out = store + d.store;
+    for (int t = tid; t < m * m; t += 256) {
+      const int i = t / m, j = t - (t / m) * m;
+      out[t] = sh[i * ld + j];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// tiled path
+// ---------------------------------------------------------------------------------------------
+
+// Extend-add into the front's storage.  grid = (row strips of 4, fronts).
+__global__ void __launch_bounds__(256)
+k_assemble(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ list,
+           double *__restrict__ store, const int32_t *__restrict__ inv_l,
+           const int32_t *__restrict__ inv_r, const double *__restrict__ K, int npe) {
+  const int f = list[blockIdx.y];
+  const FrontDesc d = fd[f];
+  const int m = d.m;
+  const int i0 = blockIdx.x * 4;
+  if (i0 >= m) return;
+  const int32_t *il = inv_l + d.idx;
+  const int32_t *ir = inv_r + d.idx;
+  const GatherCtx g = gather_ctx(fd, d, store, K, npe);
+  double *F = store + d.store;
+  const int i1 = min(i0 + 4, m);
+  for (int i = i0; i < i1; ++i) {
+    const int li = il[i], ri = ir[i];
+    for (int j = threadIdx.x; j < m; j += 256)
+      F[(int64_t)i * m + j] = gather_entry(g, li, il[j], ri, ir[j]);
+  }
+}
+
+// Panel step, part 1: LU of the pb x pb diagonal block at (p0, p0), one workgroup per front.
+template <int NB>
+__global__ void __launch_bounds__(256)
+k_panel_diag(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ fronts,
+             const int32_t *__restrict__ p0s, double *__restrict__ store, int *__restrict__ status) {
+  __shared__ double D[NB][NB + 1];
+  __shared__ int bad;
+  const int f = fronts[blockIdx.x];
+  const int p0 = p0s[blockIdx.x];
+  const FrontDesc d = fd[f];
+  const int m = d.m, pb = min(NB, d.k - p0);
+  double *F = store + d.store + (int64_t)p0 * m + p0;
+  const int tid = threadIdx.x;
+  for (int t = tid; t < pb * pb; t += 256) D[t / pb][t % pb] = F[(int64_t)(t / pb) * m + t % pb];
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (int p = 0; p < pb; ++p) {
+    const double piv = D[p][p];
+    if (!good_pivot(piv)) {
+      if (tid == 0) record_bad_pivot(status, f, p0 + p);
+      break;
+    }
+    for (int j = p + 1 + tid; j < pb; j += 256) D[p][j] = D[p][j] / piv;
+    __syncthreads();
+    const int r = pb - p - 1;
+    for (int t = tid; t < r * r; t += 256) {
+      const int i = p + 1 + t / r, j = p + 1 + t % r;
+      D[i][j] -= D[i][p] * D[p][j];
+    }
+    __syncthreads();
+  }
+  for (int t = tid; t < pb * pb; t += 256) F[(int64_t)(t / pb) * m + t % pb] = D[t / pb][t % pb];
+}
+
+// Panel step, part 2: the two triangular solves against the factored diagonal block.
+//   U12 = L11^{-1} A12 column by column (rows p0..pe-1, columns pe..m-1),
+//   L21 = A21 U11^{-1} row by row       (rows pe..m-1, columns p0..pe-1).
+// grid = (item chunks of 256, fronts); item t < m-pe is a column, otherwise a row.
+template <int NB>
+__global__ void __launch_bounds__(256)
+k_panel_trsm(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ fronts,
+             const int32_t *__restrict__ p0s, double *__restrict__ store) {
+  __shared__ double D[NB][NB + 1];
+  const int f = fronts[blockIdx.y];
+  const int p0 = p0s[blockIdx.y];
+  const FrontDesc d = fd[f];
+  const int m = d.m, pb = min(NB, d.k - p0), pe = p0 + pb;
+  const int rest = m - pe;
+  const int item = blockIdx.x * 256 + threadIdx.x;
+  if ((int)(blockIdx.x * 256) >= 2 * rest) return;   // whole block idle (uniform)
+  double *F = store + d.store;
+  for (int t = threadIdx.x; t < pb * pb; t += 256)
+    D[t / pb][t % pb] = F[(int64_t)(p0 + t / pb) * m + p0 + t % pb];
+  __syncthreads();
+  if (item >= 2 * rest) return;
+  double v[NB];
+  if (item < rest) {
+    const int j = pe + item;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) v[q] = q < pb ? F[(int64_t)(p0 + q) * m + j] : 0.0;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      if (q < pb) {
+        double s = v[q];
+#pragma unroll
+        for (int r = 0; r < q; ++r) s -= D[q][r] * v[r];
+        v[q] = s / D[q][q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+      if (q < pb) F[(int64_t)(p0 + q) * m + j] = v[q];
+  } else {
+    const int i = pe + (item - rest);
+    double *row = F + (int64_t)i * m + p0;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) v[q] = q < pb ? row[q] : 0.0;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      if (q < pb) {
+        double s = v[q];
+#pragma unroll
+        for (int r = 0; r < q; ++r) s -= v[r] * D[r][q];
+        v[q] = s;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+      if (q < pb) row[q] = v[q];
+  }
+}
+
+// Batched GEMM update C -= A B over a task list, 64 x 64 output tile per workgroup of 4 waves,
+// each wave a 32 x 32 quadrant of 2 x 2 MFMA blocks of 16 x 16.
+//   PREC 0: FP64 operands, v_mfma_f64_16x16x4f64, FP64 accumulate;
+//   PREC 1: operands rounded to FP32, v_mfma_f32_16x16x4f32, FP32 accumulate;
+//   PREC 2: operands rounded to BF16, v_mfma_f32_16x16x32_bf16, FP32 accumulate.
+// The accumulated product is subtracted from the FP64 C in every case.
+// MFMA 16x16 operand layout (lane l): A row l%16, k-group l/16; B column l%16, k-group l/16;
+// result: column l%16, rows as noted at the write-back (checked on gfx950 hardware).
+template <int PREC>
+struct GemmCfg;
+template <>
+struct GemmCfg<0> { typedef double T; static constexpr int KT = 16; };
+template <>
+struct GemmCfg<1> { typedef float T; static constexpr int KT = 16; };
+template <>
+struct GemmCfg<2> { typedef __bf16 T; static constexpr int KT = 32; };
+
+template <int PREC>
+__global__ void __launch_bounds__(256)
+k_gemm_update(const FrontDesc *__restrict__ fd, const GemmTask *__restrict__ tasks,
+              double *__restrict__ store) {
+  typedef typename GemmCfg<PREC>::T T;
+  constexpr int KT = GemmCfg<PREC>::KT;
+  constexpr int APAD = (PREC == 2) ? 8 : 1;
+  __shared__ T As[64][KT + APAD];
+  __shared__ T Bs[64][KT + APAD];    // stored transposed: Bs[col][k]
+  const GemmTask tk = tasks[blockIdx.x];
+  const FrontDesc d = fd[tk.front];
+  const int64_t ld = d.m;
+  double *F = store + d.store;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  const int li = lane & 15, lk = lane >> 4;
+  typedef typename std::conditional<PREC == 0, v4d, v4f>::type Acc;
+  Acc acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[a][b][r] = 0;
+  const int i0 = tk.i0, j0 = tk.j0;
+  for (int q = tk.q0; q < tk.q1; q += KT) {
+    // stage A[i0:i0+64, q:q+KT] and B[q:q+KT, j0:j0+64] (zero outside the task)
+    for (int t = tid; t < 64 * KT; t += 256) {
+      const int r = t / KT, c = t % KT;
+      const int gi = i0 + r, gq = q + c;
+      double va = (gi < tk.i1 && gq < tk.q1) ? F[gi * ld + gq] : 0.0;
+      As[r][c] = (T)va;
+    }
+    for (int t = tid; t < 64 * KT; t += 256) {
+      const int c = t % 64, r = t / 64;
+      const int gq = q + r, gj = j0 + c;
+      double vb = (gq < tk.q1 && gj < tk.j1) ? F[gq * ld + gj] : 0.0;
+      Bs[c][r] = (T)vb;
+    }
+    __syncthreads();
+    if constexpr (PREC == 2) {
+      v8bf av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) av[a][e] = As[32 * wr + 16 * a + li][8 * lk + e];
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) bv[b][e] = Bs[32 * wc + 16 * b + li][8 * lk + e];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
+    } else {
+#pragma unroll
+      for (int s = 0; s < KT / 4; ++s) {
+        T av[2], bv[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) av[a] = As[32 * wr + 16 * a + li][4 * s + lk];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) bv[b] = Bs[32 * wc + 16 * b + li][4 * s + lk];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            if constexpr (PREC == 0)
+              acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+            else
+              acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+          }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        // f64 16x16x4 interleaves its result rows (lane l, register r -> row 4r + l/16); the
+        // f32 16x16x4 and bf16 16x16x32 forms place them contiguously (row 4(l/16) + r)
+        const int gi = i0 + 32 * wr + 16 * a + (PREC == 0 ? 4 * r + lk : 4 * lk + r);
+        const int gj = j0 + 32 * wc + 16 * b + li;
+        if (gi < tk.i1 && gj < tk.j1) F[gi * ld + gj] -= (double)acc[a][b][r];
+      }
+}
+
+}  // namespace mf

@@ -39,14 +39,16 @@ struct PanelStep {
 };
 
 struct LevelSchedule {
-  std::vector<int32_t> small;      // fronts factored entirely in LDS
+  std::vector<int32_t> tiny;       // fronts factored by one wave each, in LDS
+  int32_t tiny_max_m = 0;
+  std::vector<int32_t> small;      // fronts factored by one workgroup each, in LDS
   int32_t small_max_m = 0;
   std::vector<int32_t> large;      // fronts assembled and factored in HBM
   int32_t large_max_m = 0;
   std::vector<PanelStep> steps;
   std::vector<GemmTask> schur;     // C22 -= L21 U12 tiles of the large fronts
-  std::vector<int32_t> all;        // every front of the class (solve)
-  int32_t max_m = 0;
+  std::vector<int32_t> all;        // every front of the class that the solve visits
+  int32_t max_m = 0, max_k = 0;
 };
 
 struct HostPlan {
@@ -67,6 +69,7 @@ struct HostPlan {
 
 // Tunables of the schedule (chosen by the autotuner or defaults).
 struct Tuning {
+  int32_t tiny_max_m = 32;     // fronts up to this width are factored one per wave
   int32_t small_max_m = 128;   // fronts up to this width are factored in LDS
   int32_t nb = 32;             // panel width of the tiled path
   int32_t tile = 64;           // GEMM output tile edge

@@ -1,0 +1,365 @@
+// solve_kernels.hpp -- gfx950 kernels of the substitution sweeps over the elimination tree, and
+// the element-by-element operators (residual, adjoint element gradient).
+//
+// A = L U in elimination order (L carries the pivots, U has a unit diagonal).  The down sweep
+// runs classes 0..H and the up sweep classes H..0 (leaves to root, then root to leaves).
+//   down, TRANS=0: L y = b    y_p = w_p / L_pp,  w_i -= L_ip y_p        (i > p)
+//   down, TRANS=1: U^T z = g  z_p = w_p,         w_j -= U_pj z_p        (j > p)
+//   up,   TRANS=0: U x = y    x_p = w_p,         w_q -= U_qp x_p        (q < p)
+//   up,   TRANS=1: L^T l = z  l_p = w_p / L_pp,  w_q -= L_pq l_p        (q < p)
+// A front's right-hand-side block W (m x nc columns, in LDS) starts, in the down sweep, as b on
+// its pivots plus its children's contribution blocks (extend-add, like the factor); its own
+// contribution block (rows k..m-1) goes to `ycb` for its parent, and its pivots' values to x.
+// In the up sweep W holds the down-sweep values on the pivots and final values on the CB rows
+// (pivots of ancestors); the CB part is applied first, then the pivots in reverse order.
+// Coefficient accessors on the front storage F (m x m row-major):
+//   down: cd(i, p) = TRANS ? U_pi = F[p][i] : L_ip = F[i][p];  diag TRANS ? 1 : F[p][p]
+//   up:   cu(q, p) = TRANS ? L_pq = F[p][q] : U_qp = F[q][p];  diag TRANS ? F[p][p] : 1
+#pragma once
+
+#include "common.hpp"
+
+namespace mf {
+
+template <bool TRANS>
+__device__ inline double cdown(const double *F, int64_t m, int i, int p) {
+  return TRANS ? F[p * m + i] : F[i * m + p];
+}
+template <bool TRANS>
+__device__ inline double cup(const double *F, int64_t m, int q, int p) {
+  return TRANS ? F[p * m + q] : F[q * m + p];
+}
+
+// Down-sweep gather of W rows [0, m) for right-hand-side columns r0 .. r0+nr-1.
+__device__ inline double down_gather(const FrontDesc &d, const FrontDesc &a, const FrontDesc &c,
+                                     const int32_t *idx, const int32_t *il, const int32_t *ir,
+                                     const double *b, const double *ycb, int nrhs, int i, int col) {
+  double v = i < d.k ? b[(int64_t)idx[i] * nrhs + col] : 0.0;
+  if (d.elem < 0) {
+    const int x = il[i], y = ir[i];
+    if (x >= 0 && !passthrough(a)) v += ycb[(a.cbrow + x) * nrhs + col];
+    if (y >= 0 && !passthrough(c)) v += ycb[(c.cbrow + y) * nrhs + col];
+  }
+  return v;
+}
+
+// ---------------------------------------------------------------------------------------------
+// One wave per front (fronts of width <= 64), four fronts per workgroup.  The front's
+// coefficients are staged in LDS once; pivots are eliminated one at a time with wave-level
+// ordering only.  LDS per wave: ldsw doubles = W (mmax x nc) + coefficients (mmax x cld).
+// ---------------------------------------------------------------------------------------------
+template <bool TRANS>
+__global__ void __launch_bounds__(256)
+k_solve_down_wave(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ list, int nlist,
+                  const double *__restrict__ store, const int32_t *__restrict__ front_idx,
+                  const int32_t *__restrict__ inv_l, const int32_t *__restrict__ inv_r,
+                  const double *b, double *x, double *__restrict__ ycb, int nrhs, int nc,
+                  int mmax, int cld, int ldsw) {
+  extern __shared__ double sm[];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double *W = sm + wv * ldsw;
+  double *C = W + mmax * nc;     // C[i * cld + p] = cd(i, p), i >= p
+  for (int li = blockIdx.x * 4 + wv; li < nlist; li += gridDim.x * 4) {
+    const int f = list[li];
+    const FrontDesc d = fd[f];
+    const int m = d.m, k = d.k;
+    const int32_t *idx = front_idx + d.idx;
+    const int32_t *il = inv_l + d.idx;
+    const int32_t *ir = inv_r + d.idx;
+    const double *F = store + d.store;
+    FrontDesc a = d, c = d;
+    if (d.elem < 0) {
+      a = fd[d.left];
+      c = fd[d.right];
+    }
+    for (int t = lane; t < m * k; t += 64) {
+      const int i = t / k, p = t - (t / k) * k;
+      C[i * cld + p] = i >= p ? cdown<TRANS>(F, m, i, p) : 0.0;
+    }
+    for (int r0 = 0; r0 < nrhs; r0 += nc) {
+      const int nr = min(nc, nrhs - r0);
+      for (int t = lane; t < m * nr; t += 64) {
+        const int i = t / nr, r = t - (t / nr) * nr;
+        W[i * nr + r] = down_gather(d, a, c, idx, il, ir, b, ycb, nrhs, i, r0 + r);
+      }
+      wave_sync();
+      for (int p = 0; p < k; ++p) {
+        const double dg = TRANS ? 1.0 : C[p * cld + p];
+        for (int t = lane; t < (m - p - 1) * nr; t += 64) {
+          const int i = p + 1 + t / nr, r = t - (t / nr) * nr;
+          W[i * nr + r] -= C[i * cld + p] * (W[p * nr + r] / dg);
+        }
+        if (lane < nr) x[(int64_t)idx[p] * nrhs + r0 + lane] = W[p * nr + lane] / dg;
+        wave_sync();
+      }
+      for (int t = lane; t < (m - k) * nr; t += 64) {
+        const int i = k + t / nr, r = t - (t / nr) * nr;
+        ycb[(d.cbrow + i - k) * nrhs + r0 + r] = W[i * nr + r];
+      }
+      wave_sync();
+    }
+  }
+}
+
+template <bool TRANS>
+__global__ void __launch_bounds__(256)
+k_solve_up_wave(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ list, int nlist,
+                const double *__restrict__ store, const int32_t *__restrict__ front_idx,
+                double *x, int nrhs, int nc, int mmax, int cld, int ldsw) {
+  extern __shared__ double sm[];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double *W = sm + wv * ldsw;
+  double *C = W + mmax * nc;     // C[q * cld + j] = cu(q, j), q < k, j >= q
+  for (int li = blockIdx.x * 4 + wv; li < nlist; li += gridDim.x * 4) {
+    const int f = list[li];
+    const FrontDesc d = fd[f];
+    const int m = d.m, k = d.k;
+    const int32_t *idx = front_idx + d.idx;
+    const double *F = store + d.store;
+    for (int t = lane; t < k * m; t += 64) {
+      const int q = t / m, j = t - (t / m) * m;
+      C[q * cld + j] = j >= q ? cup<TRANS>(F, m, q, j) : 0.0;
+    }
+    for (int r0 = 0; r0 < nrhs; r0 += nc) {
+      const int nr = min(nc, nrhs - r0);
+      for (int t = lane; t < m * nr; t += 64) {
+        const int i = t / nr, r = t - (t / nr) * nr;
+        W[i * nr + r] = x[(int64_t)idx[i] * nrhs + r0 + r];
+      }
+      wave_sync();
+      for (int t = lane; t < k * nr; t += 64) {
+        const int p = t / nr, r = t - (t / nr) * nr;
+        double s = 0.0;
+        for (int j = k; j < m; ++j) s += C[p * cld + j] * W[j * nr + r];
+        W[p * nr + r] -= s;
+      }
+      wave_sync();
+      for (int p = k - 1; p >= 0; --p) {
+        const double dg = TRANS ? C[p * cld + p] : 1.0;
+        for (int t = lane; t < p * nr; t += 64) {
+          const int q = t / nr, r = t - (t / nr) * nr;
+          W[q * nr + r] -= C[q * cld + p] * (W[p * nr + r] / dg);
+        }
+        if (lane < nr) x[(int64_t)idx[p] * nrhs + r0 + lane] = W[p * nr + lane] / dg;
+        wave_sync();
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// One workgroup per front (wider fronts), pivots in blocks of NBS.  Per block: the NBS x NBS
+// diagonal coefficient block is staged in LDS and solved sequentially by wave 0 (wave-level
+// ordering), then all waves apply the block to the remaining rows (a rectangular update reading
+// contiguous coefficient rows).  LDS: W (mmax x nc) + D (NBS x NBS+1) + Y (NBS x nc).
+// ---------------------------------------------------------------------------------------------
+constexpr int NBS = 32;
+
+template <bool TRANS>
+__global__ void __launch_bounds__(256)
+k_solve_down_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ list, int nlist,
+                   const double *__restrict__ store, const int32_t *__restrict__ front_idx,
+                   const int32_t *__restrict__ inv_l, const int32_t *__restrict__ inv_r,
+                   const double *b, double *x, double *__restrict__ ycb, int nrhs, int nc,
+                   int mmax) {
+  extern __shared__ double sm[];
+  double *W = sm;
+  double *D = W + mmax * nc;
+  double *Y = D + NBS * (NBS + 1);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int li = blockIdx.x; li < nlist; li += gridDim.x) {
+    const int f = list[li];
+    const FrontDesc d = fd[f];
+    const int m = d.m, k = d.k;
+    const int32_t *idx = front_idx + d.idx;
+    const int32_t *il = inv_l + d.idx;
+    const int32_t *ir = inv_r + d.idx;
+    const double *F = store + d.store;
+    FrontDesc a = d, c = d;
+    if (d.elem < 0) {
+      a = fd[d.left];
+      c = fd[d.right];
+    }
+    for (int r0 = 0; r0 < nrhs; r0 += nc) {
+      const int nr = min(nc, nrhs - r0);
+      for (int t = tid; t < m * nr; t += 256) {
+        const int i = t / nr, r = t - (t / nr) * nr;
+        W[i * nr + r] = down_gather(d, a, c, idx, il, ir, b, ycb, nrhs, i, r0 + r);
+      }
+      for (int p0 = 0; p0 < k; p0 += NBS) {
+        const int pb = min(NBS, k - p0), pe = p0 + pb;
+        for (int t = tid; t < pb * pb; t += 256) {
+          const int i = t / pb, p = t - (t / pb) * pb;
+          D[i * (NBS + 1) + p] = i >= p ? cdown<TRANS>(F, m, p0 + i, p0 + p) : 0.0;
+        }
+        __syncthreads();
+        if (wv == 0) {
+          for (int p = 0; p < pb; ++p) {
+            const double dg = TRANS ? 1.0 : D[p * (NBS + 1) + p];
+            for (int t = lane; t < (pb - p - 1) * nr; t += 64) {
+              const int i = p + 1 + t / nr, r = t - (t / nr) * nr;
+              W[(p0 + i) * nr + r] -= D[i * (NBS + 1) + p] * (W[(p0 + p) * nr + r] / dg);
+            }
+            if (lane < nr) {
+              const double y = W[(p0 + p) * nr + lane] / dg;
+              Y[p * nr + lane] = y;
+              x[(int64_t)idx[p0 + p] * nrhs + r0 + lane] = y;
+            }
+            wave_sync();
+          }
+        }
+        __syncthreads();
+        for (int t = tid; t < (m - pe) * nr; t += 256) {
+          const int i = pe + t / nr, r = t - (t / nr) * nr;
+          double s = 0.0;
+          for (int p = 0; p < pb; ++p) s += cdown<TRANS>(F, m, i, p0 + p) * Y[p * nr + r];
+          W[i * nr + r] -= s;
+        }
+      }
+      __syncthreads();
+      for (int t = tid; t < (m - k) * nr; t += 256) {
+        const int i = k + t / nr, r = t - (t / nr) * nr;
+        ycb[(d.cbrow + i - k) * nrhs + r0 + r] = W[i * nr + r];
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <bool TRANS>
+__global__ void __launch_bounds__(256)
+k_solve_up_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ list, int nlist,
+                 const double *__restrict__ store, const int32_t *__restrict__ front_idx,
+                 double *x, int nrhs, int nc, int mmax) {
+  extern __shared__ double sm[];
+  double *W = sm;
+  double *D = W + mmax * nc;
+  double *X = D + NBS * (NBS + 1);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int li = blockIdx.x; li < nlist; li += gridDim.x) {
+    const int f = list[li];
+    const FrontDesc d = fd[f];
+    const int m = d.m, k = d.k;
+    const int32_t *idx = front_idx + d.idx;
+    const double *F = store + d.store;
+    for (int r0 = 0; r0 < nrhs; r0 += nc) {
+      const int nr = min(nc, nrhs - r0);
+      for (int t = tid; t < m * nr; t += 256) {
+        const int i = t / nr, r = t - (t / nr) * nr;
+        W[i * nr + r] = x[(int64_t)idx[i] * nrhs + r0 + r];
+      }
+      __syncthreads();
+      for (int t = tid; t < k * nr; t += 256) {
+        const int p = t / nr, r = t - (t / nr) * nr;
+        double s = 0.0;
+        for (int j = k; j < m; ++j) s += cup<TRANS>(F, m, p, j) * W[j * nr + r];
+        W[p * nr + r] -= s;
+      }
+      for (int p0 = ((k - 1) / NBS) * NBS; p0 >= 0 && k > 0; p0 -= NBS) {
+        const int pb = min(NBS, k - p0);
+        for (int t = tid; t < pb * pb; t += 256) {
+          const int q = t / pb, p = t - (t / pb) * pb;
+          D[q * (NBS + 1) + p] = p >= q ? cup<TRANS>(F, m, p0 + q, p0 + p) : 0.0;
+        }
+        __syncthreads();
+        if (wv == 0) {
+          for (int p = pb - 1; p >= 0; --p) {
+            const double dg = TRANS ? D[p * (NBS + 1) + p] : 1.0;
+            for (int t = lane; t < p * nr; t += 64) {
+              const int q = t / nr, r = t - (t / nr) * nr;
+              W[(p0 + q) * nr + r] -= D[q * (NBS + 1) + p] * (W[(p0 + p) * nr + r] / dg);
+            }
+            if (lane < nr) {
+              const double v = W[(p0 + p) * nr + lane] / dg;
+              X[p * nr + lane] = v;
+              x[(int64_t)idx[p0 + p] * nrhs + r0 + lane] = v;
+            }
+            wave_sync();
+          }
+        }
+        __syncthreads();
+        for (int t = tid; t < p0 * nr; t += 256) {
+          const int q = t / nr, r = t - (t / nr) * nr;
+          double s = 0.0;
+          for (int p = 0; p < pb; ++p) s += cup<TRANS>(F, m, q, p0 + p) * X[p * nr + r];
+          W[q * nr + r] -= s;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Element-by-element operators (FP64).
+// ---------------------------------------------------------------------------------------------
+
+// r[v] = b[v] - sum over the (element, local node) pairs of v of K_e[a][:] x[conn_e]; the pairs
+// of each node are listed in ascending element order, so the result is deterministic.
+__global__ void __launch_bounds__(256)
+k_residual(const int64_t *__restrict__ nptr, const int32_t *__restrict__ nelem,
+           const int32_t *__restrict__ conn, const double *__restrict__ K, int npe, int64_t n,
+           const double *__restrict__ x, const double *__restrict__ b, double *__restrict__ r,
+           int nrhs) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= n * nrhs) return;
+  const int64_t v = t / nrhs;
+  const int c = (int)(t - v * nrhs);
+  double s = 0.0;
+  for (int64_t q = nptr[v]; q < nptr[v + 1]; ++q) {
+    const int32_t ea = nelem[q];
+    const int32_t e = ea / npe, a = ea - (ea / npe) * npe;
+    const double *Ke = K + ((int64_t)e * npe + a) * npe;
+    const int32_t *ce = conn + (int64_t)e * npe;
+    for (int bb = 0; bb < npe; ++bb) s += Ke[bb] * x[(int64_t)ce[bb] * nrhs + c];
+  }
+  r[t] = b[t] - s;
+}
+
+// Per-column partial sums of squares: part[block][c] over rows block*rows_per .. .
+__global__ void __launch_bounds__(256)
+k_colsq_partial(const double *__restrict__ a, int64_t n, int nrhs, int64_t rows_per,
+                double *__restrict__ part) {
+  __shared__ double red[256];
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per;
+  const int64_t r1 = min(n, r0 + rows_per);
+  for (int c = 0; c < nrhs; ++c) {
+    double s = 0.0;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += 256) {
+      const double v = a[i * nrhs + c];
+      s += v * v;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+      if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * nrhs + c] = red[0];
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_axpy(double *__restrict__ x, const double *__restrict__ dx, int64_t len) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t < len) x[t] += dx[t];
+}
+
+// gK[e][a][b] = -sum_r lam[conn_e[a]][r] u[conn_e[b]][r]
+__global__ void __launch_bounds__(256)
+k_elem_grad(const int32_t *__restrict__ conn, int64_t ne, int npe, const double *__restrict__ lam,
+            const double *__restrict__ u, int nrhs, double *__restrict__ gK) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= ne * npe * npe) return;
+  const int64_t e = t / (npe * npe);
+  const int ab = (int)(t - e * npe * npe);
+  const int a = ab / npe, bb = ab - (ab / npe) * npe;
+  const double *la = lam + (int64_t)conn[e * npe + a] * nrhs;
+  const double *ub = u + (int64_t)conn[e * npe + bb] * nrhs;
+  double s = 0.0;
+  for (int r = 0; r < nrhs; ++r) s += la[r] * ub[r];
+  gK[t] = -s;
+}
+
+}  // namespace mf

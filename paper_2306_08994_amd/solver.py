@@ -61,6 +61,7 @@ class Plan:
         self.n = int(inf.n)
         self.n_elem = int(inf.n_elem)
         self.npe = int(inf.npe)
+        self.factor_version = 0     # bumped by every factor call (autograd staleness check)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -87,6 +88,7 @@ class Plan:
         return out
 
     def set_tuning(self, small_max_m: int = 0, nb: int = 0):
+        self.factor_version += 1
         check(_lib.load().mf_set_tuning(self._h, int(small_max_m), int(nb)))
 
     # -- numerics ----------------------------------------------------------------------------
@@ -94,6 +96,7 @@ class Plan:
         if precision not in PRECISIONS:
             raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
         p = _dev_ptr(K, "K", (self.n_elem, self.npe, self.npe))
+        self.factor_version += 1
         check(_lib.load().mf_factor(self._h, p, PRECISIONS[precision], _stream()))
 
     def solve(self, b, transpose: bool = False, out=None):
@@ -139,6 +142,19 @@ class Plan:
                                        _dev_ptr(u.reshape(self.n, nrhs), "u"), nrhs,
                                        _dev_ptr(gK, "gK"), _stream()))
         return gK
+
+    def profile(self, enable: bool = True):
+        """Start (clearing counters) or stop per-launch event timing of this plan's kernels."""
+        check(_lib.load().mf_profile(self._h, int(bool(enable))))
+
+    def profile_report(self) -> dict:
+        import json
+        lib = _lib.load()
+        need = ctypes.c_int64(0)
+        check(lib.mf_profile_report(self._h, None, 0, ctypes.byref(need)))
+        buf = ctypes.create_string_buffer(int(need.value) + 16)
+        check(lib.mf_profile_report(self._h, buf, len(buf), ctypes.byref(need)))
+        return json.loads(buf.value.decode())
 
     def export_factors(self):
         """Per-front (L (m x k), U (k x m)) numpy arrays, fronts in id order."""

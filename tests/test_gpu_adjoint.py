@@ -1,0 +1,97 @@
+"""GPU: the differentiable solve (torch.autograd.Function over the transposed multifrontal
+solve) against the oracle's dense adjoint on small meshes, and against central finite
+differences (h = 1e-6) on 32 seeded coordinates at the 128 x 128, 64-RHS workload."""
+import numpy as np
+import pytest
+
+from fixtures import config_problem
+from fixtures.mesh import element_matrices, reaction_diffusion
+from tests import gpu_common as G
+
+pytestmark = pytest.mark.gpu
+
+
+def _loss(plan, k, b, S, M, u_t):
+    import torch
+    from paper_2306_08994_amd import mf_solve
+    K = k[:, None, None] * S + M
+    u = mf_solve(K, b, plan)
+    return ((u - u_t) ** 2).sum()
+
+
+@pytest.mark.parametrize("shape,nrhs", [((4, 5), 3), ((3, 3, 2), 2), ((17, 9), 4)])
+def test_adjoint_matches_oracle_dense(shape, nrhs):
+    import torch
+    from oracle import adjoint as oadj
+    from oracle.factor import global_connectivity
+    from paper_2306_08994_amd import Plan
+    dev = G.torch_dev()
+    p = reaction_diffusion("adj", shape, np.random.default_rng(7), "lognormal", 0.5, nrhs)
+    conn = global_connectivity(p)
+    kt = np.exp(np.random.default_rng(50).normal(0, 0.5, p.meshes[0].n_elem))
+    from oracle import dense
+    u_t = np.linalg.solve(dense.assemble(element_matrices(p.meshes[0], kt), conn, p.n), p.b)
+    _, lam_o, _, gk_o = oadj.dense_grads(p.K, conn, p.n, p.b, u_t, p.S[0])
+    plan = Plan(p.meshes)
+    k = torch.tensor(p.coef, device=dev, requires_grad=True)
+    b = torch.tensor(p.b, device=dev, requires_grad=True)
+    S = torch.tensor(p.S[0], device=dev)
+    M = torch.tensor(p.M[0], device=dev)
+    loss = _loss(plan, k, b, S, M, torch.tensor(u_t, device=dev))
+    loss.backward()
+    np.testing.assert_allclose(k.grad.cpu().numpy(), gk_o, rtol=1e-10, atol=1e-12 * np.abs(gk_o).max())
+    np.testing.assert_allclose(b.grad.cpu().numpy(), lam_o, rtol=1e-10, atol=1e-12 * np.abs(lam_o).max())
+
+
+def test_adjoint_finite_differences_full_size():
+    """128 x 128 Q1, k ~ lognormal(0, 0.5) as a parameter, 64 RHS, u_t from k_target."""
+    import torch
+    from paper_2306_08994_amd import Plan, mf_solve
+    dev = G.torch_dev()
+    p = config_problem(5)
+    plan = Plan(p.meshes)
+    S = torch.tensor(p.S[0], device=dev)
+    M = torch.tensor(p.M[0], device=dev)
+    b = torch.tensor(p.b, device=dev)
+    with torch.no_grad():
+        kt = torch.tensor(p.extra["k_target"], device=dev)
+        u_t = mf_solve(kt[:, None, None] * S + M, b, plan)
+    k = torch.tensor(p.coef, device=dev, requires_grad=True)
+    bb = b.clone().requires_grad_(True)
+    loss = _loss(plan, k, bb, S, M, u_t)
+    loss.backward()
+    gk = k.grad.cpu().numpy()
+    gb = bb.grad.cpu().numpy()
+    rng = np.random.default_rng(55)
+    coords = rng.choice(p.meshes[0].n_elem, size=32, replace=False)
+    h = 1e-6
+    worst = 0.0
+    with torch.no_grad():
+        for e in coords:
+            kp = k.detach().clone(); kp[e] += h
+            km = k.detach().clone(); km[e] -= h
+            fd = (float(_loss(plan, kp, b, S, M, u_t)) - float(_loss(plan, km, b, S, M, u_t))) / (2 * h)
+            tol = 1e-5 * max(abs(gk[e]), 1e-2 * np.abs(gk).max())
+            worst = max(worst, abs(fd - gk[e]) / tol)
+            assert abs(fd - gk[e]) <= tol, (e, fd, gk[e])
+        for (i, r) in zip(rng.choice(p.n, 4, replace=False), rng.choice(p.nrhs, 4)):
+            bp = b.clone(); bp[i, r] += h
+            bm = b.clone(); bm[i, r] -= h
+            fd = (float(_loss(plan, k, bp, S, M, u_t)) - float(_loss(plan, k, bm, S, M, u_t))) / (2 * h)
+            assert abs(fd - gb[i, r]) <= 1e-5 * max(abs(gb[i, r]), 1e-2 * np.abs(gb).max())
+    print(f"finite-difference check: worst |fd-ad|/tol = {worst:.3f}")
+
+
+def test_stale_factors_rejected():
+    import torch
+    from paper_2306_08994_amd import Plan, mf_solve
+    dev = G.torch_dev()
+    p = reaction_diffusion("adj", (3, 3), np.random.default_rng(1), "lognormal", 0.5, 1)
+    plan = Plan(p.meshes)
+    K = torch.tensor(p.K, device=dev, requires_grad=True)
+    b = torch.tensor(p.b, device=dev)
+    u = mf_solve(K, b, plan)
+    with torch.no_grad():
+        mf_solve(K * 2, b, plan)          # refactors the same plan
+    with pytest.raises(RuntimeError):
+        u.sum().backward()
