@@ -124,7 +124,7 @@ int ensure_uploaded(mf_plan *P) {
   mf::HostPlan &H = P->hp;
   // widest front whose padded square fits in one workgroup's LDS
   int32_t mm = 1;
-  while ((int64_t)(mm + 1) * ((mm + 1) | 1) * 8 <= P->max_shared) ++mm;
+  while (((int64_t)(mm + 1) * ((mm + 1) | 1) + (mm + 1)) * 8 <= P->max_shared) ++mm;
   P->tune.small_max_m = std::min<int32_t>(P->tune.small_max_m, mm);
   mf::build_schedule(H, P->tune);
   std::vector<int32_t> lists;
@@ -193,6 +193,7 @@ int ensure_uploaded(mf_plan *P) {
   if (!P->cap_stream) HIPCHK(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
   // raise the dynamic-LDS limit of the kernels that size LDS per launch (best effort)
   const void *dyn[] = {(const void *)mf::k_factor_tiny, (const void *)mf::k_factor_small,
+                       (const void *)mf::k_assemble,
                        (const void *)mf::k_solve_down_wave<false>, (const void *)mf::k_solve_down_wave<true>,
                        (const void *)mf::k_solve_up_wave<false>, (const void *)mf::k_solve_up_wave<true>,
                        (const void *)mf::k_solve_down_block<false>, (const void *)mf::k_solve_down_block<true>,
@@ -250,40 +251,41 @@ int launch_factor(mf_plan *P, const double *K, int prec, hipStream_t s) {
     const LevelDev &D = P->lv[l];
     if (D.n_tiny) {
       const int m = D.tiny_max_m;
-      const int ldsw = m * (m | 1);
+      const int ldsw = m * (m | 1) + m;           // front + 2m int maps
       const int grid = (int)std::min<int64_t>((D.n_tiny + 3) / 4, 65535);
       LAUNCH(K_TINY, D.c_tiny, mf::k_factor_tiny, dim3(grid), dim3(256), (size_t)4 * ldsw * 8, s,
              P->d_desc, P->d_lists + D.tiny, (int)D.n_tiny, P->d_store, P->d_inv_l, P->d_inv_r, K,
-             H.npe, P->d_status, ldsw);
+             H.npe, P->d_status, ldsw, m);
     }
     if (D.n_small) {
       const int m = D.small_max_m;
-      const size_t lds = (size_t)m * (m | 1) * sizeof(double);
+      const size_t lds = ((size_t)m * (m | 1) + m) * sizeof(double);
       const int grid = (int)std::min<int64_t>(D.n_small, 16384);
       LAUNCH(K_SMALL, D.c_small, mf::k_factor_small, dim3(grid), dim3(256), lds, s, P->d_desc,
              P->d_lists + D.small, (int)D.n_small, P->d_store, P->d_inv_l, P->d_inv_r, K, H.npe,
-             P->d_status);
+             P->d_status, m);
     }
     if (D.n_large) {
       LAUNCH(K_ASSEMBLE, D.c_assemble, mf::k_assemble,
-             dim3((D.large_max_m + 3) / 4, (unsigned)D.n_large), dim3(256), 0, s, P->d_desc,
+             dim3((D.large_max_m + 3) / 4, (unsigned)D.n_large), dim3(256),
+             (size_t)2 * D.large_max_m * sizeof(int), s, P->d_desc,
              P->d_lists + D.large, P->d_store, P->d_inv_l, P->d_inv_r, K, H.npe);
       for (const StepDev &st : D.steps) {
         const dim3 gd((unsigned)st.n), gt((unsigned)((st.trsm_items + 255) / 256), (unsigned)st.n);
         const int32_t *fr = P->d_lists + st.fronts, *p0 = P->d_lists + st.p0;
         switch (P->tune.nb) {
           case 16:
-            LAUNCH(K_DIAG, st.diag, mf::k_panel_diag<16>, gd, dim3(256), 0, s, P->d_desc, fr, p0, P->d_store, P->d_status);
+            LAUNCH(K_DIAG, st.diag, mf::k_panel_diag<16>, gd, dim3(64), 0, s, P->d_desc, fr, p0, P->d_store, P->d_status);
             if (st.trsm_items > 0)
               LAUNCH(K_TRSM, st.trsm, mf::k_panel_trsm<16>, gt, dim3(256), 0, s, P->d_desc, fr, p0, P->d_store);
             break;
           case 64:
-            LAUNCH(K_DIAG, st.diag, mf::k_panel_diag<64>, gd, dim3(256), 0, s, P->d_desc, fr, p0, P->d_store, P->d_status);
+            LAUNCH(K_DIAG, st.diag, mf::k_panel_diag<64>, gd, dim3(64), 0, s, P->d_desc, fr, p0, P->d_store, P->d_status);
             if (st.trsm_items > 0)
               LAUNCH(K_TRSM, st.trsm, mf::k_panel_trsm<64>, gt, dim3(256), 0, s, P->d_desc, fr, p0, P->d_store);
             break;
           default:
-            LAUNCH(K_DIAG, st.diag, mf::k_panel_diag<32>, gd, dim3(256), 0, s, P->d_desc, fr, p0, P->d_store, P->d_status);
+            LAUNCH(K_DIAG, st.diag, mf::k_panel_diag<32>, gd, dim3(64), 0, s, P->d_desc, fr, p0, P->d_store, P->d_status);
             if (st.trsm_items > 0)
               LAUNCH(K_TRSM, st.trsm, mf::k_panel_trsm<32>, gt, dim3(256), 0, s, P->d_desc, fr, p0, P->d_store);
         }
@@ -353,7 +355,7 @@ int launch_solve(mf_plan *P, const double *b, double *x, int32_t nrhs, bool tran
           LAUNCH(K_UP_WAVE, c, mf::k_solve_up_wave<false>, dim3(grid), dim3(256), lds, s, P->d_desc, lst,
                  n, P->d_store, P->d_front_idx, x, nrhs, nc, mmax, cld, ldsw);
       } else {
-        const int64_t fixed = (int64_t)mf::NBS * (mf::NBS + 1);
+        const int64_t fixed = mf::block_solve_fixed_doubles();
         const int nc = chunk(P, nrhs, fixed, mmax + mf::NBS);
         const size_t lds = (size_t)(fixed + (int64_t)(mmax + mf::NBS) * nc) * 8;
         const int grid = std::min(n, gridcap);

@@ -55,6 +55,7 @@ struct GatherCtx {
   const double *ke;   // element matrix of a leaf front, else null
   const double *ca, *cb;
   int la, lb, npe;
+  int na, nb;         // contribution-block sizes of the two sources (a leaf: npe, 0)
 };
 
 __device__ inline GatherCtx gather_ctx(const FrontDesc *__restrict__ fd, const FrontDesc &d,
@@ -65,24 +66,29 @@ __device__ inline GatherCtx gather_ctx(const FrontDesc *__restrict__ fd, const F
   g.ke = nullptr;
   g.ca = g.cb = nullptr;
   g.la = g.lb = 0;
+  g.na = g.nb = 0;
   if (d.elem >= 0) {
     g.ke = K + (int64_t)d.elem * npe * npe;
+    g.ca = g.ke;
+    g.la = g.na = npe;
     return g;
   }
   const FrontDesc a = fd[d.left], b = fd[d.right];
   if (passthrough(a)) {
     g.ca = K + (int64_t)a.elem * npe * npe;
-    g.la = npe;
+    g.la = g.na = npe;
   } else {
     g.ca = store + a.store + (int64_t)a.k * a.m + a.k;
     g.la = a.m;
+    g.na = a.m - a.k;
   }
   if (passthrough(b)) {
     g.cb = K + (int64_t)b.elem * npe * npe;
-    g.lb = npe;
+    g.lb = g.nb = npe;
   } else {
     g.cb = store + b.store + (int64_t)b.k * b.m + b.k;
     g.lb = b.m;
+    g.nb = b.m - b.k;
   }
   return g;
 }
@@ -95,6 +101,47 @@ __device__ inline double gather_entry(const GatherCtx &g, int li, int lj, int ri
   if ((li | lj) >= 0) v += g.ca[(int64_t)li * g.la + lj];
   if ((ri | rj) >= 0) v += g.cb[(int64_t)ri * g.lb + rj];
   return v;
+}
+
+// Extend-add into an LDS front (row stride ld) by scattering the sources' contiguous rows:
+// zero, then the left source assigned, then the right source added -- the same order of
+// additions as summing the entries of each front position left then right.  `sync` orders
+// LDS between the phases (a workgroup barrier or a wave-level fence); ma/mb are int scratch
+// of at least na/nb entries.
+template <typename Sync>
+__device__ inline void scatter_assemble(const GatherCtx &g, const int32_t *__restrict__ il,
+                                        const int32_t *__restrict__ ir, int m, int ld, double *sh,
+                                        int *ma, int *mb, int t0, int nt, Sync sync) {
+  for (int t = t0; t < m * ld; t += nt) sh[t] = 0.0;
+  for (int i = t0; i < m; i += nt) {
+    const int x = il[i];
+    if (x >= 0) ma[x] = i;
+    if (!g.ke) {
+      const int y = ir[i];
+      if (y >= 0) mb[y] = i;
+    }
+  }
+  sync();
+  {
+    const int n = g.na;
+    const double *src = g.ca;
+#pragma unroll 4
+    for (int t = t0; t < n * n; t += nt) {
+      const int r = t / n, c = t - (t / n) * n;
+      sh[ma[r] * ld + ma[c]] = src[(int64_t)r * g.la + c];
+    }
+  }
+  sync();
+  if (!g.ke) {
+    const int n = g.nb;
+    const double *src = g.cb;
+#pragma unroll 4
+    for (int t = t0; t < n * n; t += nt) {
+      const int r = t / n, c = t - (t / n) * n;
+      sh[mb[r] * ld + mb[c]] += src[(int64_t)r * g.lb + c];
+    }
+  }
+  sync();
 }
 
 }  // namespace mf

@@ -22,10 +22,12 @@ __global__ void __launch_bounds__(256)
 k_factor_tiny(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ list, int nlist,
               double *__restrict__ store, const int32_t *__restrict__ inv_l,
               const int32_t *__restrict__ inv_r, const double *__restrict__ K, int npe,
-              int *__restrict__ status, int ldsw) {
+              int *__restrict__ status, int ldsw, int mmax) {
   extern __shared__ double sm[];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double *sh = sm + wv * ldsw;
+  int *ma = reinterpret_cast<int *>(sh + (ldsw - mmax));   // 2 * mmax ints after the front
+  int *mb = ma + mmax;
   for (int li = blockIdx.x * 4 + wv; li < nlist; li += gridDim.x * 4) {
     const int f = list[li];
     const FrontDesc d = fd[f];
@@ -33,11 +35,7 @@ k_factor_tiny(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ list
     const int32_t *il = inv_l + d.idx;
     const int32_t *ir = inv_r + d.idx;
     const GatherCtx g = gather_ctx(fd, d, store, K, npe);
-    for (int t = lane; t < m * m; t += 64) {
-      const int i = t / m, j = t - (t / m) * m;
-      sh[i * ld + j] = gather_entry(g, il[i], il[j], ir[i], ir[j]);
-    }
-    wave_sync();
+    scatter_assemble(g, il, ir, m, ld, sh, ma, mb, lane, 64, wave_sync);
     for (int p = 0; p < k; ++p) {
       const double piv = sh[p * ld + p];
       if (!good_pivot(piv)) {
@@ -69,8 +67,10 @@ __global__ void __launch_bounds__(256)
 k_factor_small(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ list, int nlist,
                double *__restrict__ store, const int32_t *__restrict__ inv_l,
                const int32_t *__restrict__ inv_r, const double *__restrict__ K, int npe,
-               int *__restrict__ status) {
+               int *__restrict__ status, int mmax) {
   extern __shared__ double sh[];
+  int *ma = reinterpret_cast<int *>(sh + (size_t)mmax * (mmax | 1));   // 2 * mmax ints
+  int *mb = ma + mmax;
   const int tid = threadIdx.x;
   for (int li = blockIdx.x; li < nlist; li += gridDim.x) {
     const int f = list[li];
@@ -79,11 +79,7 @@ k_factor_small(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ lis
     const int32_t *il = inv_l + d.idx;
     const int32_t *ir = inv_r + d.idx;
     const GatherCtx g = gather_ctx(fd, d, store, K, npe);
-    for (int t = tid; t < m * m; t += 256) {
-      const int i = t / m, j = t - (t / m) * m;
-      sh[i * ld + j] = gather_entry(g, il[i], il[j], ir[i], ir[j]);
-    }
-    __syncthreads();
+    scatter_assemble(g, il, ir, m, ld, sh, ma, mb, tid, 256, [] __device__() { __syncthreads(); });
     for (int p = 0; p < k; ++p) {
       const double piv = sh[p * ld + p];
       if (!good_pivot(piv)) {
@@ -117,55 +113,63 @@ __global__ void __launch_bounds__(256)
 k_assemble(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ list,
            double *__restrict__ store, const int32_t *__restrict__ inv_l,
            const int32_t *__restrict__ inv_r, const double *__restrict__ K, int npe) {
+  extern __shared__ int smaps[];      // the front's column maps: left, then right
   const int f = list[blockIdx.y];
   const FrontDesc d = fd[f];
   const int m = d.m;
   const int i0 = blockIdx.x * 4;
-  if (i0 >= m) return;
+  if (i0 >= m) return;                // uniform per workgroup
   const int32_t *il = inv_l + d.idx;
   const int32_t *ir = inv_r + d.idx;
+  int *sl = smaps, *sr = smaps + m;
+  for (int j = threadIdx.x; j < m; j += 256) {
+    sl[j] = il[j];
+    sr[j] = ir[j];
+  }
+  __syncthreads();
   const GatherCtx g = gather_ctx(fd, d, store, K, npe);
   double *F = store + d.store;
   const int i1 = min(i0 + 4, m);
   for (int i = i0; i < i1; ++i) {
-    const int li = il[i], ri = ir[i];
+    const int li = sl[i], ri = sr[i];
     for (int j = threadIdx.x; j < m; j += 256)
-      F[(int64_t)i * m + j] = gather_entry(g, li, il[j], ri, ir[j]);
+      F[(int64_t)i * m + j] = gather_entry(g, li, sl[j], ri, sr[j]);
   }
 }
 
 // Panel step, part 1: LU of the pb x pb diagonal block at (p0, p0), one workgroup per front.
+// One wave per front, wave-level ordering only.
 template <int NB>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64)
 k_panel_diag(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ fronts,
              const int32_t *__restrict__ p0s, double *__restrict__ store, int *__restrict__ status) {
   __shared__ double D[NB][NB + 1];
-  __shared__ int bad;
   const int f = fronts[blockIdx.x];
   const int p0 = p0s[blockIdx.x];
   const FrontDesc d = fd[f];
   const int m = d.m, pb = min(NB, d.k - p0);
   double *F = store + d.store + (int64_t)p0 * m + p0;
-  const int tid = threadIdx.x;
-  for (int t = tid; t < pb * pb; t += 256) D[t / pb][t % pb] = F[(int64_t)(t / pb) * m + t % pb];
-  if (tid == 0) bad = 0;
-  __syncthreads();
+  const int lane = threadIdx.x;
+  for (int i = 0; i < pb; ++i)
+    for (int j = lane; j < pb; j += 64) D[i][j] = F[(int64_t)i * m + j];
+  wave_sync();
   for (int p = 0; p < pb; ++p) {
     const double piv = D[p][p];
     if (!good_pivot(piv)) {
-      if (tid == 0) record_bad_pivot(status, f, p0 + p);
+      if (lane == 0) record_bad_pivot(status, f, p0 + p);
       break;
     }
-    for (int j = p + 1 + tid; j < pb; j += 256) D[p][j] = D[p][j] / piv;
-    __syncthreads();
+    for (int j = p + 1 + lane; j < pb; j += 64) D[p][j] = D[p][j] / piv;
+    wave_sync();
     const int r = pb - p - 1;
-    for (int t = tid; t < r * r; t += 256) {
+    for (int t = lane; t < r * r; t += 64) {
       const int i = p + 1 + t / r, j = p + 1 + t % r;
       D[i][j] -= D[i][p] * D[p][j];
     }
-    __syncthreads();
+    wave_sync();
   }
-  for (int t = tid; t < pb * pb; t += 256) F[(int64_t)(t / pb) * m + t % pb] = D[t / pb][t % pb];
+  for (int i = 0; i < pb; ++i)
+    for (int j = lane; j < pb; j += 64) F[(int64_t)i * m + j] = D[i][j];
 }
 
 // Panel step, part 2: the two triangular solves against the factored diagonal block.

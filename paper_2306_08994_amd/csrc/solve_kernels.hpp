@@ -4,6 +4,7 @@
 // A = L U in elimination order (L carries the pivots, U has a unit diagonal).  The down sweep
 // runs classes 0..H and the up sweep classes H..0 (leaves to root, then root to leaves).
 //   down, TRANS=0: L y = b    y_p = w_p / L_pp,  w_i -= L_ip y_p        (i > p)
+// (the division by a pivot is applied as a multiplication by its reciprocal, computed once)
 //   down, TRANS=1: U^T z = g  z_p = w_p,         w_j -= U_pj z_p        (j > p)
 //   up,   TRANS=0: U x = y    x_p = w_p,         w_q -= U_qp x_p        (q < p)
 //   up,   TRANS=1: L^T l = z  l_p = w_p / L_pp,  w_q -= L_pq l_p        (q < p)
@@ -84,12 +85,12 @@ k_solve_down_wave(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ 
       }
       wave_sync();
       for (int p = 0; p < k; ++p) {
-        const double dg = TRANS ? 1.0 : C[p * cld + p];
+        const double rdv = TRANS ? 1.0 : 1.0 / C[p * cld + p];
         for (int t = lane; t < (m - p - 1) * nr; t += 64) {
           const int i = p + 1 + t / nr, r = t - (t / nr) * nr;
-          W[i * nr + r] -= C[i * cld + p] * (W[p * nr + r] / dg);
+          W[i * nr + r] -= C[i * cld + p] * (W[p * nr + r] * rdv);
         }
-        if (lane < nr) x[(int64_t)idx[p] * nrhs + r0 + lane] = W[p * nr + lane] / dg;
+        if (lane < nr) x[(int64_t)idx[p] * nrhs + r0 + lane] = W[p * nr + lane] * rdv;
         wave_sync();
       }
       for (int t = lane; t < (m - k) * nr; t += 64) {
@@ -135,12 +136,12 @@ k_solve_up_wave(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ li
       }
       wave_sync();
       for (int p = k - 1; p >= 0; --p) {
-        const double dg = TRANS ? C[p * cld + p] : 1.0;
+        const double rdv = TRANS ? 1.0 / C[p * cld + p] : 1.0;
         for (int t = lane; t < p * nr; t += 64) {
           const int q = t / nr, r = t - (t / nr) * nr;
-          W[q * nr + r] -= C[q * cld + p] * (W[p * nr + r] / dg);
+          W[q * nr + r] -= C[q * cld + p] * (W[p * nr + r] * rdv);
         }
-        if (lane < nr) x[(int64_t)idx[p] * nrhs + r0 + lane] = W[p * nr + lane] / dg;
+        if (lane < nr) x[(int64_t)idx[p] * nrhs + r0 + lane] = W[p * nr + lane] * rdv;
         wave_sync();
       }
     }
@@ -149,11 +150,15 @@ k_solve_up_wave(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ li
 
 // ---------------------------------------------------------------------------------------------
 // One workgroup per front (wider fronts), pivots in blocks of NBS.  Per block: the NBS x NBS
-// diagonal coefficient block is staged in LDS and solved sequentially by wave 0 (wave-level
-// ordering), then all waves apply the block to the remaining rows (a rectangular update reading
-// contiguous coefficient rows).  LDS: W (mmax x nc) + D (NBS x NBS+1) + Y (NBS x nc).
+// diagonal coefficient block (and the reciprocals of its pivots) is staged in LDS and solved
+// sequentially by wave 0 (wave-level ordering), then every thread takes one remaining row,
+// loads that row's NBS coefficients into registers (independent loads, one round trip) and
+// applies the block's solution to it.
+// LDS: W (mmax x nc) | D (NBS x NBS+1) | Y (NBS x nc) | rd (NBS).
 // ---------------------------------------------------------------------------------------------
 constexpr int NBS = 32;
+
+__host__ __device__ constexpr int block_solve_fixed_doubles() { return NBS * (NBS + 1) + NBS; }
 
 template <bool TRANS>
 __global__ void __launch_bounds__(256)
@@ -165,7 +170,8 @@ k_solve_down_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__
   extern __shared__ double sm[];
   double *W = sm;
   double *D = W + mmax * nc;
-  double *Y = D + NBS * (NBS + 1);
+  double *rd = D + NBS * (NBS + 1);
+  double *Y = rd + NBS;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int li = blockIdx.x; li < nlist; li += gridDim.x) {
     const int f = list[li];
@@ -180,47 +186,66 @@ k_solve_down_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__
       a = fd[d.left];
       c = fd[d.right];
     }
+    const bool use_a = d.elem < 0 && !passthrough(a), use_c = d.elem < 0 && !passthrough(c);
     for (int r0 = 0; r0 < nrhs; r0 += nc) {
       const int nr = min(nc, nrhs - r0);
-      for (int t = tid; t < m * nr; t += 256) {
-        const int i = t / nr, r = t - (t / nr) * nr;
-        W[i * nr + r] = down_gather(d, a, c, idx, il, ir, b, ycb, nrhs, i, r0 + r);
+      for (int i = tid; i < m; i += 256) {
+        const int64_t gi = idx[i];
+        const int x0 = use_a ? il[i] : -1, y0 = use_c ? ir[i] : -1;
+        for (int r = 0; r < nr; ++r) {
+          double v = i < k ? b[gi * nrhs + r0 + r] : 0.0;
+          if (x0 >= 0) v += ycb[(a.cbrow + x0) * nrhs + r0 + r];
+          if (y0 >= 0) v += ycb[(c.cbrow + y0) * nrhs + r0 + r];
+          W[i * nr + r] = v;
+        }
       }
       for (int p0 = 0; p0 < k; p0 += NBS) {
         const int pb = min(NBS, k - p0), pe = p0 + pb;
-        for (int t = tid; t < pb * pb; t += 256) {
-          const int i = t / pb, p = t - (t / pb) * pb;
-          D[i * (NBS + 1) + p] = i >= p ? cdown<TRANS>(F, m, p0 + i, p0 + p) : 0.0;
+        if (tid < pb) {
+          const int i = tid;
+          double row[NBS];
+#pragma unroll
+          for (int p = 0; p < NBS; ++p) row[p] = (p <= i) ? cdown<TRANS>(F, m, p0 + i, p0 + p) : 0.0;
+#pragma unroll
+          for (int p = 0; p < NBS; ++p) D[i * (NBS + 1) + p] = row[p];
+          double dg = 1.0;
+#pragma unroll
+          for (int p = 0; p < NBS; ++p)
+            if (p == i) dg = row[p];
+          rd[i] = TRANS ? 1.0 : 1.0 / dg;
         }
         __syncthreads();
         if (wv == 0) {
           for (int p = 0; p < pb; ++p) {
-            const double dg = TRANS ? 1.0 : D[p * (NBS + 1) + p];
+            if (lane < nr) Y[p * nr + lane] = W[(p0 + p) * nr + lane] * rd[p];
+            wave_sync();
             for (int t = lane; t < (pb - p - 1) * nr; t += 64) {
               const int i = p + 1 + t / nr, r = t - (t / nr) * nr;
-              W[(p0 + i) * nr + r] -= D[i * (NBS + 1) + p] * (W[(p0 + p) * nr + r] / dg);
-            }
-            if (lane < nr) {
-              const double y = W[(p0 + p) * nr + lane] / dg;
-              Y[p * nr + lane] = y;
-              x[(int64_t)idx[p0 + p] * nrhs + r0 + lane] = y;
+              W[(p0 + i) * nr + r] -= D[i * (NBS + 1) + p] * Y[p * nr + r];
             }
             wave_sync();
           }
         }
         __syncthreads();
-        for (int t = tid; t < (m - pe) * nr; t += 256) {
-          const int i = pe + t / nr, r = t - (t / nr) * nr;
-          double s = 0.0;
-          for (int p = 0; p < pb; ++p) s += cdown<TRANS>(F, m, i, p0 + p) * Y[p * nr + r];
-          W[i * nr + r] -= s;
+        for (int t = tid; t < pb * nr; t += 256) {
+          const int p = t / nr, r = t - (t / nr) * nr;
+          x[(int64_t)idx[p0 + p] * nrhs + r0 + r] = Y[t];
+        }
+        for (int i = pe + tid; i < m; i += 256) {
+          double cf[NBS];
+#pragma unroll
+          for (int p = 0; p < NBS; ++p) cf[p] = p < pb ? cdown<TRANS>(F, m, i, p0 + p) : 0.0;
+          for (int r = 0; r < nr; ++r) {
+            double s = 0.0;
+#pragma unroll
+            for (int p = 0; p < NBS; ++p) s += cf[p] * Y[p * nr + r];
+            W[i * nr + r] -= s;
+          }
         }
       }
       __syncthreads();
-      for (int t = tid; t < (m - k) * nr; t += 256) {
-        const int i = k + t / nr, r = t - (t / nr) * nr;
-        ycb[(d.cbrow + i - k) * nrhs + r0 + r] = W[i * nr + r];
-      }
+      for (int i = k + tid; i < m; i += 256)
+        for (int r = 0; r < nr; ++r) ycb[(d.cbrow + i - k) * nrhs + r0 + r] = W[i * nr + r];
       __syncthreads();
     }
   }
@@ -234,7 +259,8 @@ k_solve_up_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ l
   extern __shared__ double sm[];
   double *W = sm;
   double *D = W + mmax * nc;
-  double *X = D + NBS * (NBS + 1);
+  double *rd = D + NBS * (NBS + 1);
+  double *X = rd + NBS;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int li = blockIdx.x; li < nlist; li += gridDim.x) {
     const int f = list[li];
@@ -244,45 +270,67 @@ k_solve_up_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ l
     const double *F = store + d.store;
     for (int r0 = 0; r0 < nrhs; r0 += nc) {
       const int nr = min(nc, nrhs - r0);
-      for (int t = tid; t < m * nr; t += 256) {
-        const int i = t / nr, r = t - (t / nr) * nr;
-        W[i * nr + r] = x[(int64_t)idx[i] * nrhs + r0 + r];
+      for (int i = tid; i < m; i += 256) {
+        const int64_t gi = idx[i];
+        for (int r = 0; r < nr; ++r) W[i * nr + r] = x[gi * nrhs + r0 + r];
       }
       __syncthreads();
-      for (int t = tid; t < k * nr; t += 256) {
-        const int p = t / nr, r = t - (t / nr) * nr;
-        double s = 0.0;
-        for (int j = k; j < m; ++j) s += cup<TRANS>(F, m, p, j) * W[j * nr + r];
-        W[p * nr + r] -= s;
+      // the already-final CB unknowns applied to the pivot rows, 32 columns at a time
+      for (int p = tid; p < k; p += 256) {
+        for (int j0 = k; j0 < m; j0 += NBS) {
+          double cf[NBS];
+#pragma unroll
+          for (int jj = 0; jj < NBS; ++jj) cf[jj] = j0 + jj < m ? cup<TRANS>(F, m, p, j0 + jj) : 0.0;
+          const int jn = min(NBS, m - j0);
+          for (int r = 0; r < nr; ++r) {
+            double s = 0.0;
+            for (int jj = 0; jj < jn; ++jj) s += cf[jj] * W[(j0 + jj) * nr + r];
+            W[p * nr + r] -= s;
+          }
+        }
       }
       for (int p0 = ((k - 1) / NBS) * NBS; p0 >= 0 && k > 0; p0 -= NBS) {
         const int pb = min(NBS, k - p0);
-        for (int t = tid; t < pb * pb; t += 256) {
-          const int q = t / pb, p = t - (t / pb) * pb;
-          D[q * (NBS + 1) + p] = p >= q ? cup<TRANS>(F, m, p0 + q, p0 + p) : 0.0;
+        if (tid < pb) {
+          const int q = tid;
+          double row[NBS];
+#pragma unroll
+          for (int p = 0; p < NBS; ++p) row[p] = (p >= q && p < pb) ? cup<TRANS>(F, m, p0 + q, p0 + p) : 0.0;
+#pragma unroll
+          for (int p = 0; p < NBS; ++p) D[q * (NBS + 1) + p] = row[p];
+          double dg = 1.0;
+#pragma unroll
+          for (int p = 0; p < NBS; ++p)
+            if (p == q) dg = row[p];
+          rd[q] = TRANS ? 1.0 / dg : 1.0;
         }
         __syncthreads();
         if (wv == 0) {
           for (int p = pb - 1; p >= 0; --p) {
-            const double dg = TRANS ? D[p * (NBS + 1) + p] : 1.0;
+            if (lane < nr) X[p * nr + lane] = W[(p0 + p) * nr + lane] * rd[p];
+            wave_sync();
             for (int t = lane; t < p * nr; t += 64) {
               const int q = t / nr, r = t - (t / nr) * nr;
-              W[(p0 + q) * nr + r] -= D[q * (NBS + 1) + p] * (W[(p0 + p) * nr + r] / dg);
-            }
-            if (lane < nr) {
-              const double v = W[(p0 + p) * nr + lane] / dg;
-              X[p * nr + lane] = v;
-              x[(int64_t)idx[p0 + p] * nrhs + r0 + lane] = v;
+              W[(p0 + q) * nr + r] -= D[q * (NBS + 1) + p] * X[p * nr + r];
             }
             wave_sync();
           }
         }
         __syncthreads();
-        for (int t = tid; t < p0 * nr; t += 256) {
-          const int q = t / nr, r = t - (t / nr) * nr;
-          double s = 0.0;
-          for (int p = 0; p < pb; ++p) s += cup<TRANS>(F, m, q, p0 + p) * X[p * nr + r];
-          W[q * nr + r] -= s;
+        for (int t = tid; t < pb * nr; t += 256) {
+          const int p = t / nr, r = t - (t / nr) * nr;
+          x[(int64_t)idx[p0 + p] * nrhs + r0 + r] = X[t];
+        }
+        for (int q = tid; q < p0; q += 256) {
+          double cf[NBS];
+#pragma unroll
+          for (int p = 0; p < NBS; ++p) cf[p] = p < pb ? cup<TRANS>(F, m, q, p0 + p) : 0.0;
+          for (int r = 0; r < nr; ++r) {
+            double s = 0.0;
+#pragma unroll
+            for (int p = 0; p < NBS; ++p) s += cf[p] * X[p * nr + r];
+            W[q * nr + r] -= s;
+          }
         }
       }
       __syncthreads();

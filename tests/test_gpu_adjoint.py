@@ -39,8 +39,11 @@ def test_adjoint_matches_oracle_dense(shape, nrhs):
     M = torch.tensor(p.M[0], device=dev)
     loss = _loss(plan, k, b, S, M, torch.tensor(u_t, device=dev))
     loss.backward()
-    np.testing.assert_allclose(k.grad.cpu().numpy(), gk_o, rtol=1e-10, atol=1e-12 * np.abs(gk_o).max())
-    np.testing.assert_allclose(b.grad.cpu().numpy(), lam_o, rtol=1e-10, atol=1e-12 * np.abs(lam_o).max())
+    # normwise: the dense adjoint uses LAPACK (partial pivoting), the GPU the no-pivot factors
+    gk = k.grad.cpu().numpy()
+    gb = b.grad.cpu().numpy()
+    assert np.linalg.norm(gk - gk_o) <= 1e-10 * np.linalg.norm(gk_o)
+    assert G.rel_err(gb, lam_o) <= 1e-10
 
 
 def test_adjoint_finite_differences_full_size():
@@ -65,19 +68,29 @@ def test_adjoint_finite_differences_full_size():
     rng = np.random.default_rng(55)
     coords = rng.choice(p.meshes[0].n_elem, size=32, replace=False)
     h = 1e-6
+
+    def u_of(kk, bb_):
+        return mf_solve(kk[:, None, None] * S + M, bb_, plan)
+
+    def dloss(up, um):
+        # L(+) - L(-) = sum (u+ - u-)(u+ + u- - 2 u_t): the same central difference, summed
+        # without cancelling two large losses against each other
+        return float(((up - um) * (up + um - 2 * u_t)).sum())
+
     worst = 0.0
     with torch.no_grad():
         for e in coords:
             kp = k.detach().clone(); kp[e] += h
             km = k.detach().clone(); km[e] -= h
-            fd = (float(_loss(plan, kp, b, S, M, u_t)) - float(_loss(plan, km, b, S, M, u_t))) / (2 * h)
+            fd = dloss(u_of(kp, b), u_of(km, b)) / (2 * h)
             tol = 1e-5 * max(abs(gk[e]), 1e-2 * np.abs(gk).max())
             worst = max(worst, abs(fd - gk[e]) / tol)
             assert abs(fd - gk[e]) <= tol, (e, fd, gk[e])
+        kd = k.detach()
         for (i, r) in zip(rng.choice(p.n, 4, replace=False), rng.choice(p.nrhs, 4)):
             bp = b.clone(); bp[i, r] += h
             bm = b.clone(); bm[i, r] -= h
-            fd = (float(_loss(plan, k, bp, S, M, u_t)) - float(_loss(plan, k, bm, S, M, u_t))) / (2 * h)
+            fd = dloss(u_of(kd, bp), u_of(kd, bm)) / (2 * h)
             assert abs(fd - gb[i, r]) <= 1e-5 * max(abs(gb[i, r]), 1e-2 * np.abs(gb).max())
     print(f"finite-difference check: worst |fd-ad|/tol = {worst:.3f}")
 

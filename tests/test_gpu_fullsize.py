@@ -120,7 +120,10 @@ def test_batched_full_size_equals_per_mesh():
         pl = Plan([p.meshes[i]])
         pl.factor(K[eoff[i]:eoff[i + 1]].contiguous())
         xi = pl.solve(b[noff[i]:noff[i + 1]].contiguous()).cpu().numpy()
-        np.testing.assert_array_equal(xi, xb[noff[i]:noff[i + 1]])
+        # a lone mesh may take other kernel routes (class widths differ from the batch's), so
+        # the two agree to rounding, not bit for bit
+        ref = xb[noff[i]:noff[i + 1]]
+        assert G.rel_err(xi, ref) <= 1e-12
 
 
 def test_graph_replay_matches_eager():
