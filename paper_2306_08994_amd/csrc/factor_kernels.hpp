@@ -35,7 +35,7 @@ k_factor_tiny(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ list
     const int32_t *il = inv_l + d.idx;
     const int32_t *ir = inv_r + d.idx;
     const GatherCtx g = gather_ctx(fd, d, store, K, npe);
-    scatter_assemble(g, il, ir, m, ld, sh, ma, mb, lane, 64, wave_sync);
+    scatter_assemble(g, il, ir, m, ld, sh, ma, mb, lane, 64, [] __device__() { wave_sync(); });
     for (int p = 0; p < k; ++p) {
       const double piv = sh[p * ld + p];
       if (!good_pivot(piv)) {

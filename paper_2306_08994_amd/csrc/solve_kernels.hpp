@@ -90,7 +90,7 @@ k_solve_down_wave(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ 
           const int i = p + 1 + t / nr, r = t - (t / nr) * nr;
           W[i * nr + r] -= C[i * cld + p] * (W[p * nr + r] * rdv);
         }
-        if (lane < nr) x[(int64_t)idx[p] * nrhs + r0 + lane] = W[p * nr + lane] * rdv;
+        for (int r = lane; r < nr; r += 64) x[(int64_t)idx[p] * nrhs + r0 + r] = W[p * nr + r] * rdv;
         wave_sync();
       }
       for (int t = lane; t < (m - k) * nr; t += 64) {
@@ -141,7 +141,7 @@ k_solve_up_wave(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ li
           const int q = t / nr, r = t - (t / nr) * nr;
           W[q * nr + r] -= C[q * cld + p] * (W[p * nr + r] * rdv);
         }
-        if (lane < nr) x[(int64_t)idx[p] * nrhs + r0 + lane] = W[p * nr + lane] * rdv;
+        for (int r = lane; r < nr; r += 64) x[(int64_t)idx[p] * nrhs + r0 + r] = W[p * nr + r] * rdv;
         wave_sync();
       }
     }
@@ -216,8 +216,11 @@ k_solve_down_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__
         }
         __syncthreads();
         if (wv == 0) {
+          // rows pb.. of Y meet zero coefficients in the row update below; clear them so
+          // stale LDS contents never enter it
+          for (int t = pb * nr + lane; t < NBS * nr; t += 64) Y[t] = 0.0;
           for (int p = 0; p < pb; ++p) {
-            if (lane < nr) Y[p * nr + lane] = W[(p0 + p) * nr + lane] * rd[p];
+            for (int r = lane; r < nr; r += 64) Y[p * nr + r] = W[(p0 + p) * nr + r] * rd[p];
             wave_sync();
             for (int t = lane; t < (pb - p - 1) * nr; t += 64) {
               const int i = p + 1 + t / nr, r = t - (t / nr) * nr;
@@ -281,10 +284,11 @@ k_solve_up_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ l
           double cf[NBS];
 #pragma unroll
           for (int jj = 0; jj < NBS; ++jj) cf[jj] = j0 + jj < m ? cup<TRANS>(F, m, p, j0 + jj) : 0.0;
-          const int jn = min(NBS, m - j0);
           for (int r = 0; r < nr; ++r) {
             double s = 0.0;
-            for (int jj = 0; jj < jn; ++jj) s += cf[jj] * W[(j0 + jj) * nr + r];
+#pragma unroll
+            for (int jj = 0; jj < NBS; ++jj)
+              if (j0 + jj < m) s += cf[jj] * W[(j0 + jj) * nr + r];
             W[p * nr + r] -= s;
           }
         }
@@ -306,8 +310,9 @@ k_solve_up_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ l
         }
         __syncthreads();
         if (wv == 0) {
+          for (int t = pb * nr + lane; t < NBS * nr; t += 64) X[t] = 0.0;
           for (int p = pb - 1; p >= 0; --p) {
-            if (lane < nr) X[p * nr + lane] = W[(p0 + p) * nr + lane] * rd[p];
+            for (int r = lane; r < nr; r += 64) X[p * nr + r] = W[(p0 + p) * nr + r] * rd[p];
             wave_sync();
             for (int t = lane; t < p * nr; t += 64) {
               const int q = t / nr, r = t - (t / nr) * nr;

@@ -1,6 +1,7 @@
 """GPU: the differentiable solve (torch.autograd.Function over the transposed multifrontal
-solve) against the oracle's dense adjoint on small meshes, and against central finite
-differences (h = 1e-6) on 32 seeded coordinates at the 128 x 128, 64-RHS workload."""
+solve) against the oracle's dense adjoint on small meshes, and against finite differences on 32
+seeded coefficients at the 128 x 128, 64-RHS workload (central h = 1e-6, and a fourth-order
+stencil at H = 1e-4)."""
 import numpy as np
 import pytest
 
@@ -77,22 +78,33 @@ def test_adjoint_finite_differences_full_size():
         # without cancelling two large losses against each other
         return float(((up - um) * (up + um - 2 * u_t)).sum())
 
-    worst = 0.0
+    # The central difference at h = 1e-6 is limited by rounding at this size: cond(A) * eps / h
+    # is ~1e-4 relative (measured the same with an independent sparse LU on the CPU), so it is
+    # held to 1e-3; a fourth-order stencil at H = 1e-4 (truncation ~H^4) is held to 2e-5.
+    H = 1e-4
+    worst2 = worst4 = 0.0
     with torch.no_grad():
         for e in coords:
-            kp = k.detach().clone(); kp[e] += h
-            km = k.detach().clone(); km[e] -= h
-            fd = dloss(u_of(kp, b), u_of(km, b)) / (2 * h)
-            tol = 1e-5 * max(abs(gk[e]), 1e-2 * np.abs(gk).max())
-            worst = max(worst, abs(fd - gk[e]) / tol)
-            assert abs(fd - gk[e]) <= tol, (e, fd, gk[e])
+            def u_at(dk):
+                kk = k.detach().clone()
+                kk[e] += dk
+                return u_of(kk, b)
+            fd = dloss(u_at(h), u_at(-h)) / (2 * h)
+            u1, u2, u3, u4 = u_at(2 * H), u_at(H), u_at(-H), u_at(-2 * H)
+            fd4 = (-dloss(u1, u4) + 8 * dloss(u2, u3)) / (12 * H)
+            scale = max(abs(gk[e]), 1e-2 * np.abs(gk).max())
+            worst2 = max(worst2, abs(fd - gk[e]) / scale)
+            worst4 = max(worst4, abs(fd4 - gk[e]) / scale)
+            assert abs(fd - gk[e]) <= 1e-3 * scale, (e, fd, gk[e])
+            assert abs(fd4 - gk[e]) <= 2e-5 * scale, (e, fd4, gk[e])
         kd = k.detach()
         for (i, r) in zip(rng.choice(p.n, 4, replace=False), rng.choice(p.nrhs, 4)):
             bp = b.clone(); bp[i, r] += h
             bm = b.clone(); bm[i, r] -= h
             fd = dloss(u_of(kd, bp), u_of(kd, bm)) / (2 * h)
             assert abs(fd - gb[i, r]) <= 1e-5 * max(abs(gb[i, r]), 1e-2 * np.abs(gb).max())
-    print(f"finite-difference check: worst |fd-ad|/tol = {worst:.3f}")
+    print(f"finite differences vs adjoint on 32 coefficients: central h=1e-6 worst rel "
+          f"{worst2:.2e}, 4-point H=1e-4 worst rel {worst4:.2e}")
 
 
 def test_stale_factors_rejected():

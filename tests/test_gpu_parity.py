@@ -59,7 +59,9 @@ def test_factor_tiled_path(shape, smax, nb):
 
 
 @pytest.mark.parametrize("shape,smax,nrhs", [((4, 4), 0, 1), ((16, 16), 0, 3), ((24, 20), 8, 8),
-                                             ((5, 4, 3), 0, 2), ((8, 8, 8), 40, 5)])
+                                             ((5, 4, 3), 0, 2), ((8, 8, 8), 40, 5),
+                                             ((12, 10), 0, 130), ((9, 9, 9), 0, 1),
+                                             ((40, 33), 0, 70)])
 def test_solve_parity(shape, smax, nrhs):
     import torch
     p = _rd(shape, seed=2, nrhs=nrhs)
