@@ -100,9 +100,14 @@ int mf_plan_export_tree(const mf_plan *plan, int32_t *parent, int32_t *level, in
  *                workgroup with the front resident in LDS; wider fronts take the tiled path
  *                (assembly, panel LU of nb pivots at a time, MFMA Schur GEMM).  It is clipped
  *                to what fits in one workgroup's LDS on the device.  0 keeps the current value.
- *   nb           panel width of the tiled path: 16, 32 or 64.  0 keeps the current value.
+ *   nb           panel width of the tiled path's separate panel launches: 16, 32 or 64.
+ *                0 keeps the current value.
+ *   fused_max_m  tiled fronts of width <= fused_max_m run all their panels (32 pivots each) in
+ *                one workgroup, leaving only the Schur GEMM to a separate launch; wider fronts
+ *                use one launch per panel step.  Clipped to 576; -1 disables the fused route;
+ *                0 keeps the current value.
  * Invalidates a previous factorization.  Errors: MF_EINVAL. */
-int mf_set_tuning(mf_plan *plan, int32_t small_max_m, int32_t nb);
+int mf_set_tuning(mf_plan *plan, int32_t small_max_m, int32_t nb, int32_t fused_max_m);
 
 /* Numerical factorization (Table 2 over Foata classes, Sec. 3.3): for every class in order, all
  * its fronts extend-add their children's contribution blocks (a leaf takes its element

@@ -54,7 +54,7 @@ def load():
         "mf_plan_info": (c_int32, [P, POINTER(MfInfo)]),
         "mf_plan_export_tree": (c_int32, [P, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                           c_void_p]),
-        "mf_set_tuning": (c_int32, [P, c_int32, c_int32]),
+        "mf_set_tuning": (c_int32, [P, c_int32, c_int32, c_int32]),
         "mf_factor": (c_int32, [P, c_void_p, c_int32, c_void_p]),
         "mf_solve": (c_int32, [P, c_void_p, c_void_p, c_int32, c_int32, c_void_p]),
         "mf_residual": (c_int32, [P, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),

@@ -328,10 +328,22 @@ void build_schedule(HostPlan &P, const Tuning &t) {
   };
   for (auto &L : P.levels) {
     int32_t max_steps = 0;
-    for (int32_t f : L.large) max_steps = std::max(max_steps, (P.desc[f].k + nb - 1) / nb);
+    for (int32_t f : L.large) {
+      const FrontDesc &d = P.desc[f];
+      if (d.m <= t.fused_max_m) {
+        if (d.k > 0) {
+          L.fused.push_back(f);
+          L.fused_max_m = std::max(L.fused_max_m, d.m);
+        }
+      } else {
+        max_steps = std::max(max_steps, (d.k + nb - 1) / nb);
+      }
+    }
     L.steps.assign(max_steps, PanelStep());
     for (int32_t f : L.large) {
       const FrontDesc &d = P.desc[f];
+      add_tiles(L.schur, f, d.k, d.m, d.k, d.m, 0, d.k);
+      if (d.m <= t.fused_max_m) continue;
       for (int32_t s = 0; s * nb < d.k; ++s) {
         const int32_t p0 = s * nb, pe = std::min(p0 + nb, d.k);
         PanelStep &S = L.steps[s];
@@ -343,7 +355,6 @@ void build_schedule(HostPlan &P, const Tuning &t) {
         add_tiles(S.update, f, pe, d.k, d.k, d.m, p0, pe);
         add_tiles(S.update, f, d.k, d.m, pe, d.k, p0, pe);
       }
-      add_tiles(L.schur, f, d.k, d.m, d.k, d.m, 0, d.k);
     }
   }
 }

@@ -72,6 +72,14 @@ void level_costs(const mf::HostPlan &H, const mf::LevelSchedule &S, LevelDev &D,
     D.c_assemble.bytes += 8.0 * (cb + (double)d.m * d.m);
     D.c_assemble.flops += cb;
   }
+  for (int32_t f : S.fused) {
+    // the fully summed rows and columns read and written once; flops of the pivots minus the
+    // Schur product left to the GEMM
+    const mf::FrontDesc &d = H.desc[f];
+    const double m = d.m, k = d.k, c = m - k;
+    D.c_fused.bytes += 16.0 * (m * k + k * c);
+    D.c_fused.flops += elim_flops(d.m, d.k) - 2.0 * k * c * c;
+  }
   for (size_t s = 0; s < S.steps.size(); ++s) {
     const mf::PanelStep &st = S.steps[s];
     StepDev &sd = D.steps[s];
@@ -147,6 +155,9 @@ int ensure_uploaded(mf_plan *P) {
     D.large = put(S.large);
     D.n_large = (int64_t)S.large.size();
     D.large_max_m = S.large_max_m;
+    D.fused = put(S.fused);
+    D.n_fused = (int64_t)S.fused.size();
+    D.fused_max_m = S.fused_max_m;
     D.all = put(S.all);
     D.n_all = (int64_t)S.all.size();
     D.max_m = S.max_m;
@@ -193,7 +204,7 @@ int ensure_uploaded(mf_plan *P) {
   if (!P->cap_stream) HIPCHK(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
   // raise the dynamic-LDS limit of the kernels that size LDS per launch (best effort)
   const void *dyn[] = {(const void *)mf::k_factor_tiny, (const void *)mf::k_factor_small,
-                       (const void *)mf::k_assemble,
+                       (const void *)mf::k_assemble, (const void *)mf::k_front_panels<32>,
                        (const void *)mf::k_solve_down_wave<false>, (const void *)mf::k_solve_down_wave<true>,
                        (const void *)mf::k_solve_up_wave<false>, (const void *)mf::k_solve_up_wave<true>,
                        (const void *)mf::k_solve_down_block<false>, (const void *)mf::k_solve_down_block<true>,
@@ -270,6 +281,12 @@ int launch_factor(mf_plan *P, const double *K, int prec, hipStream_t s) {
              dim3((D.large_max_m + 3) / 4, (unsigned)D.n_large), dim3(256),
              (size_t)2 * D.large_max_m * sizeof(int), s, P->d_desc,
              P->d_lists + D.large, P->d_store, P->d_inv_l, P->d_inv_r, K, H.npe);
+      if (D.n_fused) {
+        const size_t lds = (size_t)(32 * 33 + 32 * mf::FP_MAXM) * sizeof(double);
+        LAUNCH(K_FUSED, D.c_fused, mf::k_front_panels<32>, dim3((unsigned)D.n_fused),
+               dim3(mf::FP_THREADS), lds, s, P->d_desc, P->d_lists + D.fused, (int)D.n_fused,
+               P->d_store, P->d_status);
+      }
       for (const StepDev &st : D.steps) {
         const dim3 gd((unsigned)st.n), gt((unsigned)((st.trsm_items + 255) / 256), (unsigned)st.n);
         const int32_t *fr = P->d_lists + st.fronts, *p0 = P->d_lists + st.p0;
@@ -333,9 +350,9 @@ int launch_solve(mf_plan *P, const double *b, double *x, int32_t nrhs, bool tran
       const int n = (int)D.n_all;
       const int mmax = std::max(1, D.max_m), kmax = std::max(1, D.max_k);
       if (D.max_m <= kWaveSolveMaxM) {
-        // per wave: W (mmax x nc) + coefficients
-        const int cld = down ? (kmax | 1) : (mmax | 1);
-        const int64_t cdoubles = down ? (int64_t)mmax * cld : (int64_t)kmax * cld;
+        // per wave: W (mmax x nc) + coefficients (mmax rows of kmax) + 64 reciprocals
+        const int cld = kmax | 1;
+        const int64_t cdoubles = (int64_t)mmax * cld + mf::kWaveRows;
         const int nc = chunk(P, nrhs, 4 * cdoubles, 4 * (int64_t)mmax);
         const int ldsw = (int)(mmax * nc + cdoubles);
         const size_t lds = (size_t)4 * ldsw * 8;
@@ -517,12 +534,15 @@ int mf_plan_export_tree(const mf_plan *P, int32_t *parent, int32_t *level, int64
   return MF_OK;
 }
 
-int mf_set_tuning(mf_plan *P, int32_t small_max_m, int32_t nb) {
+int mf_set_tuning(mf_plan *P, int32_t small_max_m, int32_t nb, int32_t fused_max_m) {
   if (!P) return fail(MF_EINVAL, "null plan");
   if (small_max_m < 0) return fail(MF_EINVAL, "small_max_m must be >= 0");
   if (nb != 0 && nb != 16 && nb != 32 && nb != 64) return fail(MF_EINVAL, "nb must be 16, 32 or 64");
+  if (fused_max_m < -1) return fail(MF_EINVAL, "fused_max_m must be >= -1");
   if (small_max_m > 0) P->tune.small_max_m = small_max_m;
   if (nb > 0) P->tune.nb = nb;
+  if (fused_max_m == -1) P->tune.fused_max_m = 0;
+  else if (fused_max_m > 0) P->tune.fused_max_m = std::min(fused_max_m, mf::FP_MAXM);
   P->uploaded = false;      // the schedule is rebuilt at the next device call
   P->factored = false;
   P->drop_graphs();

@@ -39,11 +39,11 @@ inline int fail(int code, const std::string &msg) {
   } while (0)
 
 enum Kind {
-  K_TINY, K_SMALL, K_ASSEMBLE, K_DIAG, K_TRSM, K_GEMM_PANEL, K_GEMM_SCHUR,
+  K_TINY, K_SMALL, K_ASSEMBLE, K_FUSED, K_DIAG, K_TRSM, K_GEMM_PANEL, K_GEMM_SCHUR,
   K_DOWN_WAVE, K_DOWN_BLOCK, K_UP_WAVE, K_UP_BLOCK, K_RESIDUAL, K_OTHER, K_COUNT
 };
 static const char *const kKindName[K_COUNT] = {
-    "factor_tiny", "factor_small", "assemble", "panel_diag", "panel_trsm", "gemm_panel",
+    "factor_tiny", "factor_small", "assemble", "front_panels", "panel_diag", "panel_trsm", "gemm_panel",
     "gemm_schur", "solve_down_wave", "solve_down_block", "solve_up_wave", "solve_up_block",
     "residual", "other"};
 
@@ -67,11 +67,13 @@ struct LevelDev {
   int32_t small_max_m = 0;
   int64_t large = 0, n_large = 0;
   int32_t large_max_m = 0;
+  int64_t fused = 0, n_fused = 0;
+  int32_t fused_max_m = 0;
   int64_t all = 0, n_all = 0;
   int32_t max_m = 0, max_k = 0;
   std::vector<StepDev> steps;
   int64_t schur = 0, n_schur = 0;
-  Cost c_tiny, c_small, c_assemble, c_schur;
+  Cost c_tiny, c_small, c_assemble, c_schur, c_fused;
   // solves: fixed (coefficient) bytes, bytes and flops per right-hand side
   double down_coef = 0, down_rhs_bytes = 0, down_rhs_flops = 0;
   double up_coef = 0, up_rhs_bytes = 0, up_rhs_flops = 0;

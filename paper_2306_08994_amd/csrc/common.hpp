@@ -103,6 +103,39 @@ __device__ inline double gather_entry(const GatherCtx &g, int li, int lj, int ri
   return v;
 }
 
+// One source of the extend-add: its n x n block (leading dimension lda, contiguous rows) is
+// assigned (ADD = false) or added into the LDS front at rows/columns map[.].  Loads are issued
+// in batches of four independent reads before their LDS writes, so a thread keeps several
+// memory round trips in flight.
+template <bool ADD>
+__device__ inline void scatter_source(const double *__restrict__ src, int lda, int n,
+                                      const int *map, int ld, double *sh, int t0, int nt) {
+  const int nn = n * n;
+  for (int tb = t0; tb < nn; tb += 4 * nt) {
+    double v[4];
+    int dst[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = tb + u * nt;
+      dst[u] = -1;
+      v[u] = 0.0;
+      if (t < nn) {
+        const int r = t / n, c = t - (t / n) * n;
+        v[u] = src[(int64_t)r * lda + c];
+        dst[u] = map[r] * ld + map[c];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (dst[u] >= 0) {
+        if (ADD)
+          sh[dst[u]] += v[u];
+        else
+          sh[dst[u]] = v[u];
+      }
+  }
+}
+
 // Extend-add into an LDS front (row stride ld) by scattering the sources' contiguous rows:
 // zero, then the left source assigned, then the right source added -- the same order of
 // additions as summing the entries of each front position left then right.  `sync` orders
@@ -122,25 +155,9 @@ __device__ inline void scatter_assemble(const GatherCtx &g, const int32_t *__res
     }
   }
   sync();
-  {
-    const int n = g.na;
-    const double *src = g.ca;
-#pragma unroll 4
-    for (int t = t0; t < n * n; t += nt) {
-      const int r = t / n, c = t - (t / n) * n;
-      sh[ma[r] * ld + ma[c]] = src[(int64_t)r * g.la + c];
-    }
-  }
+  scatter_source<false>(g.ca, g.la, g.na, ma, ld, sh, t0, nt);
   sync();
-  if (!g.ke) {
-    const int n = g.nb;
-    const double *src = g.cb;
-#pragma unroll 4
-    for (int t = t0; t < n * n; t += nt) {
-      const int r = t / n, c = t - (t / n) * n;
-      sh[mb[r] * ld + mb[c]] += src[(int64_t)r * g.lb + c];
-    }
-  }
+  if (!g.ke) scatter_source<true>(g.cb, g.lb, g.nb, mb, ld, sh, t0, nt);
   sync();
 }
 

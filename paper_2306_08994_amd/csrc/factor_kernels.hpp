@@ -137,8 +137,46 @@ k_assemble(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ list,
   }
 }
 
-// Panel step, part 1: LU of the pb x pb diagonal block at (p0, p0), one workgroup per front.
-// One wave per front, wave-level ordering only.
+// LU (division tasks scale the pivot row) of the pb x pb diagonal block at F (leading
+// dimension m) by one wave in LDS D, written back.  Lane j loads column j with independent
+// loads; the elimination uses wave-level ordering only.  Returns false on a bad pivot (the same
+// value on every lane) after recording it.
+template <int NB>
+__device__ inline bool wave_diag_lu(double *F, int64_t m, int pb, double (*D)[NB + 1], int lane,
+                                    int f, int p0, int *status) {
+  static_assert(NB <= 64, "one lane per column");
+  if (lane < pb) {
+    double col[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) col[i] = i < pb ? F[i * m + lane] : 0.0;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) D[i][lane] = col[i];
+  }
+  wave_sync();
+  bool ok = true;
+  for (int p = 0; p < pb; ++p) {
+    const double piv = D[p][p];
+    if (!good_pivot(piv)) {
+      if (lane == 0) record_bad_pivot(status, f, p0 + p);
+      ok = false;
+      break;
+    }
+    for (int j = p + 1 + lane; j < pb; j += 64) D[p][j] = D[p][j] / piv;
+    wave_sync();
+    for (int j = p + 1 + (lane & 31); j < pb; j += 32)
+      for (int i = p + 1 + (lane >> 5); i < pb; i += 2) D[i][j] -= D[i][p] * D[p][j];
+    wave_sync();
+  }
+  if (lane < pb) {
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+      if (i < pb) F[i * m + lane] = D[i][lane];
+  }
+  return ok;
+}
+
+// Panel step, part 1 (fronts wider than the fused kernel's limit): LU of the diagonal block,
+// one wave per front.
 template <int NB>
 __global__ void __launch_bounds__(64)
 k_panel_diag(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ fronts,
@@ -147,29 +185,8 @@ k_panel_diag(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ front
   const int f = fronts[blockIdx.x];
   const int p0 = p0s[blockIdx.x];
   const FrontDesc d = fd[f];
-  const int m = d.m, pb = min(NB, d.k - p0);
-  double *F = store + d.store + (int64_t)p0 * m + p0;
-  const int lane = threadIdx.x;
-  for (int i = 0; i < pb; ++i)
-    for (int j = lane; j < pb; j += 64) D[i][j] = F[(int64_t)i * m + j];
-  wave_sync();
-  for (int p = 0; p < pb; ++p) {
-    const double piv = D[p][p];
-    if (!good_pivot(piv)) {
-      if (lane == 0) record_bad_pivot(status, f, p0 + p);
-      break;
-    }
-    for (int j = p + 1 + lane; j < pb; j += 64) D[p][j] = D[p][j] / piv;
-    wave_sync();
-    const int r = pb - p - 1;
-    for (int t = lane; t < r * r; t += 64) {
-      const int i = p + 1 + t / r, j = p + 1 + t % r;
-      D[i][j] -= D[i][p] * D[p][j];
-    }
-    wave_sync();
-  }
-  for (int i = 0; i < pb; ++i)
-    for (int j = lane; j < pb; j += 64) F[(int64_t)i * m + j] = D[i][j];
+  const int pb = min(NB, d.k - p0);
+  wave_diag_lu<NB>(store + d.store + (int64_t)p0 * d.m + p0, d.m, pb, D, threadIdx.x, f, p0, status);
 }
 
 // Panel step, part 2: the two triangular solves against the factored diagonal block.
@@ -189,8 +206,13 @@ k_panel_trsm(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ front
   const int item = blockIdx.x * 256 + threadIdx.x;
   if ((int)(blockIdx.x * 256) >= 2 * rest) return;   // whole block idle (uniform)
   double *F = store + d.store;
-  for (int t = threadIdx.x; t < pb * pb; t += 256)
-    D[t / pb][t % pb] = F[(int64_t)(p0 + t / pb) * m + p0 + t % pb];
+  if ((int)threadIdx.x < pb) {
+    double col[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) col[i] = i < pb ? F[(int64_t)(p0 + i) * m + p0 + threadIdx.x] : 0.0;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) D[i][threadIdx.x] = col[i];
+  }
   __syncthreads();
   if (item >= 2 * rest) return;
   double v[NB];
@@ -227,6 +249,124 @@ k_panel_trsm(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ front
 #pragma unroll
     for (int q = 0; q < NB; ++q)
       if (q < pb) row[q] = v[q];
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Fused per-front partial LU of the fully summed rows and columns (fronts up to FP_MAXM wide):
+// one workgroup per front runs every panel of NB pivots -- wave 0 factors the diagonal block,
+// every thread then solves one L21 row and one U12 column against it (independent, no
+// synchronisation), and updates its L21 row across the still-to-be-eliminated columns of the
+// fully summed region.  The Schur complement C22 is left to the MFMA GEMM.
+// LDS: D (NB x NB+1) | U12 panel (NB x (m - pe)).
+// ---------------------------------------------------------------------------------------------
+constexpr int FP_THREADS = 512;
+constexpr int FP_ROWS = 2;            // rows (and columns) per thread
+constexpr int FP_MAXM = 576;          // widest front of this route (LDS and FP_ROWS bound)
+
+template <int NB>
+__global__ void __launch_bounds__(FP_THREADS)
+k_front_panels(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ list, int nlist,
+               double *__restrict__ store, int *__restrict__ status) {
+  static_assert(FP_ROWS * FP_THREADS >= FP_MAXM, "rows per thread");
+  extern __shared__ double sm[];
+  double(*D)[NB + 1] = reinterpret_cast<double(*)[NB + 1]>(sm);
+  double *Ub = sm + NB * (NB + 1);
+  __shared__ int bad;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int li = blockIdx.x; li < nlist; li += gridDim.x) {
+    const int f = list[li];
+    const FrontDesc d = fd[f];
+    const int m = d.m, k = d.k;
+    double *F = store + d.store;
+    if (tid == 0) bad = 0;
+    for (int p0 = 0; p0 < k; p0 += NB) {
+      const int pb = min(NB, k - p0), pe = p0 + pb, rest = m - pe;
+      if (wv == 0 && !wave_diag_lu<NB>(F + (int64_t)p0 * m + p0, m, pb, D, lane, f, p0, status))
+        if (lane == 0) bad = 1;
+      __syncthreads();
+      if (bad) break;
+      for (int s = 0; s < FP_ROWS; ++s) {
+        const int o = tid + s * FP_THREADS;
+        if (o < rest) {
+          // L21 row pe+o:  l = a U11^{-1}
+          double *row = F + (int64_t)(pe + o) * m + p0;
+          double v[NB];
+#pragma unroll
+          for (int q = 0; q < NB; ++q) v[q] = q < pb ? row[q] : 0.0;
+#pragma unroll
+          for (int q = 0; q < NB; ++q) {
+            if (q < pb) {
+              double t = v[q];
+#pragma unroll
+              for (int r = 0; r < q; ++r) t -= v[r] * D[r][q];
+              v[q] = t;
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < NB; ++q)
+            if (q < pb) row[q] = v[q];
+          // U12 column pe+o:  u = L11^{-1} a
+          double *colp = F + (int64_t)p0 * m + pe + o;
+#pragma unroll
+          for (int q = 0; q < NB; ++q) v[q] = q < pb ? colp[(int64_t)q * m] : 0.0;
+#pragma unroll
+          for (int q = 0; q < NB; ++q) {
+            if (q < pb) {
+              double t = v[q];
+#pragma unroll
+              for (int r = 0; r < q; ++r) t -= D[q][r] * v[r];
+              v[q] = t / D[q][q];
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < NB; ++q)
+            if (q < pb) {
+              colp[(int64_t)q * m] = v[q];
+              Ub[q * rest + o] = v[q];
+            }
+        }
+      }
+      __syncthreads();
+      // update rows pe.. over the columns of the fully summed region still to eliminate:
+      // rows < k take columns pe..m-1, rows >= k take columns pe..k-1 (C22 is the GEMM's)
+      for (int s = 0; s < FP_ROWS; ++s) {
+        const int o = tid + s * FP_THREADS;
+        if (o < rest) {
+          const int i = pe + o;
+          const int jn = (i < k ? m : k) - pe;
+          double *Ci = F + (int64_t)i * m + pe;
+          double lr[NB];              // this thread's L21 row, written above by itself
+          const double *lp = F + (int64_t)i * m + p0;
+#pragma unroll
+          for (int q = 0; q < NB; ++q) lr[q] = q < pb ? lp[q] : 0.0;
+          int j = 0;
+          for (; j + 4 <= jn; j += 4) {
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+              const double l = lr[q];
+              const double *u = Ub + q * rest + j;
+              a0 += l * u[0];
+              a1 += l * u[1];
+              a2 += l * u[2];
+              a3 += l * u[3];
+            }
+            Ci[j] -= a0;
+            Ci[j + 1] -= a1;
+            Ci[j + 2] -= a2;
+            Ci[j + 3] -= a3;
+          }
+          for (; j < jn; ++j) {
+            double a0 = 0.0;
+#pragma unroll
+            for (int q = 0; q < NB; ++q) a0 += lr[q] * Ub[q * rest + j];
+            Ci[j] -= a0;
+          }
+        }
+      }
+      __syncthreads();
+    }
   }
 }
 

@@ -45,7 +45,9 @@ struct LevelSchedule {
   int32_t small_max_m = 0;
   std::vector<int32_t> large;      // fronts assembled and factored in HBM
   int32_t large_max_m = 0;
-  std::vector<PanelStep> steps;
+  std::vector<int32_t> fused;      // large fronts whose panels run in one workgroup
+  int32_t fused_max_m = 0;
+  std::vector<PanelStep> steps;    // panel steps of the large fronts that are not fused
   std::vector<GemmTask> schur;     // C22 -= L21 U12 tiles of the large fronts
   std::vector<int32_t> all;        // every front of the class that the solve visits
   int32_t max_m = 0, max_k = 0;
@@ -72,6 +74,7 @@ struct Tuning {
   int32_t tiny_max_m = 32;     // fronts up to this width are factored one per wave
   int32_t small_max_m = 128;   // fronts up to this width are factored in LDS
   int32_t nb = 32;             // panel width of the tiled path
+  int32_t fused_max_m = 576;   // tiled fronts up to this width run all panels in one workgroup
   int32_t tile = 64;           // GEMM output tile edge
 };
 

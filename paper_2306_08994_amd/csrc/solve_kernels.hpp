@@ -45,10 +45,27 @@ __device__ inline double down_gather(const FrontDesc &d, const FrontDesc &a, con
 }
 
 // ---------------------------------------------------------------------------------------------
-// One wave per front (fronts of width <= 64), four fronts per workgroup.  The front's
-// coefficients are staged in LDS once; pivots are eliminated one at a time with wave-level
-// ordering only.  LDS per wave: ldsw doubles = W (mmax x nc) + coefficients (mmax x cld).
+// One wave per front (fronts of width <= 64), four fronts per workgroup.  Lane i owns row i of
+// the front for every global access (coefficients, gathers, results), so each lane issues its
+// loads back to back; pivots are eliminated one at a time in LDS with wave-level ordering.
+// LDS per wave: ldsw doubles = W (mmax x nc) + coefficients (cdoubles) + reciprocals (64).
 // ---------------------------------------------------------------------------------------------
+constexpr int kWaveRows = 64;
+
+// Loads n values v[u] = src[u * stride], u < n, eight independent loads at a time, into
+// dst[u * dstride] (LDS).
+__device__ inline void copy_strided(const double *__restrict__ src, int64_t stride, int n,
+                                    double *dst, int dstride) {
+  for (int u0 = 0; u0 < n; u0 += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = u0 + u < n ? src[(int64_t)(u0 + u) * stride] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (u0 + u < n) dst[(u0 + u) * dstride] = v[u];
+  }
+}
+
 template <bool TRANS>
 __global__ void __launch_bounds__(256)
 k_solve_down_wave(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ list, int nlist,
@@ -59,44 +76,57 @@ k_solve_down_wave(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ 
   extern __shared__ double sm[];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double *W = sm + wv * ldsw;
-  double *C = W + mmax * nc;     // C[i * cld + p] = cd(i, p), i >= p
+  double *C = W + mmax * nc;       // C[i * cld + p] = cd(i, p), p <= i, p < k
+  double *rdv = C + mmax * cld;    // reciprocal of each pivot's diagonal coefficient
   for (int li = blockIdx.x * 4 + wv; li < nlist; li += gridDim.x * 4) {
     const int f = list[li];
     const FrontDesc d = fd[f];
     const int m = d.m, k = d.k;
-    const int32_t *idx = front_idx + d.idx;
-    const int32_t *il = inv_l + d.idx;
-    const int32_t *ir = inv_r + d.idx;
     const double *F = store + d.store;
     FrontDesc a = d, c = d;
     if (d.elem < 0) {
       a = fd[d.left];
       c = fd[d.right];
     }
-    for (int t = lane; t < m * k; t += 64) {
-      const int i = t / k, p = t - (t / k) * k;
-      C[i * cld + p] = i >= p ? cdown<TRANS>(F, m, i, p) : 0.0;
+    const bool use_a = d.elem < 0 && !passthrough(a), use_c = d.elem < 0 && !passthrough(c);
+    const int i = lane;                               // this lane's row
+    int64_t gi = 0;
+    int xa = -1, xc = -1;
+    if (i < m) {
+      gi = front_idx[d.idx + i];
+      if (use_a) xa = inv_l[d.idx + i];
+      if (use_c) xc = inv_r[d.idx + i];
+      const int np = min(i + 1, k);
+      if (TRANS)
+        copy_strided(F + i, m, np, C + i * cld, 1);            // U[p][i], p <= i
+      else
+        copy_strided(F + (int64_t)i * m, 1, np, C + i * cld, 1);   // L[i][p], p <= i
     }
+    wave_sync();
+    if (i < k) rdv[i] = TRANS ? 1.0 : 1.0 / C[i * cld + i];
     for (int r0 = 0; r0 < nrhs; r0 += nc) {
       const int nr = min(nc, nrhs - r0);
-      for (int t = lane; t < m * nr; t += 64) {
-        const int i = t / nr, r = t - (t / nr) * nr;
-        W[i * nr + r] = down_gather(d, a, c, idx, il, ir, b, ycb, nrhs, i, r0 + r);
-      }
+      if (i < m)
+        for (int r = 0; r < nr; ++r) {
+          double v = i < k ? b[gi * nrhs + r0 + r] : 0.0;
+          if (xa >= 0) v += ycb[(a.cbrow + xa) * nrhs + r0 + r];
+          if (xc >= 0) v += ycb[(c.cbrow + xc) * nrhs + r0 + r];
+          W[i * nr + r] = v;
+        }
       wave_sync();
       for (int p = 0; p < k; ++p) {
-        const double rdv = TRANS ? 1.0 : 1.0 / C[p * cld + p];
+        const double rp = rdv[p];
         for (int t = lane; t < (m - p - 1) * nr; t += 64) {
-          const int i = p + 1 + t / nr, r = t - (t / nr) * nr;
-          W[i * nr + r] -= C[i * cld + p] * (W[p * nr + r] * rdv);
+          const int ii = p + 1 + t / nr, r = t - (t / nr) * nr;
+          W[ii * nr + r] -= C[ii * cld + p] * (W[p * nr + r] * rp);
         }
-        for (int r = lane; r < nr; r += 64) x[(int64_t)idx[p] * nrhs + r0 + r] = W[p * nr + r] * rdv;
         wave_sync();
       }
-      for (int t = lane; t < (m - k) * nr; t += 64) {
-        const int i = k + t / nr, r = t - (t / nr) * nr;
-        ycb[(d.cbrow + i - k) * nrhs + r0 + r] = W[i * nr + r];
-      }
+      // pivot rows: y = w / L_pp (row p is final after step p); CB rows: the contribution block
+      if (i < k)
+        for (int r = 0; r < nr; ++r) x[gi * nrhs + r0 + r] = W[i * nr + r] * rdv[i];
+      else if (i < m)
+        for (int r = 0; r < nr; ++r) ycb[(d.cbrow + i - k) * nrhs + r0 + r] = W[i * nr + r];
       wave_sync();
     }
   }
@@ -110,40 +140,49 @@ k_solve_up_wave(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ li
   extern __shared__ double sm[];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double *W = sm + wv * ldsw;
-  double *C = W + mmax * nc;     // C[q * cld + j] = cu(q, j), q < k, j >= q
+  double *C = W + mmax * nc;       // C[j * cld + q] = cu(q, j), q <= j, q < k  (column-major)
+  double *rdv = C + mmax * cld;
   for (int li = blockIdx.x * 4 + wv; li < nlist; li += gridDim.x * 4) {
     const int f = list[li];
     const FrontDesc d = fd[f];
     const int m = d.m, k = d.k;
-    const int32_t *idx = front_idx + d.idx;
     const double *F = store + d.store;
-    for (int t = lane; t < k * m; t += 64) {
-      const int q = t / m, j = t - (t / m) * m;
-      C[q * cld + j] = j >= q ? cup<TRANS>(F, m, q, j) : 0.0;
+    const int j = lane;                               // this lane's row / column
+    int64_t gj = 0;
+    if (j < m) {
+      gj = front_idx[d.idx + j];
+      const int nq = min(j + 1, k);
+      if (TRANS)
+        copy_strided(F + (int64_t)j * m, 1, nq, C + j * cld, 1);   // L[j][q], q <= j
+      else
+        copy_strided(F + j, m, nq, C + j * cld, 1);                // U[q][j], q <= j
     }
+    wave_sync();
+    if (j < k) rdv[j] = TRANS ? 1.0 / C[j * cld + j] : 1.0;
     for (int r0 = 0; r0 < nrhs; r0 += nc) {
       const int nr = min(nc, nrhs - r0);
-      for (int t = lane; t < m * nr; t += 64) {
-        const int i = t / nr, r = t - (t / nr) * nr;
-        W[i * nr + r] = x[(int64_t)idx[i] * nrhs + r0 + r];
-      }
+      if (j < m)
+        for (int r = 0; r < nr; ++r) W[j * nr + r] = x[gj * nrhs + r0 + r];
       wave_sync();
+      // the already-final CB unknowns applied to the pivot rows
       for (int t = lane; t < k * nr; t += 64) {
         const int p = t / nr, r = t - (t / nr) * nr;
         double s = 0.0;
-        for (int j = k; j < m; ++j) s += C[p * cld + j] * W[j * nr + r];
+        for (int jj = k; jj < m; ++jj) s += C[jj * cld + p] * W[jj * nr + r];
         W[p * nr + r] -= s;
       }
       wave_sync();
       for (int p = k - 1; p >= 0; --p) {
-        const double rdv = TRANS ? 1.0 / C[p * cld + p] : 1.0;
+        const double rp = rdv[p];
         for (int t = lane; t < p * nr; t += 64) {
           const int q = t / nr, r = t - (t / nr) * nr;
-          W[q * nr + r] -= C[q * cld + p] * (W[p * nr + r] * rdv);
+          W[q * nr + r] -= C[p * cld + q] * (W[p * nr + r] * rp);
         }
-        for (int r = lane; r < nr; r += 64) x[(int64_t)idx[p] * nrhs + r0 + r] = W[p * nr + r] * rdv;
         wave_sync();
       }
+      if (j < k)
+        for (int r = 0; r < nr; ++r) x[gj * nrhs + r0 + r] = W[j * nr + r] * rdv[j];
+      wave_sync();
     }
   }
 }
@@ -220,7 +259,11 @@ k_solve_down_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__
           // stale LDS contents never enter it
           for (int t = pb * nr + lane; t < NBS * nr; t += 64) Y[t] = 0.0;
           for (int p = 0; p < pb; ++p) {
-            for (int r = lane; r < nr; r += 64) Y[p * nr + r] = W[(p0 + p) * nr + r] * rd[p];
+            for (int r = lane; r < nr; r += 64) {
+              const double y = W[(p0 + p) * nr + r] * rd[p];
+              Y[p * nr + r] = y;
+              W[(p0 + p) * nr + r] = y;     // row p is read only through Y from here on
+            }
             wave_sync();
             for (int t = lane; t < (pb - p - 1) * nr; t += 64) {
               const int i = p + 1 + t / nr, r = t - (t / nr) * nr;
@@ -230,10 +273,6 @@ k_solve_down_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__
           }
         }
         __syncthreads();
-        for (int t = tid; t < pb * nr; t += 256) {
-          const int p = t / nr, r = t - (t / nr) * nr;
-          x[(int64_t)idx[p0 + p] * nrhs + r0 + r] = Y[t];
-        }
         for (int i = pe + tid; i < m; i += 256) {
           double cf[NBS];
 #pragma unroll
@@ -247,8 +286,14 @@ k_solve_down_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__
         }
       }
       __syncthreads();
-      for (int i = k + tid; i < m; i += 256)
-        for (int r = 0; r < nr; ++r) ycb[(d.cbrow + i - k) * nrhs + r0 + r] = W[i * nr + r];
+      for (int i = tid; i < m; i += 256) {
+        if (i < k) {
+          const int64_t gi = idx[i];
+          for (int r = 0; r < nr; ++r) x[gi * nrhs + r0 + r] = W[i * nr + r];
+        } else {
+          for (int r = 0; r < nr; ++r) ycb[(d.cbrow + i - k) * nrhs + r0 + r] = W[i * nr + r];
+        }
+      }
       __syncthreads();
     }
   }
@@ -312,7 +357,11 @@ k_solve_up_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ l
         if (wv == 0) {
           for (int t = pb * nr + lane; t < NBS * nr; t += 64) X[t] = 0.0;
           for (int p = pb - 1; p >= 0; --p) {
-            for (int r = lane; r < nr; r += 64) X[p * nr + r] = W[(p0 + p) * nr + r] * rd[p];
+            for (int r = lane; r < nr; r += 64) {
+              const double v = W[(p0 + p) * nr + r] * rd[p];
+              X[p * nr + r] = v;
+              W[(p0 + p) * nr + r] = v;
+            }
             wave_sync();
             for (int t = lane; t < p * nr; t += 64) {
               const int q = t / nr, r = t - (t / nr) * nr;
@@ -322,10 +371,6 @@ k_solve_up_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ l
           }
         }
         __syncthreads();
-        for (int t = tid; t < pb * nr; t += 256) {
-          const int p = t / nr, r = t - (t / nr) * nr;
-          x[(int64_t)idx[p0 + p] * nrhs + r0 + r] = X[t];
-        }
         for (int q = tid; q < p0; q += 256) {
           double cf[NBS];
 #pragma unroll
@@ -337,6 +382,11 @@ k_solve_up_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ l
             W[q * nr + r] -= s;
           }
         }
+      }
+      __syncthreads();
+      for (int p = tid; p < k; p += 256) {
+        const int64_t gp = idx[p];
+        for (int r = 0; r < nr; ++r) x[gp * nrhs + r0 + r] = W[p * nr + r];
       }
       __syncthreads();
     }

@@ -87,9 +87,10 @@ class Plan:
                                               ptr(out["npiv"]), ptr(out["leaf_elem"])))
         return out
 
-    def set_tuning(self, small_max_m: int = 0, nb: int = 0):
+    def set_tuning(self, small_max_m: int = 0, nb: int = 0, fused_max_m: int = 0):
+        """See mf_set_tuning: 0 keeps a value; fused_max_m=-1 disables the fused panel route."""
         self.factor_version += 1
-        check(_lib.load().mf_set_tuning(self._h, int(small_max_m), int(nb)))
+        check(_lib.load().mf_set_tuning(self._h, int(small_max_m), int(nb), int(fused_max_m)))
 
     # -- numerics ----------------------------------------------------------------------------
     def factor(self, K, precision: str = "fp64"):

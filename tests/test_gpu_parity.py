@@ -13,13 +13,13 @@ from tests import gpu_common as G
 pytestmark = pytest.mark.gpu
 
 
-def _setup(problem, small_max_m=0, nb=0):
+def _setup(problem, small_max_m=0, nb=0, fused=0):
     import torch
     from paper_2306_08994_amd import Plan
     dev = G.torch_dev()
     plan = Plan(problem.meshes)
-    if small_max_m or nb:
-        plan.set_tuning(small_max_m, nb)
+    if small_max_m or nb or fused:
+        plan.set_tuning(small_max_m, nb, fused)
     K = torch.from_numpy(problem.K).to(dev)
     b = torch.from_numpy(problem.b).to(dev)
     return plan, K, b
@@ -42,15 +42,18 @@ def test_factor_lds_path(shape):
     assert G.factor_violation(Ls, Us, fac) <= G.TOL_FACTOR
 
 
-TILED = [((64, 48), 8, 16), ((96, 80), 24, 32), ((70, 53), 40, 64), ((10, 9, 8), 16, 32),
-         ((12, 12, 12), 40, 16), ((14, 11, 9), 24, 64), ((12, 12, 12), 100, 32)]
+# (shape, LDS limit, panel width of separate panel launches, fused-route limit: -1 = off)
+TILED = [((64, 48), 8, 16, -1), ((96, 80), 24, 32, -1), ((70, 53), 40, 64, -1),
+         ((10, 9, 8), 16, 32, -1), ((12, 12, 12), 40, 16, 100), ((14, 11, 9), 24, 64, -1),
+         ((12, 12, 12), 100, 32, 0), ((64, 48), 8, 32, 0), ((14, 11, 9), 24, 32, 0),
+         ((20, 20, 20), 0, 0, 0)]
 
 
-@pytest.mark.parametrize("shape,smax,nb", TILED)
-def test_factor_tiled_path(shape, smax, nb):
+@pytest.mark.parametrize("shape,smax,nb,fused", TILED)
+def test_factor_tiled_path(shape, smax, nb, fused):
     p = _rd(shape, seed=1)
     tree, conn, fac = G.oracle_factor(p)
-    plan, K, b = _setup(p, smax, nb)
+    plan, K, b = _setup(p, smax, nb, fused)
     plan.factor(K)
     Ls, Us = plan.export_factors()
     ms = np.diff(tree.front_ptr)
@@ -58,15 +61,16 @@ def test_factor_tiled_path(shape, smax, nb):
     assert G.factor_violation(Ls, Us, fac) <= G.TOL_FACTOR
 
 
-@pytest.mark.parametrize("shape,smax,nrhs", [((4, 4), 0, 1), ((16, 16), 0, 3), ((24, 20), 8, 8),
-                                             ((5, 4, 3), 0, 2), ((8, 8, 8), 40, 5),
-                                             ((12, 10), 0, 130), ((9, 9, 9), 0, 1),
-                                             ((40, 33), 0, 70)])
-def test_solve_parity(shape, smax, nrhs):
+@pytest.mark.parametrize("shape,smax,nrhs,fused", [((4, 4), 0, 1, 0), ((16, 16), 0, 3, 0),
+                                                   ((24, 20), 8, 8, -1), ((5, 4, 3), 0, 2, 0),
+                                                   ((8, 8, 8), 40, 5, 0), ((12, 10), 0, 130, 0),
+                                                   ((9, 9, 9), 0, 1, 0), ((40, 33), 0, 70, 0),
+                                                   ((16, 16, 16), 0, 3, -1)])
+def test_solve_parity(shape, smax, nrhs, fused):
     import torch
     p = _rd(shape, seed=2, nrhs=nrhs)
     tree, conn, fac = G.oracle_factor(p)
-    plan, K, b = _setup(p, smax)
+    plan, K, b = _setup(p, smax, 0, fused)
     plan.factor(K)
     for trans in (False, True):
         x = plan.solve(b, transpose=trans).cpu().numpy()
