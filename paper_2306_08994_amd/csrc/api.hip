@@ -272,7 +272,7 @@ int launch_factor(mf_plan *P, const double *K, int prec, hipStream_t s) {
       const int m = D.small_max_m;
       const size_t lds = ((size_t)m * (m | 1) + m) * sizeof(double);
       const int grid = (int)std::min<int64_t>(D.n_small, 16384);
-      LAUNCH(K_SMALL, D.c_small, mf::k_factor_small, dim3(grid), dim3(256), lds, s, P->d_desc,
+      LAUNCH(K_SMALL, D.c_small, mf::k_factor_small, dim3(grid), dim3(mf::SM_THREADS), lds, s, P->d_desc,
              P->d_lists + D.small, (int)D.n_small, P->d_store, P->d_inv_l, P->d_inv_r, K, H.npe,
              P->d_status, m);
     }
@@ -434,11 +434,14 @@ int run_graphed(mf_plan *P, Graph *cache, int n_cache, int &next, const GraphKey
   return MF_OK;
 }
 
-int col_norms(mf_plan *P, const double *a, int64_t n, int32_t nrhs, hipStream_t s,
-              std::vector<double> &out) {
+// Column 2-norms of up to two [n][nrhs] device arrays with one host synchronisation.
+int col_norms(mf_plan *P, const double *a0, const double *a1, int64_t n, int32_t nrhs,
+              hipStream_t s, std::vector<double> *out0, std::vector<double> *out1) {
   const int64_t rows_per = 4096;
   const int64_t blocks = std::max<int64_t>(1, (n + rows_per - 1) / rows_per);
-  const size_t need = (size_t)blocks * nrhs;
+  const size_t per = (size_t)blocks * nrhs;
+  const int cnt = a1 ? 2 : 1;
+  const size_t need = per * cnt;
   if (P->part_cap < need) {
     if (P->h_part) (void)hipHostFree(P->h_part);
     P->h_part = nullptr;
@@ -447,15 +450,22 @@ int col_norms(mf_plan *P, const double *a, int64_t n, int32_t nrhs, hipStream_t 
     P->part_cap = need;
   }
   double *dpart = P->d_work + 2 * (size_t)n * nrhs;   // tail of the refinement workspace
-  hipLaunchKernelGGL(mf::k_colsq_partial, dim3((unsigned)blocks), dim3(256), 0, s, a, n, nrhs,
+  hipLaunchKernelGGL(mf::k_colsq_partial, dim3((unsigned)blocks), dim3(256), 0, s, a0, n, nrhs,
                      rows_per, dpart);
+  if (a1)
+    hipLaunchKernelGGL(mf::k_colsq_partial, dim3((unsigned)blocks), dim3(256), 0, s, a1, n, nrhs,
+                       rows_per, dpart + per);
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(P->h_part, dpart, need * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  out.assign(nrhs, 0.0);
-  for (int64_t bl = 0; bl < blocks; ++bl)
-    for (int c = 0; c < nrhs; ++c) out[c] += P->h_part[bl * nrhs + c];
-  for (int c = 0; c < nrhs; ++c) out[c] = std::sqrt(out[c]);
+  std::vector<double> *outs[2] = {out0, out1};
+  for (int v = 0; v < cnt; ++v) {
+    std::vector<double> &o = *outs[v];
+    o.assign(nrhs, 0.0);
+    for (int64_t bl = 0; bl < blocks; ++bl)
+      for (int c = 0; c < nrhs; ++c) o[c] += P->h_part[v * per + bl * nrhs + c];
+    for (int c = 0; c < nrhs; ++c) o[c] = std::sqrt(o[c]);
+  }
   return MF_OK;
 }
 
@@ -619,15 +629,14 @@ int mf_refine(const mf_plan *Pc, const double *elem_mats, const double *b, doubl
   const size_t nn = (size_t)n * nrhs;
   const size_t parts = (size_t)std::max<int64_t>(1, (n + 4095) / 4096) * nrhs;
   int rc;
-  if ((rc = grow(P, P->d_work, P->work_cap, 2 * nn + parts))) return rc;
+  if ((rc = grow(P, P->d_work, P->work_cap, 2 * nn + 2 * parts))) return rc;
   double *r = P->d_work, *dx = P->d_work + nn;
   if ((rc = mf_solve(P, b, x, nrhs, 0, hip_stream))) return rc;
   std::vector<double> bn, rn;
-  if ((rc = col_norms(P, b, n, nrhs, s, bn))) return rc;
   double rr = 0.0;
   for (int32_t it = 0;; ++it) {
     if ((rc = mf_residual(P, elem_mats, x, b, r, nrhs, hip_stream))) return rc;
-    if ((rc = col_norms(P, r, n, nrhs, s, rn))) return rc;
+    if ((rc = col_norms(P, r, it == 0 ? b : nullptr, n, nrhs, s, &rn, &bn))) return rc;
     rr = 0.0;
     for (int c = 0; c < nrhs; ++c) {
       const double q = bn[c] > 0 ? rn[c] / bn[c] : (rn[c] > 0 ? INFINITY : 0.0);

@@ -61,9 +61,15 @@ k_factor_tiny(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ list
 }
 
 // ---------------------------------------------------------------------------------------------
-// small: one workgroup per front, the whole front resident in LDS.
+// small: one workgroup of SM_THREADS per front, the whole front resident in LDS.  Thread t owns
+// column j = t mod m of the rows i = g, g + G, ... with g = t div m and G = SM_THREADS div m
+// groups.  At pivot p every owner of column j > p forms U[p][j] = F[p][j] / F[p][p] itself
+// (the division task) and subtracts F[i][p] U[p][j] from its rows i > p; the scaled row p is
+// stored one step later (nothing reads row p then), so one barrier per pivot orders the steps.
 // ---------------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(256)
+constexpr int SM_THREADS = 512;
+
+__global__ void __launch_bounds__(SM_THREADS)
 k_factor_small(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ list, int nlist,
                double *__restrict__ store, const int32_t *__restrict__ inv_l,
                const int32_t *__restrict__ inv_r, const double *__restrict__ K, int npe,
@@ -79,26 +85,41 @@ k_factor_small(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ lis
     const int32_t *il = inv_l + d.idx;
     const int32_t *ir = inv_r + d.idx;
     const GatherCtx g = gather_ctx(fd, d, store, K, npe);
-    scatter_assemble(g, il, ir, m, ld, sh, ma, mb, tid, 256, [] __device__() { __syncthreads(); });
-    for (int p = 0; p < k; ++p) {
+    scatter_assemble(g, il, ir, m, ld, sh, ma, mb, tid, SM_THREADS,
+                     [] __device__() { __syncthreads(); });
+    const int G = SM_THREADS / m;            // row groups per column (m <= SM_THREADS)
+    const int j = tid % m, grp = tid / m;
+    const bool owner = grp < G;
+    double u_prev = 0.0;
+    int p = 0;
+    for (; p < k; ++p) {
       const double piv = sh[p * ld + p];
       if (!good_pivot(piv)) {
         if (tid == 0) record_bad_pivot(status, f, p);
         break;
       }
-      for (int j = p + 1 + tid; j < m; j += 256) sh[p * ld + j] = sh[p * ld + j] / piv;
-      __syncthreads();
-      const int r = m - p - 1;
-      for (int t = tid; t < r * r; t += 256) {
-        const int i = p + 1 + t / r, j = p + 1 + (t - (t / r) * r);
-        sh[i * ld + j] -= sh[i * ld + p] * sh[p * ld + j];
+      double u = 0.0;
+      if (owner && j > p) {
+        u = sh[p * ld + j] / piv;
+        int i = p + 1 + grp;
+        for (; i + G < m; i += 2 * G) {
+          const double c0 = sh[i * ld + p], c1 = sh[(i + G) * ld + p];
+          sh[i * ld + j] -= c0 * u;
+          sh[(i + G) * ld + j] -= c1 * u;
+        }
+        if (i < m) sh[i * ld + j] -= sh[i * ld + p] * u;
       }
+      // deferred store of the scaled row p-1 (its owner group is (p-1) mod G)
+      if (owner && p > 0 && j > p - 1 && (p - 1) % G == grp) sh[(p - 1) * ld + j] = u_prev;
+      u_prev = u;
       __syncthreads();
     }
+    if (owner && p > 0 && p == k && j > p - 1 && (p - 1) % G == grp) sh[(p - 1) * ld + j] = u_prev;
+    __syncthreads();
     double *out = store + d.store;
-    for (int t = tid; t < m * m; t += 256) {
-      const int i = t / m, j = t - (t / m) * m;
-      out[t] = sh[i * ld + j];
+    for (int t = tid; t < m * m; t += SM_THREADS) {
+      const int i = t / m, jj = t - (t / m) * m;
+      out[t] = sh[i * ld + jj];
     }
     __syncthreads();
   }
