@@ -87,10 +87,8 @@ void level_costs(const mf::HostPlan &H, const mf::LevelSchedule &S, LevelDev &D,
       const mf::FrontDesc &d = H.desc[st.fronts[i]];
       const double pb = std::min(nb, d.k - st.p0[i]);
       const double rest = d.m - st.p0[i] - pb;
-      sd.diag.bytes += 16 * pb * pb;
-      sd.diag.flops += elim_flops((int32_t)pb, (int32_t)pb);
-      sd.trsm.bytes += 8 * (pb * pb + 4 * rest * pb);
-      sd.trsm.flops += 2 * rest * pb * pb;
+      sd.trsm.bytes += 8 * (2 * pb * pb + 4 * rest * pb);
+      sd.trsm.flops += elim_flops((int32_t)pb, (int32_t)pb) + 2 * rest * pb * pb;
     }
     sd.upd = gemm_cost(st.update);
   }
@@ -288,23 +286,17 @@ int launch_factor(mf_plan *P, const double *K, int prec, hipStream_t s) {
                P->d_store, P->d_status);
       }
       for (const StepDev &st : D.steps) {
-        const dim3 gd((unsigned)st.n), gt((unsigned)((st.trsm_items + 255) / 256), (unsigned)st.n);
+        const dim3 gt((unsigned)std::max<int64_t>(1, (st.trsm_items + 255) / 256), (unsigned)st.n);
         const int32_t *fr = P->d_lists + st.fronts, *p0 = P->d_lists + st.p0;
         switch (P->tune.nb) {
           case 16:
-            LAUNCH(K_DIAG, st.diag, mf::k_panel_diag<16>, gd, dim3(64), 0, s, P->d_desc, fr, p0, P->d_store, P->d_status);
-            if (st.trsm_items > 0)
-              LAUNCH(K_TRSM, st.trsm, mf::k_panel_trsm<16>, gt, dim3(256), 0, s, P->d_desc, fr, p0, P->d_store);
+            LAUNCH(K_TRSM, st.trsm, mf::k_panel_trsm<16>, gt, dim3(256), 0, s, P->d_desc, fr, p0, P->d_store, P->d_status);
             break;
           case 64:
-            LAUNCH(K_DIAG, st.diag, mf::k_panel_diag<64>, gd, dim3(64), 0, s, P->d_desc, fr, p0, P->d_store, P->d_status);
-            if (st.trsm_items > 0)
-              LAUNCH(K_TRSM, st.trsm, mf::k_panel_trsm<64>, gt, dim3(256), 0, s, P->d_desc, fr, p0, P->d_store);
+            LAUNCH(K_TRSM, st.trsm, mf::k_panel_trsm<64>, gt, dim3(256), 0, s, P->d_desc, fr, p0, P->d_store, P->d_status);
             break;
           default:
-            LAUNCH(K_DIAG, st.diag, mf::k_panel_diag<32>, gd, dim3(64), 0, s, P->d_desc, fr, p0, P->d_store, P->d_status);
-            if (st.trsm_items > 0)
-              LAUNCH(K_TRSM, st.trsm, mf::k_panel_trsm<32>, gt, dim3(256), 0, s, P->d_desc, fr, p0, P->d_store);
+            LAUNCH(K_TRSM, st.trsm, mf::k_panel_trsm<32>, gt, dim3(256), 0, s, P->d_desc, fr, p0, P->d_store, P->d_status);
         }
         if (st.n_update)
           LAUNCH(K_GEMM_PANEL, st.upd, mf::k_gemm_update<0>, dim3((unsigned)st.n_update), dim3(256), 0,

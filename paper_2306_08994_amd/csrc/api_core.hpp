@@ -39,11 +39,11 @@ inline int fail(int code, const std::string &msg) {
   } while (0)
 
 enum Kind {
-  K_TINY, K_SMALL, K_ASSEMBLE, K_FUSED, K_DIAG, K_TRSM, K_GEMM_PANEL, K_GEMM_SCHUR,
+  K_TINY, K_SMALL, K_ASSEMBLE, K_FUSED, K_TRSM, K_GEMM_PANEL, K_GEMM_SCHUR,
   K_DOWN_WAVE, K_DOWN_BLOCK, K_UP_WAVE, K_UP_BLOCK, K_RESIDUAL, K_OTHER, K_COUNT
 };
 static const char *const kKindName[K_COUNT] = {
-    "factor_tiny", "factor_small", "assemble", "front_panels", "panel_diag", "panel_trsm", "gemm_panel",
+    "factor_tiny", "factor_small", "assemble", "front_panels", "panel_lu_trsm", "gemm_panel",
     "gemm_schur", "solve_down_wave", "solve_down_block", "solve_up_wave", "solve_up_block",
     "residual", "other"};
 
@@ -57,7 +57,7 @@ struct StepDev {
   int64_t fronts = 0, p0 = 0, n = 0;
   int64_t update = 0, n_update = 0;
   int64_t trsm_items = 0;
-  Cost diag, trsm, upd;
+  Cost trsm, upd;
 };
 
 struct LevelDev {

@@ -164,7 +164,7 @@ k_assemble(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ list,
 // value on every lane) after recording it.
 template <int NB>
 __device__ inline bool wave_diag_lu(double *F, int64_t m, int pb, double (*D)[NB + 1], int lane,
-                                    int f, int p0, int *status) {
+                                    int f, int p0, int *status, bool writeback = true) {
   static_assert(NB <= 64, "one lane per column");
   if (lane < pb) {
     double col[NB];
@@ -188,7 +188,7 @@ __device__ inline bool wave_diag_lu(double *F, int64_t m, int pb, double (*D)[NB
       for (int i = p + 1 + (lane >> 5); i < pb; i += 2) D[i][j] -= D[i][p] * D[p][j];
     wave_sync();
   }
-  if (lane < pb) {
+  if (writeback && lane < pb) {
 #pragma unroll
     for (int i = 0; i < NB; ++i)
       if (i < pb) F[i * m + lane] = D[i][lane];
@@ -196,28 +196,17 @@ __device__ inline bool wave_diag_lu(double *F, int64_t m, int pb, double (*D)[NB
   return ok;
 }
 
-// Panel step, part 1 (fronts wider than the fused kernel's limit): LU of the diagonal block,
-// one wave per front.
-template <int NB>
-__global__ void __launch_bounds__(64)
-k_panel_diag(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ fronts,
-             const int32_t *__restrict__ p0s, double *__restrict__ store, int *__restrict__ status) {
-  __shared__ double D[NB][NB + 1];
-  const int f = fronts[blockIdx.x];
-  const int p0 = p0s[blockIdx.x];
-  const FrontDesc d = fd[f];
-  const int pb = min(NB, d.k - p0);
-  wave_diag_lu<NB>(store + d.store + (int64_t)p0 * d.m + p0, d.m, pb, D, threadIdx.x, f, p0, status);
-}
-
-// Panel step, part 2: the two triangular solves against the factored diagonal block.
+// Panel step of the fronts wider than the fused route: every workgroup factors the pb x pb
+// diagonal block at (p0, p0) itself (wave 0, in LDS; workgroup 0 also stores it), then its
+// threads solve against it:
 //   U12 = L11^{-1} A12 column by column (rows p0..pe-1, columns pe..m-1),
 //   L21 = A21 U11^{-1} row by row       (rows pe..m-1, columns p0..pe-1).
-// grid = (item chunks of 256, fronts); item t < m-pe is a column, otherwise a row.
+// grid = (item chunks of 256, fronts), at least one chunk; item t < m-pe is a column, else a row.
 template <int NB>
 __global__ void __launch_bounds__(256)
 k_panel_trsm(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ fronts,
-             const int32_t *__restrict__ p0s, double *__restrict__ store) {
+             const int32_t *__restrict__ p0s, double *__restrict__ store,
+             int *__restrict__ status) {
   __shared__ double D[NB][NB + 1];
   const int f = fronts[blockIdx.y];
   const int p0 = p0s[blockIdx.y];
@@ -225,15 +214,11 @@ k_panel_trsm(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ front
   const int m = d.m, pb = min(NB, d.k - p0), pe = p0 + pb;
   const int rest = m - pe;
   const int item = blockIdx.x * 256 + threadIdx.x;
-  if ((int)(blockIdx.x * 256) >= 2 * rest) return;   // whole block idle (uniform)
+  if (blockIdx.x > 0 && (int)(blockIdx.x * 256) >= 2 * rest) return;   // idle (uniform)
   double *F = store + d.store;
-  if ((int)threadIdx.x < pb) {
-    double col[NB];
-#pragma unroll
-    for (int i = 0; i < NB; ++i) col[i] = i < pb ? F[(int64_t)(p0 + i) * m + p0 + threadIdx.x] : 0.0;
-#pragma unroll
-    for (int i = 0; i < NB; ++i) D[i][threadIdx.x] = col[i];
-  }
+  if (threadIdx.x < 64)
+    wave_diag_lu<NB>(F + (int64_t)p0 * m + p0, m, pb, D, threadIdx.x, f, p0, status,
+                     blockIdx.x == 0);
   __syncthreads();
   if (item >= 2 * rest) return;
   double v[NB];
