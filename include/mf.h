@@ -95,7 +95,7 @@ int mf_plan_info(const mf_plan *plan, mf_info *out);
 int mf_plan_export_tree(const mf_plan *plan, int32_t *parent, int32_t *level, int64_t *front_ptr,
                         int32_t *front_idx, int32_t *npiv, int64_t *leaf_elem);
 
-/* Schedule tuning of an analysed plan (the autotuner's knob; defaults are used otherwise).
+/* Schedule tuning of an analysed plan (set by mf_autotune, or by hand; defaults otherwise).
  *   small_max_m  fronts of width <= small_max_m are assembled, eliminated and stored by one
  *                workgroup with the front resident in LDS; wider fronts take the tiled path
  *                (assembly, panel LU of nb pivots at a time, MFMA Schur GEMM).  It is clipped
@@ -106,8 +106,19 @@ int mf_plan_export_tree(const mf_plan *plan, int32_t *parent, int32_t *level, in
  *                one workgroup, leaving only the Schur GEMM to a separate launch; wider fronts
  *                use one launch per panel step.  Clipped to 576; -1 disables the fused route;
  *                0 keeps the current value.
+ *   tile         output tile edge of the MFMA GEMMs: 32 or 64.  0 keeps the current value.
  * Invalidates a previous factorization.  Errors: MF_EINVAL. */
-int mf_set_tuning(mf_plan *plan, int32_t small_max_m, int32_t nb, int32_t fused_max_m);
+int mf_set_tuning(mf_plan *plan, int32_t small_max_m, int32_t nb, int32_t fused_max_m,
+                  int32_t tile);
+
+/* Autotuner: factors elem_mats (device, as in mf_factor) under each candidate schedule that the
+ * workload's front widths make relevant -- GEMM tile 64/32, fused route on/off, panel width
+ * 32/64, LDS limit 128/64 -- times `reps` factorizations of each (host clock, median), keeps
+ * the fastest and leaves the plan factored with it.  report (host, cap bytes, may be NULL)
+ * receives a NUL-terminated JSON summary {"candidates": [...], "chosen": {...}}; needed (may
+ * be NULL) its size.  Synchronizes hip_stream.  Errors: as mf_factor, MF_EINVAL. */
+int mf_autotune(mf_plan *plan, const double *elem_mats, int32_t precision, int32_t reps,
+                void *hip_stream, char *report, int64_t cap, int64_t *needed);
 
 /* Numerical factorization (Table 2 over Foata classes, Sec. 3.3): for every class in order, all
  * its fronts extend-add their children's contribution blocks (a leaf takes its element

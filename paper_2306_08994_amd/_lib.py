@@ -13,7 +13,8 @@ MF_FP64, MF_SCHUR_FP32, MF_SCHUR_BF16 = 0, 1, 2
 ERROR_NAMES = {MF_EINVAL: "MF_EINVAL", MF_ENOMEM: "MF_ENOMEM", MF_EZERO_PIVOT: "MF_EZERO_PIVOT",
                MF_EHIP: "MF_EHIP", MF_ENOCONV: "MF_ENOCONV", MF_ESTATE: "MF_ESTATE"}
 
-EXPORTED = ["mf_analyse", "mf_plan_info", "mf_plan_export_tree", "mf_set_tuning", "mf_factor", "mf_solve",
+EXPORTED = ["mf_analyse", "mf_plan_info", "mf_plan_export_tree", "mf_set_tuning", "mf_autotune",
+            "mf_factor", "mf_solve",
             "mf_residual", "mf_refine", "mf_elem_grad", "mf_export_factors", "mf_profile",
             "mf_profile_report", "mf_destroy", "mf_last_error"]
 
@@ -54,7 +55,9 @@ def load():
         "mf_plan_info": (c_int32, [P, POINTER(MfInfo)]),
         "mf_plan_export_tree": (c_int32, [P, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                           c_void_p]),
-        "mf_set_tuning": (c_int32, [P, c_int32, c_int32, c_int32]),
+        "mf_set_tuning": (c_int32, [P, c_int32, c_int32, c_int32, c_int32]),
+        "mf_autotune": (c_int32, [P, c_void_p, c_int32, c_int32, c_void_p, c_char_p, c_int64,
+                                  POINTER(c_int64)]),
         "mf_factor": (c_int32, [P, c_void_p, c_int32, c_void_p]),
         "mf_solve": (c_int32, [P, c_void_p, c_void_p, c_int32, c_int32, c_void_p]),
         "mf_residual": (c_int32, [P, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),

@@ -1,6 +1,8 @@
 // api.hip -- C ABI of libmf (declared in include/mf.h).
 #include "api_core.hpp"
 
+#include <chrono>
+
 namespace mfapi {
 
 thread_local std::string g_err;
@@ -176,26 +178,29 @@ int ensure_uploaded(mf_plan *P) {
     tasks.insert(tasks.end(), S.schur.begin(), S.schur.end());
     level_costs(H, S, D, P->tune.nb);
   }
-  // node -> (element, local node) pairs in ascending element order, for the residual
-  std::vector<int64_t> nptr(H.n + 1, 0);
-  for (int64_t q = 0; q < H.n_elem * H.npe; ++q) nptr[H.conn[q] + 1]++;
-  for (int64_t v = 0; v < H.n; ++v) nptr[v + 1] += nptr[v];
-  std::vector<int32_t> nelem(H.n_elem * H.npe);
-  {
-    std::vector<int64_t> fill(nptr.begin(), nptr.end() - 1);
-    for (int64_t q = 0; q < H.n_elem * H.npe; ++q) nelem[fill[H.conn[q]]++] = (int32_t)q;
-  }
   int rc;
-  if ((rc = upload(P->d_desc, H.desc)) || (rc = upload(P->d_front_idx, H.front_idx)) ||
-      (rc = upload(P->d_inv_l, H.inv_l)) || (rc = upload(P->d_inv_r, H.inv_r)) ||
-      (rc = upload(P->d_conn, H.conn)) || (rc = upload(P->d_nptr, nptr)) ||
-      (rc = upload(P->d_nelem, nelem)) || (rc = upload(P->d_lists, lists)) ||
-      (rc = upload(P->d_tasks, tasks)))
-    return rc;
-  dfree(P->d_store);
-  if (hipMalloc((void **)&P->d_store, std::max<int64_t>(1, H.store_doubles) * sizeof(double)) != hipSuccess)
-    return fail(MF_ENOMEM, "cannot allocate " + std::to_string(H.store_doubles * 8) +
-                               " bytes of factor storage");
+  if ((rc = upload(P->d_lists, lists)) || (rc = upload(P->d_tasks, tasks))) return rc;
+  if (!P->static_up) {
+    // node -> (element, local node) pairs in ascending element order, for the residual
+    std::vector<int64_t> nptr(H.n + 1, 0);
+    for (int64_t q = 0; q < H.n_elem * H.npe; ++q) nptr[H.conn[q] + 1]++;
+    for (int64_t v = 0; v < H.n; ++v) nptr[v + 1] += nptr[v];
+    std::vector<int32_t> nelem(H.n_elem * H.npe);
+    {
+      std::vector<int64_t> fill(nptr.begin(), nptr.end() - 1);
+      for (int64_t q = 0; q < H.n_elem * H.npe; ++q) nelem[fill[H.conn[q]]++] = (int32_t)q;
+    }
+    if ((rc = upload(P->d_desc, H.desc)) || (rc = upload(P->d_front_idx, H.front_idx)) ||
+        (rc = upload(P->d_inv_l, H.inv_l)) || (rc = upload(P->d_inv_r, H.inv_r)) ||
+        (rc = upload(P->d_conn, H.conn)) || (rc = upload(P->d_nptr, nptr)) ||
+        (rc = upload(P->d_nelem, nelem)))
+      return rc;
+    dfree(P->d_store);
+    if (hipMalloc((void **)&P->d_store, std::max<int64_t>(1, H.store_doubles) * sizeof(double)) != hipSuccess)
+      return fail(MF_ENOMEM, "cannot allocate " + std::to_string(H.store_doubles * 8) +
+                                 " bytes of factor storage");
+    P->static_up = true;
+  }
   if (!P->d_status) HIPCHK(hipMalloc((void **)&P->d_status, mf::kStatusWords * sizeof(int)));
   if (!P->h_status)
     HIPCHK(hipHostMalloc((void **)&P->h_status, mf::kStatusWords * sizeof(int), hipHostMallocDefault));
@@ -298,19 +303,29 @@ int launch_factor(mf_plan *P, const double *K, int prec, hipStream_t s) {
           default:
             LAUNCH(K_TRSM, st.trsm, mf::k_panel_trsm<32>, gt, dim3(256), 0, s, P->d_desc, fr, p0, P->d_store, P->d_status);
         }
-        if (st.n_update)
-          LAUNCH(K_GEMM_PANEL, st.upd, mf::k_gemm_update<0>, dim3((unsigned)st.n_update), dim3(256), 0,
-                 s, P->d_desc, P->d_tasks + st.update, P->d_store);
+        if (st.n_update) {
+          const dim3 g((unsigned)st.n_update);
+          const mf::GemmTask *t = P->d_tasks + st.update;
+          if (P->tune.tile == 32)
+            LAUNCH(K_GEMM_PANEL, st.upd, (mf::k_gemm_update<0, 32>), g, dim3(256), 0, s, P->d_desc, t, P->d_store);
+          else
+            LAUNCH(K_GEMM_PANEL, st.upd, (mf::k_gemm_update<0, 64>), g, dim3(256), 0, s, P->d_desc, t, P->d_store);
+        }
       }
       if (D.n_schur) {
         const mf::GemmTask *t = P->d_tasks + D.schur;
         const dim3 g((unsigned)D.n_schur);
-        if (prec == MF_SCHUR_FP32)
-          LAUNCH(K_GEMM_SCHUR, D.c_schur, mf::k_gemm_update<1>, g, dim3(256), 0, s, P->d_desc, t, P->d_store);
-        else if (prec == MF_SCHUR_BF16)
-          LAUNCH(K_GEMM_SCHUR, D.c_schur, mf::k_gemm_update<2>, g, dim3(256), 0, s, P->d_desc, t, P->d_store);
-        else
-          LAUNCH(K_GEMM_SCHUR, D.c_schur, mf::k_gemm_update<0>, g, dim3(256), 0, s, P->d_desc, t, P->d_store);
+        const bool t32 = P->tune.tile == 32;
+        if (prec == MF_SCHUR_FP32) {
+          if (t32) LAUNCH(K_GEMM_SCHUR, D.c_schur, (mf::k_gemm_update<1, 32>), g, dim3(256), 0, s, P->d_desc, t, P->d_store);
+          else LAUNCH(K_GEMM_SCHUR, D.c_schur, (mf::k_gemm_update<1, 64>), g, dim3(256), 0, s, P->d_desc, t, P->d_store);
+        } else if (prec == MF_SCHUR_BF16) {
+          if (t32) LAUNCH(K_GEMM_SCHUR, D.c_schur, (mf::k_gemm_update<2, 32>), g, dim3(256), 0, s, P->d_desc, t, P->d_store);
+          else LAUNCH(K_GEMM_SCHUR, D.c_schur, (mf::k_gemm_update<2, 64>), g, dim3(256), 0, s, P->d_desc, t, P->d_store);
+        } else {
+          if (t32) LAUNCH(K_GEMM_SCHUR, D.c_schur, (mf::k_gemm_update<0, 32>), g, dim3(256), 0, s, P->d_desc, t, P->d_store);
+          else LAUNCH(K_GEMM_SCHUR, D.c_schur, (mf::k_gemm_update<0, 64>), g, dim3(256), 0, s, P->d_desc, t, P->d_store);
+        }
       }
     }
   }
@@ -536,8 +551,10 @@ int mf_plan_export_tree(const mf_plan *P, int32_t *parent, int32_t *level, int64
   return MF_OK;
 }
 
-int mf_set_tuning(mf_plan *P, int32_t small_max_m, int32_t nb, int32_t fused_max_m) {
+int mf_set_tuning(mf_plan *P, int32_t small_max_m, int32_t nb, int32_t fused_max_m, int32_t tile) {
   if (!P) return fail(MF_EINVAL, "null plan");
+  if (tile != 0 && tile != 32 && tile != 64) return fail(MF_EINVAL, "tile must be 32 or 64");
+  if (tile > 0) P->tune.tile = tile;
   if (small_max_m < 0) return fail(MF_EINVAL, "small_max_m must be >= 0");
   if (nb != 0 && nb != 16 && nb != 32 && nb != 64) return fail(MF_EINVAL, "nb must be 16, 32 or 64");
   if (fused_max_m < -1) return fail(MF_EINVAL, "fused_max_m must be >= -1");
@@ -686,6 +703,80 @@ int mf_export_factors(const mf_plan *P, double *L, double *U) {
         Uf[(int64_t)p * d.m + i] = i > p ? Fm[(int64_t)p * d.m + i] : (i == p ? 1.0 : 0.0);
       }
     off += (int64_t)d.m * d.k;
+  }
+  return MF_OK;
+}
+
+int mf_autotune(mf_plan *P, const double *elem_mats, int32_t precision, int32_t reps,
+                void *hip_stream, char *report, int64_t cap, int64_t *needed) {
+  if (!P || !elem_mats) return fail(MF_EINVAL, "null plan or element matrices");
+  if (reps < 1) return fail(MF_EINVAL, "reps must be >= 1");
+  int rc = ensure_uploaded(P);
+  if (rc) return rc;
+  // what the workload contains decides which knobs can matter
+  bool mid = false, wide = false;
+  for (int64_t f = 0; f < P->hp.F; ++f) {
+    const int32_t m = P->hp.desc[f].m;
+    if (m > 64 && m <= 128) mid = true;
+    if (m > 128) wide = true;
+  }
+  std::vector<mf::Tuning> cands;
+  const mf::Tuning base = P->tune;
+  for (int32_t tile : {64, 32})
+    for (int32_t fused : {mf::FP_MAXM, 0})
+      for (int32_t nb : {32, 64})
+        for (int32_t smax : {128, 64}) {
+          if (!wide && (tile != 64 || fused != mf::FP_MAXM || nb != 32)) continue;
+          if (fused == mf::FP_MAXM && nb != 32 && P->hp.max_m <= mf::FP_MAXM) continue;
+          if (!mid && smax != 128) continue;
+          mf::Tuning t = base;
+          t.tile = tile;
+          t.fused_max_m = fused;
+          t.nb = nb;
+          t.small_max_m = smax;
+          cands.push_back(t);
+        }
+  std::string js = "{\"candidates\": [";
+  double best = 1e300;
+  mf::Tuning best_t = base;
+  for (size_t c = 0; c < cands.size(); ++c) {
+    P->tune = cands[c];
+    P->uploaded = false;
+    P->factored = false;
+    if ((rc = mf_factor(P, elem_mats, precision, hip_stream))) return rc;   // warm-up + capture
+    std::vector<double> ts;
+    for (int32_t r = 0; r < reps; ++r) {
+      const auto t0 = std::chrono::steady_clock::now();
+      if ((rc = mf_factor(P, elem_mats, precision, hip_stream))) return rc;
+      ts.push_back(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+    }
+    std::sort(ts.begin(), ts.end());
+    const double med = ts[ts.size() / 2];
+    if (med < best) {
+      best = med;
+      best_t = cands[c];
+    }
+    char line[200];
+    std::snprintf(line, sizeof line,
+                  "%s{\"tile\": %d, \"fused_max_m\": %d, \"nb\": %d, \"small_max_m\": %d, \"ms\": %.4f}",
+                  c ? ", " : "", cands[c].tile, cands[c].fused_max_m, cands[c].nb,
+                  P->tune.small_max_m, med);
+    js += line;
+  }
+  P->tune = best_t;
+  P->uploaded = false;
+  P->factored = false;
+  if ((rc = mf_factor(P, elem_mats, precision, hip_stream))) return rc;
+  char line[200];
+  std::snprintf(line, sizeof line,
+                "], \"chosen\": {\"tile\": %d, \"fused_max_m\": %d, \"nb\": %d, \"small_max_m\": %d, \"ms\": %.4f}}",
+                P->tune.tile, P->tune.fused_max_m, P->tune.nb, P->tune.small_max_m, best);
+  js += line;
+  if (needed) *needed = (int64_t)js.size() + 1;
+  if (report && cap > 0) {
+    const size_t n = std::min<size_t>((size_t)cap - 1, js.size());
+    std::memcpy(report, js.data(), n);
+    report[n] = 0;
   }
   return MF_OK;
 }

@@ -117,7 +117,8 @@ struct mf_plan {
   mf::HostPlan hp;
   mf::Tuning tune;
   int device = -1;
-  bool uploaded = false;
+  bool uploaded = false;     // schedule (front lists, GEMM tasks) on the device
+  bool static_up = false;    // tree arrays and factor storage on the device
   bool factored = false;
   bool use_graphs = true;
   int max_shared = 65536;

@@ -393,15 +393,19 @@ struct GemmCfg<1> { typedef float T; static constexpr int KT = 16; };
 template <>
 struct GemmCfg<2> { typedef __bf16 T; static constexpr int KT = 32; };
 
-template <int PREC>
+template <int PREC, int TILE>
 __global__ void __launch_bounds__(256)
 k_gemm_update(const FrontDesc *__restrict__ fd, const GemmTask *__restrict__ tasks,
               double *__restrict__ store) {
   typedef typename GemmCfg<PREC>::T T;
   constexpr int KT = GemmCfg<PREC>::KT;
   constexpr int APAD = (PREC == 2) ? 8 : 1;
-  __shared__ T As[64][KT + APAD];
-  __shared__ T Bs[64][KT + APAD];    // stored transposed: Bs[col][k]
+  constexpr int QB = TILE / 32;            // 16 x 16 MFMA blocks per wave and dimension
+  constexpr int HALF = TILE / 2;           // each wave owns a HALF x HALF quadrant
+  constexpr int EA = TILE * KT / 256;      // staged elements of A (and of B) per thread
+  static_assert(TILE == 32 || TILE == 64, "tile");
+  __shared__ T As[TILE][KT + APAD];
+  __shared__ T Bs[TILE][KT + APAD];        // stored transposed: Bs[col][k]
   const GemmTask tk = tasks[blockIdx.x];
   const FrontDesc d = fd[tk.front];
   const int64_t ld = d.m;
@@ -410,56 +414,66 @@ k_gemm_update(const FrontDesc *__restrict__ fd, const GemmTask *__restrict__ tas
   const int wr = w >> 1, wc = w & 1;
   const int li = lane & 15, lk = lane >> 4;
   typedef typename std::conditional<PREC == 0, v4d, v4f>::type Acc;
-  Acc acc[2][2];
+  Acc acc[QB][QB];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < QB; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < QB; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[a][b][r] = 0;
   const int i0 = tk.i0, j0 = tk.j0;
-  for (int q = tk.q0; q < tk.q1; q += KT) {
-    // stage A[i0:i0+64, q:q+KT] and B[q:q+KT, j0:j0+64] (zero outside the task)
-    for (int t = tid; t < 64 * KT; t += 256) {
-      const int r = t / KT, c = t % KT;
-      const int gi = i0 + r, gq = q + c;
-      double va = (gi < tk.i1 && gq < tk.q1) ? F[gi * ld + gq] : 0.0;
-      As[r][c] = (T)va;
+  // A[i0:i0+TILE, q:q+KT] and B[q:q+KT, j0:j0+TILE], zero outside the task; the next slab is
+  // loaded into registers while the current one is multiplied
+  double ra[EA], rb[EA];
+  auto load = [&](int q) {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int t = tid + e * 256;
+      const int ar = t / KT, ac = t % KT;
+      const int gi = i0 + ar, gq = q + ac;
+      ra[e] = (gi < tk.i1 && gq < tk.q1) ? F[gi * ld + gq] : 0.0;
+      const int bc = t % TILE, br = t / TILE;
+      const int gq2 = q + br, gj = j0 + bc;
+      rb[e] = (gq2 < tk.q1 && gj < tk.j1) ? F[gq2 * ld + gj] : 0.0;
     }
-    for (int t = tid; t < 64 * KT; t += 256) {
-      const int c = t % 64, r = t / 64;
-      const int gq = q + r, gj = j0 + c;
-      double vb = (gq < tk.q1 && gj < tk.j1) ? F[gq * ld + gj] : 0.0;
-      Bs[c][r] = (T)vb;
+  };
+  if (tk.q0 < tk.q1) load(tk.q0);
+  for (int q = tk.q0; q < tk.q1; q += KT) {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int t = tid + e * 256;
+      As[t / KT][t % KT] = (T)ra[e];
+      Bs[t % TILE][t / TILE] = (T)rb[e];
     }
     __syncthreads();
+    if (q + KT < tk.q1) load(q + KT);
     if constexpr (PREC == 2) {
-      v8bf av[2], bv[2];
+      v8bf av[QB], bv[QB];
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < QB; ++a)
 #pragma unroll
-        for (int e = 0; e < 8; ++e) av[a][e] = As[32 * wr + 16 * a + li][8 * lk + e];
+        for (int e = 0; e < 8; ++e) av[a][e] = As[HALF * wr + 16 * a + li][8 * lk + e];
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
+      for (int b = 0; b < QB; ++b)
 #pragma unroll
-        for (int e = 0; e < 8; ++e) bv[b][e] = Bs[32 * wc + 16 * b + li][8 * lk + e];
+        for (int e = 0; e < 8; ++e) bv[b][e] = Bs[HALF * wc + 16 * b + li][8 * lk + e];
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < QB; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < QB; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
     } else {
 #pragma unroll
       for (int s = 0; s < KT / 4; ++s) {
-        T av[2], bv[2];
+        T av[QB], bv[QB];
 #pragma unroll
-        for (int a = 0; a < 2; ++a) av[a] = As[32 * wr + 16 * a + li][4 * s + lk];
+        for (int a = 0; a < QB; ++a) av[a] = As[HALF * wr + 16 * a + li][4 * s + lk];
 #pragma unroll
-        for (int b = 0; b < 2; ++b) bv[b] = Bs[32 * wc + 16 * b + li][4 * s + lk];
+        for (int b = 0; b < QB; ++b) bv[b] = Bs[HALF * wc + 16 * b + li][4 * s + lk];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < QB; ++a)
 #pragma unroll
-          for (int b = 0; b < 2; ++b) {
+          for (int b = 0; b < QB; ++b) {
             if constexpr (PREC == 0)
               acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
             else
@@ -470,15 +484,15 @@ k_gemm_update(const FrontDesc *__restrict__ fd, const GemmTask *__restrict__ tas
     __syncthreads();
   }
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < QB; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < QB; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         // f64 16x16x4 interleaves its result rows (lane l, register r -> row 4r + l/16); the
         // f32 16x16x4 and bf16 16x16x32 forms place them contiguously (row 4(l/16) + r)
-        const int gi = i0 + 32 * wr + 16 * a + (PREC == 0 ? 4 * r + lk : 4 * lk + r);
-        const int gj = j0 + 32 * wc + 16 * b + li;
+        const int gi = i0 + HALF * wr + 16 * a + (PREC == 0 ? 4 * r + lk : 4 * lk + r);
+        const int gj = j0 + HALF * wc + 16 * b + li;
         if (gi < tk.i1 && gj < tk.j1) F[gi * ld + gj] -= (double)acc[a][b][r];
       }
 }

@@ -87,10 +87,24 @@ class Plan:
                                               ptr(out["npiv"]), ptr(out["leaf_elem"])))
         return out
 
-    def set_tuning(self, small_max_m: int = 0, nb: int = 0, fused_max_m: int = 0):
+    def set_tuning(self, small_max_m: int = 0, nb: int = 0, fused_max_m: int = 0, tile: int = 0):
         """See mf_set_tuning: 0 keeps a value; fused_max_m=-1 disables the fused panel route."""
         self.factor_version += 1
-        check(_lib.load().mf_set_tuning(self._h, int(small_max_m), int(nb), int(fused_max_m)))
+        check(_lib.load().mf_set_tuning(self._h, int(small_max_m), int(nb), int(fused_max_m),
+                                        int(tile)))
+
+    def autotune(self, K, precision: str = "fp64", reps: int = 3) -> dict:
+        """Times the relevant schedule candidates on K, keeps the fastest (see mf_autotune)."""
+        import json
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+        p = _dev_ptr(K, "K", (self.n_elem, self.npe, self.npe))
+        self.factor_version += 1
+        buf = ctypes.create_string_buffer(1 << 16)
+        need = ctypes.c_int64(0)
+        check(_lib.load().mf_autotune(self._h, p, PRECISIONS[precision], int(reps), _stream(),
+                                      buf, len(buf), ctypes.byref(need)))
+        return json.loads(buf.value.decode())
 
     # -- numerics ----------------------------------------------------------------------------
     def factor(self, K, precision: str = "fp64"):

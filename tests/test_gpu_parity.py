@@ -13,13 +13,13 @@ from tests import gpu_common as G
 pytestmark = pytest.mark.gpu
 
 
-def _setup(problem, small_max_m=0, nb=0, fused=0):
+def _setup(problem, small_max_m=0, nb=0, fused=0, tile=0):
     import torch
     from paper_2306_08994_amd import Plan
     dev = G.torch_dev()
     plan = Plan(problem.meshes)
-    if small_max_m or nb or fused:
-        plan.set_tuning(small_max_m, nb, fused)
+    if small_max_m or nb or fused or tile:
+        plan.set_tuning(small_max_m, nb, fused, tile)
     K = torch.from_numpy(problem.K).to(dev)
     b = torch.from_numpy(problem.b).to(dev)
     return plan, K, b
@@ -42,18 +42,19 @@ def test_factor_lds_path(shape):
     assert G.factor_violation(Ls, Us, fac) <= G.TOL_FACTOR
 
 
-# (shape, LDS limit, panel width of separate panel launches, fused-route limit: -1 = off)
-TILED = [((64, 48), 8, 16, -1), ((96, 80), 24, 32, -1), ((70, 53), 40, 64, -1),
-         ((10, 9, 8), 16, 32, -1), ((12, 12, 12), 40, 16, 100), ((14, 11, 9), 24, 64, -1),
-         ((12, 12, 12), 100, 32, 0), ((64, 48), 8, 32, 0), ((14, 11, 9), 24, 32, 0),
-         ((20, 20, 20), 0, 0, 0)]
+# (shape, LDS limit, panel width of separate panel launches, fused-route limit (-1 = off),
+#  GEMM tile (0 = default 64))
+TILED = [((64, 48), 8, 16, -1, 0), ((96, 80), 24, 32, -1, 32), ((70, 53), 40, 64, -1, 0),
+         ((10, 9, 8), 16, 32, -1, 32), ((12, 12, 12), 40, 16, 100, 32),
+         ((14, 11, 9), 24, 64, -1, 0), ((12, 12, 12), 100, 32, 0, 0), ((64, 48), 8, 32, 0, 0),
+         ((14, 11, 9), 24, 32, 0, 32), ((20, 20, 20), 0, 0, 0, 0), ((20, 20, 20), 0, 64, 0, 32)]
 
 
-@pytest.mark.parametrize("shape,smax,nb,fused", TILED)
-def test_factor_tiled_path(shape, smax, nb, fused):
+@pytest.mark.parametrize("shape,smax,nb,fused,tile", TILED)
+def test_factor_tiled_path(shape, smax, nb, fused, tile):
     p = _rd(shape, seed=1)
     tree, conn, fac = G.oracle_factor(p)
-    plan, K, b = _setup(p, smax, nb, fused)
+    plan, K, b = _setup(p, smax, nb, fused, tile)
     plan.factor(K)
     Ls, Us = plan.export_factors()
     ms = np.diff(tree.front_ptr)
@@ -187,3 +188,15 @@ def test_error_paths():
         plan.factor(K.cpu())
     with pytest.raises(TypeError):
         plan.factor(K.float())
+
+
+def test_autotune_keeps_a_correct_schedule():
+    p = _rd((20, 20, 20), seed=9, nrhs=2)
+    tree, conn, fac = G.oracle_factor(p)
+    plan, K, b = _setup(p)
+    rep = plan.autotune(K, reps=1)
+    assert len(rep["candidates"]) >= 2 and "chosen" in rep
+    Ls, Us = plan.export_factors()              # autotune leaves the plan factored
+    assert G.factor_violation(Ls, Us, fac) <= G.TOL_FACTOR
+    x = plan.solve(b).cpu().numpy()
+    assert G.rel_err(x, G.oracle_solve(tree, fac, p.b)) <= G.TOL_SOLVE
