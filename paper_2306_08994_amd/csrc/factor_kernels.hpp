@@ -158,41 +158,55 @@ k_assemble(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ list,
   }
 }
 
+// Value of v in lane l of the wave (l uniform across the wave).
+__device__ inline double readlane(double v, int l) {
+  const unsigned long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffull), l);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), l);
+  return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
 // LU (division tasks scale the pivot row) of the pb x pb diagonal block at F (leading
-// dimension m) by one wave in LDS D, written back.  Lane j loads column j with independent
-// loads; the elimination uses wave-level ordering only.  Returns false on a bad pivot (the same
-// value on every lane) after recording it.
+// dimension m) by one wave, register resident: lane j holds column j.  At pivot p every lane
+// reads the pivot and the multiplier column from lane p (readlane), lane j > p divides its
+// U[p][j] and updates its column -- no LDS traffic and no synchronisation inside the block.
+// The factored block is left in LDS D (for the panel solves) and, if writeback, in F.
+// Returns false on a bad pivot (the same value on every lane) after recording it.
 template <int NB>
 __device__ inline bool wave_diag_lu(double *F, int64_t m, int pb, double (*D)[NB + 1], int lane,
                                     int f, int p0, int *status, bool writeback = true) {
   static_assert(NB <= 64, "one lane per column");
-  if (lane < pb) {
-    double col[NB];
+  double col[NB];
 #pragma unroll
-    for (int i = 0; i < NB; ++i) col[i] = i < pb ? F[i * m + lane] : 0.0;
+  for (int i = 0; i < NB; ++i) col[i] = (lane < pb && i < pb) ? F[i * m + lane] : 0.0;
+  bool ok = true;
+#pragma unroll
+  for (int p = 0; p < NB; ++p) {
+    if (p < pb) {
+      const double piv = readlane(col[p], p);
+      if (!good_pivot(piv)) {
+        if (lane == 0) record_bad_pivot(status, f, p0 + p);
+        ok = false;
+        break;
+      }
+      if (lane > p) col[p] = col[p] / piv;
+#pragma unroll
+      for (int i = p + 1; i < NB; ++i) {
+        const double mi = readlane(col[i], p);
+        if (lane > p) col[i] -= mi * col[p];
+      }
+    }
+  }
+  if (lane < NB) {
 #pragma unroll
     for (int i = 0; i < NB; ++i) D[i][lane] = col[i];
-  }
-  wave_sync();
-  bool ok = true;
-  for (int p = 0; p < pb; ++p) {
-    const double piv = D[p][p];
-    if (!good_pivot(piv)) {
-      if (lane == 0) record_bad_pivot(status, f, p0 + p);
-      ok = false;
-      break;
-    }
-    for (int j = p + 1 + lane; j < pb; j += 64) D[p][j] = D[p][j] / piv;
-    wave_sync();
-    for (int j = p + 1 + (lane & 31); j < pb; j += 32)
-      for (int i = p + 1 + (lane >> 5); i < pb; i += 2) D[i][j] -= D[i][p] * D[p][j];
-    wave_sync();
   }
   if (writeback && lane < pb) {
 #pragma unroll
     for (int i = 0; i < NB; ++i)
-      if (i < pb) F[i * m + lane] = D[i][lane];
+      if (i < pb) F[i * m + lane] = col[i];
   }
+  wave_sync();
   return ok;
 }
 
@@ -260,11 +274,15 @@ k_panel_trsm(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ front
 
 // ---------------------------------------------------------------------------------------------
 // Fused per-front partial LU of the fully summed rows and columns (fronts up to FP_MAXM wide):
-// one workgroup per front runs every panel of NB pivots -- wave 0 factors the diagonal block,
-// every thread then solves one L21 row and one U12 column against it (independent, no
-// synchronisation), and updates its L21 row across the still-to-be-eliminated columns of the
-// fully summed region.  The Schur complement C22 is left to the MFMA GEMM.
-// LDS: D (NB x NB+1) | U12 panel (NB x (m - pe)).
+// one workgroup per front runs every panel of NB pivots:
+//   1. wave 0 factors the diagonal block in LDS;
+//   2. every thread solves L21 rows against U11 (row per thread), keeping them in LDS;
+//   3. every thread solves one U12 column against L11 into registers and applies it to its
+//      column of the rest of the fully summed region: C[i][j] -= sum_q L21[i][q] U12[q][j],
+//      rows i >= pe (all of them for j < k, only the fully summed ones for j >= k).  Lanes run
+//      along columns, so every global access of the update is coalesced, and the L21 entries
+//      are LDS broadcasts.
+// The Schur complement C22 is left to the MFMA GEMM.  LDS: D (NB x NB+1) | L21 panel (m-pe x NB).
 // ---------------------------------------------------------------------------------------------
 constexpr int FP_THREADS = 512;
 constexpr int FP_ROWS = 2;            // rows (and columns) per thread
@@ -275,9 +293,10 @@ __global__ void __launch_bounds__(FP_THREADS)
 k_front_panels(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ list, int nlist,
                double *__restrict__ store, int *__restrict__ status) {
   static_assert(FP_ROWS * FP_THREADS >= FP_MAXM, "rows per thread");
+  static_assert(NB % 2 == 0, "two partial sums");
   extern __shared__ double sm[];
   double(*D)[NB + 1] = reinterpret_cast<double(*)[NB + 1]>(sm);
-  double *Ub = sm + NB * (NB + 1);
+  double *Lp = sm + NB * (NB + 1);
   __shared__ int bad;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int li = blockIdx.x; li < nlist; li += gridDim.x) {
@@ -292,83 +311,58 @@ k_front_panels(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ lis
         if (lane == 0) bad = 1;
       __syncthreads();
       if (bad) break;
-      for (int s = 0; s < FP_ROWS; ++s) {
-        const int o = tid + s * FP_THREADS;
-        if (o < rest) {
-          // L21 row pe+o:  l = a U11^{-1}
-          double *row = F + (int64_t)(pe + o) * m + p0;
-          double v[NB];
+      // L21 rows pe..m-1:  l = a U11^{-1}
+      for (int o = tid; o < rest; o += FP_THREADS) {
+        double *row = F + (int64_t)(pe + o) * m + p0;
+        double v[NB];
 #pragma unroll
-          for (int q = 0; q < NB; ++q) v[q] = q < pb ? row[q] : 0.0;
+        for (int q = 0; q < NB; ++q) v[q] = q < pb ? row[q] : 0.0;
 #pragma unroll
-          for (int q = 0; q < NB; ++q) {
-            if (q < pb) {
-              double t = v[q];
+        for (int q = 0; q < NB; ++q) {
+          if (q < pb) {
+            double t = v[q];
 #pragma unroll
-              for (int r = 0; r < q; ++r) t -= v[r] * D[r][q];
-              v[q] = t;
-            }
+            for (int r = 0; r < q; ++r) t -= v[r] * D[r][q];
+            v[q] = t;
           }
+        }
 #pragma unroll
-          for (int q = 0; q < NB; ++q)
-            if (q < pb) row[q] = v[q];
-          // U12 column pe+o:  u = L11^{-1} a
-          double *colp = F + (int64_t)p0 * m + pe + o;
-#pragma unroll
-          for (int q = 0; q < NB; ++q) v[q] = q < pb ? colp[(int64_t)q * m] : 0.0;
-#pragma unroll
-          for (int q = 0; q < NB; ++q) {
-            if (q < pb) {
-              double t = v[q];
-#pragma unroll
-              for (int r = 0; r < q; ++r) t -= D[q][r] * v[r];
-              v[q] = t / D[q][q];
-            }
-          }
-#pragma unroll
-          for (int q = 0; q < NB; ++q)
-            if (q < pb) {
-              colp[(int64_t)q * m] = v[q];
-              Ub[q * rest + o] = v[q];
-            }
+        for (int q = 0; q < NB; ++q) {
+          if (q < pb) row[q] = v[q];
+          Lp[o * NB + q] = v[q];          // zero beyond pb
         }
       }
       __syncthreads();
-      // update rows pe.. over the columns of the fully summed region still to eliminate:
-      // rows < k take columns pe..m-1, rows >= k take columns pe..k-1 (C22 is the GEMM's)
-      for (int s = 0; s < FP_ROWS; ++s) {
-        const int o = tid + s * FP_THREADS;
-        if (o < rest) {
-          const int i = pe + o;
-          const int jn = (i < k ? m : k) - pe;
-          double *Ci = F + (int64_t)i * m + pe;
-          double lr[NB];              // this thread's L21 row, written above by itself
-          const double *lp = F + (int64_t)i * m + p0;
+      // U12 columns pe..m-1:  u = L11^{-1} a, then the column's update
+      for (int o = tid; o < rest; o += FP_THREADS) {
+        const int j = pe + o;
+        double *colp = F + (int64_t)p0 * m + j;
+        double u[NB];
 #pragma unroll
-          for (int q = 0; q < NB; ++q) lr[q] = q < pb ? lp[q] : 0.0;
-          int j = 0;
-          for (; j + 4 <= jn; j += 4) {
-            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        for (int q = 0; q < NB; ++q) u[q] = q < pb ? colp[(int64_t)q * m] : 0.0;
 #pragma unroll
-            for (int q = 0; q < NB; ++q) {
-              const double l = lr[q];
-              const double *u = Ub + q * rest + j;
-              a0 += l * u[0];
-              a1 += l * u[1];
-              a2 += l * u[2];
-              a3 += l * u[3];
-            }
-            Ci[j] -= a0;
-            Ci[j + 1] -= a1;
-            Ci[j + 2] -= a2;
-            Ci[j + 3] -= a3;
+        for (int q = 0; q < NB; ++q) {
+          if (q < pb) {
+            double t = u[q];
+#pragma unroll
+            for (int r = 0; r < q; ++r) t -= D[q][r] * u[r];
+            u[q] = t / D[q][q];
           }
-          for (; j < jn; ++j) {
-            double a0 = 0.0;
+        }
 #pragma unroll
-            for (int q = 0; q < NB; ++q) a0 += lr[q] * Ub[q * rest + j];
-            Ci[j] -= a0;
+        for (int q = 0; q < NB; ++q)
+          if (q < pb) colp[(int64_t)q * m] = u[q];
+        const int iend = j < k ? m : k;
+        double *Cj = F + j;
+        for (int i = pe; i < iend; ++i) {
+          const double *lr = Lp + (i - pe) * NB;
+          double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+          for (int q = 0; q < NB / 2; ++q) {
+            a0 += lr[2 * q] * u[2 * q];
+            a1 += lr[2 * q + 1] * u[2 * q + 1];
           }
+          Cj[(int64_t)i * m] -= a0 + a1;
         }
       }
       __syncthreads();
