@@ -253,6 +253,11 @@ k_solve_down_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__
             if (p == i) dg = row[p];
           rd[i] = TRANS ? 1.0 : 1.0 / dg;
         }
+        // this thread's first remaining row: its coefficients are fetched while wave 0 solves
+        const int i1 = pe + tid;
+        double cf1[NBS];
+#pragma unroll
+        for (int p = 0; p < NBS; ++p) cf1[p] = (i1 < m && p < pb) ? cdown<TRANS>(F, m, i1, p0 + p) : 0.0;
         __syncthreads();
         if (wv == 0) {
           // rows pb.. of Y meet zero coefficients in the row update below; clear them so
@@ -273,7 +278,14 @@ k_solve_down_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__
           }
         }
         __syncthreads();
-        for (int i = pe + tid; i < m; i += 256) {
+        if (i1 < m)
+          for (int r = 0; r < nr; ++r) {
+            double s = 0.0;
+#pragma unroll
+            for (int p = 0; p < NBS; ++p) s += cf1[p] * Y[p * nr + r];
+            W[i1 * nr + r] -= s;
+          }
+        for (int i = i1 + 256; i < m; i += 256) {
           double cf[NBS];
 #pragma unroll
           for (int p = 0; p < NBS; ++p) cf[p] = p < pb ? cdown<TRANS>(F, m, i, p0 + p) : 0.0;
@@ -353,6 +365,10 @@ k_solve_up_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ l
             if (p == q) dg = row[p];
           rd[q] = TRANS ? 1.0 / dg : 1.0;
         }
+        const int q1 = tid;                       // this thread's first remaining row
+        double cf1[NBS];
+#pragma unroll
+        for (int p = 0; p < NBS; ++p) cf1[p] = (q1 < p0 && p < pb) ? cup<TRANS>(F, m, q1, p0 + p) : 0.0;
         __syncthreads();
         if (wv == 0) {
           for (int t = pb * nr + lane; t < NBS * nr; t += 64) X[t] = 0.0;
@@ -371,7 +387,14 @@ k_solve_up_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ l
           }
         }
         __syncthreads();
-        for (int q = tid; q < p0; q += 256) {
+        if (q1 < p0)
+          for (int r = 0; r < nr; ++r) {
+            double s = 0.0;
+#pragma unroll
+            for (int p = 0; p < NBS; ++p) s += cf1[p] * X[p * nr + r];
+            W[q1 * nr + r] -= s;
+          }
+        for (int q = q1 + 256; q < p0; q += 256) {
           double cf[NBS];
 #pragma unroll
           for (int p = 0; p < NBS; ++p) cf[p] = p < pb ? cup<TRANS>(F, m, q, p0 + p) : 0.0;
