@@ -192,6 +192,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="run a few steps and a 1 GiB device copy (HBM counter calibration) only")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -219,6 +221,17 @@ def main():
         plan.factor(K)
         return plan.refine(K, b, tol=1e-12, max_it=5, x=x)
 
+    if args.pmc_probe:
+        for _ in range(3):
+            step()
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        _sync()
+        print(json.dumps({"pmc_probe": True, "copy_bytes": src.numel() * 8,
+                          "schedule": tuned["chosen"]}))
+        return
     t_step, t_dev, (_, its, rr) = time_steps(step, args.steps, args.warmup)
     t_fac, _, _ = time_steps(lambda: plan.factor(K), args.steps, 1)
     t_sol, _, _ = time_steps(lambda: plan.solve(b, out=x), args.steps, 1)
