@@ -30,13 +30,14 @@ import numpy as np
 class Mesh:
     dim: int
     shape: tuple            # elements per axis
-    conn: np.ndarray        # (E, 2**dim) int32 global node ids in tensor-product local order
+    conn: np.ndarray        # (E, (p+1)**dim) int32 global node ids in tensor-product local order
     ijk: np.ndarray         # (E, dim) int32 element index coordinates
     h: tuple                # element edge length per axis
+    p: int = 1              # polynomial degree per axis (Q_p Lagrange elements)
 
     @property
     def npe(self) -> int:
-        return 1 << self.dim
+        return (self.p + 1) ** self.dim
 
     @property
     def n_elem(self) -> int:
@@ -44,7 +45,7 @@ class Mesh:
 
     @property
     def n_nodes(self) -> int:
-        return int(np.prod([s + 1 for s in self.shape]))
+        return int(np.prod([self.p * s + 1 for s in self.shape]))
 
 
 @dataclass
@@ -96,6 +97,99 @@ def structured_q1(shape: Sequence[int], lengths: Optional[Sequence[float]] = Non
     return Mesh(dim, shape, conn.astype(np.int32), ijk.astype(np.int32), h)
 
 
+def structured_qp(shape: Sequence[int], p: int, lengths: Optional[Sequence[float]] = None) -> Mesh:
+    """Uniform mesh of Q_p Lagrange elements (equispaced nodes, p = 1..3).  Nodes form the
+    (p*nx+1) x (p*ny+1)[ x (p*nz+1)] lattice, lattice point (I, J[, K]) has id
+    I + (p*nx+1)*(J + (p*ny+1)*K); local node a = c_x + (p+1)*c_y [+ (p+1)^2*c_z] with
+    c in {0..p} sits at lattice point p*(i, j[, k]) + c.  p = 1 is ``structured_q1``."""
+    p = int(p)
+    if p < 1 or p > 3:
+        raise ValueError(f"polynomial degree {p} not in 1..3")
+    q1 = structured_q1(shape, lengths)
+    dim, ijk = q1.dim, q1.ijk.astype(np.int64)
+    if p == 1:
+        return q1
+    nstride = np.cumprod([1] + [p * s + 1 for s in q1.shape[:-1]]).astype(np.int64)
+    npe = (p + 1) ** dim
+    conn = np.empty((ijk.shape[0], npe), dtype=np.int64)
+    for a in range(npe):
+        c = np.array([(a // (p + 1) ** d) % (p + 1) for d in range(dim)], dtype=np.int64)
+        conn[:, a] = ((p * ijk + c) * nstride).sum(axis=1)
+    return Mesh(dim, q1.shape, conn.astype(np.int32), q1.ijk, q1.h, p)
+
+
+def lagrange_1d(p: int, t: np.ndarray):
+    """Values and derivatives (d/dt) of the p+1 Lagrange polynomials on the nodes i/p of [0, 1]
+    at the points t: two arrays (len(t), p+1)."""
+    nodes = np.arange(p + 1) / p
+    t = np.asarray(t, dtype=np.float64)
+    val = np.ones((t.size, p + 1))
+    der = np.zeros((t.size, p + 1))
+    for i in range(p + 1):
+        others = [j for j in range(p + 1) if j != i]
+        den = np.prod([nodes[i] - nodes[j] for j in others])
+        fac = [(t - nodes[j]) for j in others]
+        val[:, i] = np.prod(fac, axis=0) / den
+        for s_ in range(len(others)):
+            der[:, i] += np.prod([fac[r] for r in range(len(others)) if r != s_], axis=0) / den
+    return val, der
+
+
+def _tensor_basis(h: Sequence[float], p: int):
+    """phi (Q, npe), grad (Q, npe, dim), weights (Q,) at the (p+1)^dim Gauss-Legendre points of
+    an element with edge lengths h (exact for the mass and stiffness integrands of Q_p)."""
+    dim = len(h)
+    x, w = np.polynomial.legendre.leggauss(p + 1)
+    t, wt = (x + 1.0) / 2.0, w / 2.0
+    B, D = lagrange_1d(p, t)
+    npe = (p + 1) ** dim
+    pts = list(np.ndindex(*([p + 1] * dim)))
+    phi = np.ones((len(pts), npe))
+    grad = np.ones((len(pts), npe, dim))
+    wq = np.empty(len(pts))
+    for qi, q in enumerate(pts):
+        wq[qi] = float(np.prod([wt[q[d]] * h[d] for d in range(dim)]))
+        for a in range(npe):
+            c = [(a // (p + 1) ** d) % (p + 1) for d in range(dim)]
+            for d in range(dim):
+                phi[qi, a] *= B[q[d], c[d]]
+                for e in range(dim):
+                    grad[qi, a, e] *= (D[q[d], c[d]] / h[d]) if d == e else B[q[d], c[d]]
+    return phi, grad, wq, pts, t
+
+
+def qp_reference_matrices(h: Sequence[float], p: int):
+    """Stiffness S, mass M and advection parts C[d] of one Q_p element with edge lengths h, by
+    (p+1)-point Gauss-Legendre per axis on tensor-product Lagrange bases."""
+    h = tuple(float(x) for x in h)
+    phi, grad, wq, _, _ = _tensor_basis(h, p)
+    S = np.einsum("q,qad,qbd->ab", wq, grad, grad)
+    M = np.einsum("q,qa,qb->ab", wq, phi, phi)
+    C = [np.einsum("q,qa,qb->ab", wq, phi, grad[:, :, d]) for d in range(len(h))]
+    return S, M, C
+
+
+def load_vector(mesh: Mesh, f) -> np.ndarray:
+    """b_i = int f phi_i over the mesh, by (p+1)-point Gauss-Legendre per axis on each element;
+    f maps an (N, dim) array of points to N values."""
+    phi, _, wq, pts, t = _tensor_basis(mesh.h, mesh.p)
+    dim = mesh.dim
+    off = np.asarray(mesh.ijk, dtype=np.float64) * np.asarray(mesh.h)[None, :]   # (E, dim)
+    loc = np.array([[t[q[d]] * mesh.h[d] for d in range(dim)] for q in pts])  # (Q, dim)
+    fx = f((off[:, None, :] + loc[None, :, :]).reshape(-1, dim)).reshape(mesh.n_elem, len(pts))
+    be = (fx * wq[None, :]) @ phi                                               # (E, npe)
+    b = np.zeros(mesh.n_nodes)
+    np.add.at(b, mesh.conn.reshape(-1), be.reshape(-1))
+    return b
+
+
+def node_coords(mesh: Mesh) -> np.ndarray:
+    """(n_nodes, dim) coordinates of the lattice nodes."""
+    ax = [np.arange(mesh.p * s + 1) * (hd / mesh.p) for s, hd in zip(mesh.shape, mesh.h)]
+    g = np.meshgrid(*ax, indexing="ij")
+    return np.stack([x.ravel(order="F") for x in g], axis=1)
+
+
 def q1_reference_matrices(h: Sequence[float]):
     """Stiffness S, mass M and advection parts C[d] (C[d][a,b] = int phi_a d(phi_b)/dx_d)
     of one Q1 element with edge lengths ``h``, by 2-point Gauss-Legendre per axis."""
@@ -128,9 +222,14 @@ def q1_reference_matrices(h: Sequence[float]):
     return S, M, C
 
 
+def reference_matrices(mesh: Mesh):
+    """(S, M, C) of the mesh's element: the Q1 closed construction for p = 1, else Q_p."""
+    return q1_reference_matrices(mesh.h) if mesh.p == 1 else qp_reference_matrices(mesh.h, mesh.p)
+
+
 def element_matrices(mesh: Mesh, coef: np.ndarray, vel: Optional[np.ndarray] = None) -> np.ndarray:
     """K_e = coef_e * S + M (+ sum_d vel_e[d] * C[d]) for every element, shape (E, npe, npe)."""
-    S, M, C = q1_reference_matrices(mesh.h)
+    S, M, C = reference_matrices(mesh)
     K = coef[:, None, None] * S[None] + M[None]
     if vel is not None:
         for d in range(mesh.dim):
@@ -183,6 +282,36 @@ def advection_diffusion(name: str, sides: np.ndarray, rng, sigma: float, nrhs: i
     b = rng.normal(0.0, 1.0, size=(n, nrhs))
     return Problem(name, meshes, np.concatenate(Ks), b, np.concatenate(coefs), Ss, Ms,
                    vel=np.concatenate(vels))
+
+
+def l2_projection(name: str, shape, p: int, rng, nrhs: int, f=None) -> Problem:
+    """The paper's model problem (Sec. 2.1, eqs. L2_proj and Linear_system): the Q_p mass-matrix
+    system M u = b with b_i = (f, phi_i).  Without ``f`` the right-hand sides are the load
+    vectors of f_r(x) = cos(w_r . x + c_r), w_r ~ N(0, 4^2)^dim, c_r ~ U[0, 2 pi), drawn in the
+    order w, c per column; with ``f`` every column is f's load vector."""
+    mesh = structured_qp(shape, p)
+    S, M, _ = reference_matrices(mesh)
+    K = np.ascontiguousarray(np.broadcast_to(M, (mesh.n_elem,) + M.shape))
+    cols = []
+    for _ in range(nrhs):
+        if f is not None:
+            cols.append(load_vector(mesh, f))
+            continue
+        w = rng.normal(0.0, 4.0, size=mesh.dim)
+        c = rng.uniform(0.0, 2.0 * np.pi)
+        cols.append(load_vector(mesh, lambda x, w=w, c=c: np.cos(x @ w + c)))
+    b = np.ascontiguousarray(np.stack(cols, axis=1))
+    return Problem(name, [mesh], K, b, np.zeros(mesh.n_elem), [S], [M], extra={"p": p})
+
+
+# The paper's benchmark axis (Sec. 5): L2 projection with linear, quadratic and cubic bases up
+# to 3e5 unknowns.  All three use the same 547 x 547 node lattice (299,209 unknowns).
+L2_SHAPES = {1: (546, 546), 2: (273, 273), 3: (182, 182)}
+
+
+def l2_workload(p: int, shape=None, nrhs: int = 1) -> Problem:
+    """Seeded L2-projection workload of degree p (seed 100 + p)."""
+    return l2_projection(f"l2p{p}", shape or L2_SHAPES[p], p, np.random.default_rng(100 + p), nrhs)
 
 
 CONFIGS = {

@@ -44,10 +44,13 @@ typedef struct mf_plan mf_plan;   /* opaque: host analysis, device plan, factor 
 
 /* One structured or unstructured mesh of tensor-product elements.
  *   dim       2 or 3
- *   npe       nodes per element, must equal 2^dim (Q1 elements)
+ *   npe       nodes per element: (p+1)^dim for Q_p Lagrange elements, p = 1, 2, 3 (the
+ *             linear, quadratic and cubic bases of Sec. 5); equal for all meshes of a batch
  *   n_nodes   nodes of this mesh; ids 0..n_nodes-1, every node used by some element
  *   n_elem    elements of this mesh (>= 1)
- *   conn      host [n_elem][npe] node ids, local node a = c_x + 2 c_y (+ 4 c_z)
+ *   conn      host [n_elem][npe] node ids in the element's local order; the element matrices
+ *             passed to mf_factor / mf_refine use the same order (the tree depends only on
+ *             which nodes an element has, not on their order)
  *   elem_ijk  host [n_elem][dim] integer element coordinates, pairwise distinct; they drive the
  *             nested-dissection bisection of the elimination tree                        */
 typedef struct {

@@ -78,7 +78,13 @@ std::string analyse(int32_t n_mesh, const int32_t *dims, const int32_t *npes,
   for (int32_t mi = 0; mi < n_mesh; ++mi) {
     if (dims[mi] != 2 && dims[mi] != 3) return "mesh " + std::to_string(mi) + ": dim must be 2 or 3";
     if (dims[mi] != P.dim) return "all meshes of a batch must have the same dim";
-    if (npes[mi] != (1 << dims[mi])) return "mesh " + std::to_string(mi) + ": npe must be 2^dim";
+    {
+      // Q_p Lagrange elements, p = 1..3: (p+1)^dim nodes per element
+      bool ok = false;
+      for (int q = 2; q <= 4; ++q) ok |= npes[mi] == (dims[mi] == 2 ? q * q : q * q * q);
+      if (!ok) return "mesh " + std::to_string(mi) + ": npe must be (p+1)^dim with p in 1..3";
+    }
+    if (npes[mi] != P.npe) return "all meshes of a batch must have the same npe";
     if (n_elems[mi] < 1 || n_nodes[mi] < 1) return "mesh " + std::to_string(mi) + ": empty";
     if (!conns[mi] || !ijks[mi]) return "mesh " + std::to_string(mi) + ": null conn or elem_ijk";
     if (n_elems[mi] > INT32_MAX / 4 || n_nodes[mi] > INT32_MAX / 4)

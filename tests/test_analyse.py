@@ -11,7 +11,7 @@ import re
 import numpy as np
 import pytest
 
-from fixtures import config_problem, structured_q1
+from fixtures import config_problem, structured_q1, structured_qp
 from oracle.tree import build_tree, front_flops
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -40,6 +40,13 @@ def _compare(meshes):
                                    (1, 1, 1), (2, 2, 2), (3, 2, 5), (4, 4, 4)])
 def test_tree_bit_exact(shape):
     _compare([structured_q1(shape)])
+
+
+@pytest.mark.parametrize("shape,p", [((3, 5), 2), ((4, 4), 3), ((7, 4), 2), ((2, 3, 2), 2),
+                                     ((2, 2, 2), 3)])
+def test_high_order_tree_bit_exact(shape, p):
+    """Quadratic and cubic elements: interior and edge nodes change pivots and front widths."""
+    _compare([structured_qp(shape, p)])
 
 
 def test_batched_tree_bit_exact():
@@ -119,3 +126,6 @@ def test_error_paths():
     unused.conn[0, 1] = 2   # node 0 no longer used
     _bad([unused], "not used")
     _bad([m, structured_q1((2, 2, 2))], "same dim")
+    _bad([m, structured_qp((2, 2), 2)], "same npe")
+    odd = structured_qp((2, 2), 2); odd.conn = odd.conn[:, :8].copy()
+    _bad([odd], "npe must be")
