@@ -13,7 +13,8 @@ time, with the operation counts of the method itself (division, multiplication a
 subtraction tasks), not dense n^3.
 
 Extra fields: per-kernel event timing of the same step (roofline of the dominant kernel),
-the batched and mixed-precision variants, and the CPU oracle on the host (cpu_baseline).
+the batched and mixed-precision variants, the L2 projection with linear, quadratic and cubic
+bases at 299,209 unknowns, and the CPU oracle on the host (cpu_baseline).
 Prints one JSON line.
 """
 import argparse
@@ -153,6 +154,41 @@ def variant_mixed(steps, warmup):
     return out
 
 
+def variant_l2(steps, warmup):
+    """The paper's own benchmark axis (Sec. 5): the L2 projection M u = b with linear, quadratic
+    and cubic bases on a 547 x 547 node lattice (299,209 unknowns, the paper's 3e5 limit), one
+    load vector; step = factor + solve + FP64 refinement to relres <= 1e-12."""
+    import torch
+    from fixtures import l2_workload
+    from paper_2306_08994_amd import Plan
+    out = {"workload": "2D L2 projection (mass matrix), 299,209 unknowns, 1 RHS, FP64"}
+    for deg in (1, 2, 3):
+        p = l2_workload(deg)
+        plan = Plan(p.meshes)
+        K = torch.from_numpy(p.K).cuda()
+        b = torch.from_numpy(p.b).cuda()
+        x = torch.empty_like(b)
+        inf = plan.info
+        flops = inf["factor_flops"] + p.nrhs * inf["solve_flops_per_rhs"]
+        sched = plan.autotune(K, reps=2)["chosen"]
+
+        def step():
+            plan.factor(K)
+            return plan.refine(K, b, tol=1e-12, max_it=5, x=x)
+        wall, dev, (_, its, rr) = time_steps(step, steps, warmup)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.factor(K)
+        _sync()
+        tf = (time.perf_counter() - t0) / steps
+        out[f"p{deg}"] = {"elements": list(p.meshes[0].shape), "fronts": inf["n_fronts"],
+                          "max_front": inf["max_m"], "factor_flops": inf["factor_flops"],
+                          "ms_per_system": wall * 1e3, "ms_factor": tf * 1e3,
+                          "gflops": flops / wall / 1e9, "refine_corrections": its,
+                          "relres": rr, "schedule": sched}
+    return out
+
+
 def variant_batched(steps, warmup):
     """256 independent 2D advection-diffusion meshes (sides 32..128) in one batch: every class
     of all meshes in one launch sequence; FP64 and FP32-Schur, refined to 1e-12."""
@@ -270,6 +306,7 @@ def main():
         vs = max(3, args.steps // 4)
         out["mixed_precision_3d"] = variant_mixed(vs, 2)
         out["batched_256_meshes"] = variant_batched(vs, 2)
+        out["l2_projection_p123"] = variant_l2(vs, 2)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

@@ -177,3 +177,45 @@ def test_profile_report():
     assert 0.95 * plan.info["factor_flops"] <= fl <= 1.5 * plan.info["factor_flops"]
     for k in rep["kernels"]:
         assert k["ms"] > 0 and k["launches"] > 0
+
+
+@pytest.mark.parametrize("deg", [1, 2, 3])
+def test_l2_projection_full_size(deg):
+    """The paper's benchmark axis at its largest size (Sec. 5): L2 projection with linear,
+    quadratic and cubic bases at 299,209 unknowns.  Sampled fronts against the oracle, then the
+    relative residual of the direct solve and after FP64 refinement, and the reproduction of a
+    function of the space (f of degree <= p per axis is its own projection)."""
+    import torch
+    from fixtures import l2_projection, l2_workload, node_coords, L2_SHAPES
+    from paper_2306_08994_amd import Plan
+    dev = G.torch_dev()
+    p = l2_workload(deg)
+    tree = build_tree(p.meshes)
+    conn = ofac.global_connectivity(p)
+    plan = Plan(p.meshes)
+    K = torch.from_numpy(p.K).to(dev)
+    b = torch.from_numpy(p.b).to(dev)
+    plan.factor(K)
+    Ls, Us = plan.export_factors()
+    rng = np.random.default_rng(deg)
+    roots = []
+    for l in (5, 7):
+        cand = np.flatnonzero(tree.level == l)
+        roots += [int(f) for f in rng.choice(cand, size=min(3, len(cand)), replace=False)]
+    L, U = _subtree_oracle(tree, p, conn, roots)
+    worst = max(max(G.front_violation(Ls[f], L[f]), G.front_violation(Us[f], U[f])) for f in L)
+    assert worst <= G.TOL_FACTOR, worst
+    x0 = plan.solve(b)
+    rr0 = G.relres(p, conn, x0.cpu().numpy())
+    x, its, rr = plan.refine(K, b, tol=1e-12, max_it=5)
+    assert rr <= 1e-12 and G.relres(p, conn, x.cpu().numpy()) <= 1e-12
+
+    def f(xy):
+        return np.prod(1.0 + xy + 0.5 * xy ** deg, axis=1)
+    pf = l2_projection("f", L2_SHAPES[deg], deg, None, 1, f=f)
+    u = plan.solve(torch.from_numpy(pf.b).to(dev)).cpu().numpy()[:, 0]
+    exact = f(node_coords(pf.meshes[0]))
+    err = np.abs(u - exact).max() / np.abs(exact).max()
+    assert err <= 1e-10, err
+    print(f"L2 projection p={deg}: sampled fronts {worst:.1e}, direct relres {rr0:.2e}, "
+          f"{its} corrections -> {rr:.2e}, reproduction error {err:.1e}")

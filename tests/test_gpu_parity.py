@@ -200,3 +200,53 @@ def test_autotune_keeps_a_correct_schedule():
     assert G.factor_violation(Ls, Us, fac) <= G.TOL_FACTOR
     x = plan.solve(b).cpu().numpy()
     assert G.rel_err(x, G.oracle_solve(tree, fac, p.b)) <= G.TOL_SOLVE
+
+
+# Quadratic and cubic elements: larger leaves that eliminate interior unknowns, fronts built
+# from edge/face nodes.  (shape, p, LDS limit, fused-route limit) -- the limits force the
+# tiled routes on small meshes.
+HIGH_ORDER = [((6, 5), 2, 0, 0), ((5, 4), 3, 0, 0), ((3, 3, 2), 2, 0, 0), ((2, 2, 2), 3, 0, 0),
+              ((24, 20), 2, 40, -1), ((16, 13), 3, 40, 0), ((5, 5, 4), 2, 64, 0)]
+
+
+@pytest.mark.parametrize("shape,deg,smax,fused", HIGH_ORDER)
+def test_high_order_parity(shape, deg, smax, fused):
+    from fixtures import l2_projection
+    from fixtures.mesh import element_matrices, structured_qp
+    p = l2_projection("t", shape, deg, np.random.default_rng(8), 3)
+    tree, conn, fac = G.oracle_factor(p)
+    plan, K, b = _setup(p, smax, 0, fused)
+    plan.factor(K)
+    Ls, Us = plan.export_factors()
+    assert G.factor_violation(Ls, Us, fac) <= G.TOL_FACTOR
+    for trans in (False, True):
+        x = plan.solve(b, transpose=trans).cpu().numpy()
+        assert G.rel_err(x, G.oracle_solve(tree, fac, p.b, trans)) <= G.TOL_SOLVE, trans
+    # diffusion with a lognormal coefficient on the same mesh
+    m = structured_qp(shape, deg)
+    p.K = element_matrices(m, np.exp(np.random.default_rng(9).normal(0, 1, m.n_elem)))
+    tree, conn, fac = G.oracle_factor(p)
+    plan, K, b = _setup(p, smax, 0, fused)
+    plan.factor(K)
+    Ls, Us = plan.export_factors()
+    assert G.factor_violation(Ls, Us, fac) <= G.TOL_FACTOR
+    x = plan.solve(b).cpu().numpy()
+    assert G.rel_err(x, G.oracle_solve(tree, fac, p.b)) <= G.TOL_SOLVE
+    assert G.relres(p, conn, x) <= G.TOL_RELRES
+
+
+def test_high_order_residual_and_elem_grad():
+    import torch
+    from fixtures import l2_projection
+    from oracle import adjoint as oadj
+    from oracle import residual as ores
+    p = l2_projection("t", (4, 3, 2), 3, np.random.default_rng(3), 2)
+    plan, K, b = _setup(p)
+    conn = p.meshes[0].conn.astype(np.int64)
+    x = np.random.default_rng(4).normal(size=b.shape)
+    xt = torch.from_numpy(x).to(b.device)
+    r = plan.residual(K, xt, b).cpu().numpy()
+    np.testing.assert_allclose(r, ores.residual(p.K, conn, x, p.b), rtol=1e-13, atol=1e-13)
+    lam = np.random.default_rng(5).normal(size=b.shape)
+    gK = plan.elem_grad(torch.from_numpy(lam).to(b.device), xt).cpu().numpy()
+    np.testing.assert_allclose(gK, oadj.elem_grad(conn, lam, x), rtol=1e-13, atol=1e-13)
