@@ -117,6 +117,9 @@ void level_costs(const mf::HostPlan &H, const mf::LevelSchedule &S, LevelDev &D,
 
 }  // namespace
 
+// Fronts of a class whose widest front is above this take the workgroup-per-front block solves.
+constexpr int kWaveSolveMaxM = 64;
+
 int ensure_uploaded(mf_plan *P) {
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
@@ -199,6 +202,29 @@ int ensure_uploaded(mf_plan *P) {
     if (hipMalloc((void **)&P->d_store, std::max<int64_t>(1, H.store_doubles) * sizeof(double)) != hipSuccess)
       return fail(MF_ENOMEM, "cannot allocate " + std::to_string(H.store_doubles * 8) +
                                  " bytes of factor storage");
+    // diagonal-block inverses for every front of the classes the block solves handle
+    std::vector<int64_t> doff(H.desc.size(), -1);
+    std::vector<int2> dtasks;
+    int64_t dtot = 0;
+    constexpr int64_t kPair = 2 * mf::NBS * mf::NBS;
+    for (const mf::LevelSchedule &S : H.levels) {
+      if (S.max_m <= kWaveSolveMaxM) continue;
+      for (int32_t f : S.all) {
+        const int32_t k = H.desc[f].k;
+        if (k <= 0) continue;
+        doff[f] = dtot;
+        for (int32_t p0 = 0; p0 < k; p0 += mf::NBS) dtasks.push_back(make_int2(f, p0));
+        dtot += (int64_t)((k + mf::NBS - 1) / mf::NBS) * kPair;
+      }
+    }
+    if ((rc = upload(P->d_dinv_off, doff)) || (rc = upload(P->d_dinv_tasks, dtasks))) return rc;
+    P->n_dinv_tasks = (int64_t)dtasks.size();
+    P->c_dinv.bytes = 8.0 * P->n_dinv_tasks * (mf::NBS * mf::NBS + kPair);
+    P->c_dinv.flops = P->n_dinv_tasks * 2.0 * mf::NBS * mf::NBS * mf::NBS / 3.0;
+    dfree(P->d_dinv);
+    if (hipMalloc((void **)&P->d_dinv, std::max<int64_t>(1, dtot) * sizeof(double)) != hipSuccess)
+      return fail(MF_ENOMEM, "cannot allocate " + std::to_string(dtot * 8) +
+                                 " bytes of diagonal-block inverses");
     P->static_up = true;
   }
   if (!P->d_status) HIPCHK(hipMalloc((void **)&P->d_status, mf::kStatusWords * sizeof(int)));
@@ -329,11 +355,15 @@ int launch_factor(mf_plan *P, const double *K, int prec, hipStream_t s) {
       }
     }
   }
+  if (P->n_dinv_tasks) {
+    const int grid = (int)std::min<int64_t>((P->n_dinv_tasks + 3) / 4, 65535);
+    LAUNCH(K_DIAG_INV, P->c_dinv, mf::k_diag_inverse, dim3(grid), dim3(256), 0, s, P->d_desc,
+           P->d_dinv_tasks, (int)P->n_dinv_tasks, P->d_store, P->d_dinv_off, P->d_dinv);
+  }
   HIPCHK(hipGetLastError());
   return MF_OK;
 }
 
-constexpr int kWaveSolveMaxM = 64;
 
 // Largest power-of-two column chunk (<= nrhs) whose LDS footprint fits.
 int chunk(const mf_plan *P, int32_t nrhs, int64_t fixed_doubles, int64_t per_col_doubles) {
@@ -385,16 +415,18 @@ int launch_solve(mf_plan *P, const double *b, double *x, int32_t nrhs, bool tran
         const int grid = std::min(n, gridcap);
         if (down && trans)
           LAUNCH(K_DOWN_BLOCK, c, mf::k_solve_down_block<true>, dim3(grid), dim3(256), lds, s, P->d_desc,
-                 lst, n, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, b, x, P->d_ycb, nrhs, nc, mmax);
+                 lst, n, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, b, x, P->d_ycb, nrhs, nc, mmax,
+                 P->d_dinv, P->d_dinv_off);
         else if (down)
           LAUNCH(K_DOWN_BLOCK, c, mf::k_solve_down_block<false>, dim3(grid), dim3(256), lds, s, P->d_desc,
-                 lst, n, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, b, x, P->d_ycb, nrhs, nc, mmax);
+                 lst, n, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, b, x, P->d_ycb, nrhs, nc, mmax,
+                 P->d_dinv, P->d_dinv_off);
         else if (trans)
           LAUNCH(K_UP_BLOCK, c, mf::k_solve_up_block<true>, dim3(grid), dim3(256), lds, s, P->d_desc, lst,
-                 n, P->d_store, P->d_front_idx, x, nrhs, nc, mmax);
+                 n, P->d_store, P->d_front_idx, x, nrhs, nc, mmax, P->d_dinv, P->d_dinv_off);
         else
           LAUNCH(K_UP_BLOCK, c, mf::k_solve_up_block<false>, dim3(grid), dim3(256), lds, s, P->d_desc, lst,
-                 n, P->d_store, P->d_front_idx, x, nrhs, nc, mmax);
+                 n, P->d_store, P->d_front_idx, x, nrhs, nc, mmax, P->d_dinv, P->d_dinv_off);
       }
     }
   }

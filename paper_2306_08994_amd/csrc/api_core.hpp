@@ -40,12 +40,12 @@ inline int fail(int code, const std::string &msg) {
 
 enum Kind {
   K_TINY, K_SMALL, K_ASSEMBLE, K_FUSED, K_TRSM, K_GEMM_PANEL, K_GEMM_SCHUR,
-  K_DOWN_WAVE, K_DOWN_BLOCK, K_UP_WAVE, K_UP_BLOCK, K_RESIDUAL, K_OTHER, K_COUNT
+  K_DOWN_WAVE, K_DOWN_BLOCK, K_UP_WAVE, K_UP_BLOCK, K_RESIDUAL, K_DIAG_INV, K_OTHER, K_COUNT
 };
 static const char *const kKindName[K_COUNT] = {
     "factor_tiny", "factor_small", "assemble", "front_panels", "panel_lu_trsm", "gemm_panel",
     "gemm_schur", "solve_down_wave", "solve_down_block", "solve_up_wave", "solve_up_block",
-    "residual", "other"};
+    "residual", "diag_block_inverse", "other"};
 
 // Algorithmic traffic and work of one launch (bytes that must cross HBM at least once, flops
 // of the method's own operation count).
@@ -129,6 +129,12 @@ struct mf_plan {
   int32_t *d_lists = nullptr;
   mf::GemmTask *d_tasks = nullptr;
   double *d_store = nullptr;
+  // inverses of the diagonal blocks of the fronts the block solves handle (see k_diag_inverse)
+  double *d_dinv = nullptr;
+  int64_t *d_dinv_off = nullptr;
+  int2 *d_dinv_tasks = nullptr;
+  int64_t n_dinv_tasks = 0;
+  mfapi::Cost c_dinv;
   int *d_status = nullptr;
   int *h_status = nullptr;
   double *d_ycb = nullptr;
@@ -171,6 +177,9 @@ struct mf_plan {
     mfapi::dfree(d_lists);
     mfapi::dfree(d_tasks);
     mfapi::dfree(d_store);
+    mfapi::dfree(d_dinv);
+    mfapi::dfree(d_dinv_off);
+    mfapi::dfree(d_dinv_tasks);
     mfapi::dfree(d_status);
     mfapi::dfree(d_ycb);
     mfapi::dfree(d_work);

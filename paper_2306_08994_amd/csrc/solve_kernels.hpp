@@ -188,16 +188,95 @@ k_solve_up_wave(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ li
 }
 
 // ---------------------------------------------------------------------------------------------
-// One workgroup per front (wider fronts), pivots in blocks of NBS.  Per block: the NBS x NBS
-// diagonal coefficient block (and the reciprocals of its pivots) is staged in LDS and solved
-// sequentially by wave 0 (wave-level ordering), then every thread takes one remaining row,
-// loads that row's NBS coefficients into registers (independent loads, one round trip) and
-// applies the block's solution to it.
-// LDS: W (mmax x nc) | D (NBS x NBS+1) | Y (NBS x nc) | rd (NBS).
+// Inverses of the NBS x NBS diagonal blocks of L and U of every front that the block solves
+// handle, computed once after the factorization, so that a block solve applies a diagonal block
+// as one matrix-vector product instead of NBS dependent substitution steps.  For a front f with
+// k > 0, dinv + dinv_off[f] holds ceil(k / NBS) pairs of NBS x NBS row-major blocks: inv(L_BB)
+// (lower, pivots on the diagonal), then inv(U_BB) (unit upper); a ragged last block is padded
+// with the identity.  One wave per (front, block) task: lanes 0..NBS-1 form the columns of
+// inv(L_BB) by forward substitution, lanes NBS..2NBS-1 those of inv(U_BB) by back substitution,
+// each column in registers against the block staged in LDS.
 // ---------------------------------------------------------------------------------------------
 constexpr int NBS = 32;
+static_assert(2 * NBS == 64, "one wave forms both inverses of a block");
 
-__host__ __device__ constexpr int block_solve_fixed_doubles() { return NBS * (NBS + 1) + NBS; }
+__global__ void __launch_bounds__(256)
+k_diag_inverse(const FrontDesc *__restrict__ fd, const int2 *__restrict__ tasks, int ntasks,
+               const double *__restrict__ store, const int64_t *__restrict__ dinv_off,
+               double *__restrict__ dinv) {
+  __shared__ double Bs[4][NBS][NBS + 1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double(*B)[NBS + 1] = Bs[wv];
+  const int j = lane & (NBS - 1);
+  for (int t = blockIdx.x * 4 + wv; t < ntasks; t += gridDim.x * 4) {
+    const int2 tk = tasks[t];
+    const FrontDesc d = fd[tk.x];
+    const int p0 = tk.y, pb = min(NBS, d.k - p0);
+    const double *F = store + d.store + (int64_t)p0 * d.m + p0;
+    for (int e = lane; e < NBS * NBS; e += 64) {
+      const int i = e / NBS, c = e % NBS;
+      B[i][c] = (i < pb && c < pb) ? F[(int64_t)i * d.m + c] : (i == c ? 1.0 : 0.0);
+    }
+    wave_sync();
+    double z[NBS];
+    if (lane < NBS) {
+#pragma unroll
+      for (int i = 0; i < NBS; ++i) {          // L z = e_j
+        double s = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+        for (int p = 0; p < i; ++p) s -= B[i][p] * z[p];
+        z[i] = s / B[i][i];
+      }
+    } else {
+#pragma unroll
+      for (int i = NBS - 1; i >= 0; --i) {     // U z = e_j, unit diagonal
+        double s = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+        for (int p = i + 1; p < NBS; ++p) s -= B[i][p] * z[p];
+        z[i] = s;
+      }
+    }
+    double *out = dinv + dinv_off[tk.x] + (int64_t)(p0 / NBS) * 2 * NBS * NBS +
+                  (lane < NBS ? 0 : NBS * NBS);
+#pragma unroll
+    for (int i = 0; i < NBS; ++i) out[i * NBS + j] = z[i];
+    wave_sync();
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// One workgroup per front (fronts wider than the wave route), pivots in blocks of NBS.  Per
+// block: the inverse of the diagonal block (staged in LDS) gives the block's unknowns in one
+// matrix-vector product, thread (q, r) forming row q for right-hand side r; then every thread
+// applies them to its remaining rows, with each row's NBS coefficients in registers.  The next
+// block's inverse and the coefficients of a thread's first remaining row of the next block are
+// loaded one block ahead, so their latency overlaps the current block's work.
+// LDS: W (mmax x nc) | M (NBS x NBS+1, the diagonal block's inverse) | Y (NBS x nc).
+// ---------------------------------------------------------------------------------------------
+__host__ __device__ constexpr int block_solve_fixed_doubles() { return NBS * (NBS + 1); }
+
+constexpr int kInvPerThread = NBS * NBS / 256;
+
+// The inverse a sweep applies for the diagonal block starting at pivot p0, read in memory order
+// (coalesced): down: TRANS ? inv(U)^T : inv(L); up: TRANS ? inv(L)^T : inv(U).
+template <bool TRANS, bool UP>
+__device__ inline void load_block_inverse(const double *dv, int p0, int tid, double *v) {
+  const double *M = dv + (int64_t)(p0 / NBS) * 2 * NBS * NBS + ((UP != TRANS) ? NBS * NBS : 0);
+#pragma unroll
+  for (int u = 0; u < kInvPerThread; ++u) v[u] = M[tid + 256 * u];
+}
+// ... and stored into LDS as Ms[q][p] = entry (q, p) of the applied matrix.
+template <bool TRANS>
+__device__ inline void store_block_inverse(const double *v, int tid, double *Ms) {
+#pragma unroll
+  for (int u = 0; u < kInvPerThread; ++u) {
+    const int e = tid + 256 * u, a = e / NBS, c = e % NBS;
+    if (TRANS)
+      Ms[c * (NBS + 1) + a] = v[u];
+    else
+      Ms[a * (NBS + 1) + c] = v[u];
+  }
+}
 
 template <bool TRANS>
 __global__ void __launch_bounds__(256)
@@ -205,13 +284,13 @@ k_solve_down_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__
                    const double *__restrict__ store, const int32_t *__restrict__ front_idx,
                    const int32_t *__restrict__ inv_l, const int32_t *__restrict__ inv_r,
                    const double *b, double *x, double *__restrict__ ycb, int nrhs, int nc,
-                   int mmax) {
+                   int mmax, const double *__restrict__ dinv,
+                   const int64_t *__restrict__ dinv_off) {
   extern __shared__ double sm[];
   double *W = sm;
-  double *D = W + mmax * nc;
-  double *rd = D + NBS * (NBS + 1);
-  double *Y = rd + NBS;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  double *Ms = W + mmax * nc;
+  double *Y = Ms + NBS * (NBS + 1);
+  const int tid = threadIdx.x;
   for (int li = blockIdx.x; li < nlist; li += gridDim.x) {
     const int f = list[li];
     const FrontDesc d = fd[f];
@@ -220,6 +299,7 @@ k_solve_down_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__
     const int32_t *il = inv_l + d.idx;
     const int32_t *ir = inv_r + d.idx;
     const double *F = store + d.store;
+    const double *dv = k > 0 ? dinv + dinv_off[f] : nullptr;
     FrontDesc a = d, c = d;
     if (d.elem < 0) {
       a = fd[d.left];
@@ -228,6 +308,13 @@ k_solve_down_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__
     const bool use_a = d.elem < 0 && !passthrough(a), use_c = d.elem < 0 && !passthrough(c);
     for (int r0 = 0; r0 < nrhs; r0 += nc) {
       const int nr = min(nc, nrhs - r0);
+      double mv[kInvPerThread], cf[NBS];
+      if (k > 0) {
+        load_block_inverse<TRANS, false>(dv, 0, tid, mv);
+        const int pb = min(NBS, k), i1 = pb + tid;
+#pragma unroll
+        for (int p = 0; p < NBS; ++p) cf[p] = (i1 < m && p < pb) ? cdown<TRANS>(F, m, i1, p) : 0.0;
+      }
       for (int i = tid; i < m; i += 256) {
         const int64_t gi = idx[i];
         const int x0 = use_a ? il[i] : -1, y0 = use_c ? ir[i] : -1;
@@ -238,63 +325,54 @@ k_solve_down_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__
           W[i * nr + r] = v;
         }
       }
+      if (k > 0) store_block_inverse<TRANS>(mv, tid, Ms);
       for (int p0 = 0; p0 < k; p0 += NBS) {
         const int pb = min(NBS, k - p0), pe = p0 + pb;
-        if (tid < pb) {
-          const int i = tid;
-          double row[NBS];
-#pragma unroll
-          for (int p = 0; p < NBS; ++p) row[p] = (p <= i) ? cdown<TRANS>(F, m, p0 + i, p0 + p) : 0.0;
-#pragma unroll
-          for (int p = 0; p < NBS; ++p) D[i * (NBS + 1) + p] = row[p];
-          double dg = 1.0;
+        __syncthreads();            // rows p0.. of W final, Ms holds this block's inverse
+        for (int t = tid; t < pb * nr; t += 256) {
+          const int q = t / nr, r = t - (t / nr) * nr;
+          double s = 0.0;
+          for (int p = 0; p < pb; ++p) s += Ms[q * (NBS + 1) + p] * W[(p0 + p) * nr + r];
+          Y[q * nr + r] = s;
+        }
+        // one block ahead: the next inverse, and this thread's first row of the next block
+        double cfn[NBS];
+        const bool more = pe < k;
+        if (more) {
+          load_block_inverse<TRANS, false>(dv, pe, tid, mv);
+          const int pbn = min(NBS, k - pe), i1n = pe + pbn + tid;
 #pragma unroll
           for (int p = 0; p < NBS; ++p)
-            if (p == i) dg = row[p];
-          rd[i] = TRANS ? 1.0 : 1.0 / dg;
+            cfn[p] = (i1n < m && p < pbn) ? cdown<TRANS>(F, m, i1n, pe + p) : 0.0;
         }
-        // this thread's first remaining row: its coefficients are fetched while wave 0 solves
+        __syncthreads();            // Y complete, every read of Ms and of rows p0..pe-1 done
+        for (int t = tid; t < pb * nr; t += 256) {
+          const int q = t / nr, r = t - (t / nr) * nr;
+          W[(p0 + q) * nr + r] = Y[q * nr + r];
+        }
         const int i1 = pe + tid;
-        double cf1[NBS];
-#pragma unroll
-        for (int p = 0; p < NBS; ++p) cf1[p] = (i1 < m && p < pb) ? cdown<TRANS>(F, m, i1, p0 + p) : 0.0;
-        __syncthreads();
-        if (wv == 0) {
-          // rows pb.. of Y meet zero coefficients in the row update below; clear them so
-          // stale LDS contents never enter it
-          for (int t = pb * nr + lane; t < NBS * nr; t += 64) Y[t] = 0.0;
-          for (int p = 0; p < pb; ++p) {
-            for (int r = lane; r < nr; r += 64) {
-              const double y = W[(p0 + p) * nr + r] * rd[p];
-              Y[p * nr + r] = y;
-              W[(p0 + p) * nr + r] = y;     // row p is read only through Y from here on
-            }
-            wave_sync();
-            for (int t = lane; t < (pb - p - 1) * nr; t += 64) {
-              const int i = p + 1 + t / nr, r = t - (t / nr) * nr;
-              W[(p0 + i) * nr + r] -= D[i * (NBS + 1) + p] * Y[p * nr + r];
-            }
-            wave_sync();
-          }
-        }
-        __syncthreads();
         if (i1 < m)
           for (int r = 0; r < nr; ++r) {
             double s = 0.0;
 #pragma unroll
-            for (int p = 0; p < NBS; ++p) s += cf1[p] * Y[p * nr + r];
+            for (int p = 0; p < NBS; ++p) s += cf[p] * Y[p * nr + r];
             W[i1 * nr + r] -= s;
           }
         for (int i = i1 + 256; i < m; i += 256) {
-          double cf[NBS];
+          double cr[NBS];
 #pragma unroll
-          for (int p = 0; p < NBS; ++p) cf[p] = p < pb ? cdown<TRANS>(F, m, i, p0 + p) : 0.0;
+          for (int p = 0; p < NBS; ++p) cr[p] = p < pb ? cdown<TRANS>(F, m, i, p0 + p) : 0.0;
           for (int r = 0; r < nr; ++r) {
             double s = 0.0;
 #pragma unroll
-            for (int p = 0; p < NBS; ++p) s += cf[p] * Y[p * nr + r];
+            for (int p = 0; p < NBS; ++p) s += cr[p] * Y[p * nr + r];
             W[i * nr + r] -= s;
           }
+        }
+        if (more) {
+          store_block_inverse<TRANS>(mv, tid, Ms);
+#pragma unroll
+          for (int p = 0; p < NBS; ++p) cf[p] = cfn[p];
         }
       }
       __syncthreads();
@@ -315,95 +393,108 @@ template <bool TRANS>
 __global__ void __launch_bounds__(256)
 k_solve_up_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ list, int nlist,
                  const double *__restrict__ store, const int32_t *__restrict__ front_idx,
-                 double *x, int nrhs, int nc, int mmax) {
+                 double *x, int nrhs, int nc, int mmax, const double *__restrict__ dinv,
+                 const int64_t *__restrict__ dinv_off) {
   extern __shared__ double sm[];
   double *W = sm;
-  double *D = W + mmax * nc;
-  double *rd = D + NBS * (NBS + 1);
-  double *X = rd + NBS;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  double *Ms = W + mmax * nc;
+  double *Y = Ms + NBS * (NBS + 1);
+  const int tid = threadIdx.x;
   for (int li = blockIdx.x; li < nlist; li += gridDim.x) {
     const int f = list[li];
     const FrontDesc d = fd[f];
     const int m = d.m, k = d.k;
     const int32_t *idx = front_idx + d.idx;
     const double *F = store + d.store;
+    const double *dv = k > 0 ? dinv + dinv_off[f] : nullptr;
+    const int plast = k > 0 ? ((k - 1) / NBS) * NBS : 0;
     for (int r0 = 0; r0 < nrhs; r0 += nc) {
       const int nr = min(nc, nrhs - r0);
+      double mv[kInvPerThread], cf[NBS];
+      if (k > 0) {
+        load_block_inverse<TRANS, true>(dv, plast, tid, mv);
+        const int pb = k - plast;
+#pragma unroll
+        for (int p = 0; p < NBS; ++p) cf[p] = (tid < plast && p < pb) ? cup<TRANS>(F, m, tid, plast + p) : 0.0;
+      }
       for (int i = tid; i < m; i += 256) {
         const int64_t gi = idx[i];
         for (int r = 0; r < nr; ++r) W[i * nr + r] = x[gi * nrhs + r0 + r];
       }
       __syncthreads();
-      // the already-final CB unknowns applied to the pivot rows, 32 columns at a time
+      // the already-final CB unknowns applied to the pivot rows, NBS columns at a time, the
+      // next chunk's coefficients loaded while the current one is applied
       for (int p = tid; p < k; p += 256) {
-        for (int j0 = k; j0 < m; j0 += NBS) {
-          double cf[NBS];
+        double c0[NBS], c1[NBS];
 #pragma unroll
-          for (int jj = 0; jj < NBS; ++jj) cf[jj] = j0 + jj < m ? cup<TRANS>(F, m, p, j0 + jj) : 0.0;
+        for (int jj = 0; jj < NBS; ++jj) c0[jj] = k + jj < m ? cup<TRANS>(F, m, p, k + jj) : 0.0;
+        for (int j0 = k; j0 < m; j0 += NBS) {
+          const bool nxt = j0 + NBS < m;
+          if (nxt) {
+#pragma unroll
+            for (int jj = 0; jj < NBS; ++jj)
+              c1[jj] = j0 + NBS + jj < m ? cup<TRANS>(F, m, p, j0 + NBS + jj) : 0.0;
+          }
           for (int r = 0; r < nr; ++r) {
             double s = 0.0;
 #pragma unroll
             for (int jj = 0; jj < NBS; ++jj)
-              if (j0 + jj < m) s += cf[jj] * W[(j0 + jj) * nr + r];
+              if (j0 + jj < m) s += c0[jj] * W[(j0 + jj) * nr + r];
             W[p * nr + r] -= s;
+          }
+          if (nxt) {
+#pragma unroll
+            for (int jj = 0; jj < NBS; ++jj) c0[jj] = c1[jj];
           }
         }
       }
-      for (int p0 = ((k - 1) / NBS) * NBS; p0 >= 0 && k > 0; p0 -= NBS) {
+      if (k > 0) store_block_inverse<TRANS>(mv, tid, Ms);
+      for (int p0 = plast; p0 >= 0 && k > 0; p0 -= NBS) {
         const int pb = min(NBS, k - p0);
-        if (tid < pb) {
-          const int q = tid;
-          double row[NBS];
-#pragma unroll
-          for (int p = 0; p < NBS; ++p) row[p] = (p >= q && p < pb) ? cup<TRANS>(F, m, p0 + q, p0 + p) : 0.0;
-#pragma unroll
-          for (int p = 0; p < NBS; ++p) D[q * (NBS + 1) + p] = row[p];
-          double dg = 1.0;
+        __syncthreads();            // rows p0.. of W final, Ms holds this block's inverse
+        for (int t = tid; t < pb * nr; t += 256) {
+          const int q = t / nr, r = t - (t / nr) * nr;
+          double s = 0.0;
+          for (int p = 0; p < pb; ++p) s += Ms[q * (NBS + 1) + p] * W[(p0 + p) * nr + r];
+          Y[q * nr + r] = s;
+        }
+        // one block ahead (the previous block of pivots): its inverse and this thread's row
+        // tid's coefficients in that block's columns
+        double cfn[NBS];
+        const bool more = p0 > 0;
+        if (more) {
+          load_block_inverse<TRANS, true>(dv, p0 - NBS, tid, mv);
 #pragma unroll
           for (int p = 0; p < NBS; ++p)
-            if (p == q) dg = row[p];
-          rd[q] = TRANS ? 1.0 / dg : 1.0;
+            cfn[p] = tid < p0 - NBS ? cup<TRANS>(F, m, tid, p0 - NBS + p) : 0.0;
         }
-        const int q1 = tid;                       // this thread's first remaining row
-        double cf1[NBS];
-#pragma unroll
-        for (int p = 0; p < NBS; ++p) cf1[p] = (q1 < p0 && p < pb) ? cup<TRANS>(F, m, q1, p0 + p) : 0.0;
-        __syncthreads();
-        if (wv == 0) {
-          for (int t = pb * nr + lane; t < NBS * nr; t += 64) X[t] = 0.0;
-          for (int p = pb - 1; p >= 0; --p) {
-            for (int r = lane; r < nr; r += 64) {
-              const double v = W[(p0 + p) * nr + r] * rd[p];
-              X[p * nr + r] = v;
-              W[(p0 + p) * nr + r] = v;
-            }
-            wave_sync();
-            for (int t = lane; t < p * nr; t += 64) {
-              const int q = t / nr, r = t - (t / nr) * nr;
-              W[(p0 + q) * nr + r] -= D[q * (NBS + 1) + p] * X[p * nr + r];
-            }
-            wave_sync();
-          }
+        __syncthreads();            // Y complete, every read of Ms and of rows p0.. done
+        for (int t = tid; t < pb * nr; t += 256) {
+          const int q = t / nr, r = t - (t / nr) * nr;
+          W[(p0 + q) * nr + r] = Y[q * nr + r];
         }
-        __syncthreads();
-        if (q1 < p0)
+        if (tid < p0)
           for (int r = 0; r < nr; ++r) {
             double s = 0.0;
 #pragma unroll
-            for (int p = 0; p < NBS; ++p) s += cf1[p] * X[p * nr + r];
-            W[q1 * nr + r] -= s;
+            for (int p = 0; p < NBS; ++p) s += cf[p] * Y[p * nr + r];
+            W[tid * nr + r] -= s;
           }
-        for (int q = q1 + 256; q < p0; q += 256) {
-          double cf[NBS];
+        for (int q = tid + 256; q < p0; q += 256) {
+          double cr[NBS];
 #pragma unroll
-          for (int p = 0; p < NBS; ++p) cf[p] = p < pb ? cup<TRANS>(F, m, q, p0 + p) : 0.0;
+          for (int p = 0; p < NBS; ++p) cr[p] = p < pb ? cup<TRANS>(F, m, q, p0 + p) : 0.0;
           for (int r = 0; r < nr; ++r) {
             double s = 0.0;
 #pragma unroll
-            for (int p = 0; p < NBS; ++p) s += cf[p] * X[p * nr + r];
+            for (int p = 0; p < NBS; ++p) s += cr[p] * Y[p * nr + r];
             W[q * nr + r] -= s;
           }
+        }
+        if (more) {
+          store_block_inverse<TRANS>(mv, tid, Ms);
+#pragma unroll
+          for (int p = 0; p < NBS; ++p) cf[p] = cfn[p];
         }
       }
       __syncthreads();

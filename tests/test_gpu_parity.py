@@ -231,8 +231,13 @@ def test_high_order_parity(shape, deg, smax, fused):
     Ls, Us = plan.export_factors()
     assert G.factor_violation(Ls, Us, fac) <= G.TOL_FACTOR
     x = plan.solve(b).cpu().numpy()
-    assert G.rel_err(x, G.oracle_solve(tree, fac, p.b)) <= G.TOL_SOLVE
-    assert G.relres(p, conn, x) <= G.TOL_RELRES
+    xo = G.oracle_solve(tree, fac, p.b)
+    assert G.rel_err(x, xo) <= G.TOL_SOLVE
+    # a direct FP64 solve of this system (cond ~4e5) leaves relres ~1.5e-12 in the oracle too:
+    # hold the direct solve to the oracle's residual, and the refined one to 1e-12
+    assert G.relres(p, conn, x) <= max(G.TOL_RELRES, 4 * G.relres(p, conn, xo))
+    _, its, rr = plan.refine(K, b, tol=1e-12, max_it=5)
+    assert rr <= G.TOL_RELRES
 
 
 def test_high_order_residual_and_elem_grad():
