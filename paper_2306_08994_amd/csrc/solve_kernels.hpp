@@ -329,10 +329,13 @@ k_solve_down_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__
       for (int p0 = 0; p0 < k; p0 += NBS) {
         const int pb = min(NBS, k - p0), pe = p0 + pb;
         __syncthreads();            // rows p0.. of W final, Ms holds this block's inverse
-        for (int t = tid; t < pb * nr; t += 256) {
+        // rows pb.. of Y are zero: they meet zero coefficients in the row updates below, and
+        // stale LDS contents must never enter them
+        for (int t = tid; t < NBS * nr; t += 256) {
           const int q = t / nr, r = t - (t / nr) * nr;
           double s = 0.0;
-          for (int p = 0; p < pb; ++p) s += Ms[q * (NBS + 1) + p] * W[(p0 + p) * nr + r];
+          if (q < pb)
+            for (int p = 0; p < pb; ++p) s += Ms[q * (NBS + 1) + p] * W[(p0 + p) * nr + r];
           Y[q * nr + r] = s;
         }
         // one block ahead: the next inverse, and this thread's first row of the next block
@@ -452,10 +455,13 @@ k_solve_up_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ l
       for (int p0 = plast; p0 >= 0 && k > 0; p0 -= NBS) {
         const int pb = min(NBS, k - p0);
         __syncthreads();            // rows p0.. of W final, Ms holds this block's inverse
-        for (int t = tid; t < pb * nr; t += 256) {
+        // rows pb.. of Y are zero: they meet zero coefficients in the row updates below, and
+        // stale LDS contents must never enter them
+        for (int t = tid; t < NBS * nr; t += 256) {
           const int q = t / nr, r = t - (t / nr) * nr;
           double s = 0.0;
-          for (int p = 0; p < pb; ++p) s += Ms[q * (NBS + 1) + p] * W[(p0 + p) * nr + r];
+          if (q < pb)
+            for (int p = 0; p < pb; ++p) s += Ms[q * (NBS + 1) + p] * W[(p0 + p) * nr + r];
           Y[q * nr + r] = s;
         }
         // one block ahead (the previous block of pivots): its inverse and this thread's row
