@@ -311,7 +311,7 @@ int launch_factor(mf_plan *P, const double *K, int prec, hipStream_t s) {
              (size_t)2 * D.large_max_m * sizeof(int), s, P->d_desc,
              P->d_lists + D.large, P->d_store, P->d_inv_l, P->d_inv_r, K, H.npe);
       if (D.n_fused) {
-        const size_t lds = (size_t)(32 * 33 + 32 * mf::FP_MAXM) * sizeof(double);
+        const size_t lds = (size_t)(32 * 33 + 32 + 32 * mf::FP_MAXM) * sizeof(double);
         LAUNCH(K_FUSED, D.c_fused, mf::k_front_panels<32>, dim3((unsigned)D.n_fused),
                dim3(mf::FP_THREADS), lds, s, P->d_desc, P->d_lists + D.fused, (int)D.n_fused,
                P->d_store, P->d_status);
@@ -410,8 +410,8 @@ int launch_solve(mf_plan *P, const double *b, double *x, int32_t nrhs, bool tran
                  n, P->d_store, P->d_front_idx, x, nrhs, nc, mmax, cld, ldsw);
       } else {
         const int64_t fixed = mf::block_solve_fixed_doubles();
-        const int nc = chunk(P, nrhs, fixed, mmax + mf::NBS);
-        const size_t lds = (size_t)(fixed + (int64_t)(mmax + mf::NBS) * nc) * 8;
+        const int nc = chunk(P, nrhs, fixed, mf::block_solve_col_doubles(mmax));
+        const size_t lds = (size_t)(fixed + (int64_t)mf::block_solve_col_doubles(mmax) * nc) * 8;
         const int grid = std::min(n, gridcap);
         if (down && trans)
           LAUNCH(K_DOWN_BLOCK, c, mf::k_solve_down_block<true>, dim3(grid), dim3(256), lds, s, P->d_desc,

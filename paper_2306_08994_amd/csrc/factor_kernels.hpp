@@ -167,47 +167,64 @@ __device__ inline double readlane(double v, int l) {
 }
 
 // LU (division tasks scale the pivot row) of the pb x pb diagonal block at F (leading
-// dimension m) by one wave, register resident: lane j holds column j.  At pivot p every lane
-// reads the pivot and the multiplier column from lane p (readlane), lane j > p divides its
-// U[p][j] and updates its column -- no LDS traffic and no synchronisation inside the block.
-// The factored block is left in LDS D (for the panel solves) and, if writeback, in F.
-// Returns false on a bad pivot (the same value on every lane) after recording it.
+// dimension m) by one wave, register resident: lane j holds column j of the block, padded with
+// the identity beyond pb so that every step runs unconditionally.  At pivot p every lane reads
+// the pivot and the multiplier column from lane p (readlane), lane j > p divides its U[p][j]
+// and updates its column -- no LDS traffic and no synchronisation inside the block.
+// The factored (padded) block is left in LDS D and the pivots' reciprocals in rd (for the panel
+// solves), and, if writeback, the pb x pb block in F.  Returns false on a bad pivot (the same
+// value on every lane) after recording the first one.
 template <int NB>
-__device__ inline bool wave_diag_lu(double *F, int64_t m, int pb, double (*D)[NB + 1], int lane,
-                                    int f, int p0, int *status, bool writeback = true) {
+__device__ __forceinline__ bool wave_diag_lu(double *F, int64_t m, int pb, double (*D)[NB + 1],
+                                             double *rd, int lane, int f, int p0, int *status,
+                                             bool writeback = true) {
   static_assert(NB <= 64, "one lane per column");
+  const bool in = lane < pb;
+  const double *src = F + (in ? lane : 0);
   double col[NB];
 #pragma unroll
-  for (int i = 0; i < NB; ++i) col[i] = (lane < pb && i < pb) ? F[i * m + lane] : 0.0;
-  bool ok = true;
+  for (int i = 0; i < NB; ++i) {
+    const double v = src[(int64_t)min(i, pb - 1) * m];
+    col[i] = (in && i < pb) ? v : (i == lane ? 1.0 : 0.0);
+  }
+  int bad = NB;
 #pragma unroll
   for (int p = 0; p < NB; ++p) {
-    if (p < pb) {
-      const double piv = readlane(col[p], p);
-      if (!good_pivot(piv)) {
-        if (lane == 0) record_bad_pivot(status, f, p0 + p);
-        ok = false;
-        break;
-      }
-      if (lane > p) col[p] = col[p] / piv;
+    const double piv = readlane(col[p], p);
+    if (bad == NB && !good_pivot(piv)) bad = p;
+    const bool act = lane > p;
+    const double u = act ? col[p] / piv : col[p];
+    col[p] = u;
+    const double ua = act ? u : 0.0;
 #pragma unroll
-      for (int i = p + 1; i < NB; ++i) {
-        const double mi = readlane(col[i], p);
-        if (lane > p) col[i] -= mi * col[p];
-      }
-    }
+    for (int i = p + 1; i < NB; ++i) col[i] -= readlane(col[i], p) * ua;
   }
+  if (bad < pb && lane == 0) record_bad_pivot(status, f, p0 + bad);
   if (lane < NB) {
 #pragma unroll
     for (int i = 0; i < NB; ++i) D[i][lane] = col[i];
   }
-  if (writeback && lane < pb) {
+  if (writeback && in) {
+    if (pb == NB) {
 #pragma unroll
-    for (int i = 0; i < NB; ++i)
-      if (i < pb) F[i * m + lane] = col[i];
+      for (int i = 0; i < NB; ++i) F[i * m + lane] = col[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+        if (i < pb) F[i * m + lane] = col[i];
+    }
   }
   wave_sync();
-  return ok;
+  if (lane < NB) rd[lane] = 1.0 / D[lane][lane];
+  wave_sync();
+  return bad >= pb;
+}
+
+// The same as a call (the fused per-front kernel keeps its registers for the panel updates).
+template <int NB>
+__device__ __noinline__ bool wave_diag_lu_call(double *F, int64_t m, int pb, double (*D)[NB + 1],
+                                               double *rd, int lane, int f, int p0, int *status) {
+  return wave_diag_lu<NB>(F, m, pb, D, rd, lane, f, p0, status, true);
 }
 
 // Panel step of the fronts wider than the fused route: every workgroup factors the pb x pb
@@ -216,12 +233,15 @@ __device__ inline bool wave_diag_lu(double *F, int64_t m, int pb, double (*D)[NB
 //   U12 = L11^{-1} A12 column by column (rows p0..pe-1, columns pe..m-1),
 //   L21 = A21 U11^{-1} row by row       (rows pe..m-1, columns p0..pe-1).
 // grid = (item chunks of 256, fronts), at least one chunk; item t < m-pe is a column, else a row.
+// Positions beyond pb load clamped (finite) values; the identity padding of D keeps them out of
+// the first pb results, and only those are stored.
 template <int NB>
 __global__ void __launch_bounds__(256)
 k_panel_trsm(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ fronts,
              const int32_t *__restrict__ p0s, double *__restrict__ store,
              int *__restrict__ status) {
   __shared__ double D[NB][NB + 1];
+  __shared__ double rd[NB];
   const int f = fronts[blockIdx.y];
   const int p0 = p0s[blockIdx.y];
   const FrontDesc d = fd[f];
@@ -231,44 +251,57 @@ k_panel_trsm(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ front
   if (blockIdx.x > 0 && (int)(blockIdx.x * 256) >= 2 * rest) return;   // idle (uniform)
   double *F = store + d.store;
   if (threadIdx.x < 64)
-    wave_diag_lu<NB>(F + (int64_t)p0 * m + p0, m, pb, D, threadIdx.x, f, p0, status,
+    wave_diag_lu<NB>(F + (int64_t)p0 * m + p0, m, pb, D, rd, threadIdx.x, f, p0, status,
                      blockIdx.x == 0);
   __syncthreads();
   if (item >= 2 * rest) return;
   double v[NB];
   if (item < rest) {
-    const int j = pe + item;
+    double *cp = F + (int64_t)p0 * m + pe + item;
 #pragma unroll
-    for (int q = 0; q < NB; ++q) v[q] = q < pb ? F[(int64_t)(p0 + q) * m + j] : 0.0;
+    for (int q = 0; q < NB; ++q) v[q] = cp[(int64_t)min(q, pb - 1) * m];
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
-      if (q < pb) {
-        double s = v[q];
+      double s0 = v[q], s1 = 0.0;
 #pragma unroll
-        for (int r = 0; r < q; ++r) s -= D[q][r] * v[r];
-        v[q] = s / D[q][q];
+      for (int r = 0; r + 1 < q; r += 2) {
+        s0 -= D[q][r] * v[r];
+        s1 -= D[q][r + 1] * v[r + 1];
       }
+      if (q & 1) s0 -= D[q][q - 1] * v[q - 1];
+      v[q] = (s0 + s1) * rd[q];
     }
+    if (pb == NB) {
 #pragma unroll
-    for (int q = 0; q < NB; ++q)
-      if (q < pb) F[(int64_t)(p0 + q) * m + j] = v[q];
+      for (int q = 0; q < NB; ++q) cp[(int64_t)q * m] = v[q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < NB; ++q)
+        if (q < pb) cp[(int64_t)q * m] = v[q];
+    }
   } else {
-    const int i = pe + (item - rest);
-    double *row = F + (int64_t)i * m + p0;
+    double *row = F + (int64_t)(pe + item - rest) * m + p0;
 #pragma unroll
-    for (int q = 0; q < NB; ++q) v[q] = q < pb ? row[q] : 0.0;
+    for (int q = 0; q < NB; ++q) v[q] = row[min(q, pb - 1)];
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
-      if (q < pb) {
-        double s = v[q];
+      double s0 = v[q], s1 = 0.0;
 #pragma unroll
-        for (int r = 0; r < q; ++r) s -= v[r] * D[r][q];
-        v[q] = s;
+      for (int r = 0; r + 1 < q; r += 2) {
+        s0 -= v[r] * D[r][q];
+        s1 -= v[r + 1] * D[r + 1][q];
       }
+      if (q & 1) s0 -= v[q - 1] * D[q - 1][q];
+      v[q] = s0 + s1;
     }
+    if (pb == NB) {
 #pragma unroll
-    for (int q = 0; q < NB; ++q)
-      if (q < pb) row[q] = v[q];
+      for (int q = 0; q < NB; ++q) row[q] = v[q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < NB; ++q)
+        if (q < pb) row[q] = v[q];
+    }
   }
 }
 
@@ -296,7 +329,8 @@ k_front_panels(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ lis
   static_assert(NB % 2 == 0, "two partial sums");
   extern __shared__ double sm[];
   double(*D)[NB + 1] = reinterpret_cast<double(*)[NB + 1]>(sm);
-  double *Lp = sm + NB * (NB + 1);
+  double *rd = sm + NB * (NB + 1);
+  double *Lp = rd + NB;
   __shared__ int bad;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int li = blockIdx.x; li < nlist; li += gridDim.x) {
@@ -307,7 +341,7 @@ k_front_panels(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ lis
     if (tid == 0) bad = 0;
     for (int p0 = 0; p0 < k; p0 += NB) {
       const int pb = min(NB, k - p0), pe = p0 + pb, rest = m - pe;
-      if (wv == 0 && !wave_diag_lu<NB>(F + (int64_t)p0 * m + p0, m, pb, D, lane, f, p0, status))
+      if (wv == 0 && !wave_diag_lu_call<NB>(F + (int64_t)p0 * m + p0, m, pb, D, rd, lane, f, p0, status))
         if (lane == 0) bad = 1;
       __syncthreads();
       if (bad) break;
@@ -346,7 +380,7 @@ k_front_panels(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ lis
             double t = u[q];
 #pragma unroll
             for (int r = 0; r < q; ++r) t -= D[q][r] * u[r];
-            u[q] = t / D[q][q];
+            u[q] = t * rd[q];
           }
         }
 #pragma unroll
@@ -354,7 +388,29 @@ k_front_panels(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ lis
           if (q < pb) colp[(int64_t)q * m] = u[q];
         const int iend = j < k ? m : k;
         double *Cj = F + j;
-        for (int i = pe; i < iend; ++i) {
+        // four rows per round: their loads issue together
+        int i = pe;
+        for (; i + 4 <= iend; i += 4) {
+          double c[4], a0[4], a1[4];
+#pragma unroll
+          for (int w = 0; w < 4; ++w) {
+            c[w] = Cj[(int64_t)(i + w) * m];
+            a0[w] = 0.0;
+            a1[w] = 0.0;
+          }
+#pragma unroll
+          for (int w = 0; w < 4; ++w) {
+            const double *lr = Lp + (i + w - pe) * NB;
+#pragma unroll
+            for (int q = 0; q < NB / 2; ++q) {
+              a0[w] += lr[2 * q] * u[2 * q];
+              a1[w] += lr[2 * q + 1] * u[2 * q + 1];
+            }
+          }
+#pragma unroll
+          for (int w = 0; w < 4; ++w) Cj[(int64_t)(i + w) * m] = c[w] - (a0[w] + a1[w]);
+        }
+        for (; i < iend; ++i) {
           const double *lr = Lp + (i - pe) * NB;
           double a0 = 0.0, a1 = 0.0;
 #pragma unroll

@@ -247,13 +247,26 @@ k_diag_inverse(const FrontDesc *__restrict__ fd, const int2 *__restrict__ tasks,
 // ---------------------------------------------------------------------------------------------
 // One workgroup per front (fronts wider than the wave route), pivots in blocks of NBS.  Per
 // block: the inverse of the diagonal block (staged in LDS) gives the block's unknowns in one
-// matrix-vector product, thread (q, r) forming row q for right-hand side r; then every thread
-// applies them to its remaining rows, with each row's NBS coefficients in registers.  The next
-// block's inverse and the coefficients of a thread's first remaining row of the next block are
-// loaded one block ahead, so their latency overlaps the current block's work.
-// LDS: W (mmax x nc) | M (NBS x NBS+1, the diagonal block's inverse) | Y (NBS x nc).
+// matrix-vector product, thread (q, r) forming row q for right-hand side r; then the remaining
+// rows take the block's contribution.  Coefficients of the remaining rows are read in tiles of
+// kTileRows x NBS, each tile loaded cooperatively so that the lanes of a load run along
+// contiguous memory (along a row of F without TRANS, along a column with TRANS), staged in LDS
+// and applied row per thread; the next tile (and the next block's inverse and first tile) is
+// loaded while the current one is applied.
+// Inner loops run over all NBS positions without bound checks: loads clamp their index into the
+// front (a clamped value only ever meets a zero), W carries NBS zero rows after row m-1, the
+// inverse of a ragged block is identity-padded and Y's unused rows are zero.
+// LDS, right-hand side major (a column r of W is contiguous, so block offsets are immediates):
+// W (nc columns of ldw >= m + NBS, ldw odd) | M (NBS x NBS+1, the block inverse) |
+// T (kTileRows x NBS+1 coefficient tile) | Y (nc x NBS).
 // ---------------------------------------------------------------------------------------------
-__host__ __device__ constexpr int block_solve_fixed_doubles() { return NBS * (NBS + 1); }
+constexpr int kTileRows = 128;
+constexpr int kTileLoads = kTileRows * NBS / 256;
+__host__ __device__ constexpr int block_solve_fixed_doubles() {
+  return NBS * (NBS + 1) + kTileRows * (NBS + 1);
+}
+// doubles of LDS per right-hand-side column for fronts up to mmax wide: W column + Y column
+__host__ __device__ constexpr int block_solve_col_doubles(int mmax) { return ((mmax + NBS) | 1) + NBS; }
 
 constexpr int kInvPerThread = NBS * NBS / 256;
 
@@ -278,6 +291,99 @@ __device__ inline void store_block_inverse(const double *v, int tid, double *Ms)
   }
 }
 
+// Tile element u of this thread: row i (of kTileRows) and column p (of NBS).  Without TRANS a
+// load's lanes run along a row (32 consecutive columns), with TRANS along the rows.
+template <bool TRANS>
+__device__ inline void tile_pos(int tid, int u, int &i, int &p) {
+  const int e = tid + 256 * u;
+  if (TRANS) {
+    i = e % kTileRows;
+    p = e / kTileRows;
+  } else {
+    i = e / NBS;
+    p = e % NBS;
+  }
+}
+
+// Coefficients C(rb + i, c0 + p) of either sweep (cd and cu are the same access:
+// TRANS ? F[col][row] : F[row][col]), rows clamped below r_hi and columns below m.
+template <bool TRANS>
+__device__ inline void tile_load(const double *F, int m, int rb, int r_hi, int c0, int tid,
+                                 double *v) {
+#pragma unroll
+  for (int u = 0; u < kTileLoads; ++u) {
+    int i, p;
+    tile_pos<TRANS>(tid, u, i, p);
+    const int row = min(rb + i, r_hi - 1), col = min(c0 + p, m - 1);
+    v[u] = TRANS ? F[(int64_t)col * m + row] : F[(int64_t)row * m + col];
+  }
+}
+template <bool TRANS>
+__device__ inline void tile_store(const double *v, int tid, double *T) {
+#pragma unroll
+  for (int u = 0; u < kTileLoads; ++u) {
+    int i, p;
+    tile_pos<TRANS>(tid, u, i, p);
+    T[i * (NBS + 1) + p] = v[u];
+  }
+}
+
+// W[r][row] -= sum_p C(row, c0 + p) X[r][p] for rows [r_lo, r_hi) and column blocks c0 in
+// [c_lo, c_hi) (step NBS), X of block c0 at xf(c0) with column stride ldx.  `pre` holds the
+// first tile (r_lo, c_lo), loaded by the caller.  Ends with a barrier.
+template <bool TRANS, typename XF>
+__device__ inline void rect_update(const double *F, int m, int r_lo, int r_hi, int c_lo, int c_hi,
+                                   XF xf, int ldx, double *W, int ldw, int nr, double *T,
+                                   int tid, double *pre) {
+  const int i = tid % kTileRows, r1 = tid / kTileRows;
+  for (int c0 = c_lo; c0 < c_hi; c0 += NBS) {
+    const double *X = xf(c0);
+    for (int rb = r_lo; rb < r_hi; rb += kTileRows) {
+      tile_store<TRANS>(pre, tid, T);
+      int nrb = rb + kTileRows, nc0 = c0;
+      if (nrb >= r_hi) {
+        nrb = r_lo;
+        nc0 = c0 + NBS;
+      }
+      if (nc0 < c_hi) tile_load<TRANS>(F, m, nrb, r_hi, nc0, tid, pre);
+      __syncthreads();
+      if (rb + i < r_hi) {
+        double c[NBS];
+#pragma unroll
+        for (int p = 0; p < NBS; ++p) c[p] = T[i * (NBS + 1) + p];
+        for (int r = r1; r < nr; r += 256 / kTileRows) {
+          const double *xr = X + r * ldx;
+          double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+          for (int p = 0; p < NBS; p += 2) {
+            s0 += c[p] * xr[p];
+            s1 += c[p + 1] * xr[p + 1];
+          }
+          W[r * ldw + rb + i] -= s0 + s1;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Y[r][q] = sum_p M[q][p] W[r][p0 + p] for q < pb, 0 for pb <= q < NBS.
+__device__ inline void block_matvec(const double *Ms, const double *W, int ldw, double *Y, int p0,
+                                    int pb, int nr, int tid) {
+  for (int t = tid; t < NBS * nr; t += 256) {
+    const int r = t / NBS, q = t % NBS;
+    const double *w = W + r * ldw + p0;
+    const double *mq = Ms + q * (NBS + 1);
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int p = 0; p < NBS; p += 2) {
+      s0 += mq[p] * w[p];
+      s1 += mq[p + 1] * w[p + 1];
+    }
+    Y[r * NBS + q] = q < pb ? s0 + s1 : 0.0;
+  }
+}
+
 template <bool TRANS>
 __global__ void __launch_bounds__(256)
 k_solve_down_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ list, int nlist,
@@ -287,9 +393,11 @@ k_solve_down_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__
                    int mmax, const double *__restrict__ dinv,
                    const int64_t *__restrict__ dinv_off) {
   extern __shared__ double sm[];
+  const int ldw = (mmax + NBS) | 1;
   double *W = sm;
-  double *Ms = W + mmax * nc;
-  double *Y = Ms + NBS * (NBS + 1);
+  double *Ms = W + ldw * nc;
+  double *T = Ms + NBS * (NBS + 1);
+  double *Y = T + kTileRows * (NBS + 1);
   const int tid = threadIdx.x;
   for (int li = blockIdx.x; li < nlist; li += gridDim.x) {
     const int f = list[li];
@@ -308,12 +416,11 @@ k_solve_down_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__
     const bool use_a = d.elem < 0 && !passthrough(a), use_c = d.elem < 0 && !passthrough(c);
     for (int r0 = 0; r0 < nrhs; r0 += nc) {
       const int nr = min(nc, nrhs - r0);
-      double mv[kInvPerThread], cf[NBS];
+      double mv[kInvPerThread], pre[kTileLoads];
       if (k > 0) {
         load_block_inverse<TRANS, false>(dv, 0, tid, mv);
-        const int pb = min(NBS, k), i1 = pb + tid;
-#pragma unroll
-        for (int p = 0; p < NBS; ++p) cf[p] = (i1 < m && p < pb) ? cdown<TRANS>(F, m, i1, p) : 0.0;
+        const int pe = min(NBS, k);
+        if (pe < m) tile_load<TRANS>(F, m, pe, m, 0, tid, pre);
       }
       for (int i = tid; i < m; i += 256) {
         const int64_t gi = idx[i];
@@ -322,69 +429,38 @@ k_solve_down_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__
           double v = i < k ? b[gi * nrhs + r0 + r] : 0.0;
           if (x0 >= 0) v += ycb[(a.cbrow + x0) * nrhs + r0 + r];
           if (y0 >= 0) v += ycb[(c.cbrow + y0) * nrhs + r0 + r];
-          W[i * nr + r] = v;
+          W[r * ldw + i] = v;
         }
       }
+      for (int t = tid; t < NBS * nr; t += 256) W[(t / NBS) * ldw + m + t % NBS] = 0.0;
       if (k > 0) store_block_inverse<TRANS>(mv, tid, Ms);
       for (int p0 = 0; p0 < k; p0 += NBS) {
         const int pb = min(NBS, k - p0), pe = p0 + pb;
         __syncthreads();            // rows p0.. of W final, Ms holds this block's inverse
-        // rows pb.. of Y are zero: they meet zero coefficients in the row updates below, and
-        // stale LDS contents must never enter them
-        for (int t = tid; t < NBS * nr; t += 256) {
-          const int q = t / nr, r = t - (t / nr) * nr;
-          double s = 0.0;
-          if (q < pb)
-            for (int p = 0; p < pb; ++p) s += Ms[q * (NBS + 1) + p] * W[(p0 + p) * nr + r];
-          Y[q * nr + r] = s;
-        }
-        // one block ahead: the next inverse, and this thread's first row of the next block
-        double cfn[NBS];
+        block_matvec(Ms, W, ldw, Y, p0, pb, nr, tid);
         const bool more = pe < k;
-        if (more) {
-          load_block_inverse<TRANS, false>(dv, pe, tid, mv);
-          const int pbn = min(NBS, k - pe), i1n = pe + pbn + tid;
-#pragma unroll
-          for (int p = 0; p < NBS; ++p)
-            cfn[p] = (i1n < m && p < pbn) ? cdown<TRANS>(F, m, i1n, pe + p) : 0.0;
-        }
+        if (more) load_block_inverse<TRANS, false>(dv, pe, tid, mv);
         __syncthreads();            // Y complete, every read of Ms and of rows p0..pe-1 done
         for (int t = tid; t < pb * nr; t += 256) {
-          const int q = t / nr, r = t - (t / nr) * nr;
-          W[(p0 + q) * nr + r] = Y[q * nr + r];
+          const int r = t / pb, q = t - (t / pb) * pb;
+          W[r * ldw + p0 + q] = Y[r * NBS + q];
         }
-        const int i1 = pe + tid;
-        if (i1 < m)
-          for (int r = 0; r < nr; ++r) {
-            double s = 0.0;
-#pragma unroll
-            for (int p = 0; p < NBS; ++p) s += cf[p] * Y[p * nr + r];
-            W[i1 * nr + r] -= s;
-          }
-        for (int i = i1 + 256; i < m; i += 256) {
-          double cr[NBS];
-#pragma unroll
-          for (int p = 0; p < NBS; ++p) cr[p] = p < pb ? cdown<TRANS>(F, m, i, p0 + p) : 0.0;
-          for (int r = 0; r < nr; ++r) {
-            double s = 0.0;
-#pragma unroll
-            for (int p = 0; p < NBS; ++p) s += cr[p] * Y[p * nr + r];
-            W[i * nr + r] -= s;
-          }
-        }
+        if (pe < m)
+          rect_update<TRANS>(F, m, pe, m, p0, p0 + 1, [&](int) { return (const double *)Y; },
+                             NBS, W, ldw, nr, T, tid, pre);
         if (more) {
           store_block_inverse<TRANS>(mv, tid, Ms);
-#pragma unroll
-          for (int p = 0; p < NBS; ++p) cf[p] = cfn[p];
+          const int pen = pe + min(NBS, k - pe);
+          if (pen < m) tile_load<TRANS>(F, m, pen, m, pe, tid, pre);
         }
       }
       __syncthreads();
       for (int i = tid; i < m; i += 256) {
         if (i < k) {
           const int64_t gi = idx[i];
-          for (int r = 0; r < nr; ++r) x[gi * nrhs + r0 + r] = W[i * nr + r];
+          for (int r = 0; r < nr; ++r) x[gi * nrhs + r0 + r] = W[r * ldw + i];
         } else {
-          for (int r = 0; r < nr; ++r) ycb[(d.cbrow + i - k) * nrhs + r0 + r] = W[i * nr + r];
+          for (int r = 0; r < nr; ++r) ycb[(d.cbrow + i - k) * nrhs + r0 + r] = W[r * ldw + i];
         }
       }
       __syncthreads();
@@ -399,9 +475,11 @@ k_solve_up_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ l
                  double *x, int nrhs, int nc, int mmax, const double *__restrict__ dinv,
                  const int64_t *__restrict__ dinv_off) {
   extern __shared__ double sm[];
+  const int ldw = (mmax + NBS) | 1;
   double *W = sm;
-  double *Ms = W + mmax * nc;
-  double *Y = Ms + NBS * (NBS + 1);
+  double *Ms = W + ldw * nc;
+  double *T = Ms + NBS * (NBS + 1);
+  double *Y = T + kTileRows * (NBS + 1);
   const int tid = threadIdx.x;
   for (int li = blockIdx.x; li < nlist; li += gridDim.x) {
     const int f = list[li];
@@ -413,100 +491,45 @@ k_solve_up_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ l
     const int plast = k > 0 ? ((k - 1) / NBS) * NBS : 0;
     for (int r0 = 0; r0 < nrhs; r0 += nc) {
       const int nr = min(nc, nrhs - r0);
-      double mv[kInvPerThread], cf[NBS];
-      if (k > 0) {
-        load_block_inverse<TRANS, true>(dv, plast, tid, mv);
-        const int pb = k - plast;
-#pragma unroll
-        for (int p = 0; p < NBS; ++p) cf[p] = (tid < plast && p < pb) ? cup<TRANS>(F, m, tid, plast + p) : 0.0;
-      }
+      double mv[kInvPerThread], pre[kTileLoads];
+      if (k > 0) load_block_inverse<TRANS, true>(dv, plast, tid, mv);
+      if (k > 0 && k < m) tile_load<TRANS>(F, m, 0, k, k, tid, pre);
       for (int i = tid; i < m; i += 256) {
         const int64_t gi = idx[i];
-        for (int r = 0; r < nr; ++r) W[i * nr + r] = x[gi * nrhs + r0 + r];
+        for (int r = 0; r < nr; ++r) W[r * ldw + i] = x[gi * nrhs + r0 + r];
       }
-      __syncthreads();
-      // the already-final CB unknowns applied to the pivot rows, NBS columns at a time, the
-      // next chunk's coefficients loaded while the current one is applied
-      for (int p = tid; p < k; p += 256) {
-        double c0[NBS], c1[NBS];
-#pragma unroll
-        for (int jj = 0; jj < NBS; ++jj) c0[jj] = k + jj < m ? cup<TRANS>(F, m, p, k + jj) : 0.0;
-        for (int j0 = k; j0 < m; j0 += NBS) {
-          const bool nxt = j0 + NBS < m;
-          if (nxt) {
-#pragma unroll
-            for (int jj = 0; jj < NBS; ++jj)
-              c1[jj] = j0 + NBS + jj < m ? cup<TRANS>(F, m, p, j0 + NBS + jj) : 0.0;
-          }
-          for (int r = 0; r < nr; ++r) {
-            double s = 0.0;
-#pragma unroll
-            for (int jj = 0; jj < NBS; ++jj)
-              if (j0 + jj < m) s += c0[jj] * W[(j0 + jj) * nr + r];
-            W[p * nr + r] -= s;
-          }
-          if (nxt) {
-#pragma unroll
-            for (int jj = 0; jj < NBS; ++jj) c0[jj] = c1[jj];
-          }
-        }
+      for (int t = tid; t < NBS * nr; t += 256) W[(t / NBS) * ldw + m + t % NBS] = 0.0;
+      // the already-final CB unknowns applied to the pivot rows (columns beyond m meet W's
+      // zero rows)
+      if (k > 0 && k < m)
+        rect_update<TRANS>(F, m, 0, k, k, m, [&](int c0) { return (const double *)(W + c0); },
+                           ldw, W, ldw, nr, T, tid, pre);
+      if (k > 0) {
+        store_block_inverse<TRANS>(mv, tid, Ms);
+        if (plast > 0) tile_load<TRANS>(F, m, 0, plast, plast, tid, pre);
       }
-      if (k > 0) store_block_inverse<TRANS>(mv, tid, Ms);
       for (int p0 = plast; p0 >= 0 && k > 0; p0 -= NBS) {
         const int pb = min(NBS, k - p0);
         __syncthreads();            // rows p0.. of W final, Ms holds this block's inverse
-        // rows pb.. of Y are zero: they meet zero coefficients in the row updates below, and
-        // stale LDS contents must never enter them
-        for (int t = tid; t < NBS * nr; t += 256) {
-          const int q = t / nr, r = t - (t / nr) * nr;
-          double s = 0.0;
-          if (q < pb)
-            for (int p = 0; p < pb; ++p) s += Ms[q * (NBS + 1) + p] * W[(p0 + p) * nr + r];
-          Y[q * nr + r] = s;
-        }
-        // one block ahead (the previous block of pivots): its inverse and this thread's row
-        // tid's coefficients in that block's columns
-        double cfn[NBS];
+        block_matvec(Ms, W, ldw, Y, p0, pb, nr, tid);
         const bool more = p0 > 0;
-        if (more) {
-          load_block_inverse<TRANS, true>(dv, p0 - NBS, tid, mv);
-#pragma unroll
-          for (int p = 0; p < NBS; ++p)
-            cfn[p] = tid < p0 - NBS ? cup<TRANS>(F, m, tid, p0 - NBS + p) : 0.0;
-        }
+        if (more) load_block_inverse<TRANS, true>(dv, p0 - NBS, tid, mv);
         __syncthreads();            // Y complete, every read of Ms and of rows p0.. done
         for (int t = tid; t < pb * nr; t += 256) {
-          const int q = t / nr, r = t - (t / nr) * nr;
-          W[(p0 + q) * nr + r] = Y[q * nr + r];
-        }
-        if (tid < p0)
-          for (int r = 0; r < nr; ++r) {
-            double s = 0.0;
-#pragma unroll
-            for (int p = 0; p < NBS; ++p) s += cf[p] * Y[p * nr + r];
-            W[tid * nr + r] -= s;
-          }
-        for (int q = tid + 256; q < p0; q += 256) {
-          double cr[NBS];
-#pragma unroll
-          for (int p = 0; p < NBS; ++p) cr[p] = p < pb ? cup<TRANS>(F, m, q, p0 + p) : 0.0;
-          for (int r = 0; r < nr; ++r) {
-            double s = 0.0;
-#pragma unroll
-            for (int p = 0; p < NBS; ++p) s += cr[p] * Y[p * nr + r];
-            W[q * nr + r] -= s;
-          }
+          const int r = t / pb, q = t - (t / pb) * pb;
+          W[r * ldw + p0 + q] = Y[r * NBS + q];
         }
         if (more) {
+          rect_update<TRANS>(F, m, 0, p0, p0, p0 + 1, [&](int) { return (const double *)Y; },
+                             NBS, W, ldw, nr, T, tid, pre);
           store_block_inverse<TRANS>(mv, tid, Ms);
-#pragma unroll
-          for (int p = 0; p < NBS; ++p) cf[p] = cfn[p];
+          if (p0 - NBS > 0) tile_load<TRANS>(F, m, 0, p0 - NBS, p0 - NBS, tid, pre);
         }
       }
       __syncthreads();
       for (int p = tid; p < k; p += 256) {
         const int64_t gp = idx[p];
-        for (int r = 0; r < nr; ++r) x[gp * nrhs + r0 + r] = W[p * nr + r];
+        for (int r = 0; r < nr; ++r) x[gp * nrhs + r0 + r] = W[r * ldw + p];
       }
       __syncthreads();
     }
