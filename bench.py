@@ -18,8 +18,10 @@ bases at 299,209 unknowns, and the CPU oracle on the host (cpu_baseline).
 Prints one JSON line.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import subprocess
 import sys
 import time
@@ -56,18 +58,51 @@ def time_steps(fn, steps, warmup):
     return wall, ev0.elapsed_time(ev1) / 1e3 / steps, out
 
 
+# Source file of each profiled kernel kind (a measured HBM traffic figure is used only while
+# the kernel's source is unchanged since the counters were taken).
+KIND_SOURCE = {
+    "factor_tiny": "factor_kernels.hpp", "factor_small": "factor_kernels.hpp",
+    "assemble": "factor_kernels.hpp", "front_panels": "factor_kernels.hpp",
+    "panel_lu_trsm": "factor_kernels.hpp", "gemm_panel": "factor_kernels.hpp",
+    "gemm_schur": "factor_kernels.hpp", "solve_down_wave": "solve_kernels.hpp",
+    "solve_down_block": "solve_kernels.hpp", "solve_up_wave": "solve_kernels.hpp",
+    "solve_up_block": "solve_kernels.hpp", "diag_block_inverse": "solve_kernels.hpp",
+}
+TRAFFIC_TAG = re.compile(r"<!-- traffic kind=(\S+) source=(\S+) sha256=([0-9a-f]{64}) "
+                         r"bytes_per_launch=([0-9.eE+]+) -->")
+
+
+def measured_traffic(kind):
+    """HBM bytes per launch of `kind` from a committed counter summary under profiles/, if the
+    kernel's source still hashes to what it was when the counters were taken; else None."""
+    src = KIND_SOURCE.get(kind)
+    pdir = os.path.join(ROOT, "profiles")
+    if not src or not os.path.isdir(pdir):
+        return None
+    path = os.path.join(ROOT, "paper_2306_08994_amd", "csrc", src)
+    digest = hashlib.sha256(open(path, "rb").read()).hexdigest()
+    for name in sorted(os.listdir(pdir)):
+        if not name.endswith(".md"):
+            continue
+        for m in TRAFFIC_TAG.finditer(open(os.path.join(pdir, name)).read()):
+            if m.group(1) == kind and m.group(2) == src and m.group(3) == digest:
+                return float(m.group(4))
+    return None
+
+
 def roofline_of(report):
     """Dominant kernel (largest summed event time) and its achieved fraction of peak."""
     ks = report["kernels"]
     top = max(ks, key=lambda k: k["ms"])
     sec = top["ms"] / 1e3
+    traffic = measured_traffic(top["name"])
     if top["name"].startswith("gemm"):
         ach = top["flops"] / sec / 1e12
         return top, {"bound": "mfma", "achieved": ach, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
-                     "frac": ach / FP64_PEAK_TFS, "traffic": None}
+                     "frac": ach / FP64_PEAK_TFS, "traffic": traffic}
     ach = top["bytes"] / sec / 1e9
     return top, {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                 "frac": ach / HBM_PEAK_GBS, "traffic": None}
+                 "frac": ach / HBM_PEAK_GBS, "traffic": traffic}
 
 
 CPU_SNIPPET = r"""
@@ -258,6 +293,12 @@ def main():
         return plan.refine(K, b, tol=1e-12, max_it=5, x=x)
 
     if args.pmc_probe:
+        # launches of each kernel kind in one step (a profiled step), then 3 plain steps: the
+        # counters of a kind are read from its last 3 x launches dispatches
+        plan.profile(True)
+        step()
+        per_step = {k["name"]: k["launches"] for k in plan.profile_report()["kernels"]}
+        plan.profile(False)
         for _ in range(3):
             step()
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)   # 1 GiB
@@ -265,8 +306,8 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         _sync()
-        print(json.dumps({"pmc_probe": True, "copy_bytes": src.numel() * 8,
-                          "schedule": tuned["chosen"]}))
+        print(json.dumps({"pmc_probe": True, "copy_bytes": src.numel() * 8, "plain_steps": 3,
+                          "launches_per_step": per_step, "schedule": tuned["chosen"]}))
         return
     t_step, t_dev, (_, its, rr) = time_steps(step, args.steps, args.warmup)
     t_fac, _, _ = time_steps(lambda: plan.factor(K), args.steps, 1)
