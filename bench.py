@@ -263,6 +263,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--tuning", default=None,
+                    help="tile,fused_max_m,nb,small_max_m: use this schedule instead of autotuning "
+                         "(fused_max_m 0 = fused route off), e.g. for counter runs, where the "
+                         "serialised dispatches distort the autotuner's timings")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="run a few steps and a 1 GiB device copy (HBM counter calibration) only")
     args = ap.parse_args()
@@ -286,7 +290,13 @@ def main():
     x = torch.empty_like(b)
     info = plan.info
     nrhs = p.nrhs
-    tuned = plan.autotune(K, reps=3)          # schedule chosen on this workload, before timing
+    if args.tuning:
+        t_, f_, nb_, sm_ = (int(v) for v in args.tuning.split(","))
+        plan.set_tuning(sm_, nb_, f_ if f_ > 0 else -1, t_)
+        tuned = {"chosen": {"tile": t_, "fused_max_m": f_, "nb": nb_, "small_max_m": sm_,
+                            "given": True}}
+    else:
+        tuned = plan.autotune(K, reps=3)      # schedule chosen on this workload, before timing
 
     def step():
         plan.factor(K)
