@@ -104,6 +104,7 @@ void level_costs(const mf::HostPlan &H, const mf::LevelSchedule &S, LevelDev &D,
         const mf::FrontDesc &x = H.desc[c];
         if (!(x.elem >= 0 && x.k == 0)) ch += x.m - x.k;
       }
+    const double c = m - k;
     D.down_coef += 8 * (m * k - k * (k - 1) / 2);
     D.down_rhs_bytes += 8 * (k + ch + (m - k) + k);
     D.up_coef += 8 * (m * k - k * (k - 1) / 2);
@@ -111,8 +112,24 @@ void level_costs(const mf::HostPlan &H, const mf::LevelSchedule &S, LevelDev &D,
     for (int32_t p = 0; p < d.k; ++p) {
       D.down_rhs_flops += 1 + 2 * (m - p - 1);
       D.up_rhs_flops += 2 * (m - p - 1);
+      D.tri_down_flops += 1 + 2 * (k - p - 1);
+      D.tri_up_flops += 2 * (k - p - 1);
     }
+    D.tri_coef += 8 * (k * (k + 1) / 2);
+    D.tri_down_rhs_bytes += 8 * 3 * k;                 // b and child values in, y out
+    D.tri_up_rhs_bytes += 8 * 2 * k;
+    D.rect_coef += 8 * c * k;
+    D.rect_down_rhs_bytes += 8 * (k + ch + c);         // y in, child values in, CB out
+    D.rect_up_rhs_bytes += 8 * (c + 2 * k);
+    D.rect_flops += 2 * c * k;
   }
+}
+
+// Threads per row of the rectangular-part tasks: columns per group 64 tpr >= the widest row.
+int32_t rect_tpr(int32_t plen) {
+  int32_t t = 1;
+  while (t < 8 && mf::kRectPer * t < plen) t *= 2;
+  return t;
 }
 
 }  // namespace
@@ -181,8 +198,38 @@ int ensure_uploaded(mf_plan *P) {
     tasks.insert(tasks.end(), S.schur.begin(), S.schur.end());
     level_costs(H, S, D, P->tune.nb);
   }
+  // rectangular-part tasks of the classes the block solves handle
+  std::vector<int4> rect;
+  for (size_t l = 0; l < H.levels.size(); ++l) {
+    const mf::LevelSchedule &S = H.levels[l];
+    LevelDev &D = P->lv[l];
+    if (S.max_m <= kWaveSolveMaxM) continue;
+    int32_t kmax = 0, cmax = 0;
+    for (int32_t f : S.all) {
+      kmax = std::max(kmax, H.desc[f].k);
+      cmax = std::max(cmax, H.desc[f].m - H.desc[f].k);
+    }
+    D.tpr_down = rect_tpr(kmax);
+    D.tpr_up = rect_tpr(cmax);
+    const int32_t sd = 256 / D.tpr_down, su = 256 / D.tpr_up;
+    D.rdown = (int64_t)rect.size();
+    for (int32_t f : S.all) {
+      const mf::FrontDesc &d = H.desc[f];
+      for (int32_t r = d.k; r < d.m; r += sd) rect.push_back(make_int4(f, r, std::min(sd, d.m - r), 0));
+    }
+    D.n_rdown = (int64_t)rect.size() - D.rdown;
+    D.rup = (int64_t)rect.size();
+    for (int32_t f : S.all) {
+      const mf::FrontDesc &d = H.desc[f];
+      if (d.m == d.k) continue;
+      for (int32_t r = 0; r < d.k; r += su) rect.push_back(make_int4(f, r, std::min(su, d.k - r), 0));
+    }
+    D.n_rup = (int64_t)rect.size() - D.rup;
+  }
   int rc;
-  if ((rc = upload(P->d_lists, lists)) || (rc = upload(P->d_tasks, tasks))) return rc;
+  if ((rc = upload(P->d_lists, lists)) || (rc = upload(P->d_tasks, tasks)) ||
+      (rc = upload(P->d_rect, rect)))
+    return rc;
   if (!P->static_up) {
     // node -> (element, local node) pairs in ascending element order, for the residual
     std::vector<int64_t> nptr(H.n + 1, 0);
@@ -409,24 +456,54 @@ int launch_solve(mf_plan *P, const double *b, double *x, int32_t nrhs, bool tran
           LAUNCH(K_UP_WAVE, c, mf::k_solve_up_wave<false>, dim3(grid), dim3(256), lds, s, P->d_desc, lst,
                  n, P->d_store, P->d_front_idx, x, nrhs, nc, mmax, cld, ldsw);
       } else {
+        // the pivot block (one workgroup per front, blocks of NBS in sequence) and the
+        // rectangular part (many workgroups): down triangle then rect, up rect then triangle
+        Cost ct, cr;
+        ct.bytes = D.tri_coef + nrhs * (down ? D.tri_down_rhs_bytes : D.tri_up_rhs_bytes);
+        ct.flops = nrhs * (down ? D.tri_down_flops : D.tri_up_flops);
+        cr.bytes = D.rect_coef + nrhs * (down ? D.rect_down_rhs_bytes : D.rect_up_rhs_bytes);
+        cr.flops = nrhs * D.rect_flops;
         const int64_t fixed = mf::block_solve_fixed_doubles();
-        const int nc = chunk(P, nrhs, fixed, mf::block_solve_col_doubles(mmax));
-        const size_t lds = (size_t)(fixed + (int64_t)mf::block_solve_col_doubles(mmax) * nc) * 8;
+        const int nc = chunk(P, nrhs, fixed, mf::block_solve_col_doubles(kmax));
+        const size_t lds = (size_t)(fixed + (int64_t)mf::block_solve_col_doubles(kmax) * nc) * 8;
         const int grid = std::min(n, gridcap);
-        if (down && trans)
-          LAUNCH(K_DOWN_BLOCK, c, mf::k_solve_down_block<true>, dim3(grid), dim3(256), lds, s, P->d_desc,
-                 lst, n, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, b, x, P->d_ycb, nrhs, nc, mmax,
-                 P->d_dinv, P->d_dinv_off);
-        else if (down)
-          LAUNCH(K_DOWN_BLOCK, c, mf::k_solve_down_block<false>, dim3(grid), dim3(256), lds, s, P->d_desc,
-                 lst, n, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, b, x, P->d_ycb, nrhs, nc, mmax,
-                 P->d_dinv, P->d_dinv_off);
-        else if (trans)
-          LAUNCH(K_UP_BLOCK, c, mf::k_solve_up_block<true>, dim3(grid), dim3(256), lds, s, P->d_desc, lst,
-                 n, P->d_store, P->d_front_idx, x, nrhs, nc, mmax, P->d_dinv, P->d_dinv_off);
-        else
-          LAUNCH(K_UP_BLOCK, c, mf::k_solve_up_block<false>, dim3(grid), dim3(256), lds, s, P->d_desc, lst,
-                 n, P->d_store, P->d_front_idx, x, nrhs, nc, mmax, P->d_dinv, P->d_dinv_off);
+        const int tpr = down ? D.tpr_down : D.tpr_up;
+        const int64_t nt = down ? D.n_rdown : D.n_rup;
+        const int4 *rt = P->d_rect + (down ? D.rdown : D.rup);
+        const size_t rlds = (size_t)(mf::kRectPer * tpr + 256) * mf::kRectRhs * 8;
+        if (down) {
+          if (trans)
+            LAUNCH(K_DOWN_BLOCK, ct, mf::k_solve_down_block<true>, dim3(grid), dim3(256), lds, s, P->d_desc,
+                   lst, n, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, b, x, P->d_ycb, nrhs, nc, kmax,
+                   P->d_dinv, P->d_dinv_off);
+          else
+            LAUNCH(K_DOWN_BLOCK, ct, mf::k_solve_down_block<false>, dim3(grid), dim3(256), lds, s, P->d_desc,
+                   lst, n, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, b, x, P->d_ycb, nrhs, nc, kmax,
+                   P->d_dinv, P->d_dinv_off);
+          if (nt) {
+            if (trans)
+              LAUNCH(K_DOWN_RECT, cr, (mf::k_solve_rect<true, false>), dim3((unsigned)nt), dim3(256), rlds, s,
+                     P->d_desc, rt, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, x, P->d_ycb, nrhs, tpr);
+            else
+              LAUNCH(K_DOWN_RECT, cr, (mf::k_solve_rect<false, false>), dim3((unsigned)nt), dim3(256), rlds, s,
+                     P->d_desc, rt, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, x, P->d_ycb, nrhs, tpr);
+          }
+        } else {
+          if (nt) {
+            if (trans)
+              LAUNCH(K_UP_RECT, cr, (mf::k_solve_rect<true, true>), dim3((unsigned)nt), dim3(256), rlds, s,
+                     P->d_desc, rt, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, x, P->d_ycb, nrhs, tpr);
+            else
+              LAUNCH(K_UP_RECT, cr, (mf::k_solve_rect<false, true>), dim3((unsigned)nt), dim3(256), rlds, s,
+                     P->d_desc, rt, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, x, P->d_ycb, nrhs, tpr);
+          }
+          if (trans)
+            LAUNCH(K_UP_BLOCK, ct, mf::k_solve_up_block<true>, dim3(grid), dim3(256), lds, s, P->d_desc, lst,
+                   n, P->d_store, P->d_front_idx, x, nrhs, nc, kmax, P->d_dinv, P->d_dinv_off);
+          else
+            LAUNCH(K_UP_BLOCK, ct, mf::k_solve_up_block<false>, dim3(grid), dim3(256), lds, s, P->d_desc, lst,
+                   n, P->d_store, P->d_front_idx, x, nrhs, nc, kmax, P->d_dinv, P->d_dinv_off);
+        }
       }
     }
   }

@@ -40,12 +40,13 @@ inline int fail(int code, const std::string &msg) {
 
 enum Kind {
   K_TINY, K_SMALL, K_ASSEMBLE, K_FUSED, K_TRSM, K_GEMM_PANEL, K_GEMM_SCHUR,
-  K_DOWN_WAVE, K_DOWN_BLOCK, K_UP_WAVE, K_UP_BLOCK, K_RESIDUAL, K_DIAG_INV, K_OTHER, K_COUNT
+  K_DOWN_WAVE, K_DOWN_BLOCK, K_UP_WAVE, K_UP_BLOCK, K_DOWN_RECT, K_UP_RECT, K_RESIDUAL,
+  K_DIAG_INV, K_OTHER, K_COUNT
 };
 static const char *const kKindName[K_COUNT] = {
     "factor_tiny", "factor_small", "assemble", "front_panels", "panel_lu_trsm", "gemm_panel",
     "gemm_schur", "solve_down_wave", "solve_down_block", "solve_up_wave", "solve_up_block",
-    "residual", "diag_block_inverse", "other"};
+    "solve_down_rect", "solve_up_rect", "residual", "diag_block_inverse", "other"};
 
 // Algorithmic traffic and work of one launch (bytes that must cross HBM at least once, flops
 // of the method's own operation count).
@@ -74,9 +75,16 @@ struct LevelDev {
   std::vector<StepDev> steps;
   int64_t schur = 0, n_schur = 0;
   Cost c_tiny, c_small, c_assemble, c_schur, c_fused;
-  // solves: fixed (coefficient) bytes, bytes and flops per right-hand side
+  // solves: fixed (coefficient) bytes, bytes and flops per right-hand side; for the block
+  // route split into the triangle (pivot block) and the rectangular (contribution) part
   double down_coef = 0, down_rhs_bytes = 0, down_rhs_flops = 0;
   double up_coef = 0, up_rhs_bytes = 0, up_rhs_flops = 0;
+  double tri_coef = 0, tri_down_rhs_bytes = 0, tri_up_rhs_bytes = 0, tri_down_flops = 0,
+         tri_up_flops = 0;
+  double rect_coef = 0, rect_down_rhs_bytes = 0, rect_up_rhs_bytes = 0, rect_flops = 0;
+  // rectangular-part tasks (int4: front, first row, rows, 0) and threads per row
+  int64_t rdown = 0, n_rdown = 0, rup = 0, n_rup = 0;
+  int32_t tpr_down = 1, tpr_up = 1;
 };
 
 struct ProfRec {
@@ -128,6 +136,7 @@ struct mf_plan {
   int32_t *d_nelem = nullptr;
   int32_t *d_lists = nullptr;
   mf::GemmTask *d_tasks = nullptr;
+  int4 *d_rect = nullptr;
   double *d_store = nullptr;
   // inverses of the diagonal blocks of the fronts the block solves handle (see k_diag_inverse)
   double *d_dinv = nullptr;
@@ -176,6 +185,7 @@ struct mf_plan {
     mfapi::dfree(d_nelem);
     mfapi::dfree(d_lists);
     mfapi::dfree(d_tasks);
+    mfapi::dfree(d_rect);
     mfapi::dfree(d_store);
     mfapi::dfree(d_dinv);
     mfapi::dfree(d_dinv_off);

@@ -250,16 +250,27 @@ k_panel_trsm(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ front
   const int item = blockIdx.x * 256 + threadIdx.x;
   if (blockIdx.x > 0 && (int)(blockIdx.x * 256) >= 2 * rest) return;   // idle (uniform)
   double *F = store + d.store;
+  // this thread's column (item < rest) or row, loaded before the diagonal block is factored so
+  // that the load latency overlaps the factorization
+  const bool has = item < 2 * rest, colitem = item < rest;
+  double *cp = F + (int64_t)p0 * m + pe + item;
+  double *row = F + (int64_t)(pe + item - rest) * m + p0;
+  double v[NB];
+  if (has) {
+    if (colitem) {
+#pragma unroll
+      for (int q = 0; q < NB; ++q) v[q] = cp[(int64_t)min(q, pb - 1) * m];
+    } else {
+#pragma unroll
+      for (int q = 0; q < NB; ++q) v[q] = row[min(q, pb - 1)];
+    }
+  }
   if (threadIdx.x < 64)
     wave_diag_lu<NB>(F + (int64_t)p0 * m + p0, m, pb, D, rd, threadIdx.x, f, p0, status,
                      blockIdx.x == 0);
   __syncthreads();
-  if (item >= 2 * rest) return;
-  double v[NB];
-  if (item < rest) {
-    double *cp = F + (int64_t)p0 * m + pe + item;
-#pragma unroll
-    for (int q = 0; q < NB; ++q) v[q] = cp[(int64_t)min(q, pb - 1) * m];
+  if (!has) return;
+  if (colitem) {
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
       double s0 = v[q], s1 = 0.0;
@@ -280,9 +291,6 @@ k_panel_trsm(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ front
         if (q < pb) cp[(int64_t)q * m] = v[q];
     }
   } else {
-    double *row = F + (int64_t)(pe + item - rest) * m + p0;
-#pragma unroll
-    for (int q = 0; q < NB; ++q) v[q] = row[min(q, pb - 1)];
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
       double s0 = v[q], s1 = 0.0;

@@ -265,8 +265,8 @@ constexpr int kTileLoads = kTileRows * NBS / 256;
 __host__ __device__ constexpr int block_solve_fixed_doubles() {
   return NBS * (NBS + 1) + kTileRows * (NBS + 1);
 }
-// doubles of LDS per right-hand-side column for fronts up to mmax wide: W column + Y column
-__host__ __device__ constexpr int block_solve_col_doubles(int mmax) { return ((mmax + NBS) | 1) + NBS; }
+// doubles of LDS per right-hand-side column for up to kmax pivots: W column + Y column
+__host__ __device__ constexpr int block_solve_col_doubles(int kmax) { return ((kmax + NBS) | 1) + NBS; }
 
 constexpr int kInvPerThread = NBS * NBS / 256;
 
@@ -389,11 +389,11 @@ __global__ void __launch_bounds__(256)
 k_solve_down_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ list, int nlist,
                    const double *__restrict__ store, const int32_t *__restrict__ front_idx,
                    const int32_t *__restrict__ inv_l, const int32_t *__restrict__ inv_r,
-                   const double *b, double *x, double *__restrict__ ycb, int nrhs, int nc,
-                   int mmax, const double *__restrict__ dinv,
+                   const double *b, double *x, const double *__restrict__ ycb, int nrhs, int nc,
+                   int kmax, const double *__restrict__ dinv,
                    const int64_t *__restrict__ dinv_off) {
   extern __shared__ double sm[];
-  const int ldw = (mmax + NBS) | 1;
+  const int ldw = (kmax + NBS) | 1;
   double *W = sm;
   double *Ms = W + ldw * nc;
   double *T = Ms + NBS * (NBS + 1);
@@ -403,11 +403,12 @@ k_solve_down_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__
     const int f = list[li];
     const FrontDesc d = fd[f];
     const int m = d.m, k = d.k;
+    if (k == 0) continue;
     const int32_t *idx = front_idx + d.idx;
     const int32_t *il = inv_l + d.idx;
     const int32_t *ir = inv_r + d.idx;
     const double *F = store + d.store;
-    const double *dv = k > 0 ? dinv + dinv_off[f] : nullptr;
+    const double *dv = dinv + dinv_off[f];
     FrontDesc a = d, c = d;
     if (d.elem < 0) {
       a = fd[d.left];
@@ -417,23 +418,20 @@ k_solve_down_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__
     for (int r0 = 0; r0 < nrhs; r0 += nc) {
       const int nr = min(nc, nrhs - r0);
       double mv[kInvPerThread], pre[kTileLoads];
-      if (k > 0) {
-        load_block_inverse<TRANS, false>(dv, 0, tid, mv);
-        const int pe = min(NBS, k);
-        if (pe < m) tile_load<TRANS>(F, m, pe, m, 0, tid, pre);
-      }
-      for (int i = tid; i < m; i += 256) {
+      load_block_inverse<TRANS, false>(dv, 0, tid, mv);
+      if (NBS < k) tile_load<TRANS>(F, m, NBS, k, 0, tid, pre);
+      for (int i = tid; i < k; i += 256) {
         const int64_t gi = idx[i];
         const int x0 = use_a ? il[i] : -1, y0 = use_c ? ir[i] : -1;
         for (int r = 0; r < nr; ++r) {
-          double v = i < k ? b[gi * nrhs + r0 + r] : 0.0;
+          double v = b[gi * nrhs + r0 + r];
           if (x0 >= 0) v += ycb[(a.cbrow + x0) * nrhs + r0 + r];
           if (y0 >= 0) v += ycb[(c.cbrow + y0) * nrhs + r0 + r];
           W[r * ldw + i] = v;
         }
       }
-      for (int t = tid; t < NBS * nr; t += 256) W[(t / NBS) * ldw + m + t % NBS] = 0.0;
-      if (k > 0) store_block_inverse<TRANS>(mv, tid, Ms);
+      for (int t = tid; t < NBS * nr; t += 256) W[(t / NBS) * ldw + k + t % NBS] = 0.0;
+      store_block_inverse<TRANS>(mv, tid, Ms);
       for (int p0 = 0; p0 < k; p0 += NBS) {
         const int pb = min(NBS, k - p0), pe = p0 + pb;
         __syncthreads();            // rows p0.. of W final, Ms holds this block's inverse
@@ -445,23 +443,18 @@ k_solve_down_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__
           const int r = t / pb, q = t - (t / pb) * pb;
           W[r * ldw + p0 + q] = Y[r * NBS + q];
         }
-        if (pe < m)
-          rect_update<TRANS>(F, m, pe, m, p0, p0 + 1, [&](int) { return (const double *)Y; },
-                             NBS, W, ldw, nr, T, tid, pre);
         if (more) {
+          rect_update<TRANS>(F, m, pe, k, p0, p0 + 1, [&](int) { return (const double *)Y; },
+                             NBS, W, ldw, nr, T, tid, pre);
           store_block_inverse<TRANS>(mv, tid, Ms);
           const int pen = pe + min(NBS, k - pe);
-          if (pen < m) tile_load<TRANS>(F, m, pen, m, pe, tid, pre);
+          if (pen < k) tile_load<TRANS>(F, m, pen, k, pe, tid, pre);
         }
       }
       __syncthreads();
-      for (int i = tid; i < m; i += 256) {
-        if (i < k) {
-          const int64_t gi = idx[i];
-          for (int r = 0; r < nr; ++r) x[gi * nrhs + r0 + r] = W[r * ldw + i];
-        } else {
-          for (int r = 0; r < nr; ++r) ycb[(d.cbrow + i - k) * nrhs + r0 + r] = W[r * ldw + i];
-        }
+      for (int i = tid; i < k; i += 256) {
+        const int64_t gi = idx[i];
+        for (int r = 0; r < nr; ++r) x[gi * nrhs + r0 + r] = W[r * ldw + i];
       }
       __syncthreads();
     }
@@ -472,10 +465,10 @@ template <bool TRANS>
 __global__ void __launch_bounds__(256)
 k_solve_up_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ list, int nlist,
                  const double *__restrict__ store, const int32_t *__restrict__ front_idx,
-                 double *x, int nrhs, int nc, int mmax, const double *__restrict__ dinv,
+                 double *x, int nrhs, int nc, int kmax, const double *__restrict__ dinv,
                  const int64_t *__restrict__ dinv_off) {
   extern __shared__ double sm[];
-  const int ldw = (mmax + NBS) | 1;
+  const int ldw = (kmax + NBS) | 1;
   double *W = sm;
   double *Ms = W + ldw * nc;
   double *T = Ms + NBS * (NBS + 1);
@@ -485,30 +478,24 @@ k_solve_up_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ l
     const int f = list[li];
     const FrontDesc d = fd[f];
     const int m = d.m, k = d.k;
+    if (k == 0) continue;
     const int32_t *idx = front_idx + d.idx;
     const double *F = store + d.store;
-    const double *dv = k > 0 ? dinv + dinv_off[f] : nullptr;
-    const int plast = k > 0 ? ((k - 1) / NBS) * NBS : 0;
+    const double *dv = dinv + dinv_off[f];
+    const int plast = ((k - 1) / NBS) * NBS;
     for (int r0 = 0; r0 < nrhs; r0 += nc) {
       const int nr = min(nc, nrhs - r0);
       double mv[kInvPerThread], pre[kTileLoads];
-      if (k > 0) load_block_inverse<TRANS, true>(dv, plast, tid, mv);
-      if (k > 0 && k < m) tile_load<TRANS>(F, m, 0, k, k, tid, pre);
-      for (int i = tid; i < m; i += 256) {
+      load_block_inverse<TRANS, true>(dv, plast, tid, mv);
+      if (plast > 0) tile_load<TRANS>(F, m, 0, plast, plast, tid, pre);
+      // the pivots' values, the contribution of the already-final CB unknowns applied
+      for (int i = tid; i < k; i += 256) {
         const int64_t gi = idx[i];
         for (int r = 0; r < nr; ++r) W[r * ldw + i] = x[gi * nrhs + r0 + r];
       }
-      for (int t = tid; t < NBS * nr; t += 256) W[(t / NBS) * ldw + m + t % NBS] = 0.0;
-      // the already-final CB unknowns applied to the pivot rows (columns beyond m meet W's
-      // zero rows)
-      if (k > 0 && k < m)
-        rect_update<TRANS>(F, m, 0, k, k, m, [&](int c0) { return (const double *)(W + c0); },
-                           ldw, W, ldw, nr, T, tid, pre);
-      if (k > 0) {
-        store_block_inverse<TRANS>(mv, tid, Ms);
-        if (plast > 0) tile_load<TRANS>(F, m, 0, plast, plast, tid, pre);
-      }
-      for (int p0 = plast; p0 >= 0 && k > 0; p0 -= NBS) {
+      for (int t = tid; t < NBS * nr; t += 256) W[(t / NBS) * ldw + k + t % NBS] = 0.0;
+      store_block_inverse<TRANS>(mv, tid, Ms);
+      for (int p0 = plast; p0 >= 0; p0 -= NBS) {
         const int pb = min(NBS, k - p0);
         __syncthreads();            // rows p0.. of W final, Ms holds this block's inverse
         block_matvec(Ms, W, ldw, Y, p0, pb, nr, tid);
@@ -533,6 +520,94 @@ k_solve_up_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ l
       }
       __syncthreads();
     }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// The rectangular part of a wide front's sweep, off the front's sequential block path and
+// spread over many workgroups:
+//   down: the contribution-block rows i in [k, m):  ycb_i = w_i - sum_{p < k} cd(i, p) y_p
+//         (w_i gathered from the children's contribution blocks, y_p = x[idx[p]] as the
+//         triangle kernel of the same class left it);
+//   up:   the pivot rows i in [0, k):  x[idx[i]] -= sum_{p in [k, m)} cu(i, p) x[idx[p]]
+//         (before the triangle kernel of the class).
+// cd and cu are the same access (TRANS ? F[p][i] : F[i][p]).  A task is a slab of output rows
+// of one front; tpr threads share a row, each holding the coefficients of every tpr-th column
+// of a group of 64 tpr columns in registers (all loads of a group in flight at once; lanes run
+// along contiguous memory), the input values of the group in LDS.  The tpr partial sums of a
+// row are combined in a fixed order.  Right-hand sides in chunks of kRectRhs.
+// LDS: V (64 tpr x kRectRhs) | P (256 x kRectRhs).
+// ---------------------------------------------------------------------------------------------
+constexpr int kRectPer = 64;     // coefficients per thread per column group
+constexpr int kRectRhs = 8;
+
+template <bool TRANS, bool UP>
+__global__ void __launch_bounds__(256)
+k_solve_rect(const FrontDesc *__restrict__ fd, const int4 *__restrict__ tasks,
+             const double *__restrict__ store, const int32_t *__restrict__ front_idx,
+             const int32_t *__restrict__ inv_l, const int32_t *__restrict__ inv_r, double *x,
+             double *ycb, int nrhs, int tpr) {
+  extern __shared__ double sm[];
+  const int gcols = kRectPer * tpr;
+  double *V = sm;
+  double *P = sm + gcols * kRectRhs;
+  const int4 tk = tasks[blockIdx.x];
+  const FrontDesc d = fd[tk.x];
+  const int m = d.m, k = d.k, row0 = tk.y, rows = tk.z;
+  const int S = 256 / tpr, tid = threadIdx.x;
+  const int rl = TRANS ? tid % S : tid / tpr, sub = TRANS ? tid / S : tid % tpr;
+  const int i = row0 + min(rl, rows - 1);
+  const int plo = UP ? k : 0, phi = UP ? m : k;
+  const double *F = store + d.store;
+  const int32_t *idx = front_idx + d.idx;
+  for (int r0 = 0; r0 < nrhs; r0 += kRectRhs) {
+    const int nr = min(kRectRhs, nrhs - r0);
+    double acc[kRectRhs];
+#pragma unroll
+    for (int r = 0; r < kRectRhs; ++r) acc[r] = 0.0;
+    for (int c0 = plo; c0 < phi; c0 += gcols) {
+      double c[kRectPer];
+#pragma unroll
+      for (int j = 0; j < kRectPer; ++j) {
+        const int p = min(c0 + sub + tpr * j, phi - 1);
+        c[j] = TRANS ? F[(int64_t)p * m + i] : F[(int64_t)i * m + p];
+      }
+      __syncthreads();          // the previous group's V is no longer read
+      for (int t = tid; t < gcols * kRectRhs; t += 256) {
+        const int p = c0 + t / kRectRhs, r = t % kRectRhs;
+        V[t] = (p < phi && r < nr) ? x[(int64_t)idx[p] * nrhs + r0 + r] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < kRectPer; ++j) {
+        const double *vr = V + (sub + tpr * j) * kRectRhs;
+#pragma unroll
+        for (int r = 0; r < kRectRhs; ++r) acc[r] += c[j] * vr[r];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRectRhs; ++r) P[(rl * tpr + sub) * kRectRhs + r] = acc[r];
+    __syncthreads();
+    for (int t = tid; t < rows * nr; t += 256) {
+      const int q = t / nr, r = t - (t / nr) * nr, row = row0 + q;
+      double sum = 0.0;
+      for (int u = 0; u < tpr; ++u) sum += P[(q * tpr + u) * kRectRhs + r];
+      if (UP) {
+        double *xp = x + (int64_t)idx[row] * nrhs + r0 + r;
+        *xp = *xp - sum;
+      } else {
+        double v = 0.0;
+        if (d.elem < 0) {
+          const FrontDesc a = fd[d.left], cc = fd[d.right];
+          const int xa = inv_l[d.idx + row], xc = inv_r[d.idx + row];
+          if (xa >= 0 && !passthrough(a)) v += ycb[(a.cbrow + xa) * nrhs + r0 + r];
+          if (xc >= 0 && !passthrough(cc)) v += ycb[(cc.cbrow + xc) * nrhs + r0 + r];
+        }
+        ycb[(d.cbrow + row - k) * nrhs + r0 + r] = v - sum;
+      }
+    }
+    __syncthreads();            // P is read before the next chunk writes it
   }
 }
 
