@@ -136,6 +136,8 @@ int32_t rect_tpr(int32_t plen) {
 
 // Fronts of a class whose widest front is above this take the workgroup-per-front block solves.
 constexpr int kWaveSolveMaxM = 64;
+// Largest (m - k) k of a class from which its rectangular part is a launch of its own.
+constexpr int64_t kSplitDownCK = 16384, kSplitUpCK = 8192;
 
 int ensure_uploaded(mf_plan *P) {
   int dev = 0;
@@ -205,25 +207,34 @@ int ensure_uploaded(mf_plan *P) {
     LevelDev &D = P->lv[l];
     if (S.max_m <= kWaveSolveMaxM) continue;
     int32_t kmax = 0, cmax = 0;
+    int64_t ckmax = 0;
     for (int32_t f : S.all) {
-      kmax = std::max(kmax, H.desc[f].k);
-      cmax = std::max(cmax, H.desc[f].m - H.desc[f].k);
+      const mf::FrontDesc &d = H.desc[f];
+      kmax = std::max(kmax, d.k);
+      cmax = std::max(cmax, d.m - d.k);
+      ckmax = std::max<int64_t>(ckmax, (int64_t)(d.m - d.k) * d.k);
     }
+    // a separate launch costs a few dependent memory round trips; it pays once the
+    // rectangular part is large (measured on the 256 x 256 grid: from c k = 16K down, 8K up)
+    D.split_down = ckmax >= kSplitDownCK;
+    D.split_up = ckmax >= kSplitUpCK;
     D.tpr_down = rect_tpr(kmax);
     D.tpr_up = rect_tpr(cmax);
     const int32_t sd = 256 / D.tpr_down, su = 256 / D.tpr_up;
     D.rdown = (int64_t)rect.size();
-    for (int32_t f : S.all) {
-      const mf::FrontDesc &d = H.desc[f];
-      for (int32_t r = d.k; r < d.m; r += sd) rect.push_back(make_int4(f, r, std::min(sd, d.m - r), 0));
-    }
+    if (D.split_down)
+      for (int32_t f : S.all) {
+        const mf::FrontDesc &d = H.desc[f];
+        for (int32_t r = d.k; r < d.m; r += sd) rect.push_back(make_int4(f, r, std::min(sd, d.m - r), 0));
+      }
     D.n_rdown = (int64_t)rect.size() - D.rdown;
     D.rup = (int64_t)rect.size();
-    for (int32_t f : S.all) {
-      const mf::FrontDesc &d = H.desc[f];
-      if (d.m == d.k) continue;
-      for (int32_t r = 0; r < d.k; r += su) rect.push_back(make_int4(f, r, std::min(su, d.k - r), 0));
-    }
+    if (D.split_up)
+      for (int32_t f : S.all) {
+        const mf::FrontDesc &d = H.desc[f];
+        if (d.m == d.k) continue;
+        for (int32_t r = 0; r < d.k; r += su) rect.push_back(make_int4(f, r, std::min(su, d.k - r), 0));
+      }
     D.n_rup = (int64_t)rect.size() - D.rup;
   }
   int rc;
@@ -283,8 +294,14 @@ int ensure_uploaded(mf_plan *P) {
                        (const void *)mf::k_assemble, (const void *)mf::k_front_panels<32>,
                        (const void *)mf::k_solve_down_wave<false>, (const void *)mf::k_solve_down_wave<true>,
                        (const void *)mf::k_solve_up_wave<false>, (const void *)mf::k_solve_up_wave<true>,
-                       (const void *)mf::k_solve_down_block<false>, (const void *)mf::k_solve_down_block<true>,
-                       (const void *)mf::k_solve_up_block<false>, (const void *)mf::k_solve_up_block<true>};
+                       (const void *)mf::k_solve_down_block<false, false>,
+                       (const void *)mf::k_solve_down_block<true, false>,
+                       (const void *)mf::k_solve_down_block<false, true>,
+                       (const void *)mf::k_solve_down_block<true, true>,
+                       (const void *)mf::k_solve_up_block<false, false>,
+                       (const void *)mf::k_solve_up_block<true, false>,
+                       (const void *)mf::k_solve_up_block<false, true>,
+                       (const void *)mf::k_solve_up_block<true, true>};
   for (const void *fn : dyn)
     (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, P->max_shared);
   (void)hipGetLastError();
@@ -463,47 +480,54 @@ int launch_solve(mf_plan *P, const double *b, double *x, int32_t nrhs, bool tran
         ct.flops = nrhs * (down ? D.tri_down_flops : D.tri_up_flops);
         cr.bytes = D.rect_coef + nrhs * (down ? D.rect_down_rhs_bytes : D.rect_up_rhs_bytes);
         cr.flops = nrhs * D.rect_flops;
+        const bool split = down ? D.split_down : D.split_up;
+        const int rmax = split ? kmax : mmax;
+        if (!split) {
+          ct.bytes = (down ? D.down_coef : D.up_coef) + nrhs * (down ? D.down_rhs_bytes : D.up_rhs_bytes);
+          ct.flops = nrhs * (down ? D.down_rhs_flops : D.up_rhs_flops);
+        }
         const int64_t fixed = mf::block_solve_fixed_doubles();
-        const int nc = chunk(P, nrhs, fixed, mf::block_solve_col_doubles(kmax));
-        const size_t lds = (size_t)(fixed + (int64_t)mf::block_solve_col_doubles(kmax) * nc) * 8;
+        const int nc = chunk(P, nrhs, fixed, mf::block_solve_col_doubles(rmax));
+        const size_t lds = (size_t)(fixed + (int64_t)mf::block_solve_col_doubles(rmax) * nc) * 8;
         const int grid = std::min(n, gridcap);
         const int tpr = down ? D.tpr_down : D.tpr_up;
         const int64_t nt = down ? D.n_rdown : D.n_rup;
         const int4 *rt = P->d_rect + (down ? D.rdown : D.rup);
         const size_t rlds = (size_t)(mf::kRectPer * tpr + 256) * mf::kRectRhs * 8;
+#define MF_DOWN_BLOCK(TR, FU)                                                                   \
+  LAUNCH(K_DOWN_BLOCK, ct, (mf::k_solve_down_block<TR, FU>), dim3(grid), dim3(256), lds, s,     \
+         P->d_desc, lst, n, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, b, x, P->d_ycb, \
+         nrhs, nc, rmax, P->d_dinv, P->d_dinv_off)
+#define MF_UP_BLOCK(TR, FU)                                                                     \
+  LAUNCH(K_UP_BLOCK, ct, (mf::k_solve_up_block<TR, FU>), dim3(grid), dim3(256), lds, s,         \
+         P->d_desc, lst, n, P->d_store, P->d_front_idx, x, nrhs, nc, rmax, P->d_dinv,           \
+         P->d_dinv_off)
+#define MF_RECT(KIND, TR, UP)                                                                   \
+  LAUNCH(KIND, cr, (mf::k_solve_rect<TR, UP>), dim3((unsigned)nt), dim3(256), rlds, s,          \
+         P->d_desc, rt, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, x, P->d_ycb, nrhs,  \
+         tpr)
         if (down) {
-          if (trans)
-            LAUNCH(K_DOWN_BLOCK, ct, mf::k_solve_down_block<true>, dim3(grid), dim3(256), lds, s, P->d_desc,
-                   lst, n, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, b, x, P->d_ycb, nrhs, nc, kmax,
-                   P->d_dinv, P->d_dinv_off);
-          else
-            LAUNCH(K_DOWN_BLOCK, ct, mf::k_solve_down_block<false>, dim3(grid), dim3(256), lds, s, P->d_desc,
-                   lst, n, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, b, x, P->d_ycb, nrhs, nc, kmax,
-                   P->d_dinv, P->d_dinv_off);
-          if (nt) {
-            if (trans)
-              LAUNCH(K_DOWN_RECT, cr, (mf::k_solve_rect<true, false>), dim3((unsigned)nt), dim3(256), rlds, s,
-                     P->d_desc, rt, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, x, P->d_ycb, nrhs, tpr);
-            else
-              LAUNCH(K_DOWN_RECT, cr, (mf::k_solve_rect<false, false>), dim3((unsigned)nt), dim3(256), rlds, s,
-                     P->d_desc, rt, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, x, P->d_ycb, nrhs, tpr);
+          if (split) {
+            if (trans) MF_DOWN_BLOCK(true, false); else MF_DOWN_BLOCK(false, false);
+            if (nt) {
+              if (trans) MF_RECT(K_DOWN_RECT, true, false); else MF_RECT(K_DOWN_RECT, false, false);
+            }
+          } else {
+            if (trans) MF_DOWN_BLOCK(true, true); else MF_DOWN_BLOCK(false, true);
           }
         } else {
-          if (nt) {
-            if (trans)
-              LAUNCH(K_UP_RECT, cr, (mf::k_solve_rect<true, true>), dim3((unsigned)nt), dim3(256), rlds, s,
-                     P->d_desc, rt, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, x, P->d_ycb, nrhs, tpr);
-            else
-              LAUNCH(K_UP_RECT, cr, (mf::k_solve_rect<false, true>), dim3((unsigned)nt), dim3(256), rlds, s,
-                     P->d_desc, rt, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, x, P->d_ycb, nrhs, tpr);
+          if (split) {
+            if (nt) {
+              if (trans) MF_RECT(K_UP_RECT, true, true); else MF_RECT(K_UP_RECT, false, true);
+            }
+            if (trans) MF_UP_BLOCK(true, false); else MF_UP_BLOCK(false, false);
+          } else {
+            if (trans) MF_UP_BLOCK(true, true); else MF_UP_BLOCK(false, true);
           }
-          if (trans)
-            LAUNCH(K_UP_BLOCK, ct, mf::k_solve_up_block<true>, dim3(grid), dim3(256), lds, s, P->d_desc, lst,
-                   n, P->d_store, P->d_front_idx, x, nrhs, nc, kmax, P->d_dinv, P->d_dinv_off);
-          else
-            LAUNCH(K_UP_BLOCK, ct, mf::k_solve_up_block<false>, dim3(grid), dim3(256), lds, s, P->d_desc, lst,
-                   n, P->d_store, P->d_front_idx, x, nrhs, nc, kmax, P->d_dinv, P->d_dinv_off);
         }
+#undef MF_DOWN_BLOCK
+#undef MF_UP_BLOCK
+#undef MF_RECT
       }
     }
   }

@@ -85,6 +85,7 @@ struct LevelDev {
   // rectangular-part tasks (int4: front, first row, rows, 0) and threads per row
   int64_t rdown = 0, n_rdown = 0, rup = 0, n_rup = 0;
   int32_t tpr_down = 1, tpr_up = 1;
+  bool split_down = false, split_up = false;   // rectangular part in its own launch
 };
 
 struct ProfRec {

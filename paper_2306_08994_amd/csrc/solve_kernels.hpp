@@ -265,8 +265,8 @@ constexpr int kTileLoads = kTileRows * NBS / 256;
 __host__ __device__ constexpr int block_solve_fixed_doubles() {
   return NBS * (NBS + 1) + kTileRows * (NBS + 1);
 }
-// doubles of LDS per right-hand-side column for up to kmax pivots: W column + Y column
-__host__ __device__ constexpr int block_solve_col_doubles(int kmax) { return ((kmax + NBS) | 1) + NBS; }
+// doubles of LDS per right-hand-side column for up to rmax rows of W: W column + Y column
+__host__ __device__ constexpr int block_solve_col_doubles(int rmax) { return ((rmax + NBS) | 1) + NBS; }
 
 constexpr int kInvPerThread = NBS * NBS / 256;
 
@@ -384,16 +384,20 @@ __device__ inline void block_matvec(const double *Ms, const double *W, int ldw, 
   }
 }
 
-template <bool TRANS>
+// FULL = true: the whole front in one workgroup (rows [0, m): the pivots' triangle, then the
+// contribution rows in the same block loop; up: the contribution columns applied first).
+// FULL = false: the pivots' triangle only; the rectangular part runs in k_solve_rect (after
+// this kernel in the down sweep, before it in the up sweep).
+template <bool TRANS, bool FULL>
 __global__ void __launch_bounds__(256)
 k_solve_down_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ list, int nlist,
                    const double *__restrict__ store, const int32_t *__restrict__ front_idx,
                    const int32_t *__restrict__ inv_l, const int32_t *__restrict__ inv_r,
-                   const double *b, double *x, const double *__restrict__ ycb, int nrhs, int nc,
-                   int kmax, const double *__restrict__ dinv,
+                   const double *b, double *x, double *__restrict__ ycb, int nrhs, int nc,
+                   int rmax, const double *__restrict__ dinv,
                    const int64_t *__restrict__ dinv_off) {
   extern __shared__ double sm[];
-  const int ldw = (kmax + NBS) | 1;
+  const int ldw = (rmax + NBS) | 1;
   double *W = sm;
   double *Ms = W + ldw * nc;
   double *T = Ms + NBS * (NBS + 1);
@@ -403,12 +407,13 @@ k_solve_down_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__
     const int f = list[li];
     const FrontDesc d = fd[f];
     const int m = d.m, k = d.k;
-    if (k == 0) continue;
+    const int rows = FULL ? m : k;          // rows this kernel solves for
+    if (rows == 0) continue;
     const int32_t *idx = front_idx + d.idx;
     const int32_t *il = inv_l + d.idx;
     const int32_t *ir = inv_r + d.idx;
     const double *F = store + d.store;
-    const double *dv = dinv + dinv_off[f];
+    const double *dv = k > 0 ? dinv + dinv_off[f] : nullptr;
     FrontDesc a = d, c = d;
     if (d.elem < 0) {
       a = fd[d.left];
@@ -418,20 +423,23 @@ k_solve_down_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__
     for (int r0 = 0; r0 < nrhs; r0 += nc) {
       const int nr = min(nc, nrhs - r0);
       double mv[kInvPerThread], pre[kTileLoads];
-      load_block_inverse<TRANS, false>(dv, 0, tid, mv);
-      if (NBS < k) tile_load<TRANS>(F, m, NBS, k, 0, tid, pre);
-      for (int i = tid; i < k; i += 256) {
+      if (k > 0) {
+        load_block_inverse<TRANS, false>(dv, 0, tid, mv);
+        const int pe = min(NBS, k);
+        if (pe < rows) tile_load<TRANS>(F, m, pe, rows, 0, tid, pre);
+      }
+      for (int i = tid; i < rows; i += 256) {
         const int64_t gi = idx[i];
         const int x0 = use_a ? il[i] : -1, y0 = use_c ? ir[i] : -1;
         for (int r = 0; r < nr; ++r) {
-          double v = b[gi * nrhs + r0 + r];
+          double v = i < k ? b[gi * nrhs + r0 + r] : 0.0;
           if (x0 >= 0) v += ycb[(a.cbrow + x0) * nrhs + r0 + r];
           if (y0 >= 0) v += ycb[(c.cbrow + y0) * nrhs + r0 + r];
           W[r * ldw + i] = v;
         }
       }
-      for (int t = tid; t < NBS * nr; t += 256) W[(t / NBS) * ldw + k + t % NBS] = 0.0;
-      store_block_inverse<TRANS>(mv, tid, Ms);
+      for (int t = tid; t < NBS * nr; t += 256) W[(t / NBS) * ldw + rows + t % NBS] = 0.0;
+      if (k > 0) store_block_inverse<TRANS>(mv, tid, Ms);
       for (int p0 = 0; p0 < k; p0 += NBS) {
         const int pb = min(NBS, k - p0), pe = p0 + pb;
         __syncthreads();            // rows p0.. of W final, Ms holds this block's inverse
@@ -443,32 +451,37 @@ k_solve_down_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__
           const int r = t / pb, q = t - (t / pb) * pb;
           W[r * ldw + p0 + q] = Y[r * NBS + q];
         }
-        if (more) {
-          rect_update<TRANS>(F, m, pe, k, p0, p0 + 1, [&](int) { return (const double *)Y; },
+        if (pe < rows)
+          rect_update<TRANS>(F, m, pe, rows, p0, p0 + 1, [&](int) { return (const double *)Y; },
                              NBS, W, ldw, nr, T, tid, pre);
+        if (more) {
           store_block_inverse<TRANS>(mv, tid, Ms);
           const int pen = pe + min(NBS, k - pe);
-          if (pen < k) tile_load<TRANS>(F, m, pen, k, pe, tid, pre);
+          if (pen < rows) tile_load<TRANS>(F, m, pen, rows, pe, tid, pre);
         }
       }
       __syncthreads();
-      for (int i = tid; i < k; i += 256) {
-        const int64_t gi = idx[i];
-        for (int r = 0; r < nr; ++r) x[gi * nrhs + r0 + r] = W[r * ldw + i];
+      for (int i = tid; i < rows; i += 256) {
+        if (i < k) {
+          const int64_t gi = idx[i];
+          for (int r = 0; r < nr; ++r) x[gi * nrhs + r0 + r] = W[r * ldw + i];
+        } else {
+          for (int r = 0; r < nr; ++r) ycb[(d.cbrow + i - k) * nrhs + r0 + r] = W[r * ldw + i];
+        }
       }
       __syncthreads();
     }
   }
 }
 
-template <bool TRANS>
+template <bool TRANS, bool FULL>
 __global__ void __launch_bounds__(256)
 k_solve_up_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ list, int nlist,
                  const double *__restrict__ store, const int32_t *__restrict__ front_idx,
-                 double *x, int nrhs, int nc, int kmax, const double *__restrict__ dinv,
+                 double *x, int nrhs, int nc, int rmax, const double *__restrict__ dinv,
                  const int64_t *__restrict__ dinv_off) {
   extern __shared__ double sm[];
-  const int ldw = (kmax + NBS) | 1;
+  const int ldw = (rmax + NBS) | 1;
   double *W = sm;
   double *Ms = W + ldw * nc;
   double *T = Ms + NBS * (NBS + 1);
@@ -479,21 +492,32 @@ k_solve_up_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ l
     const FrontDesc d = fd[f];
     const int m = d.m, k = d.k;
     if (k == 0) continue;
+    const int rows = FULL ? m : k;          // rows of W: the pivots (+ the CB values if FULL)
     const int32_t *idx = front_idx + d.idx;
     const double *F = store + d.store;
     const double *dv = dinv + dinv_off[f];
     const int plast = ((k - 1) / NBS) * NBS;
+    const bool cb = FULL && k < m;
     for (int r0 = 0; r0 < nrhs; r0 += nc) {
       const int nr = min(nc, nrhs - r0);
       double mv[kInvPerThread], pre[kTileLoads];
       load_block_inverse<TRANS, true>(dv, plast, tid, mv);
-      if (plast > 0) tile_load<TRANS>(F, m, 0, plast, plast, tid, pre);
-      // the pivots' values, the contribution of the already-final CB unknowns applied
-      for (int i = tid; i < k; i += 256) {
+      if (cb)
+        tile_load<TRANS>(F, m, 0, k, k, tid, pre);
+      else if (plast > 0)
+        tile_load<TRANS>(F, m, 0, plast, plast, tid, pre);
+      for (int i = tid; i < rows; i += 256) {
         const int64_t gi = idx[i];
         for (int r = 0; r < nr; ++r) W[r * ldw + i] = x[gi * nrhs + r0 + r];
       }
-      for (int t = tid; t < NBS * nr; t += 256) W[(t / NBS) * ldw + k + t % NBS] = 0.0;
+      for (int t = tid; t < NBS * nr; t += 256) W[(t / NBS) * ldw + rows + t % NBS] = 0.0;
+      if (cb) {
+        // the already-final CB unknowns applied to the pivot rows (columns beyond m meet W's
+        // zero rows)
+        rect_update<TRANS>(F, m, 0, k, k, m, [&](int c0) { return (const double *)(W + c0); },
+                           ldw, W, ldw, nr, T, tid, pre);
+        if (plast > 0) tile_load<TRANS>(F, m, 0, plast, plast, tid, pre);
+      }
       store_block_inverse<TRANS>(mv, tid, Ms);
       for (int p0 = plast; p0 >= 0; p0 -= NBS) {
         const int pb = min(NBS, k - p0);
