@@ -98,6 +98,26 @@ int mf_plan_info(const mf_plan *plan, mf_info *out);
 int mf_plan_export_tree(const mf_plan *plan, int32_t *parent, int32_t *level, int64_t *front_ptr,
                         int32_t *front_idx, int32_t *npiv, int64_t *leaf_elem);
 
+/* Scalar-task trace of the factorization and its Foata classes (Sec. 3, Sec. 3.3), a host
+ * analysis for tiny meshes (at most 4096 unknowns and 5e7 tasks).  The tasks: division T1 per
+ * pivot and later entry of its row, multiplication T2 and subtraction T3 per pivot and pair of
+ * later front entries, assertion T4 per global entry; the dependencies J1..J4, subtractions into
+ * one entry ordered by their pivots' elimination order.  out receives the task counts, the
+ * number of Foata classes (every task in the earliest class after its predecessors), how many
+ * of them hold a single task type, the number of classes of the 4-periodic schedule (every task
+ * in the earliest such class congruent to its type: T4 1, T1 2, T2 3, T3 0 mod 4), and whether
+ * the front classes (tree heights) order every dependency between two fronts' tasks.
+ * hist (host, may be NULL) receives hist[c * 4 + t] = tasks of type t (T1, T2, T3, T4) in
+ * Foata class c, for c < cap / 4; needed (may be NULL) the entries it takes, 4 (classes + 1).
+ * Errors: MF_EINVAL (null plan, mesh too large). */
+typedef struct {
+  int64_t tasks[4];
+  int32_t fnf_classes, fnf_single_type_classes, typed_classes, levels_order_dependencies;
+} mf_trace_info;
+
+int mf_task_trace(const mf_plan *plan, mf_trace_info *out, int64_t *hist, int64_t cap,
+                  int64_t *needed);
+
 /* Schedule tuning of an analysed plan (set by mf_autotune, or by hand; defaults otherwise).
  *   small_max_m  fronts of width <= small_max_m are assembled, eliminated and stored by one
  *                workgroup with the front resident in LDS; wider fronts take the tiled path

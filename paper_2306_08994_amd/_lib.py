@@ -13,7 +13,8 @@ MF_FP64, MF_SCHUR_FP32, MF_SCHUR_BF16 = 0, 1, 2
 ERROR_NAMES = {MF_EINVAL: "MF_EINVAL", MF_ENOMEM: "MF_ENOMEM", MF_EZERO_PIVOT: "MF_EZERO_PIVOT",
                MF_EHIP: "MF_EHIP", MF_ENOCONV: "MF_ENOCONV", MF_ESTATE: "MF_ESTATE"}
 
-EXPORTED = ["mf_analyse", "mf_plan_info", "mf_plan_export_tree", "mf_set_tuning", "mf_autotune",
+EXPORTED = ["mf_analyse", "mf_plan_info", "mf_plan_export_tree", "mf_task_trace", "mf_set_tuning",
+            "mf_autotune",
             "mf_factor", "mf_solve",
             "mf_residual", "mf_refine", "mf_elem_grad", "mf_export_factors", "mf_profile",
             "mf_profile_report", "mf_destroy", "mf_last_error"]
@@ -22,6 +23,12 @@ EXPORTED = ["mf_analyse", "mf_plan_info", "mf_plan_export_tree", "mf_set_tuning"
 class MfMesh(ctypes.Structure):
     _fields_ = [("dim", c_int32), ("npe", c_int32), ("n_nodes", c_int64), ("n_elem", c_int64),
                 ("conn", POINTER(c_int32)), ("elem_ijk", POINTER(c_int32))]
+
+
+class MfTraceInfo(ctypes.Structure):
+    _fields_ = [("tasks", c_int64 * 4), ("fnf_classes", c_int32),
+                ("fnf_single_type_classes", c_int32), ("typed_classes", c_int32),
+                ("levels_order_dependencies", c_int32)]
 
 
 class MfInfo(ctypes.Structure):
@@ -55,6 +62,7 @@ def load():
         "mf_plan_info": (c_int32, [P, POINTER(MfInfo)]),
         "mf_plan_export_tree": (c_int32, [P, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                           c_void_p]),
+        "mf_task_trace": (c_int32, [P, POINTER(MfTraceInfo), c_void_p, c_int64, POINTER(c_int64)]),
         "mf_set_tuning": (c_int32, [P, c_int32, c_int32, c_int32, c_int32]),
         "mf_autotune": (c_int32, [P, c_void_p, c_int32, c_int32, c_void_p, c_char_p, c_int64,
                                   POINTER(c_int64)]),

@@ -50,9 +50,12 @@ def build(verbose: bool = False) -> str:
     obj_b = os.path.join(BUILD, "api.o")
     _run(["g++", "-O2", "-std=c++17", "-fPIC", "-c", os.path.join(CSRC, "analyse.cpp"), "-o", obj_a]
          + inc, verbose)
+    obj_t = os.path.join(BUILD, "trace.o")
+    _run(["g++", "-O2", "-std=c++17", "-fPIC", "-c", os.path.join(CSRC, "trace.cpp"), "-o", obj_t]
+         + inc, verbose)
     _run([hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, "api.hip"), "-o", obj_b] + inc, verbose)
     tmp = LIB + ".tmp"
-    _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", obj_a, obj_b, "-o", tmp], verbose)
+    _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", obj_a, obj_t, obj_b, "-o", tmp], verbose)
     os.replace(tmp, LIB)
     return LIB
 

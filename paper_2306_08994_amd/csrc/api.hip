@@ -684,6 +684,23 @@ int mf_plan_export_tree(const mf_plan *P, int32_t *parent, int32_t *level, int64
   return MF_OK;
 }
 
+int mf_task_trace(const mf_plan *P, mf_trace_info *out, int64_t *hist, int64_t cap,
+                  int64_t *needed) {
+  if (!P || !out) return fail(MF_EINVAL, "null plan or output");
+  mf::TraceSummary t;
+  std::vector<int64_t> h;
+  const std::string err = mf::task_trace(P->hp, t, h);
+  if (!err.empty()) return fail(MF_EINVAL, err);
+  for (int i = 0; i < 4; ++i) out->tasks[i] = t.tasks[i];
+  out->fnf_classes = t.fnf_classes;
+  out->fnf_single_type_classes = t.fnf_single_type_classes;
+  out->typed_classes = t.typed_classes;
+  out->levels_order_dependencies = t.levels_order_dependencies;
+  if (needed) *needed = (int64_t)h.size();
+  if (hist && cap > 0) std::memcpy(hist, h.data(), std::min<int64_t>(cap, (int64_t)h.size()) * sizeof(int64_t));
+  return MF_OK;
+}
+
 int mf_set_tuning(mf_plan *P, int32_t small_max_m, int32_t nb, int32_t fused_max_m, int32_t tile) {
   if (!P) return fail(MF_EINVAL, "null plan");
   if (tile != 0 && tile != 32 && tile != 64) return fail(MF_EINVAL, "tile must be 32 or 64");

@@ -19,6 +19,7 @@
 #include "../../include/mf.h"
 #include "common.hpp"
 #include "factor_kernels.hpp"
+#include "trace.hpp"
 #include "plan.hpp"
 #include "solve_kernels.hpp"
 

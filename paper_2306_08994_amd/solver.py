@@ -87,6 +87,24 @@ class Plan:
                                               ptr(out["npiv"]), ptr(out["leaf_elem"])))
         return out
 
+    def task_trace(self) -> dict:
+        """Scalar-task trace of the factorization and its Foata classes (mf_task_trace): task
+        counts, class counts and the per-class histogram hist[c, t] (t: T1, T2, T3, T4)."""
+        lib = _lib.load()
+        info = _lib.MfTraceInfo()
+        need = ctypes.c_int64(0)
+        check(lib.mf_task_trace(self._h, ctypes.byref(info), None, 0, ctypes.byref(need)))
+        hist = np.zeros(int(need.value), np.int64)
+        check(lib.mf_task_trace(self._h, ctypes.byref(info), ctypes.c_void_p(hist.ctypes.data),
+                                int(need.value), ctypes.byref(need)))
+        return {"tasks": {"T1": int(info.tasks[0]), "T2": int(info.tasks[1]),
+                          "T3": int(info.tasks[2]), "T4": int(info.tasks[3])},
+                "fnf_classes": int(info.fnf_classes),
+                "fnf_single_type_classes": int(info.fnf_single_type_classes),
+                "typed_classes": int(info.typed_classes),
+                "front_levels_order_dependencies": bool(info.levels_order_dependencies),
+                "hist": hist.reshape(-1, 4)}
+
     def set_tuning(self, small_max_m: int = 0, nb: int = 0, fused_max_m: int = 0, tile: int = 0):
         """See mf_set_tuning: 0 keeps a value; fused_max_m=-1 disables the fused panel route."""
         self.factor_version += 1
