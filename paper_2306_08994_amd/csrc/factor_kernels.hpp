@@ -167,13 +167,10 @@ __device__ inline double readlane(double v, int l) {
 }
 
 // LU (division tasks scale the pivot row) of the pb x pb diagonal block at F (leading
-// dimension m) by one wave, padded with the identity beyond pb so every step runs
-// unconditionally.  The 64 lanes form an 8 x 8 grid, lane (br, bc) holding the B x B sub-block
-// of rows B br.., columns B bc.. (B = NB / 8) in registers.  At pivot p the lanes that hold
-// column p and row p publish them in LDS (two buffers alternating by step, in the first rows
-// of D); after a wave-level fence every lane reads the pivot, its rows' multipliers and its
-// columns' row entries, scales the row entries by the pivot's reciprocal (the division task)
-// and updates its sub-block -- each step one LDS round trip for the whole wave.
+// dimension m) by one wave, register resident: lane j holds column j of the block, padded with
+// the identity beyond pb so that every step runs unconditionally.  At pivot p every lane reads
+// the pivot and the multiplier column from lane p (readlane), lane j > p divides its U[p][j]
+// and updates its column -- no LDS traffic and no synchronisation inside the block.
 // The factored (padded) block is left in LDS D and the pivots' reciprocals in rd (for the panel
 // solves), and, if writeback, the pb x pb block in F.  Returns false on a bad pivot (the same
 // value on every lane) after recording the first one.
@@ -181,68 +178,40 @@ template <int NB>
 __device__ __forceinline__ bool wave_diag_lu(double *F, int64_t m, int pb, double (*D)[NB + 1],
                                              double *rd, int lane, int f, int p0, int *status,
                                              bool writeback = true) {
-  static_assert(NB % 8 == 0 && NB <= 64, "8 x 8 lanes of square sub-blocks");
-  constexpr int B = NB / 8;
-  const int br = lane >> 3, bc = lane & 7;
-  double a[B][B];
+  static_assert(NB <= 64, "one lane per column");
+  const bool in = lane < pb;
+  const double *src = F + (in ? lane : 0);
+  double col[NB];
 #pragma unroll
-  for (int ii = 0; ii < B; ++ii) {
-    const int i = B * br + ii;
-#pragma unroll
-    for (int jj = 0; jj < B; ++jj) {
-      const int j = B * bc + jj;
-      const double v = F[(int64_t)min(i, pb - 1) * m + min(j, pb - 1)];
-      a[ii][jj] = (i < pb && j < pb) ? v : (i == j ? 1.0 : 0.0);
-    }
+  for (int i = 0; i < NB; ++i) {
+    const double v = src[(int64_t)min(i, pb - 1) * m];
+    col[i] = (in && i < pb) ? v : (i == lane ? 1.0 : 0.0);
   }
   int bad = NB;
 #pragma unroll
   for (int p = 0; p < NB; ++p) {
-    const int pbk = p / B, po = p % B;
-    double *colb = D[(p & 1) * 2];
-    double *rowb = D[(p & 1) * 2 + 1];
-    if (bc == pbk) {
-#pragma unroll
-      for (int ii = 0; ii < B; ++ii) colb[B * br + ii] = a[ii][po];
-    }
-    if (br == pbk) {
-#pragma unroll
-      for (int jj = 0; jj < B; ++jj) rowb[B * bc + jj] = a[po][jj];
-    }
-    wave_sync();
-    const double piv = rowb[p];
+    const double piv = readlane(col[p], p);
     if (bad == NB && !good_pivot(piv)) bad = p;
-    const double rp = 1.0 / piv;
-    double u[B], l[B];
+    const bool act = lane > p;
+    const double u = act ? col[p] / piv : col[p];
+    col[p] = u;
+    const double ua = act ? u : 0.0;
 #pragma unroll
-    for (int jj = 0; jj < B; ++jj) u[jj] = (B * bc + jj > p) ? rowb[B * bc + jj] * rp : 0.0;
-#pragma unroll
-    for (int ii = 0; ii < B; ++ii) l[ii] = (B * br + ii > p) ? colb[B * br + ii] : 0.0;
-    if (br == pbk) {
-#pragma unroll
-      for (int jj = 0; jj < B; ++jj)
-        if (B * bc + jj > p) a[po][jj] = u[jj];
-    }
-#pragma unroll
-    for (int ii = 0; ii < B; ++ii)
-#pragma unroll
-      for (int jj = 0; jj < B; ++jj) a[ii][jj] -= l[ii] * u[jj];
+    for (int i = p + 1; i < NB; ++i) col[i] -= readlane(col[i], p) * ua;
   }
   if (bad < pb && lane == 0) record_bad_pivot(status, f, p0 + bad);
-  wave_sync();
+  if (lane < NB) {
 #pragma unroll
-  for (int ii = 0; ii < B; ++ii)
+    for (int i = 0; i < NB; ++i) D[i][lane] = col[i];
+  }
+  if (writeback && in) {
+    if (pb == NB) {
 #pragma unroll
-    for (int jj = 0; jj < B; ++jj) D[B * br + ii][B * bc + jj] = a[ii][jj];
-  if (writeback) {
+      for (int i = 0; i < NB; ++i) F[i * m + lane] = col[i];
+    } else {
 #pragma unroll
-    for (int ii = 0; ii < B; ++ii) {
-      const int i = B * br + ii;
-#pragma unroll
-      for (int jj = 0; jj < B; ++jj) {
-        const int j = B * bc + jj;
-        if (i < pb && j < pb) F[(int64_t)i * m + j] = a[ii][jj];
-      }
+      for (int i = 0; i < NB; ++i)
+        if (i < pb) F[i * m + lane] = col[i];
     }
   }
   wave_sync();

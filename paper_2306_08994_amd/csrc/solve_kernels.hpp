@@ -328,61 +328,42 @@ __device__ inline void tile_store(const double *v, int tid, double *T) {
   }
 }
 
-// Tiles of a rectangular update over rows [r_lo, r_hi) and column blocks [c_lo, c_hi) are
-// taken column block by column block, row tile by row tile; tile t starts at (rb, c0).
-__device__ inline int row_tiles(int r_lo, int r_hi) { return (r_hi - r_lo + kTileRows - 1) / kTileRows; }
-__device__ inline int n_tiles(int r_lo, int r_hi, int c_lo, int c_hi) {
-  return row_tiles(r_lo, r_hi) * ((c_hi - c_lo + NBS - 1) / NBS);
-}
-// Loads the first two tiles (two tiles are always in flight) into pre0 and pre1.
-template <bool TRANS>
-__device__ inline void tiles_prefetch(const double *F, int m, int r_lo, int r_hi, int c_lo,
-                                      int c_hi, int tid, double *pre0, double *pre1) {
-  const int nrt = row_tiles(r_lo, r_hi), nt = n_tiles(r_lo, r_hi, c_lo, c_hi);
-  if (nt > 0) tile_load<TRANS>(F, m, r_lo, r_hi, c_lo, tid, pre0);
-  if (nt > 1)
-    tile_load<TRANS>(F, m, r_lo + (1 % nrt) * kTileRows, r_hi, c_lo + (1 / nrt) * NBS, tid, pre1);
-}
-
 // W[r][row] -= sum_p C(row, c0 + p) X[r][p] for rows [r_lo, r_hi) and column blocks c0 in
-// [c_lo, c_hi) (step NBS), X of block c0 at xf(c0) with column stride ldx.  Tile t is staged
-// from pre[t mod 2] (the caller loaded tiles 0 and 1, tiles_prefetch); consuming it issues the
-// loads of tile t + 2 into the same buffer.  Ends with a barrier.
+// [c_lo, c_hi) (step NBS), X of block c0 at xf(c0) with column stride ldx.  `pre` holds the
+// first tile (r_lo, c_lo), loaded by the caller.  Ends with a barrier.
 template <bool TRANS, typename XF>
 __device__ inline void rect_update(const double *F, int m, int r_lo, int r_hi, int c_lo, int c_hi,
                                    XF xf, int ldx, double *W, int ldw, int nr, double *T,
-                                   int tid, double *pre0, double *pre1) {
+                                   int tid, double *pre) {
   const int i = tid % kTileRows, r1 = tid / kTileRows;
-  const int nrt = row_tiles(r_lo, r_hi), nt = n_tiles(r_lo, r_hi, c_lo, c_hi);
-  for (int t = 0; t < nt; ++t) {
-    const int rb = r_lo + (t % nrt) * kTileRows, c0 = c_lo + (t / nrt) * NBS;
+  for (int c0 = c_lo; c0 < c_hi; c0 += NBS) {
     const double *X = xf(c0);
-    const int t2 = t + 2;
-    const int rb2 = r_lo + (t2 % nrt) * kTileRows, c2 = c_lo + (t2 / nrt) * NBS;
-    if (t & 1) {
-      tile_store<TRANS>(pre1, tid, T);
-      if (t2 < nt) tile_load<TRANS>(F, m, rb2, r_hi, c2, tid, pre1);
-    } else {
-      tile_store<TRANS>(pre0, tid, T);
-      if (t2 < nt) tile_load<TRANS>(F, m, rb2, r_hi, c2, tid, pre0);
-    }
-    __syncthreads();
-    if (rb + i < r_hi) {
-      double c[NBS];
-#pragma unroll
-      for (int p = 0; p < NBS; ++p) c[p] = T[i * (NBS + 1) + p];
-      for (int r = r1; r < nr; r += 256 / kTileRows) {
-        const double *xr = X + r * ldx;
-        double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-        for (int p = 0; p < NBS; p += 2) {
-          s0 += c[p] * xr[p];
-          s1 += c[p + 1] * xr[p + 1];
-        }
-        W[r * ldw + rb + i] -= s0 + s1;
+    for (int rb = r_lo; rb < r_hi; rb += kTileRows) {
+      tile_store<TRANS>(pre, tid, T);
+      int nrb = rb + kTileRows, nc0 = c0;
+      if (nrb >= r_hi) {
+        nrb = r_lo;
+        nc0 = c0 + NBS;
       }
+      if (nc0 < c_hi) tile_load<TRANS>(F, m, nrb, r_hi, nc0, tid, pre);
+      __syncthreads();
+      if (rb + i < r_hi) {
+        double c[NBS];
+#pragma unroll
+        for (int p = 0; p < NBS; ++p) c[p] = T[i * (NBS + 1) + p];
+        for (int r = r1; r < nr; r += 256 / kTileRows) {
+          const double *xr = X + r * ldx;
+          double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+          for (int p = 0; p < NBS; p += 2) {
+            s0 += c[p] * xr[p];
+            s1 += c[p + 1] * xr[p + 1];
+          }
+          W[r * ldw + rb + i] -= s0 + s1;
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 
@@ -441,11 +422,11 @@ k_solve_down_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__
     const bool use_a = d.elem < 0 && !passthrough(a), use_c = d.elem < 0 && !passthrough(c);
     for (int r0 = 0; r0 < nrhs; r0 += nc) {
       const int nr = min(nc, nrhs - r0);
-      double mv[kInvPerThread], pre0[kTileLoads], pre1[kTileLoads];
+      double mv[kInvPerThread], pre[kTileLoads];
       if (k > 0) {
         load_block_inverse<TRANS, false>(dv, 0, tid, mv);
         const int pe = min(NBS, k);
-        if (pe < rows) tiles_prefetch<TRANS>(F, m, pe, rows, 0, 1, tid, pre0, pre1);
+        if (pe < rows) tile_load<TRANS>(F, m, pe, rows, 0, tid, pre);
       }
       for (int i = tid; i < rows; i += 256) {
         const int64_t gi = idx[i];
@@ -472,11 +453,11 @@ k_solve_down_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__
         }
         if (pe < rows)
           rect_update<TRANS>(F, m, pe, rows, p0, p0 + 1, [&](int) { return (const double *)Y; },
-                             NBS, W, ldw, nr, T, tid, pre0, pre1);
+                             NBS, W, ldw, nr, T, tid, pre);
         if (more) {
           store_block_inverse<TRANS>(mv, tid, Ms);
           const int pen = pe + min(NBS, k - pe);
-          if (pen < rows) tiles_prefetch<TRANS>(F, m, pen, rows, pe, pe + 1, tid, pre0, pre1);
+          if (pen < rows) tile_load<TRANS>(F, m, pen, rows, pe, tid, pre);
         }
       }
       __syncthreads();
@@ -519,12 +500,12 @@ k_solve_up_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ l
     const bool cb = FULL && k < m;
     for (int r0 = 0; r0 < nrhs; r0 += nc) {
       const int nr = min(nc, nrhs - r0);
-      double mv[kInvPerThread], pre0[kTileLoads], pre1[kTileLoads];
+      double mv[kInvPerThread], pre[kTileLoads];
       load_block_inverse<TRANS, true>(dv, plast, tid, mv);
       if (cb)
-        tiles_prefetch<TRANS>(F, m, 0, k, k, m, tid, pre0, pre1);
+        tile_load<TRANS>(F, m, 0, k, k, tid, pre);
       else if (plast > 0)
-        tiles_prefetch<TRANS>(F, m, 0, plast, plast, plast + 1, tid, pre0, pre1);
+        tile_load<TRANS>(F, m, 0, plast, plast, tid, pre);
       for (int i = tid; i < rows; i += 256) {
         const int64_t gi = idx[i];
         for (int r = 0; r < nr; ++r) W[r * ldw + i] = x[gi * nrhs + r0 + r];
@@ -534,8 +515,8 @@ k_solve_up_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ l
         // the already-final CB unknowns applied to the pivot rows (columns beyond m meet W's
         // zero rows)
         rect_update<TRANS>(F, m, 0, k, k, m, [&](int c0) { return (const double *)(W + c0); },
-                           ldw, W, ldw, nr, T, tid, pre0, pre1);
-        if (plast > 0) tiles_prefetch<TRANS>(F, m, 0, plast, plast, plast + 1, tid, pre0, pre1);
+                           ldw, W, ldw, nr, T, tid, pre);
+        if (plast > 0) tile_load<TRANS>(F, m, 0, plast, plast, tid, pre);
       }
       store_block_inverse<TRANS>(mv, tid, Ms);
       for (int p0 = plast; p0 >= 0; p0 -= NBS) {
@@ -551,10 +532,9 @@ k_solve_up_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ l
         }
         if (more) {
           rect_update<TRANS>(F, m, 0, p0, p0, p0 + 1, [&](int) { return (const double *)Y; },
-                             NBS, W, ldw, nr, T, tid, pre0, pre1);
+                             NBS, W, ldw, nr, T, tid, pre);
           store_block_inverse<TRANS>(mv, tid, Ms);
-          if (p0 - NBS > 0)
-            tiles_prefetch<TRANS>(F, m, 0, p0 - NBS, p0 - NBS, p0 - NBS + 1, tid, pre0, pre1);
+          if (p0 - NBS > 0) tile_load<TRANS>(F, m, 0, p0 - NBS, p0 - NBS, tid, pre);
         }
       }
       __syncthreads();
