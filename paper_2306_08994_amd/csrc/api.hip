@@ -125,12 +125,6 @@ void level_costs(const mf::HostPlan &H, const mf::LevelSchedule &S, LevelDev &D,
   }
 }
 
-// Threads per row of the rectangular-part tasks: columns per group 64 tpr >= the widest row.
-int32_t rect_tpr(int32_t plen) {
-  int32_t t = 1;
-  while (t < 8 && mf::kRectPer * t < plen) t *= 2;
-  return t;
-}
 
 }  // namespace
 
@@ -218,9 +212,7 @@ int ensure_uploaded(mf_plan *P) {
     // rectangular part is large (measured on the 256 x 256 grid: from c k = 16K down, 8K up)
     D.split_down = ckmax >= kSplitDownCK;
     D.split_up = ckmax >= kSplitUpCK;
-    D.tpr_down = rect_tpr(kmax);
-    D.tpr_up = rect_tpr(cmax);
-    const int32_t sd = 256 / D.tpr_down, su = 256 / D.tpr_up;
+    const int32_t sd = mf::kRectRows, su = mf::kRectRows;
     D.rdown = (int64_t)rect.size();
     if (D.split_down)
       for (int32_t f : S.all) {
@@ -490,10 +482,9 @@ int launch_solve(mf_plan *P, const double *b, double *x, int32_t nrhs, bool tran
         const int nc = chunk(P, nrhs, fixed, mf::block_solve_col_doubles(rmax));
         const size_t lds = (size_t)(fixed + (int64_t)mf::block_solve_col_doubles(rmax) * nc) * 8;
         const int grid = std::min(n, gridcap);
-        const int tpr = down ? D.tpr_down : D.tpr_up;
         const int64_t nt = down ? D.n_rdown : D.n_rup;
         const int4 *rt = P->d_rect + (down ? D.rdown : D.rup);
-        const size_t rlds = (size_t)(mf::kRectPer * tpr + 256) * mf::kRectRhs * 8;
+        const size_t rlds = (size_t)16 * mf::kRectLdv * 8;
 #define MF_DOWN_BLOCK(TR, FU)                                                                   \
   LAUNCH(K_DOWN_BLOCK, ct, (mf::k_solve_down_block<TR, FU>), dim3(grid), dim3(256), lds, s,     \
          P->d_desc, lst, n, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, b, x, P->d_ycb, \
@@ -504,8 +495,7 @@ int launch_solve(mf_plan *P, const double *b, double *x, int32_t nrhs, bool tran
          P->d_dinv_off)
 #define MF_RECT(KIND, TR, UP)                                                                   \
   LAUNCH(KIND, cr, (mf::k_solve_rect<TR, UP>), dim3((unsigned)nt), dim3(256), rlds, s,          \
-         P->d_desc, rt, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, x, P->d_ycb, nrhs,  \
-         tpr)
+         P->d_desc, rt, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, x, P->d_ycb, nrhs)
         if (down) {
           if (split) {
             if (trans) MF_DOWN_BLOCK(true, false); else MF_DOWN_BLOCK(false, false);

@@ -83,9 +83,8 @@ struct LevelDev {
   double tri_coef = 0, tri_down_rhs_bytes = 0, tri_up_rhs_bytes = 0, tri_down_flops = 0,
          tri_up_flops = 0;
   double rect_coef = 0, rect_down_rhs_bytes = 0, rect_up_rhs_bytes = 0, rect_flops = 0;
-  // rectangular-part tasks (int4: front, first row, rows, 0) and threads per row
+  // rectangular-part tasks (int4: front, first row, rows, 0)
   int64_t rdown = 0, n_rdown = 0, rup = 0, n_rup = 0;
-  int32_t tpr_down = 1, tpr_up = 1;
   bool split_down = false, split_up = false;   // rectangular part in its own launch
 };
 

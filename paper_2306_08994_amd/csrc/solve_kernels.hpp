@@ -328,6 +328,37 @@ __device__ inline void tile_store(const double *v, int tid, double *T) {
   }
 }
 
+// W[r][rb + i] -= sum_p T[i][p] X[r][p] for the kTileRows rows of a staged tile (rows at or
+// beyond r_hi skipped) and the nr right-hand sides, on the matrix cores: wave w takes rows
+// 32 w.. as two 16-row blocks, right-hand sides in blocks of 16 (v_mfma_f64_16x16x4f64: A lane
+// l = row l%16, k l/16; B lane l = column l%16, k l/16; result lane l, register r = row
+// 4r + l/16, column l%16).
+__device__ inline void tile_apply_mfma(const double *T, const double *X, int ldx, double *W,
+                                       int ldw, int rb, int r_hi, int nr, int tid) {
+  static_assert(kTileRows == 128 && NBS % 4 == 0, "four waves of 32 rows");
+  const int lane = tid & 63, wv = tid >> 6, li = lane & 15, lk = lane >> 4;
+  for (int cb = 0; cb < nr; cb += 16) {
+    v4d acc[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+    const int col = cb + li;
+#pragma unroll
+    for (int s = 0; s < NBS / 4; ++s) {
+      const double bv = col < nr ? X[col * ldx + 4 * s + lk] : 0.0;
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const double av = T[(32 * wv + 16 * a + li) * (NBS + 1) + 4 * s + lk];
+        acc[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[a], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = rb + 32 * wv + 16 * a + 4 * r + lk;
+        if (row < r_hi && col < nr) W[col * ldw + row] -= acc[a][r];
+      }
+  }
+}
+
 // W[r][row] -= sum_p C(row, c0 + p) X[r][p] for rows [r_lo, r_hi) and column blocks c0 in
 // [c_lo, c_hi) (step NBS), X of block c0 at xf(c0) with column stride ldx.  `pre` holds the
 // first tile (r_lo, c_lo), loaded by the caller.  Ends with a barrier.
@@ -335,7 +366,6 @@ template <bool TRANS, typename XF>
 __device__ inline void rect_update(const double *F, int m, int r_lo, int r_hi, int c_lo, int c_hi,
                                    XF xf, int ldx, double *W, int ldw, int nr, double *T,
                                    int tid, double *pre) {
-  const int i = tid % kTileRows, r1 = tid / kTileRows;
   for (int c0 = c_lo; c0 < c_hi; c0 += NBS) {
     const double *X = xf(c0);
     for (int rb = r_lo; rb < r_hi; rb += kTileRows) {
@@ -347,40 +377,32 @@ __device__ inline void rect_update(const double *F, int m, int r_lo, int r_hi, i
       }
       if (nc0 < c_hi) tile_load<TRANS>(F, m, nrb, r_hi, nc0, tid, pre);
       __syncthreads();
-      if (rb + i < r_hi) {
-        double c[NBS];
-#pragma unroll
-        for (int p = 0; p < NBS; ++p) c[p] = T[i * (NBS + 1) + p];
-        for (int r = r1; r < nr; r += 256 / kTileRows) {
-          const double *xr = X + r * ldx;
-          double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-          for (int p = 0; p < NBS; p += 2) {
-            s0 += c[p] * xr[p];
-            s1 += c[p + 1] * xr[p + 1];
-          }
-          W[r * ldw + rb + i] -= s0 + s1;
-        }
-      }
+      tile_apply_mfma(T, X, ldx, W, ldw, rb, r_hi, nr, tid);
       __syncthreads();
     }
   }
 }
 
-// Y[r][q] = sum_p M[q][p] W[r][p0 + p] for q < pb, 0 for pb <= q < NBS.
+// Y[r][q] = sum_p M[q][p] W[r][p0 + p] for q < pb, 0 for pb <= q < NBS, on the matrix cores:
+// (wave, 16-column block) pairs over the two 16-row blocks of M and the nr right-hand sides.
 __device__ inline void block_matvec(const double *Ms, const double *W, int ldw, double *Y, int p0,
                                     int pb, int nr, int tid) {
-  for (int t = tid; t < NBS * nr; t += 256) {
-    const int r = t / NBS, q = t % NBS;
-    const double *w = W + r * ldw + p0;
-    const double *mq = Ms + q * (NBS + 1);
-    double s0 = 0.0, s1 = 0.0;
+  const int lane = tid & 63, wv = tid >> 6, li = lane & 15, lk = lane >> 4;
+  const int a = wv & 1;                      // row block of M
+  for (int cb = 16 * (wv >> 1); cb < nr; cb += 32) {
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    const int col = cb + li;
 #pragma unroll
-    for (int p = 0; p < NBS; p += 2) {
-      s0 += mq[p] * w[p];
-      s1 += mq[p + 1] * w[p + 1];
+    for (int s = 0; s < NBS / 4; ++s) {
+      const double bv = col < nr ? W[col * ldw + p0 + 4 * s + lk] : 0.0;
+      const double av = Ms[(16 * a + li) * (NBS + 1) + 4 * s + lk];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
     }
-    Y[r * NBS + q] = q < pb ? s0 + s1 : 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int q = 16 * a + 4 * r + lk;
+      if (col < nr) Y[col * NBS + q] = q < pb ? acc[r] : 0.0;
+    }
   }
 }
 
@@ -555,83 +577,86 @@ k_solve_up_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ l
 //         triangle kernel of the same class left it);
 //   up:   the pivot rows i in [0, k):  x[idx[i]] -= sum_{p in [k, m)} cu(i, p) x[idx[p]]
 //         (before the triangle kernel of the class).
-// cd and cu are the same access (TRANS ? F[p][i] : F[i][p]).  A task is a slab of output rows
-// of one front; tpr threads share a row, each holding the coefficients of every tpr-th column
-// of a group of 64 tpr columns in registers (all loads of a group in flight at once; lanes run
-// along contiguous memory), the input values of the group in LDS.  The tpr partial sums of a
-// row are combined in a fixed order.  Right-hand sides in chunks of kRectRhs.
-// LDS: V (64 tpr x kRectRhs) | P (256 x kRectRhs).
+// cd and cu are the same access (TRANS ? F[p][i] : F[i][p]).  A task is a slab of up to 64
+// output rows of one front; wave w takes 16 of them and computes them on the matrix cores
+// (v_mfma_f64_16x16x4f64, right-hand sides as the 16 columns of B), each lane holding its
+// A-operand coefficients of a group of kRectCols columns in registers, so all loads of a group
+// are in flight at once; the input values of the group sit in LDS.  The values the result is
+// combined with (children's contributions down, the pivots' values up) are loaded at the start.
+// Right-hand sides in chunks of 16.  LDS: V (16 x kRectCols + 4).
 // ---------------------------------------------------------------------------------------------
-constexpr int kRectPer = 64;     // coefficients per thread per column group
-constexpr int kRectRhs = 8;
+constexpr int kRectCols = 256;   // columns per group (64 MFMA steps of 4)
+constexpr int kRectRows = 64;    // output rows per task (4 waves x 16)
+constexpr int kRectLdv = kRectCols + 4;
 
 template <bool TRANS, bool UP>
 __global__ void __launch_bounds__(256)
 k_solve_rect(const FrontDesc *__restrict__ fd, const int4 *__restrict__ tasks,
              const double *__restrict__ store, const int32_t *__restrict__ front_idx,
              const int32_t *__restrict__ inv_l, const int32_t *__restrict__ inv_r, double *x,
-             double *ycb, int nrhs, int tpr) {
+             double *ycb, int nrhs) {
   extern __shared__ double sm[];
-  const int gcols = kRectPer * tpr;
   double *V = sm;
-  double *P = sm + gcols * kRectRhs;
   const int4 tk = tasks[blockIdx.x];
   const FrontDesc d = fd[tk.x];
   const int m = d.m, k = d.k, row0 = tk.y, rows = tk.z;
-  const int S = 256 / tpr, tid = threadIdx.x;
-  const int rl = TRANS ? tid % S : tid / tpr, sub = TRANS ? tid / S : tid % tpr;
-  const int i = row0 + min(rl, rows - 1);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, li = lane & 15, lk = lane >> 4;
   const int plo = UP ? k : 0, phi = UP ? m : k;
   const double *F = store + d.store;
   const int32_t *idx = front_idx + d.idx;
-  for (int r0 = 0; r0 < nrhs; r0 += kRectRhs) {
-    const int nr = min(kRectRhs, nrhs - r0);
-    double acc[kRectRhs];
+  const int arow = row0 + min(16 * wv + li, rows - 1);     // this lane's A-operand row
+  FrontDesc ca = d, cc = d;
+  if (!UP && d.elem < 0) {
+    ca = fd[d.left];
+    cc = fd[d.right];
+  }
+  for (int r0 = 0; r0 < nrhs; r0 += 16) {
+    const int nr = min(16, nrhs - r0), col = li;
+    // the values the product is combined with, for this lane's four result entries
+    double base[4];
 #pragma unroll
-    for (int r = 0; r < kRectRhs; ++r) acc[r] = 0.0;
-    for (int c0 = plo; c0 < phi; c0 += gcols) {
-      double c[kRectPer];
+    for (int r = 0; r < 4; ++r) {
+      const int orow = 16 * wv + 4 * r + lk, row = row0 + orow;
+      base[r] = 0.0;
+      if (orow < rows && col < nr) {
+        if (UP) {
+          base[r] = x[(int64_t)idx[row] * nrhs + r0 + col];
+        } else if (d.elem < 0) {
+          const int xa = inv_l[d.idx + row], xc = inv_r[d.idx + row];
+          if (xa >= 0 && !passthrough(ca)) base[r] += ycb[(ca.cbrow + xa) * nrhs + r0 + col];
+          if (xc >= 0 && !passthrough(cc)) base[r] += ycb[(cc.cbrow + xc) * nrhs + r0 + col];
+        }
+      }
+    }
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    for (int c0 = plo; c0 < phi; c0 += kRectCols) {
+      double av[kRectCols / 4];
 #pragma unroll
-      for (int j = 0; j < kRectPer; ++j) {
-        const int p = min(c0 + sub + tpr * j, phi - 1);
-        c[j] = TRANS ? F[(int64_t)p * m + i] : F[(int64_t)i * m + p];
+      for (int s = 0; s < kRectCols / 4; ++s) {
+        const int p = min(c0 + 4 * s + lk, phi - 1);
+        av[s] = TRANS ? F[(int64_t)p * m + arow] : F[(int64_t)arow * m + p];
       }
       __syncthreads();          // the previous group's V is no longer read
-      for (int t = tid; t < gcols * kRectRhs; t += 256) {
-        const int p = c0 + t / kRectRhs, r = t % kRectRhs;
-        V[t] = (p < phi && r < nr) ? x[(int64_t)idx[p] * nrhs + r0 + r] : 0.0;
+      for (int t = tid; t < 16 * kRectCols; t += 256) {
+        const int r = t / kRectCols, q = t - (t / kRectCols) * kRectCols, p = c0 + q;
+        V[r * kRectLdv + q] = (p < phi && r < nr) ? x[(int64_t)idx[p] * nrhs + r0 + r] : 0.0;
       }
       __syncthreads();
 #pragma unroll
-      for (int j = 0; j < kRectPer; ++j) {
-        const double *vr = V + (sub + tpr * j) * kRectRhs;
+      for (int s = 0; s < kRectCols / 4; ++s)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], V[col * kRectLdv + 4 * s + lk], acc, 0, 0, 0);
+    }
 #pragma unroll
-        for (int r = 0; r < kRectRhs; ++r) acc[r] += c[j] * vr[r];
+    for (int r = 0; r < 4; ++r) {
+      const int orow = 16 * wv + 4 * r + lk, row = row0 + orow;
+      if (orow < rows && col < nr) {
+        if (UP)
+          x[(int64_t)idx[row] * nrhs + r0 + col] = base[r] - acc[r];
+        else
+          ycb[(d.cbrow + row - k) * nrhs + r0 + col] = base[r] - acc[r];
       }
     }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < kRectRhs; ++r) P[(rl * tpr + sub) * kRectRhs + r] = acc[r];
-    __syncthreads();
-    for (int t = tid; t < rows * nr; t += 256) {
-      const int q = t / nr, r = t - (t / nr) * nr, row = row0 + q;
-      double sum = 0.0;
-      for (int u = 0; u < tpr; ++u) sum += P[(q * tpr + u) * kRectRhs + r];
-      if (UP) {
-        double *xp = x + (int64_t)idx[row] * nrhs + r0 + r;
-        *xp = *xp - sum;
-      } else {
-        double v = 0.0;
-        if (d.elem < 0) {
-          const FrontDesc a = fd[d.left], cc = fd[d.right];
-          const int xa = inv_l[d.idx + row], xc = inv_r[d.idx + row];
-          if (xa >= 0 && !passthrough(a)) v += ycb[(a.cbrow + xa) * nrhs + r0 + r];
-          if (xc >= 0 && !passthrough(cc)) v += ycb[(cc.cbrow + xc) * nrhs + r0 + r];
-        }
-        ycb[(d.cbrow + row - k) * nrhs + r0 + r] = v - sum;
-      }
-    }
-    __syncthreads();            // P is read before the next chunk writes it
+    __syncthreads();            // V is rewritten by the next chunk
   }
 }
 
