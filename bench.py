@@ -224,6 +224,34 @@ def variant_l2(steps, warmup):
     return out
 
 
+def variant_table3(steps, warmup):
+    """The 256 x 256 workload with the connectivity-only tree of Table 3 (element fronts sorted
+    by lowest node id, joined in adjacent pairs) instead of nested dissection: the same step,
+    the tree's own operation count."""
+    import torch
+    from fixtures import config_problem
+    from paper_2306_08994_amd import Plan
+    p = config_problem(2)
+    p.meshes[0].ijk = None
+    plan = Plan(p.meshes)
+    K = torch.from_numpy(p.K).cuda()
+    b = torch.from_numpy(p.b).cuda()
+    x = torch.empty_like(b)
+    inf = plan.info
+    flops = inf["factor_flops"] + p.nrhs * inf["solve_flops_per_rhs"]
+    sched = plan.autotune(K, reps=2)["chosen"]
+
+    def step():
+        plan.factor(K)
+        return plan.refine(K, b, tol=1e-12, max_it=5, x=x)
+    wall, dev, (_, its, rr) = time_steps(step, steps, warmup)
+    return {"workload": "2D Q1 256x256 reaction-diffusion, 8 RHS, FP64, tree of Table 3",
+            "fronts": inf["n_fronts"], "classes": inf["height"] + 1, "max_front": inf["max_m"],
+            "factor_flops": inf["factor_flops"], "ms_per_system": wall * 1e3,
+            "gflops": flops / wall / 1e9, "refine_corrections": its, "relres": rr,
+            "schedule": sched}
+
+
 def variant_batched(steps, warmup):
     """256 independent 2D advection-diffusion meshes (sides 32..128) in one batch: every class
     of all meshes in one launch sequence; FP64 and FP32-Schur, refined to 1e-12."""
@@ -358,6 +386,7 @@ def main():
         out["mixed_precision_3d"] = variant_mixed(vs, 2)
         out["batched_256_meshes"] = variant_batched(vs, 2)
         out["l2_projection_p123"] = variant_l2(vs, 2)
+        out["tree_of_table3"] = variant_table3(vs, 2)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

@@ -52,7 +52,9 @@ typedef struct mf_plan mf_plan;   /* opaque: host analysis, device plan, factor 
  *             passed to mf_factor / mf_refine use the same order (the tree depends only on
  *             which nodes an element has, not on their order)
  *   elem_ijk  host [n_elem][dim] integer element coordinates, pairwise distinct; they drive the
- *             nested-dissection bisection of the elimination tree                        */
+ *             nested-dissection bisection of the elimination tree.  NULL: connectivity only,
+ *             the tree of Table 3 (element fronts sorted by lowest node id, joined in adjacent
+ *             pairs round after round, an odd last front carried to the next round)        */
 typedef struct {
   int32_t dim, npe;
   int64_t n_nodes, n_elem;

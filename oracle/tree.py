@@ -11,10 +11,13 @@ owns it alone (Table 2's membership-count condition).  Sec. 3.3 executes the fro
 class in Foata normal form.
 
 Readings taken where the paper is not explicit:
-  * Tree rule: recursive coordinate bisection of the element index box (nested dissection).
+  * Tree rule (meshes with element coordinates): recursive coordinate bisection of the element
+    index box (nested dissection).
     Split the axis with the most elements (ties: lowest axis), cut at lo + floor(len/2), lower
     half is the left child, recurse down to single elements.  Fronts are numbered in post-order
-    (left subtree, right subtree, node).
+    (left subtree, right subtree, node).  Without coordinates (connectivity only) the tree is
+    Table 3 literally: sort the element fronts by lowest node id (ties: element id), join
+    adjacent pairs round after round, carry an odd last front to the next round.
   * Node v is a pivot of front F iff F is the lowest common ancestor of all elements that
     contain v (the first front whose element set holds every element touching v).
   * Contribution block: CB(leaf) = element nodes minus its pivots;
@@ -98,16 +101,42 @@ def _bisect(ijk: np.ndarray, elems: np.ndarray, out: list) -> int:
     return len(out) - 1
 
 
-def _one_mesh(conn: np.ndarray, ijk: np.ndarray, n_nodes: int):
+def _pairing(conn: np.ndarray, out: list) -> int:
+    """Table 3: element fronts sorted by lowest node id (ties: element id), joined in adjacent
+    pairs round after round, an odd last front carried; appends fronts in post-order."""
+    order = sorted(range(conn.shape[0]), key=lambda e: (int(conn[e].min()), e))
+    items = [("leaf", e) for e in order]
+    while len(items) > 1:
+        joined = [(items[i], items[i + 1]) for i in range(0, len(items) - 1, 2)]
+        if len(items) % 2 == 1:
+            joined.append(items[-1])
+        items = joined
+
+    def emit(node) -> int:
+        if node[0] == "leaf":
+            out.append((-1, -1, int(node[1])))
+            return len(out) - 1
+        left = emit(node[0])
+        right = emit(node[1])
+        out.append((left, right, -1))
+        return len(out) - 1
+
+    return emit(items[0])
+
+
+def _one_mesh(conn: np.ndarray, ijk, n_nodes: int):
     E = conn.shape[0]
     if E < 1:
         raise ValueError("empty mesh")
-    if np.unique(ijk, axis=0).shape[0] != E:
+    if ijk is not None and np.unique(ijk, axis=0).shape[0] != E:
         raise ValueError("duplicate element coordinates")
     if conn.min() < 0 or conn.max() >= n_nodes:
         raise ValueError("node id out of range")
     nodes = []
-    _bisect(ijk.astype(np.int64), np.arange(E, dtype=np.int64), nodes)
+    if ijk is None:
+        _pairing(conn, nodes)
+    else:
+        _bisect(np.asarray(ijk).astype(np.int64), np.arange(E, dtype=np.int64), nodes)
     F = len(nodes)
     left = np.array([t[0] for t in nodes], dtype=np.int64)
     right = np.array([t[1] for t in nodes], dtype=np.int64)
@@ -173,8 +202,8 @@ def build_tree(meshes) -> Tree:
     e_off = 0
     for mi, mesh in enumerate(meshes):
         conn = np.asarray(mesh.conn, dtype=np.int64)
-        parent, left, right, elem, level, npiv, lists = _one_mesh(conn, np.asarray(mesh.ijk),
-                                                                 mesh.n_nodes)
+        ijk = None if mesh.ijk is None else np.asarray(mesh.ijk)
+        parent, left, right, elem, level, npiv, lists = _one_mesh(conn, ijk, mesh.n_nodes)
         shift = lambda a: np.where(a >= 0, a + f_off, -1)
         parts["parent"].append(shift(parent))
         parts["left"].append(shift(left))

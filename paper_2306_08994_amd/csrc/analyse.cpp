@@ -2,10 +2,12 @@
 // contribution-block sets, front index lists, extend-add maps and the launch schedule.
 //
 // Tree (Sec. 2.4, Table 3): the leaves are the element matrices and fronts are joined pairwise
-// into a binary tree that follows the mesh.  The pairing used here is recursive coordinate
-// bisection of the element index box: split the axis holding the most elements (ties: the
-// lowest axis) at lo + floor(len/2), lower half first, down to single elements.  Fronts are
-// numbered in post-order, mesh after mesh.
+// into a binary tree that follows the mesh.  With element coordinates the pairing is recursive
+// coordinate bisection of the element index box: split the axis holding the most elements
+// (ties: the lowest axis) at lo + floor(len/2), lower half first, down to single elements.
+// Without them (connectivity only) it is Table 3's rule: sort the element fronts by lowest node
+// id, join adjacent pairs round after round, carry an odd last front.  Fronts are numbered in
+// post-order, mesh after mesh.
 // Pivots (Table 2, Sec. 3.2): a node is eliminated by the first front that holds every element
 // touching it -- the lowest common ancestor of those elements' leaves.
 // Index list of a front: its pivots ascending, then its contribution block (the children's
@@ -65,6 +67,76 @@ int32_t bisect(const int32_t *ijk, int dim, int32_t *elems, int64_t b, int64_t e
   return id;
 }
 
+// Table 3 literally: the element fronts sorted by their lowest node id (ties: element id) are
+// joined in adjacent pairs, round after round, an odd last front carried to the next round,
+// until one front remains.  The tree is then numbered in post-order.
+void pairing_tree(const int32_t *conn, int npe, int64_t ne, MeshTree &t) {
+  std::vector<int64_t> key(ne);
+  for (int64_t e = 0; e < ne; ++e) {
+    int32_t lo = INT32_MAX;
+    for (int a = 0; a < npe; ++a) lo = std::min(lo, conn[e * npe + a]);
+    key[e] = ((int64_t)lo << 32) | (int64_t)e;
+  }
+  std::vector<int32_t> order(ne);
+  std::iota(order.begin(), order.end(), 0);
+  std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+  std::vector<int32_t> L, R, E, items, next;
+  for (int32_t e : order) {
+    items.push_back((int32_t)L.size());
+    L.push_back(-1);
+    R.push_back(-1);
+    E.push_back(e);
+  }
+  while (items.size() > 1) {
+    next.clear();
+    for (size_t i = 0; i + 1 < items.size(); i += 2) {
+      next.push_back((int32_t)L.size());
+      L.push_back(items[i]);
+      R.push_back(items[i + 1]);
+      E.push_back(-1);
+    }
+    if (items.size() % 2 == 1) next.push_back(items.back());
+    items.swap(next);
+  }
+  // post-order renumbering
+  std::vector<int32_t> post(L.size(), -1), lo_of(L.size(), -1);
+  std::vector<std::pair<int32_t, int>> st;
+  st.push_back({items[0], 0});
+  t.left.clear();
+  t.right.clear();
+  t.elem.clear();
+  t.lo.clear();
+  while (!st.empty()) {
+    auto &[v, state] = st.back();
+    if (L[v] >= 0 && state == 0) {
+      state = 1;
+      st.push_back({L[v], 0});
+      continue;
+    }
+    if (L[v] >= 0 && state == 1) {
+      state = 2;
+      st.push_back({R[v], 0});
+      continue;
+    }
+    const int32_t id = (int32_t)t.left.size();
+    post[v] = id;
+    if (L[v] >= 0) {
+      t.left.push_back(post[L[v]]);
+      t.right.push_back(post[R[v]]);
+      t.elem.push_back(-1);
+      t.lo.push_back(lo_of[L[v]]);
+      lo_of[v] = lo_of[L[v]];
+    } else {
+      t.left.push_back(-1);
+      t.right.push_back(-1);
+      t.elem.push_back(E[v]);
+      t.lo.push_back(id);
+      lo_of[v] = id;
+    }
+    st.pop_back();
+  }
+}
+
 }  // namespace
 
 std::string analyse(int32_t n_mesh, const int32_t *dims, const int32_t *npes,
@@ -86,7 +158,7 @@ std::string analyse(int32_t n_mesh, const int32_t *dims, const int32_t *npes,
     }
     if (npes[mi] != P.npe) return "all meshes of a batch must have the same npe";
     if (n_elems[mi] < 1 || n_nodes[mi] < 1) return "mesh " + std::to_string(mi) + ": empty";
-    if (!conns[mi] || !ijks[mi]) return "mesh " + std::to_string(mi) + ": null conn or elem_ijk";
+    if (!conns[mi]) return "mesh " + std::to_string(mi) + ": null conn";
     if (n_elems[mi] > INT32_MAX / 4 || n_nodes[mi] > INT32_MAX / 4)
       return "mesh " + std::to_string(mi) + ": too large";
     P.n += n_nodes[mi];
@@ -130,8 +202,7 @@ std::string analyse(int32_t n_mesh, const int32_t *dims, const int32_t *npes,
     }
     for (int64_t v = 0; v < nn; ++v)
       if (!used[v]) return "mesh " + std::to_string(mi) + ": node " + std::to_string(v) + " is not used";
-    {
-      std::vector<int64_t> key(ne);
+    if (ijk) {
       std::vector<int32_t> ord(ne);
       std::iota(ord.begin(), ord.end(), 0);
       std::sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
@@ -146,9 +217,13 @@ std::string analyse(int32_t n_mesh, const int32_t *dims, const int32_t *npes,
     // tree
     MeshTree T;
     T.left.reserve(2 * ne);
-    std::vector<int32_t> elems(ne);
-    std::iota(elems.begin(), elems.end(), 0);
-    bisect(ijk, dim, elems.data(), 0, ne, T);
+    if (ijk) {
+      std::vector<int32_t> elems(ne);
+      std::iota(elems.begin(), elems.end(), 0);
+      bisect(ijk, dim, elems.data(), 0, ne, T);
+    } else {
+      pairing_tree(conn, npe, ne, T);
+    }
     const int64_t Fm = (int64_t)T.left.size();
     std::vector<int32_t> par(Fm, -1), leaf_of(ne);
     for (int64_t f = 0; f < Fm; ++f) {

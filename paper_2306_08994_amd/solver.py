@@ -35,7 +35,7 @@ class Plan:
     """Analysed elimination tree of one mesh or a batch of meshes (see mf_analyse).
 
     ``meshes``: objects with ``conn`` (E, npe) and ``ijk`` (E, dim) integer arrays, ``dim`` and
-    ``n_nodes`` (``fixtures.Mesh`` satisfies this)."""
+    ``n_nodes`` (``fixtures.Mesh`` satisfies this).  ``ijk`` None: connectivity-only tree."""
 
     def __init__(self, meshes: Sequence):
         lib = _lib.load()
@@ -43,14 +43,15 @@ class Plan:
         arr = (_lib.MfMesh * len(meshes))()
         for i, m in enumerate(meshes):
             conn = np.ascontiguousarray(m.conn, dtype=np.int32)
-            ijk = np.ascontiguousarray(m.ijk, dtype=np.int32)
+            ijk = None if m.ijk is None else np.ascontiguousarray(m.ijk, dtype=np.int32)
             self._keep += [conn, ijk]
             arr[i].dim = int(m.dim)
             arr[i].npe = int(conn.shape[1])
             arr[i].n_nodes = int(m.n_nodes)
             arr[i].n_elem = int(conn.shape[0])
             arr[i].conn = conn.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
-            arr[i].elem_ijk = ijk.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+            arr[i].elem_ijk = (None if ijk is None
+                               else ijk.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
         h = ctypes.c_void_p()
         check(lib.mf_analyse(len(meshes), arr, ctypes.byref(h)))
         self._h = h

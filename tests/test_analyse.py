@@ -49,6 +49,34 @@ def test_high_order_tree_bit_exact(shape, p):
     _compare([structured_qp(shape, p)])
 
 
+def _no_coords(mesh):
+    mesh.ijk = None
+    return mesh
+
+
+@pytest.mark.parametrize("shape,p", [((1, 1), 1), ((3, 1), 1), ((5, 4), 1), ((7, 3), 2),
+                                     ((2, 3, 2), 1), ((16, 16), 1), ((6, 5), 3)])
+def test_connectivity_only_tree_bit_exact(shape, p):
+    """Table 3's pairing (no element coordinates) against the oracle's."""
+    _compare([_no_coords(structured_qp(shape, p))])
+
+
+def test_connectivity_only_relabelled_mesh():
+    """Node ids and element order scrambled: the pairing follows the lowest node ids."""
+    m = structured_q1((6, 5))
+    rng = np.random.default_rng(3)
+    perm = rng.permutation(m.n_nodes)
+    m.conn = perm[m.conn].astype(np.int32)
+    m.conn = m.conn[rng.permutation(m.n_elem)]
+    _compare([_no_coords(m)])
+
+
+def test_connectivity_only_batch_mixed():
+    a = structured_q1((4, 3))
+    b = _no_coords(structured_q1((5, 2)))
+    _compare([a, b])
+
+
 def test_batched_tree_bit_exact():
     p = config_problem(4, n_mesh=6, side_range=(1, 9))
     _compare(p.meshes)

@@ -255,3 +255,45 @@ def test_high_order_residual_and_elem_grad():
     lam = np.random.default_rng(5).normal(size=b.shape)
     gK = plan.elem_grad(torch.from_numpy(lam).to(b.device), xt).cpu().numpy()
     np.testing.assert_allclose(gK, oadj.elem_grad(conn, lam, x), rtol=1e-13, atol=1e-13)
+
+
+def _relabelled(shape, seed):
+    m = structured_q1(shape)
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(m.n_nodes)
+    m.conn = perm[m.conn].astype(np.int32)
+    order = rng.permutation(m.n_elem)
+    m.conn, m.ijk = m.conn[order], None
+    return m
+
+
+@pytest.mark.parametrize("case", ["2d", "3d", "relabelled", "q2"])
+def test_connectivity_only_tree_parity(case):
+    """Trees of Table 3 (connectivity only): uneven heights from carried fronts, fronts joining
+    elements that share no node; factor and both solves against the oracle."""
+    from fixtures import l2_projection
+    from fixtures.mesh import element_matrices, structured_qp
+    rng = np.random.default_rng(11)
+    if case == "2d":
+        m = structured_q1((37, 23))
+    elif case == "3d":
+        m = structured_q1((9, 7, 6))
+    elif case == "q2":
+        m = structured_qp((13, 11), 2)
+    else:
+        m = _relabelled((30, 25), 5)
+    m.ijk = None
+    coef = np.exp(rng.normal(0, 1, m.n_elem))
+    p = reaction_diffusion("t", (1, 1), rng, "lognormal", 1.0, 2)
+    p.meshes = [m]
+    p.K = element_matrices(m, coef)
+    p.coef = coef
+    p.b = rng.normal(size=(m.n_nodes, 3))
+    tree, conn, fac = G.oracle_factor(p)
+    plan, K, b = _setup(p)
+    plan.factor(K)
+    Ls, Us = plan.export_factors()
+    assert G.factor_violation(Ls, Us, fac) <= G.TOL_FACTOR
+    for trans in (False, True):
+        x = plan.solve(b, transpose=trans).cpu().numpy()
+        assert G.rel_err(x, G.oracle_solve(tree, fac, p.b, trans)) <= G.TOL_SOLVE, trans

@@ -201,3 +201,46 @@ def test_flop_counts_config1():
     mul = sum((t.m(f) - p - 1) ** 2 for f in range(t.n_fronts) for p in range(int(t.npiv[f])))
     assert fac == div + 2 * mul
     assert (fac, sol, cb2) == (106228, 14225, 22618)
+
+
+# ---- Table 3 (connectivity only): sort by lowest node id, join adjacent pairs, carry odd ----
+
+def _pairing_tree(shape):
+    m = structured_q1(shape)
+    m.ijk = None
+    return m, build_tree([m])
+
+
+def test_pairing_strip_of_power_of_two_is_bisection():
+    """On a 1 x 2^a strip the lowest-node order is the element order, so pairing adjacent fronts
+    round by round is exactly halving: the bisection tree."""
+    for a in (1, 2, 3, 4):
+        m = structured_q1((1 << a, 1))
+        t_bis = build_tree([m])
+        m2, t_pair = _pairing_tree((1 << a, 1))
+        np.testing.assert_array_equal(t_bis.parent, t_pair.parent)
+        np.testing.assert_array_equal(t_bis.leaf_elem, t_pair.leaf_elem)
+        np.testing.assert_array_equal(t_bis.front_idx, t_pair.front_idx)
+
+
+def test_pairing_carries_the_odd_front():
+    """Five elements in a row: rounds [01][23] 4 -> [0123] 4 -> [[0123] 4].  Post-order ids:
+    e0 0, e1 1, (01) 2, e2 3, e3 4, (23) 5, (0123) 6, e4 7, root 8."""
+    m, t = _pairing_tree((5, 1))
+    np.testing.assert_array_equal(t.parent, [2, 2, 6, 5, 5, 6, 8, 8, -1])
+    np.testing.assert_array_equal(t.leaf_elem, [0, 1, -1, 2, 3, -1, -1, 4, -1])
+    np.testing.assert_array_equal(t.level, [0, 0, 1, 0, 0, 1, 2, 0, 3])
+    # the carried element's own nodes (its far edge) are eliminated at the root only if shared:
+    # node 5 (bottom right corner of e4) belongs to e4 alone -> pivot of its leaf
+    assert 5 in t.pivots(7)
+
+
+@pytest.mark.parametrize("E", [1, 2, 3, 7, 12, 33])
+def test_pairing_counts(E):
+    """F = 2E - 1 fronts and height ceil(log2 E) (each round halves the list, rounding up)."""
+    m, t = _pairing_tree((E, 1))
+    assert t.n_fronts == 2 * E - 1
+    assert t.height == int(np.ceil(np.log2(E))) if E > 1 else t.height == 0
+    # every node is a pivot exactly once
+    piv = np.concatenate([t.pivots(f) for f in range(t.n_fronts)])
+    assert sorted(piv.tolist()) == list(range(m.n_nodes))
