@@ -275,6 +275,11 @@ int ensure_uploaded(mf_plan *P) {
     if (hipMalloc((void **)&P->d_dinv, std::max<int64_t>(1, dtot) * sizeof(double)) != hipSuccess)
       return fail(MF_ENOMEM, "cannot allocate " + std::to_string(dtot * 8) +
                                  " bytes of diagonal-block inverses");
+    // per-front arrival counters of the panel steps (zero between launches, see k_panel_trsm)
+    dfree(P->d_arrive);
+    if (hipMalloc((void **)&P->d_arrive, std::max<int64_t>(1, H.F) * sizeof(int)) != hipSuccess)
+      return fail(MF_ENOMEM, "cannot allocate the panel arrival counters");
+    HIPCHK(hipMemset(P->d_arrive, 0, std::max<int64_t>(1, H.F) * sizeof(int)));
     P->static_up = true;
   }
   if (!P->d_status) HIPCHK(hipMalloc((void **)&P->d_status, mf::kStatusWords * sizeof(int)));
@@ -377,13 +382,16 @@ int launch_factor(mf_plan *P, const double *K, int prec, hipStream_t s) {
         const int32_t *fr = P->d_lists + st.fronts, *p0 = P->d_lists + st.p0;
         switch (P->tune.nb) {
           case 16:
-            LAUNCH(K_TRSM, st.trsm, mf::k_panel_trsm<16>, gt, dim3(256), 0, s, P->d_desc, fr, p0, P->d_store, P->d_status);
+            LAUNCH(K_TRSM, st.trsm, mf::k_panel_trsm<16>, gt, dim3(256), 0, s, P->d_desc, fr, p0, P->d_store, P->d_status,
+                   P->d_arrive);
             break;
           case 64:
-            LAUNCH(K_TRSM, st.trsm, mf::k_panel_trsm<64>, gt, dim3(256), 0, s, P->d_desc, fr, p0, P->d_store, P->d_status);
+            LAUNCH(K_TRSM, st.trsm, mf::k_panel_trsm<64>, gt, dim3(256), 0, s, P->d_desc, fr, p0, P->d_store, P->d_status,
+                   P->d_arrive);
             break;
           default:
-            LAUNCH(K_TRSM, st.trsm, mf::k_panel_trsm<32>, gt, dim3(256), 0, s, P->d_desc, fr, p0, P->d_store, P->d_status);
+            LAUNCH(K_TRSM, st.trsm, mf::k_panel_trsm<32>, gt, dim3(256), 0, s, P->d_desc, fr, p0, P->d_store, P->d_status,
+                   P->d_arrive);
         }
         if (st.n_update) {
           const dim3 g((unsigned)st.n_update);

@@ -146,6 +146,7 @@ struct mf_plan {
   int64_t n_dinv_tasks = 0;
   mfapi::Cost c_dinv;
   int *d_status = nullptr;
+  int *d_arrive = nullptr;    // [F] arrival counters of the panel steps
   int *h_status = nullptr;
   double *d_ycb = nullptr;
   size_t ycb_cap = 0;
@@ -192,6 +193,7 @@ struct mf_plan {
     mfapi::dfree(d_dinv_off);
     mfapi::dfree(d_dinv_tasks);
     mfapi::dfree(d_status);
+    mfapi::dfree(d_arrive);
     mfapi::dfree(d_ycb);
     mfapi::dfree(d_work);
     if (h_status) (void)hipHostFree(h_status);

@@ -228,18 +228,22 @@ __device__ __noinline__ bool wave_diag_lu_call(double *F, int64_t m, int pb, dou
 }
 
 // Panel step of the fronts wider than the fused route: every workgroup factors the pb x pb
-// diagonal block at (p0, p0) itself (wave 0, in LDS; workgroup 0 also stores it), then its
-// threads solve against it:
+// diagonal block at (p0, p0) itself (wave 0, in LDS), then its threads solve against it:
 //   U12 = L11^{-1} A12 column by column (rows p0..pe-1, columns pe..m-1),
 //   L21 = A21 U11^{-1} row by row       (rows pe..m-1, columns p0..pe-1).
 // grid = (item chunks of 256, fronts), at least one chunk; item t < m-pe is a column, else a row.
 // Positions beyond pb load clamped (finite) values; the identity padding of D keeps them out of
 // the first pb results, and only those are stored.
+// The factored diagonal block overwrites the block that the other workgroups of the front read,
+// and a workgroup may start only after another has finished (more workgroups than fit on the
+// chip at once), so the store is left to the workgroup that arrives last: each workgroup counts
+// itself in arrive[f] once its copy is loaded, and the one that sees every other arrival stores
+// the block and resets the counter to zero for the next panel step.
 template <int NB>
 __global__ void __launch_bounds__(256)
 k_panel_trsm(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ fronts,
              const int32_t *__restrict__ p0s, double *__restrict__ store,
-             int *__restrict__ status) {
+             int *__restrict__ status, int *__restrict__ arrive) {
   __shared__ double D[NB][NB + 1];
   __shared__ double rd[NB];
   const int f = fronts[blockIdx.y];
@@ -265,50 +269,69 @@ k_panel_trsm(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ front
       for (int q = 0; q < NB; ++q) v[q] = row[min(q, pb - 1)];
     }
   }
+  // workgroups that take part (the others returned above): at least one
+  const int nact = max(1, (2 * rest + 255) / 256);
   if (threadIdx.x < 64)
     wave_diag_lu<NB>(F + (int64_t)p0 * m + p0, m, pb, D, rd, threadIdx.x, f, p0, status,
-                     blockIdx.x == 0);
+                     nact == 1);
   __syncthreads();
-  if (!has) return;
-  if (colitem) {
+  if (has) {
+    if (colitem) {
 #pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      double s0 = v[q], s1 = 0.0;
+      for (int q = 0; q < NB; ++q) {
+        double s0 = v[q], s1 = 0.0;
 #pragma unroll
-      for (int r = 0; r + 1 < q; r += 2) {
-        s0 -= D[q][r] * v[r];
-        s1 -= D[q][r + 1] * v[r + 1];
+        for (int r = 0; r + 1 < q; r += 2) {
+          s0 -= D[q][r] * v[r];
+          s1 -= D[q][r + 1] * v[r + 1];
+        }
+        if (q & 1) s0 -= D[q][q - 1] * v[q - 1];
+        v[q] = (s0 + s1) * rd[q];
       }
-      if (q & 1) s0 -= D[q][q - 1] * v[q - 1];
-      v[q] = (s0 + s1) * rd[q];
-    }
-    if (pb == NB) {
+      if (pb == NB) {
 #pragma unroll
-      for (int q = 0; q < NB; ++q) cp[(int64_t)q * m] = v[q];
+        for (int q = 0; q < NB; ++q) cp[(int64_t)q * m] = v[q];
+      } else {
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+          if (q < pb) cp[(int64_t)q * m] = v[q];
+      }
     } else {
 #pragma unroll
-      for (int q = 0; q < NB; ++q)
-        if (q < pb) cp[(int64_t)q * m] = v[q];
-    }
-  } else {
+      for (int q = 0; q < NB; ++q) {
+        double s0 = v[q], s1 = 0.0;
 #pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      double s0 = v[q], s1 = 0.0;
-#pragma unroll
-      for (int r = 0; r + 1 < q; r += 2) {
-        s0 -= v[r] * D[r][q];
-        s1 -= v[r + 1] * D[r + 1][q];
+        for (int r = 0; r + 1 < q; r += 2) {
+          s0 -= v[r] * D[r][q];
+          s1 -= v[r + 1] * D[r + 1][q];
+        }
+        if (q & 1) s0 -= v[q - 1] * D[q - 1][q];
+        v[q] = s0 + s1;
       }
-      if (q & 1) s0 -= v[q - 1] * D[q - 1][q];
-      v[q] = s0 + s1;
+      if (pb == NB) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) row[q] = v[q];
+      } else {
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+          if (q < pb) row[q] = v[q];
+      }
     }
-    if (pb == NB) {
-#pragma unroll
-      for (int q = 0; q < NB; ++q) row[q] = v[q];
-    } else {
-#pragma unroll
-      for (int q = 0; q < NB; ++q)
-        if (q < pb) row[q] = v[q];
+  }
+  if (nact > 1 && threadIdx.x < 64) {
+    // every thread of this workgroup is past its reads of the diagonal block (the LU consumed
+    // them before the barrier); count this workgroup and store the block if it is the last
+    int prev = 0;
+    if (threadIdx.x == 0)
+      prev = __hip_atomic_fetch_add(arrive + f, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    prev = __builtin_amdgcn_readlane(prev, 0);
+    if (prev == nact - 1) {
+      const int lane = threadIdx.x;
+      if (lane < pb) {
+        double *dst = F + (int64_t)p0 * m + p0 + lane;
+        for (int i = 0; i < pb; ++i) dst[(int64_t)i * m] = D[i][lane];
+      }
+      if (lane == 0) __hip_atomic_store(arrive + f, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }

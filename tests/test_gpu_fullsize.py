@@ -179,6 +179,36 @@ def test_profile_report():
         assert k["ms"] > 0 and k["launches"] > 0
 
 
+def test_connectivity_only_tree_full_size():
+    """The 256 x 256 model problem on the Table 3 tree (no element coordinates).  Its class of
+    height 9 holds 126 fronts of width 771 whose panel steps launch more workgroups than the
+    chip holds at once, so workgroups of one front run one after another: every front of the
+    classes up to height 12 (all of their subtrees) against the oracle, then the residual."""
+    import torch
+    from paper_2306_08994_amd import Plan
+    dev = G.torch_dev()
+    p = config_problem(2)
+    for m in p.meshes:
+        m.ijk = None
+    tree = build_tree(p.meshes)
+    conn = ofac.global_connectivity(p)
+    plan = Plan(p.meshes)
+    plan.set_tuning(64, 32, -1, 32)
+    K = torch.from_numpy(p.K).to(dev)
+    b = torch.from_numpy(p.b).to(dev)
+    plan.factor(K)
+    Ls, Us = plan.export_factors()
+    L, U = _subtree_oracle(tree, p, conn, [int(f) for f in np.flatnonzero(tree.level == 12)])
+    worst = max(max(G.front_violation(Ls[f], L[f]), G.front_violation(Us[f], U[f])) for f in L)
+    assert worst <= G.TOL_FACTOR, worst
+    x0 = plan.solve(b)
+    rr0 = G.relres(p, conn, x0.cpu().numpy())
+    assert rr0 <= 1e-10, rr0
+    x, its, rr = plan.refine(K, b, tol=1e-12, max_it=5)
+    assert rr <= 1e-12
+    print(f"Table 3 tree 256x256: {len(L)} fronts {worst:.1e}, direct relres {rr0:.2e}")
+
+
 @pytest.mark.parametrize("deg", [1, 2, 3])
 def test_l2_projection_full_size(deg):
     """The paper's benchmark axis at its largest size (Sec. 5): L2 projection with linear,
