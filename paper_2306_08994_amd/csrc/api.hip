@@ -573,9 +573,10 @@ int run_graphed(mf_plan *P, Graph *cache, int n_cache, int &next, const GraphKey
 }
 
 // Column 2-norms of up to two [n][nrhs] device arrays with one host synchronisation.
+constexpr int64_t kNormRows = 512;   // rows per partial sum
 int col_norms(mf_plan *P, const double *a0, const double *a1, int64_t n, int32_t nrhs,
               hipStream_t s, std::vector<double> *out0, std::vector<double> *out1) {
-  const int64_t rows_per = 4096;
+  const int64_t rows_per = kNormRows;
   const int64_t blocks = std::max<int64_t>(1, (n + rows_per - 1) / rows_per);
   const size_t per = (size_t)blocks * nrhs;
   const int cnt = a1 ? 2 : 1;
@@ -784,7 +785,7 @@ int mf_refine(const mf_plan *Pc, const double *elem_mats, const double *b, doubl
   hipStream_t s = (hipStream_t)hip_stream;
   const int64_t n = P->hp.n;
   const size_t nn = (size_t)n * nrhs;
-  const size_t parts = (size_t)std::max<int64_t>(1, (n + 4095) / 4096) * nrhs;
+  const size_t parts = (size_t)std::max<int64_t>(1, (n + kNormRows - 1) / kNormRows) * nrhs;
   int rc;
   if ((rc = grow(P, P->d_work, P->work_cap, 2 * nn + 2 * parts))) return rc;
   double *r = P->d_work, *dx = P->d_work + nn;

@@ -687,12 +687,31 @@ k_residual(const int64_t *__restrict__ nptr, const int32_t *__restrict__ nelem,
 }
 
 // Per-column partial sums of squares: part[block][c] over rows block*rows_per .. .
+// When nrhs divides 256, the block walks its rows x columns range in flat order, 256 entries per
+// round: every thread keeps one column (its index mod nrhs) and all loads are contiguous; the
+// per-thread sums of a column are then added in a fixed order, so the result is deterministic.
+// Otherwise one column after another.
 __global__ void __launch_bounds__(256)
 k_colsq_partial(const double *__restrict__ a, int64_t n, int nrhs, int64_t rows_per,
                 double *__restrict__ part) {
   __shared__ double red[256];
   const int64_t r0 = (int64_t)blockIdx.x * rows_per;
   const int64_t r1 = min(n, r0 + rows_per);
+  if (256 % nrhs == 0) {
+    double s = 0.0;
+    for (int64_t i = r0 * nrhs + threadIdx.x; i < r1 * nrhs; i += 256) {
+      const double v = a[i];
+      s += v * v;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if ((int)threadIdx.x < nrhs) {
+      double t = 0.0;
+      for (int j = threadIdx.x; j < 256; j += nrhs) t += red[j];
+      part[(int64_t)blockIdx.x * nrhs + threadIdx.x] = t;
+    }
+    return;
+  }
   for (int c = 0; c < nrhs; ++c) {
     double s = 0.0;
     for (int64_t i = r0 + threadIdx.x; i < r1; i += 256) {
