@@ -375,7 +375,6 @@ void build_schedule(HostPlan &P, const Tuning &t) {
     const FrontDesc &d = P.desc[f];
     if (d.elem >= 0 && d.k == 0) continue;   // pass-through leaf: read directly by its parent
     LevelSchedule &L = P.levels[d.level];
-    L.all.push_back((int32_t)f);
     L.max_m = std::max(L.max_m, d.m);
     L.max_k = std::max(L.max_k, d.k);
     if (d.m <= std::min(t.tiny_max_m, t.small_max_m)) {
@@ -388,6 +387,14 @@ void build_schedule(HostPlan &P, const Tuning &t) {
       L.large.push_back((int32_t)f);
       L.large_max_m = std::max(L.large_max_m, d.m);
     }
+  }
+  // the solve's list of a class: the tiny fronts first (their wave records are then a prefix
+  // of the class's records), then the rest; fronts of a class are independent
+  for (auto &L : P.levels) {
+    L.all.clear();
+    L.all.insert(L.all.end(), L.tiny.begin(), L.tiny.end());
+    L.all.insert(L.all.end(), L.small.begin(), L.small.end());
+    L.all.insert(L.all.end(), L.large.begin(), L.large.end());
   }
   const int32_t nb = t.nb, T = t.tile;
   auto add_tiles = [&](std::vector<GemmTask> &out, int32_t f, int32_t i0, int32_t i1, int32_t j0,

@@ -229,9 +229,47 @@ int ensure_uploaded(mf_plan *P) {
       }
     D.n_rup = (int64_t)rect.size() - D.rup;
   }
+  // wave records, one per entry of every class's front list (the tiny fronts come first)
+  std::vector<mf::WaveRec> wrec;
+  wrec.reserve(H.F);
+  for (size_t l = 0; l < H.levels.size(); ++l) {
+    P->lv[l].rall = (int64_t)wrec.size();
+    for (int32_t f : H.levels[l].all) {
+      const mf::FrontDesc &d = H.desc[f];
+      mf::WaveRec r;
+      std::memset(&r, 0, sizeof r);
+      r.f = f;
+      r.m = d.m;
+      r.k = d.k;
+      r.store = d.store;
+      r.idx = d.idx;
+      r.cbrow = d.cbrow;
+      r.ycb[0] = r.ycb[1] = -1;
+      const int64_t e2 = (int64_t)H.npe * H.npe;
+      if (d.elem >= 0) {
+        r.src[0] = -1 - (int64_t)d.elem * e2;
+        r.ld[0] = r.n[0] = H.npe;
+      } else {
+        const int32_t ch[2] = {d.left, d.right};
+        for (int s2 = 0; s2 < 2; ++s2) {
+          const mf::FrontDesc &c = H.desc[ch[s2]];
+          if (c.elem >= 0 && c.k == 0) {       // pass-through leaf: its element matrix
+            r.src[s2] = -1 - (int64_t)c.elem * e2;
+            r.ld[s2] = r.n[s2] = H.npe;
+          } else {
+            r.src[s2] = c.store + (int64_t)c.k * c.m + c.k;
+            r.ld[s2] = c.m;
+            r.n[s2] = c.m - c.k;
+            r.ycb[s2] = c.cbrow;
+          }
+        }
+      }
+      wrec.push_back(r);
+    }
+  }
   int rc;
   if ((rc = upload(P->d_lists, lists)) || (rc = upload(P->d_tasks, tasks)) ||
-      (rc = upload(P->d_rect, rect)))
+      (rc = upload(P->d_rect, rect)) || (rc = upload(P->d_wrec, wrec)))
     return rc;
   if (!P->static_up) {
     // node -> (element, local node) pairs in ascending element order, for the residual
@@ -287,7 +325,9 @@ int ensure_uploaded(mf_plan *P) {
     HIPCHK(hipHostMalloc((void **)&P->h_status, mf::kStatusWords * sizeof(int), hipHostMallocDefault));
   if (!P->cap_stream) HIPCHK(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
   // raise the dynamic-LDS limit of the kernels that size LDS per launch (best effort)
-  const void *dyn[] = {(const void *)mf::k_factor_tiny, (const void *)mf::k_factor_small,
+  const void *dyn[] = {(const void *)mf::k_factor_tiny<1>, (const void *)mf::k_factor_tiny<4>,
+                       (const void *)mf::k_factor_tiny<9>, (const void *)mf::k_factor_tiny<16>,
+                       (const void *)mf::k_factor_small,
                        (const void *)mf::k_assemble, (const void *)mf::k_front_panels<32>,
                        (const void *)mf::k_solve_down_wave<false>, (const void *)mf::k_solve_down_wave<true>,
                        (const void *)mf::k_solve_up_wave<false>, (const void *)mf::k_solve_up_wave<true>,
@@ -354,9 +394,20 @@ int launch_factor(mf_plan *P, const double *K, int prec, hipStream_t s) {
       const int m = D.tiny_max_m;
       const int ldsw = m * (m | 1) + m;           // front + 2m int maps
       const int grid = (int)std::min<int64_t>((D.n_tiny + 3) / 4, 65535);
-      LAUNCH(K_TINY, D.c_tiny, mf::k_factor_tiny, dim3(grid), dim3(256), (size_t)4 * ldsw * 8, s,
-             P->d_desc, P->d_lists + D.tiny, (int)D.n_tiny, P->d_store, P->d_inv_l, P->d_inv_r, K,
-             H.npe, P->d_status, ldsw, m);
+      const mf::WaveRec *rc0 = P->d_wrec + D.rall;   // the tiny fronts lead the class's list
+      if (m > mf::kTinyMaxM) return fail(MF_EINVAL, "tiny route front wider than the kernel's limit");
+      if (m <= 8)
+        LAUNCH(K_TINY, D.c_tiny, mf::k_factor_tiny<1>, dim3(grid), dim3(256), (size_t)4 * ldsw * 8, s,
+               rc0, (int)D.n_tiny, P->d_store, P->d_inv_l, P->d_inv_r, K, P->d_status, ldsw, m);
+      else if (m <= 16)
+        LAUNCH(K_TINY, D.c_tiny, mf::k_factor_tiny<4>, dim3(grid), dim3(256), (size_t)4 * ldsw * 8, s,
+               rc0, (int)D.n_tiny, P->d_store, P->d_inv_l, P->d_inv_r, K, P->d_status, ldsw, m);
+      else if (m <= 24)
+        LAUNCH(K_TINY, D.c_tiny, mf::k_factor_tiny<9>, dim3(grid), dim3(256), (size_t)4 * ldsw * 8, s,
+               rc0, (int)D.n_tiny, P->d_store, P->d_inv_l, P->d_inv_r, K, P->d_status, ldsw, m);
+      else
+        LAUNCH(K_TINY, D.c_tiny, mf::k_factor_tiny<16>, dim3(grid), dim3(256), (size_t)4 * ldsw * 8, s,
+               rc0, (int)D.n_tiny, P->d_store, P->d_inv_l, P->d_inv_r, K, P->d_status, ldsw, m);
     }
     if (D.n_small) {
       const int m = D.small_max_m;
@@ -448,6 +499,7 @@ int launch_solve(mf_plan *P, const double *b, double *x, int32_t nrhs, bool tran
       c.bytes = (down ? D.down_coef : D.up_coef) + nrhs * (down ? D.down_rhs_bytes : D.up_rhs_bytes);
       c.flops = nrhs * (down ? D.down_rhs_flops : D.up_rhs_flops);
       const int32_t *lst = P->d_lists + D.all;
+      const mf::WaveRec *rec = P->d_wrec + D.rall;
       const int n = (int)D.n_all;
       const int mmax = std::max(1, D.max_m), kmax = std::max(1, D.max_k);
       if (D.max_m <= kWaveSolveMaxM) {
@@ -459,18 +511,18 @@ int launch_solve(mf_plan *P, const double *b, double *x, int32_t nrhs, bool tran
         const size_t lds = (size_t)4 * ldsw * 8;
         const int grid = (int)std::min<int64_t>((n + 3) / 4, gridcap);
         if (down && trans)
-          LAUNCH(K_DOWN_WAVE, c, mf::k_solve_down_wave<true>, dim3(grid), dim3(256), lds, s, P->d_desc,
-                 lst, n, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, b, x, P->d_ycb, nrhs, nc,
+          LAUNCH(K_DOWN_WAVE, c, mf::k_solve_down_wave<true>, dim3(grid), dim3(256), lds, s, rec,
+                 n, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, b, x, P->d_ycb, nrhs, nc,
                  mmax, cld, ldsw);
         else if (down)
-          LAUNCH(K_DOWN_WAVE, c, mf::k_solve_down_wave<false>, dim3(grid), dim3(256), lds, s, P->d_desc,
-                 lst, n, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, b, x, P->d_ycb, nrhs, nc,
+          LAUNCH(K_DOWN_WAVE, c, mf::k_solve_down_wave<false>, dim3(grid), dim3(256), lds, s, rec,
+                 n, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, b, x, P->d_ycb, nrhs, nc,
                  mmax, cld, ldsw);
         else if (trans)
-          LAUNCH(K_UP_WAVE, c, mf::k_solve_up_wave<true>, dim3(grid), dim3(256), lds, s, P->d_desc, lst,
+          LAUNCH(K_UP_WAVE, c, mf::k_solve_up_wave<true>, dim3(grid), dim3(256), lds, s, rec,
                  n, P->d_store, P->d_front_idx, x, nrhs, nc, mmax, cld, ldsw);
         else
-          LAUNCH(K_UP_WAVE, c, mf::k_solve_up_wave<false>, dim3(grid), dim3(256), lds, s, P->d_desc, lst,
+          LAUNCH(K_UP_WAVE, c, mf::k_solve_up_wave<false>, dim3(grid), dim3(256), lds, s, rec,
                  n, P->d_store, P->d_front_idx, x, nrhs, nc, mmax, cld, ldsw);
       } else {
         // the pivot block (one workgroup per front, blocks of NBS in sequence) and the

@@ -72,6 +72,7 @@ struct LevelDev {
   int64_t fused = 0, n_fused = 0;
   int32_t fused_max_m = 0;
   int64_t all = 0, n_all = 0;
+  int64_t rall = 0;            // first wave record of the class (records follow `all`)
   int32_t max_m = 0, max_k = 0;
   std::vector<StepDev> steps;
   int64_t schur = 0, n_schur = 0;
@@ -138,6 +139,7 @@ struct mf_plan {
   int32_t *d_lists = nullptr;
   mf::GemmTask *d_tasks = nullptr;
   int4 *d_rect = nullptr;
+  mf::WaveRec *d_wrec = nullptr;   // wave records of every class's front list, class after class
   double *d_store = nullptr;
   // inverses of the diagonal blocks of the fronts the block solves handle (see k_diag_inverse)
   double *d_dinv = nullptr;
@@ -188,6 +190,7 @@ struct mf_plan {
     mfapi::dfree(d_lists);
     mfapi::dfree(d_tasks);
     mfapi::dfree(d_rect);
+    mfapi::dfree(d_wrec);
     mfapi::dfree(d_store);
     mfapi::dfree(d_dinv);
     mfapi::dfree(d_dinv_off);

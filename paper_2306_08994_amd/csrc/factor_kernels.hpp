@@ -16,42 +16,113 @@
 namespace mf {
 
 // ---------------------------------------------------------------------------------------------
-// tiny: one wave per front, four fronts per workgroup, grid-stride over the class's list.
+// tiny: one wave per front (m <= kTinyMaxM), four fronts per workgroup, grid-stride over the
+// class's wave records.  The record (uniform: scalar loads), then the extend-add maps and every
+// entry of both sources, held in registers (U per lane), in one round of loads; then the
+// scatter into the LDS front, the k pivot steps and the store of the front.
 // ---------------------------------------------------------------------------------------------
+constexpr int kTinyMaxM = 32;
+
+__device__ __forceinline__ const double *rec_source(int64_t src, const double *store,
+                                                    const double *K) {
+  return src >= 0 ? store + src : K + (-1 - src);
+}
+
+// Entries t = lane + 64 u (u < U) of an n x n source (row-major, rows ld apart) into v; zero
+// where t >= n * n (n = 0: nothing).
+template <int U>
+__device__ __forceinline__ void stage_source(const double *__restrict__ src, int ld, int n,
+                                             int lane, double (&v)[U]) {
+  const int nn = n > 0 ? n : 1;
+  int r = lane / nn, c = lane - r * nn;
+  const int q = 64 / nn, rem = 64 - q * nn;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    v[u] = r < n ? src[r * ld + c] : 0.0;          // 32-bit offsets: n, ld <= kTinyMaxM
+    c += rem;
+    r += q;
+    if (c >= nn) {
+      c -= nn;
+      ++r;
+    }
+  }
+}
+
+// The staged entries assigned (ADD = false) or added into the LDS front at map[row], map[col].
+template <bool ADD, int U>
+__device__ __forceinline__ void scatter_staged(const double (&v)[U], int n, const int *map, int ld,
+                                               double *sh, int lane) {
+  const int nn = n > 0 ? n : 1;
+  int r = lane / nn, c = lane - r * nn;
+  const int q = 64 / nn, rem = 64 - q * nn;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (r < n) {
+      const int dst = map[r] * ld + map[c];
+      if (ADD)
+        sh[dst] += v[u];
+      else
+        sh[dst] = v[u];
+    }
+    c += rem;
+    r += q;
+    if (c >= nn) {
+      c -= nn;
+      ++r;
+    }
+  }
+}
+
+// U = ceil(mmax^2 / 64): the class's widest tiny front bounds every source (a child's CB and an
+// element matrix are never wider than the front they enter).
+template <int U>
 __global__ void __launch_bounds__(256)
-k_factor_tiny(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ list, int nlist,
-              double *__restrict__ store, const int32_t *__restrict__ inv_l,
-              const int32_t *__restrict__ inv_r, const double *__restrict__ K, int npe,
-              int *__restrict__ status, int ldsw, int mmax) {
+k_factor_tiny(const WaveRec *__restrict__ recs, int nrec, double *__restrict__ store,
+              const int32_t *__restrict__ inv_l, const int32_t *__restrict__ inv_r,
+              const double *__restrict__ K, int *__restrict__ status, int ldsw, int mmax) {
   extern __shared__ double sm[];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform: scalar loads of the record
   double *sh = sm + wv * ldsw;
   int *ma = reinterpret_cast<int *>(sh + (ldsw - mmax));   // 2 * mmax ints after the front
   int *mb = ma + mmax;
-  for (int li = blockIdx.x * 4 + wv; li < nlist; li += gridDim.x * 4) {
-    const int f = list[li];
-    const FrontDesc d = fd[f];
-    const int m = d.m, k = d.k, ld = m | 1;
-    const int32_t *il = inv_l + d.idx;
-    const int32_t *ir = inv_r + d.idx;
-    const GatherCtx g = gather_ctx(fd, d, store, K, npe);
-    scatter_assemble(g, il, ir, m, ld, sh, ma, mb, lane, 64, [] __device__() { wave_sync(); });
+  for (int li = blockIdx.x * 4 + wv; li < nrec; li += gridDim.x * 4) {
+    const WaveRec r = recs[li];
+    const int m = r.m, k = r.k, ld = m | 1;
+    int xa = -1, xb = -1;
+    if (lane < m) {
+      xa = inv_l[r.idx + lane];
+      if (r.n[1] > 0) xb = inv_r[r.idx + lane];
+    }
+    double va[U], vb[U];
+    stage_source<U>(rec_source(r.src[0], store, K), r.ld[0], r.n[0], lane, va);
+    stage_source<U>(rec_source(r.src[1], store, K), r.ld[1], r.n[1], lane, vb);
+    for (int t = lane; t < m * ld; t += 64) sh[t] = 0.0;
+    if (xa >= 0) ma[xa] = lane;
+    if (xb >= 0) mb[xb] = lane;
+    wave_sync();
+    // the left source assigned, then the right one added: each front entry is summed left
+    // then right, as in the extend-add of the two children
+    scatter_staged<false, U>(va, r.n[0], ma, ld, sh, lane);
+    wave_sync();
+    scatter_staged<true, U>(vb, r.n[1], mb, ld, sh, lane);
+    wave_sync();
     for (int p = 0; p < k; ++p) {
       const double piv = sh[p * ld + p];
       if (!good_pivot(piv)) {
-        if (lane == 0) record_bad_pivot(status, f, p);
+        if (lane == 0) record_bad_pivot(status, r.f, p);
         break;
       }
       for (int j = p + 1 + lane; j < m; j += 64) sh[p * ld + j] = sh[p * ld + j] / piv;
       wave_sync();
-      const int r = m - p - 1;
-      for (int t = lane; t < r * r; t += 64) {
-        const int i = p + 1 + t / r, j = p + 1 + (t - (t / r) * r);
+      const int rr = m - p - 1;
+      for (int t = lane; t < rr * rr; t += 64) {
+        const int i = p + 1 + t / rr, j = p + 1 + (t - (t / rr) * rr);
         sh[i * ld + j] -= sh[i * ld + p] * sh[p * ld + j];
       }
       wave_sync();
     }
-    double *out = store + d.store;
+    double *out = store + r.store;
     for (int t = lane; t < m * m; t += 64) {
       const int i = t / m, j = t - (t / m) * m;
       out[t] = sh[i * ld + j];

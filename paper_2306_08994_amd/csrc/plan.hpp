@@ -20,6 +20,25 @@ struct FrontDesc {
 };
 static_assert(sizeof(FrontDesc) == 48, "FrontDesc layout");
 
+// Per-front record of the one-wave-per-front kernels (the tiny factor route and the wave
+// solves), one per entry of a class's front list: everything the wave needs before its first
+// gather, so that the record (uniform, scalar loads), then the maps and the sources in one
+// round trip, are the whole dependency chain.  88 bytes.
+struct WaveRec {
+  int64_t store;    // offset (doubles) of the front's m x m storage
+  int64_t idx;      // offset into front_idx / inv_l / inv_r
+  int64_t cbrow;    // first row of the front's contribution block in a solve's CB buffer
+  int64_t src[2];   // extend-add sources: >= 0 offset (doubles) into the store of a child's CB
+                    // (its (k, k) entry); < 0: -1 - offset of an element matrix in K
+  int64_t ycb[2];   // first CB-buffer row of each child that passes one to the solve, else -1
+  int32_t f;        // front id
+  int32_t m, k;     // width and pivots
+  int32_t ld[2];    // leading dimension of each source
+  int32_t n[2];     // size of each (square) source, 0 = absent
+  int32_t pad;
+};
+static_assert(sizeof(WaveRec) == 88, "WaveRec layout");
+
 // One tile of a batched GEMM update  C[i0:i1, j0:j1] -= A[i0:i1, q0:q1] * B[q0:q1, j0:j1],
 // where A, B and C are all views of the same front storage (row-major, leading dimension m).
 struct GemmTask {

@@ -68,27 +68,23 @@ __device__ inline void copy_strided(const double *__restrict__ src, int64_t stri
 
 template <bool TRANS>
 __global__ void __launch_bounds__(256)
-k_solve_down_wave(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ list, int nlist,
+k_solve_down_wave(const WaveRec *__restrict__ recs, int nrec,
                   const double *__restrict__ store, const int32_t *__restrict__ front_idx,
                   const int32_t *__restrict__ inv_l, const int32_t *__restrict__ inv_r,
                   const double *b, double *x, double *__restrict__ ycb, int nrhs, int nc,
                   int mmax, int cld, int ldsw) {
   extern __shared__ double sm[];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   double *W = sm + wv * ldsw;
   double *C = W + mmax * nc;       // C[i * cld + p] = cd(i, p), p <= i, p < k
   double *rdv = C + mmax * cld;    // reciprocal of each pivot's diagonal coefficient
-  for (int li = blockIdx.x * 4 + wv; li < nlist; li += gridDim.x * 4) {
-    const int f = list[li];
-    const FrontDesc d = fd[f];
+  for (int li = blockIdx.x * 4 + wv; li < nrec; li += gridDim.x * 4) {
+    const WaveRec d = recs[li];
     const int m = d.m, k = d.k;
     const double *F = store + d.store;
-    FrontDesc a = d, c = d;
-    if (d.elem < 0) {
-      a = fd[d.left];
-      c = fd[d.right];
-    }
-    const bool use_a = d.elem < 0 && !passthrough(a), use_c = d.elem < 0 && !passthrough(c);
+    // children that pass a contribution block (a pass-through leaf passes none)
+    const bool use_a = d.ycb[0] >= 0, use_c = d.ycb[1] >= 0;
     const int i = lane;                               // this lane's row
     int64_t gi = 0;
     int xa = -1, xc = -1;
@@ -109,8 +105,8 @@ k_solve_down_wave(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ 
       if (i < m)
         for (int r = 0; r < nr; ++r) {
           double v = i < k ? b[gi * nrhs + r0 + r] : 0.0;
-          if (xa >= 0) v += ycb[(a.cbrow + xa) * nrhs + r0 + r];
-          if (xc >= 0) v += ycb[(c.cbrow + xc) * nrhs + r0 + r];
+          if (xa >= 0) v += ycb[(d.ycb[0] + xa) * nrhs + r0 + r];
+          if (xc >= 0) v += ycb[(d.ycb[1] + xc) * nrhs + r0 + r];
           W[i * nr + r] = v;
         }
       wave_sync();
@@ -134,17 +130,17 @@ k_solve_down_wave(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ 
 
 template <bool TRANS>
 __global__ void __launch_bounds__(256)
-k_solve_up_wave(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ list, int nlist,
+k_solve_up_wave(const WaveRec *__restrict__ recs, int nrec,
                 const double *__restrict__ store, const int32_t *__restrict__ front_idx,
                 double *x, int nrhs, int nc, int mmax, int cld, int ldsw) {
   extern __shared__ double sm[];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   double *W = sm + wv * ldsw;
   double *C = W + mmax * nc;       // C[j * cld + q] = cu(q, j), q <= j, q < k  (column-major)
   double *rdv = C + mmax * cld;
-  for (int li = blockIdx.x * 4 + wv; li < nlist; li += gridDim.x * 4) {
-    const int f = list[li];
-    const FrontDesc d = fd[f];
+  for (int li = blockIdx.x * 4 + wv; li < nrec; li += gridDim.x * 4) {
+    const WaveRec d = recs[li];
     const int m = d.m, k = d.k;
     const double *F = store + d.store;
     const int j = lane;                               // this lane's row / column
@@ -205,7 +201,8 @@ k_diag_inverse(const FrontDesc *__restrict__ fd, const int2 *__restrict__ tasks,
                const double *__restrict__ store, const int64_t *__restrict__ dinv_off,
                double *__restrict__ dinv) {
   __shared__ double Bs[4][NBS][NBS + 1];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   double(*B)[NBS + 1] = Bs[wv];
   const int j = lane & (NBS - 1);
   for (int t = blockIdx.x * 4 + wv; t < ntasks; t += gridDim.x * 4) {
