@@ -62,8 +62,8 @@ def time_steps(fn, steps, warmup):
 # the kernel's source is unchanged since the counters were taken).
 KIND_SOURCE = {
     "factor_tiny": "factor_kernels.hpp", "factor_small": "factor_kernels.hpp",
-    "assemble": "factor_kernels.hpp", "front_panels": "factor_kernels.hpp",
-    "panel_lu_trsm": "factor_kernels.hpp", "gemm_panel": "factor_kernels.hpp",
+    "assemble": "factor_kernels.hpp", "front_panels": "panel_kernels.hpp",
+    "panel_lu_trsm": "panel_kernels.hpp", "gemm_panel": "factor_kernels.hpp",
     "gemm_schur": "factor_kernels.hpp", "solve_down_wave": "solve_kernels.hpp",
     "solve_down_block": "solve_kernels.hpp", "solve_up_wave": "solve_kernels.hpp",
     "solve_up_block": "solve_kernels.hpp", "diag_block_inverse": "solve_kernels.hpp",

@@ -177,6 +177,18 @@ int mf_refine(const mf_plan *plan, const double *elem_mats, const double *b, dou
               int32_t nrhs, double tol, int32_t max_it, int32_t *its, double *relres,
               void *hip_stream);
 
+/* mf_factor followed by mf_refine in one call, with the forward substitution of the first
+ * solve overlapped with the factorization: class l of the forward sweep depends only on classes
+ * <= l of the factorization (the elimination tree orders it, Sec. 2.4 / Sec. 3.3), so it runs
+ * on a second stream of the plan while the upper classes are still being factored; the
+ * backward sweep and the refinement loop follow on hip_stream.  The same kernels in the same
+ * per-class order as mf_factor then mf_refine, so x and the factors are identical to theirs.
+ * Arguments and errors: those of mf_factor and mf_refine (MF_EZERO_PIVOT leaves no valid
+ * factor and x unspecified).  Synchronizes hip_stream at least twice. */
+int mf_factor_refine(mf_plan *plan, const double *elem_mats, int32_t precision, const double *b,
+                     double *x, int32_t nrhs, double tol, int32_t max_it, int32_t *its,
+                     double *relres, void *hip_stream);
+
 /* Adjoint element gradient: gK[e][a][b] = -sum_r lam[conn_e[a]][r] * u[conn_e[b]][r], the
  * derivative of a loss through A = sum_e P_e^T K_e P_e given lam = A^{-T} dL/du.
  * lam, u device [n][nrhs]; gK device [n_elem][npe][npe].  Asynchronous. */

@@ -16,7 +16,7 @@ ERROR_NAMES = {MF_EINVAL: "MF_EINVAL", MF_ENOMEM: "MF_ENOMEM", MF_EZERO_PIVOT: "
 EXPORTED = ["mf_analyse", "mf_plan_info", "mf_plan_export_tree", "mf_task_trace", "mf_set_tuning",
             "mf_autotune",
             "mf_factor", "mf_solve",
-            "mf_residual", "mf_refine", "mf_elem_grad", "mf_export_factors", "mf_profile",
+            "mf_residual", "mf_refine", "mf_factor_refine", "mf_elem_grad", "mf_export_factors", "mf_profile",
             "mf_profile_report", "mf_destroy", "mf_last_error"]
 
 
@@ -71,6 +71,8 @@ def load():
         "mf_residual": (c_int32, [P, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
         "mf_refine": (c_int32, [P, c_void_p, c_void_p, c_void_p, c_int32, c_double, c_int32,
                                 POINTER(c_int32), dp, c_void_p]),
+        "mf_factor_refine": (c_int32, [P, c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_double,
+                                       c_int32, POINTER(c_int32), dp, c_void_p]),
         "mf_elem_grad": (c_int32, [P, c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
         "mf_export_factors": (c_int32, [P, c_void_p, c_void_p]),
         "mf_profile": (c_int32, [P, c_int32]),

@@ -404,13 +404,14 @@ void build_schedule(HostPlan &P, const Tuning &t) {
       for (int32_t j = j0; j < j1; j += T) {
         GemmTask g;
         g.front = f;
+        g.store = P.desc[f].store;
+        g.ld = P.desc[f].m;
         g.i0 = i;
         g.i1 = std::min(i + T, i1);
         g.j0 = j;
         g.j1 = std::min(j + T, j1);
         g.q0 = q0;
         g.q1 = q1;
-        g.pad = 0;
         out.push_back(g);
       }
   };

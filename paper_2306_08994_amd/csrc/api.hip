@@ -153,6 +153,7 @@ int ensure_uploaded(mf_plan *P) {
   mf::build_schedule(H, P->tune);
   std::vector<int32_t> lists;
   std::vector<mf::GemmTask> tasks;
+  std::vector<mf::PanelRec> panel;
   P->lv.assign(H.levels.size(), LevelDev());
   auto put = [&](const std::vector<int32_t> &v) {
     const int64_t off = (int64_t)lists.size();
@@ -181,8 +182,17 @@ int ensure_uploaded(mf_plan *P) {
     for (const mf::PanelStep &st : S.steps) {
       StepDev sd;
       sd.n = (int64_t)st.fronts.size();
-      sd.fronts = put(st.fronts);
-      sd.p0 = put(st.p0);
+      sd.prec = (int64_t)panel.size();
+      for (size_t i = 0; i < st.fronts.size(); ++i) {
+        const mf::FrontDesc &d = H.desc[st.fronts[i]];
+        mf::PanelRec r;
+        r.store = d.store;
+        r.m = d.m;
+        r.k = d.k;
+        r.p0 = st.p0[i];
+        r.f = st.fronts[i];
+        panel.push_back(r);
+      }
       sd.update = (int64_t)tasks.size();
       sd.n_update = (int64_t)st.update.size();
       tasks.insert(tasks.end(), st.update.begin(), st.update.end());
@@ -194,7 +204,15 @@ int ensure_uploaded(mf_plan *P) {
     tasks.insert(tasks.end(), S.schur.begin(), S.schur.end());
     level_costs(H, S, D, P->tune.nb);
   }
-  // rectangular-part tasks of the classes the block solves handle
+  // wave records follow the class lists, class after class
+  {
+    int64_t off = 0;
+    for (size_t l = 0; l < H.levels.size(); ++l) {
+      P->lv[l].rall = off;
+      off += (int64_t)H.levels[l].all.size();
+    }
+  }
+  // rectangular-part tasks of the classes the block solves handle (x: the front's wave record)
   std::vector<int4> rect;
   for (size_t l = 0; l < H.levels.size(); ++l) {
     const mf::LevelSchedule &S = H.levels[l];
@@ -215,61 +233,25 @@ int ensure_uploaded(mf_plan *P) {
     const int32_t sd = mf::kRectRows, su = mf::kRectRows;
     D.rdown = (int64_t)rect.size();
     if (D.split_down)
-      for (int32_t f : S.all) {
-        const mf::FrontDesc &d = H.desc[f];
-        for (int32_t r = d.k; r < d.m; r += sd) rect.push_back(make_int4(f, r, std::min(sd, d.m - r), 0));
+      for (size_t i = 0; i < S.all.size(); ++i) {
+        const mf::FrontDesc &d = H.desc[S.all[i]];
+        const int32_t ri = (int32_t)(D.rall + (int64_t)i);
+        for (int32_t r = d.k; r < d.m; r += sd) rect.push_back(make_int4(ri, r, std::min(sd, d.m - r), 0));
       }
     D.n_rdown = (int64_t)rect.size() - D.rdown;
     D.rup = (int64_t)rect.size();
     if (D.split_up)
-      for (int32_t f : S.all) {
-        const mf::FrontDesc &d = H.desc[f];
+      for (size_t i = 0; i < S.all.size(); ++i) {
+        const mf::FrontDesc &d = H.desc[S.all[i]];
+        const int32_t ri = (int32_t)(D.rall + (int64_t)i);
         if (d.m == d.k) continue;
-        for (int32_t r = 0; r < d.k; r += su) rect.push_back(make_int4(f, r, std::min(su, d.k - r), 0));
+        for (int32_t r = 0; r < d.k; r += su) rect.push_back(make_int4(ri, r, std::min(su, d.k - r), 0));
       }
     D.n_rup = (int64_t)rect.size() - D.rup;
   }
-  // wave records, one per entry of every class's front list (the tiny fronts come first)
-  std::vector<mf::WaveRec> wrec;
-  wrec.reserve(H.F);
-  for (size_t l = 0; l < H.levels.size(); ++l) {
-    P->lv[l].rall = (int64_t)wrec.size();
-    for (int32_t f : H.levels[l].all) {
-      const mf::FrontDesc &d = H.desc[f];
-      mf::WaveRec r;
-      std::memset(&r, 0, sizeof r);
-      r.f = f;
-      r.m = d.m;
-      r.k = d.k;
-      r.store = d.store;
-      r.idx = d.idx;
-      r.cbrow = d.cbrow;
-      r.ycb[0] = r.ycb[1] = -1;
-      const int64_t e2 = (int64_t)H.npe * H.npe;
-      if (d.elem >= 0) {
-        r.src[0] = -1 - (int64_t)d.elem * e2;
-        r.ld[0] = r.n[0] = H.npe;
-      } else {
-        const int32_t ch[2] = {d.left, d.right};
-        for (int s2 = 0; s2 < 2; ++s2) {
-          const mf::FrontDesc &c = H.desc[ch[s2]];
-          if (c.elem >= 0 && c.k == 0) {       // pass-through leaf: its element matrix
-            r.src[s2] = -1 - (int64_t)c.elem * e2;
-            r.ld[s2] = r.n[s2] = H.npe;
-          } else {
-            r.src[s2] = c.store + (int64_t)c.k * c.m + c.k;
-            r.ld[s2] = c.m;
-            r.n[s2] = c.m - c.k;
-            r.ycb[s2] = c.cbrow;
-          }
-        }
-      }
-      wrec.push_back(r);
-    }
-  }
   int rc;
   if ((rc = upload(P->d_lists, lists)) || (rc = upload(P->d_tasks, tasks)) ||
-      (rc = upload(P->d_rect, rect)) || (rc = upload(P->d_wrec, wrec)))
+      (rc = upload(P->d_rect, rect)) || (rc = upload(P->d_panel, panel)))
     return rc;
   if (!P->static_up) {
     // node -> (element, local node) pairs in ascending element order, for the residual
@@ -295,7 +277,10 @@ int ensure_uploaded(mf_plan *P) {
     std::vector<int2> dtasks;
     int64_t dtot = 0;
     constexpr int64_t kPair = 2 * mf::NBS * mf::NBS;
-    for (const mf::LevelSchedule &S : H.levels) {
+    P->dinv_lvl.assign(H.levels.size() + 1, 0);
+    for (size_t l = 0; l < H.levels.size(); ++l) {
+      const mf::LevelSchedule &S = H.levels[l];
+      P->dinv_lvl[l] = (int64_t)dtasks.size();
       if (S.max_m <= kWaveSolveMaxM) continue;
       for (int32_t f : S.all) {
         const int32_t k = H.desc[f].k;
@@ -305,7 +290,9 @@ int ensure_uploaded(mf_plan *P) {
         dtot += (int64_t)((k + mf::NBS - 1) / mf::NBS) * kPair;
       }
     }
+    P->dinv_lvl[H.levels.size()] = (int64_t)dtasks.size();
     if ((rc = upload(P->d_dinv_off, doff)) || (rc = upload(P->d_dinv_tasks, dtasks))) return rc;
+    P->h_dinv_off = doff;
     P->n_dinv_tasks = (int64_t)dtasks.size();
     P->c_dinv.bytes = 8.0 * P->n_dinv_tasks * (mf::NBS * mf::NBS + kPair);
     P->c_dinv.flops = P->n_dinv_tasks * 2.0 * mf::NBS * mf::NBS * mf::NBS / 3.0;
@@ -320,10 +307,55 @@ int ensure_uploaded(mf_plan *P) {
     HIPCHK(hipMemset(P->d_arrive, 0, std::max<int64_t>(1, H.F) * sizeof(int)));
     P->static_up = true;
   }
+  // wave records, one per entry of every class's front list (the tiny fronts come first)
+  std::vector<mf::WaveRec> wrec;
+  wrec.reserve(H.F);
+  for (size_t l = 0; l < H.levels.size(); ++l) {
+    for (int32_t f : H.levels[l].all) {
+      const mf::FrontDesc &d = H.desc[f];
+      mf::WaveRec r;
+      std::memset(&r, 0, sizeof r);
+      r.f = f;
+      r.m = d.m;
+      r.k = d.k;
+      r.store = d.store;
+      r.idx = d.idx;
+      r.cbrow = d.cbrow;
+      r.ycb[0] = r.ycb[1] = -1;
+      r.dinv = P->h_dinv_off[f];
+      const int64_t e2 = (int64_t)H.npe * H.npe;
+      if (d.elem >= 0) {
+        r.src[0] = -1 - (int64_t)d.elem * e2;
+        r.ld[0] = r.n[0] = H.npe;
+      } else {
+        const int32_t ch[2] = {d.left, d.right};
+        for (int s2 = 0; s2 < 2; ++s2) {
+          const mf::FrontDesc &c = H.desc[ch[s2]];
+          if (c.elem >= 0 && c.k == 0) {       // pass-through leaf: its element matrix
+            r.src[s2] = -1 - (int64_t)c.elem * e2;
+            r.ld[s2] = r.n[s2] = H.npe;
+          } else {
+            r.src[s2] = c.store + (int64_t)c.k * c.m + c.k;
+            r.ld[s2] = c.m;
+            r.n[s2] = c.m - c.k;
+            r.ycb[s2] = c.cbrow;
+          }
+        }
+      }
+      wrec.push_back(r);
+    }
+  }
+  if ((rc = upload(P->d_wrec, wrec))) return rc;
   if (!P->d_status) HIPCHK(hipMalloc((void **)&P->d_status, mf::kStatusWords * sizeof(int)));
   if (!P->h_status)
     HIPCHK(hipHostMalloc((void **)&P->h_status, mf::kStatusWords * sizeof(int), hipHostMallocDefault));
   if (!P->cap_stream) HIPCHK(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+  if (!P->side_stream) HIPCHK(hipStreamCreateWithFlags(&P->side_stream, hipStreamNonBlocking));
+  while (P->lvl_events.size() < H.levels.size() + 2) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    P->lvl_events.push_back(e);
+  }
   // raise the dynamic-LDS limit of the kernels that size LDS per launch (best effort)
   const void *dyn[] = {(const void *)mf::k_factor_tiny<1>, (const void *)mf::k_factor_tiny<4>,
                        (const void *)mf::k_factor_tiny<9>, (const void *)mf::k_factor_tiny<16>,
@@ -385,10 +417,9 @@ struct Scope {
     hipLaunchKernelGGL(kern, grid, block, lds, stream, __VA_ARGS__);                     \
   } while (0)
 
-int launch_factor(mf_plan *P, const double *K, int prec, hipStream_t s) {
-  const mf::HostPlan &H = P->hp;
-  hipLaunchKernelGGL(mf::k_clear_status, dim3(1), dim3(64), 0, s, P->d_status);
-  for (size_t l = 0; l < P->lv.size(); ++l) {
+// The launches of class l of the factorization.
+int factor_level(mf_plan *P, const double *K, int prec, size_t l, hipStream_t s) {
+  {
     const LevelDev &D = P->lv[l];
     if (D.n_tiny) {
       const int m = D.tiny_max_m;
@@ -413,15 +444,15 @@ int launch_factor(mf_plan *P, const double *K, int prec, hipStream_t s) {
       const int m = D.small_max_m;
       const size_t lds = ((size_t)m * (m | 1) + m) * sizeof(double);
       const int grid = (int)std::min<int64_t>(D.n_small, 16384);
-      LAUNCH(K_SMALL, D.c_small, mf::k_factor_small, dim3(grid), dim3(mf::SM_THREADS), lds, s, P->d_desc,
-             P->d_lists + D.small, (int)D.n_small, P->d_store, P->d_inv_l, P->d_inv_r, K, H.npe,
+      LAUNCH(K_SMALL, D.c_small, mf::k_factor_small, dim3(grid), dim3(mf::SM_THREADS), lds, s,
+             P->d_wrec + D.rall + D.n_tiny, (int)D.n_small, P->d_store, P->d_inv_l, P->d_inv_r, K,
              P->d_status, m);
     }
     if (D.n_large) {
       LAUNCH(K_ASSEMBLE, D.c_assemble, mf::k_assemble,
              dim3((D.large_max_m + 3) / 4, (unsigned)D.n_large), dim3(256),
-             (size_t)2 * D.large_max_m * sizeof(int), s, P->d_desc,
-             P->d_lists + D.large, P->d_store, P->d_inv_l, P->d_inv_r, K, H.npe);
+             (size_t)2 * D.large_max_m * sizeof(int), s,
+             P->d_wrec + D.rall + D.n_tiny + D.n_small, P->d_store, P->d_inv_l, P->d_inv_r, K);
       if (D.n_fused) {
         const size_t lds = (size_t)(32 * 33 + 32 + 32 * mf::FP_MAXM) * sizeof(double);
         LAUNCH(K_FUSED, D.c_fused, mf::k_front_panels<32>, dim3((unsigned)D.n_fused),
@@ -430,27 +461,27 @@ int launch_factor(mf_plan *P, const double *K, int prec, hipStream_t s) {
       }
       for (const StepDev &st : D.steps) {
         const dim3 gt((unsigned)std::max<int64_t>(1, (st.trsm_items + 255) / 256), (unsigned)st.n);
-        const int32_t *fr = P->d_lists + st.fronts, *p0 = P->d_lists + st.p0;
+        const mf::PanelRec *pr = P->d_panel + st.prec;
         switch (P->tune.nb) {
           case 16:
-            LAUNCH(K_TRSM, st.trsm, mf::k_panel_trsm<16>, gt, dim3(256), 0, s, P->d_desc, fr, p0, P->d_store, P->d_status,
+            LAUNCH(K_TRSM, st.trsm, mf::k_panel_trsm<16>, gt, dim3(256), 0, s, pr, P->d_store, P->d_status,
                    P->d_arrive);
             break;
           case 64:
-            LAUNCH(K_TRSM, st.trsm, mf::k_panel_trsm<64>, gt, dim3(256), 0, s, P->d_desc, fr, p0, P->d_store, P->d_status,
+            LAUNCH(K_TRSM, st.trsm, mf::k_panel_trsm<64>, gt, dim3(256), 0, s, pr, P->d_store, P->d_status,
                    P->d_arrive);
             break;
           default:
-            LAUNCH(K_TRSM, st.trsm, mf::k_panel_trsm<32>, gt, dim3(256), 0, s, P->d_desc, fr, p0, P->d_store, P->d_status,
+            LAUNCH(K_TRSM, st.trsm, mf::k_panel_trsm<32>, gt, dim3(256), 0, s, pr, P->d_store, P->d_status,
                    P->d_arrive);
         }
         if (st.n_update) {
           const dim3 g((unsigned)st.n_update);
           const mf::GemmTask *t = P->d_tasks + st.update;
           if (P->tune.tile == 32)
-            LAUNCH(K_GEMM_PANEL, st.upd, (mf::k_gemm_update<0, 32>), g, dim3(256), 0, s, P->d_desc, t, P->d_store);
+            LAUNCH(K_GEMM_PANEL, st.upd, (mf::k_gemm_update<0, 32>), g, dim3(256), 0, s, t, P->d_store);
           else
-            LAUNCH(K_GEMM_PANEL, st.upd, (mf::k_gemm_update<0, 64>), g, dim3(256), 0, s, P->d_desc, t, P->d_store);
+            LAUNCH(K_GEMM_PANEL, st.upd, (mf::k_gemm_update<0, 64>), g, dim3(256), 0, s, t, P->d_store);
         }
       }
       if (D.n_schur) {
@@ -458,23 +489,39 @@ int launch_factor(mf_plan *P, const double *K, int prec, hipStream_t s) {
         const dim3 g((unsigned)D.n_schur);
         const bool t32 = P->tune.tile == 32;
         if (prec == MF_SCHUR_FP32) {
-          if (t32) LAUNCH(K_GEMM_SCHUR, D.c_schur, (mf::k_gemm_update<1, 32>), g, dim3(256), 0, s, P->d_desc, t, P->d_store);
-          else LAUNCH(K_GEMM_SCHUR, D.c_schur, (mf::k_gemm_update<1, 64>), g, dim3(256), 0, s, P->d_desc, t, P->d_store);
+          if (t32) LAUNCH(K_GEMM_SCHUR, D.c_schur, (mf::k_gemm_update<1, 32>), g, dim3(256), 0, s, t, P->d_store);
+          else LAUNCH(K_GEMM_SCHUR, D.c_schur, (mf::k_gemm_update<1, 64>), g, dim3(256), 0, s, t, P->d_store);
         } else if (prec == MF_SCHUR_BF16) {
-          if (t32) LAUNCH(K_GEMM_SCHUR, D.c_schur, (mf::k_gemm_update<2, 32>), g, dim3(256), 0, s, P->d_desc, t, P->d_store);
-          else LAUNCH(K_GEMM_SCHUR, D.c_schur, (mf::k_gemm_update<2, 64>), g, dim3(256), 0, s, P->d_desc, t, P->d_store);
+          if (t32) LAUNCH(K_GEMM_SCHUR, D.c_schur, (mf::k_gemm_update<2, 32>), g, dim3(256), 0, s, t, P->d_store);
+          else LAUNCH(K_GEMM_SCHUR, D.c_schur, (mf::k_gemm_update<2, 64>), g, dim3(256), 0, s, t, P->d_store);
         } else {
-          if (t32) LAUNCH(K_GEMM_SCHUR, D.c_schur, (mf::k_gemm_update<0, 32>), g, dim3(256), 0, s, P->d_desc, t, P->d_store);
-          else LAUNCH(K_GEMM_SCHUR, D.c_schur, (mf::k_gemm_update<0, 64>), g, dim3(256), 0, s, P->d_desc, t, P->d_store);
+          if (t32) LAUNCH(K_GEMM_SCHUR, D.c_schur, (mf::k_gemm_update<0, 32>), g, dim3(256), 0, s, t, P->d_store);
+          else LAUNCH(K_GEMM_SCHUR, D.c_schur, (mf::k_gemm_update<0, 64>), g, dim3(256), 0, s, t, P->d_store);
         }
       }
     }
   }
-  if (P->n_dinv_tasks) {
-    const int grid = (int)std::min<int64_t>((P->n_dinv_tasks + 3) / 4, 65535);
-    LAUNCH(K_DIAG_INV, P->c_dinv, mf::k_diag_inverse, dim3(grid), dim3(256), 0, s, P->d_desc,
-           P->d_dinv_tasks, (int)P->n_dinv_tasks, P->d_store, P->d_dinv_off, P->d_dinv);
-  }
+  return MF_OK;
+}
+
+// Diagonal-block inverses of the tasks [lo, hi) (the tasks are ordered class by class).
+void dinv_launch(mf_plan *P, int64_t lo, int64_t hi, hipStream_t s) {
+  if (hi <= lo) return;
+  Cost c;
+  const double frac = (double)(hi - lo) / (double)std::max<int64_t>(1, P->n_dinv_tasks);
+  c.bytes = P->c_dinv.bytes * frac;
+  c.flops = P->c_dinv.flops * frac;
+  const int grid = (int)std::min<int64_t>((hi - lo + 3) / 4, 65535);
+  LAUNCH(K_DIAG_INV, c, mf::k_diag_inverse, dim3(grid), dim3(256), 0, s, P->d_desc,
+         P->d_dinv_tasks + lo, (int)(hi - lo), P->d_store, P->d_dinv_off, P->d_dinv);
+}
+
+int launch_factor(mf_plan *P, const double *K, int prec, hipStream_t s) {
+  hipLaunchKernelGGL(mf::k_clear_status, dim3(1), dim3(64), 0, s, P->d_status);
+  int rc;
+  for (size_t l = 0; l < P->lv.size(); ++l)
+    if ((rc = factor_level(P, K, prec, l, s))) return rc;
+  dinv_launch(P, 0, P->n_dinv_tasks, s);
   HIPCHK(hipGetLastError());
   return MF_OK;
 }
@@ -487,18 +534,17 @@ int chunk(const mf_plan *P, int32_t nrhs, int64_t fixed_doubles, int64_t per_col
   return nc;
 }
 
-int launch_solve(mf_plan *P, const double *b, double *x, int32_t nrhs, bool trans, hipStream_t s) {
+// The launches of class l of the forward (down) or backward sweep.
+void solve_level(mf_plan *P, const double *b, double *x, int32_t nrhs, bool trans, bool down,
+                 size_t l, hipStream_t s) {
   const int gridcap = 16384;
-  for (int pass = 0; pass < 2; ++pass) {
-    const bool down = pass == 0;
-    for (size_t step = 0; step < P->lv.size(); ++step) {
-      const size_t l = down ? step : P->lv.size() - 1 - step;
+  {
+    {
       const LevelDev &D = P->lv[l];
-      if (!D.n_all) continue;
+      if (!D.n_all) return;
       Cost c;
       c.bytes = (down ? D.down_coef : D.up_coef) + nrhs * (down ? D.down_rhs_bytes : D.up_rhs_bytes);
       c.flops = nrhs * (down ? D.down_rhs_flops : D.up_rhs_flops);
-      const int32_t *lst = P->d_lists + D.all;
       const mf::WaveRec *rec = P->d_wrec + D.rall;
       const int n = (int)D.n_all;
       const int mmax = std::max(1, D.max_m), kmax = std::max(1, D.max_k);
@@ -547,15 +593,14 @@ int launch_solve(mf_plan *P, const double *b, double *x, int32_t nrhs, bool tran
         const size_t rlds = (size_t)16 * mf::kRectLdv * 8;
 #define MF_DOWN_BLOCK(TR, FU)                                                                   \
   LAUNCH(K_DOWN_BLOCK, ct, (mf::k_solve_down_block<TR, FU>), dim3(grid), dim3(256), lds, s,     \
-         P->d_desc, lst, n, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, b, x, P->d_ycb, \
-         nrhs, nc, rmax, P->d_dinv, P->d_dinv_off)
+         rec, n, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, b, x, P->d_ycb,            \
+         nrhs, nc, rmax, P->d_dinv)
 #define MF_UP_BLOCK(TR, FU)                                                                     \
   LAUNCH(K_UP_BLOCK, ct, (mf::k_solve_up_block<TR, FU>), dim3(grid), dim3(256), lds, s,         \
-         P->d_desc, lst, n, P->d_store, P->d_front_idx, x, nrhs, nc, rmax, P->d_dinv,           \
-         P->d_dinv_off)
+         rec, n, P->d_store, P->d_front_idx, x, nrhs, nc, rmax, P->d_dinv)
 #define MF_RECT(KIND, TR, UP)                                                                   \
   LAUNCH(KIND, cr, (mf::k_solve_rect<TR, UP>), dim3((unsigned)nt), dim3(256), rlds, s,          \
-         P->d_desc, rt, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, x, P->d_ycb, nrhs)
+         P->d_wrec, rt, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, x, P->d_ycb, nrhs)
         if (down) {
           if (split) {
             if (trans) MF_DOWN_BLOCK(true, false); else MF_DOWN_BLOCK(false, false);
@@ -581,6 +626,37 @@ int launch_solve(mf_plan *P, const double *b, double *x, int32_t nrhs, bool tran
       }
     }
   }
+}
+
+int launch_solve(mf_plan *P, const double *b, double *x, int32_t nrhs, bool trans, hipStream_t s) {
+  for (size_t l = 0; l < P->lv.size(); ++l) solve_level(P, b, x, nrhs, trans, true, l, s);
+  for (size_t l = P->lv.size(); l-- > 0;) solve_level(P, b, x, nrhs, trans, false, l, s);
+  HIPCHK(hipGetLastError());
+  return MF_OK;
+}
+
+// Factorization and the solve of A x = b with the forward sweep overlapped: class l of the
+// forward sweep needs only classes <= l of the factorization (and their diagonal-block
+// inverses), so it runs on a second stream as soon as they are done, while the latency-bound
+// upper classes of the factorization occupy a fraction of the chip; the backward sweep follows
+// on s once both streams have joined.  The same kernels in the same per-class order as
+// launch_factor then launch_solve, so the results are identical.
+int launch_factor_solve(mf_plan *P, const double *K, int prec, const double *b, double *x,
+                        int32_t nrhs, hipStream_t s) {
+  hipStream_t side = P->side_stream;
+  const size_t L = P->lv.size();
+  hipLaunchKernelGGL(mf::k_clear_status, dim3(1), dim3(64), 0, s, P->d_status);
+  int rc;
+  for (size_t l = 0; l < L; ++l) {
+    if ((rc = factor_level(P, K, prec, l, s))) return rc;
+    HIPCHK(hipEventRecord(P->lvl_events[l], s));
+    HIPCHK(hipStreamWaitEvent(side, P->lvl_events[l], 0));
+    dinv_launch(P, P->dinv_lvl[l], P->dinv_lvl[l + 1], side);
+    solve_level(P, b, x, nrhs, false, true, l, side);
+  }
+  HIPCHK(hipEventRecord(P->lvl_events[L], side));
+  HIPCHK(hipStreamWaitEvent(s, P->lvl_events[L], 0));
+  for (size_t l = L; l-- > 0;) solve_level(P, b, x, nrhs, false, false, l, s);
   HIPCHK(hipGetLastError());
   return MF_OK;
 }
@@ -827,13 +903,10 @@ int mf_residual(const mf_plan *P, const double *elem_mats, const double *x, cons
   return MF_OK;
 }
 
-int mf_refine(const mf_plan *Pc, const double *elem_mats, const double *b, double *x,
-              int32_t nrhs, double tol, int32_t max_it, int32_t *its, double *relres,
-              void *hip_stream) {
-  mf_plan *P = const_cast<mf_plan *>(Pc);
-  if (!P || !elem_mats || !b || !x) return fail(MF_EINVAL, "null argument");
-  if (nrhs < 1 || max_it < 0 || !(tol >= 0)) return fail(MF_EINVAL, "bad nrhs, max_it or tol");
-  if (!P->factored) return fail(MF_ESTATE, "no valid factorization: call mf_factor first");
+// The refinement loop from x = the direct solution: residual, norms, corrections.
+static int refine_loop(mf_plan *P, const double *elem_mats, const double *b, double *x,
+                       int32_t nrhs, double tol, int32_t max_it, int32_t *its, double *relres,
+                       void *hip_stream) {
   hipStream_t s = (hipStream_t)hip_stream;
   const int64_t n = P->hp.n;
   const size_t nn = (size_t)n * nrhs;
@@ -841,7 +914,6 @@ int mf_refine(const mf_plan *Pc, const double *elem_mats, const double *b, doubl
   int rc;
   if ((rc = grow(P, P->d_work, P->work_cap, 2 * nn + 2 * parts))) return rc;
   double *r = P->d_work, *dx = P->d_work + nn;
-  if ((rc = mf_solve(P, b, x, nrhs, 0, hip_stream))) return rc;
   std::vector<double> bn, rn;
   double rr = 0.0;
   for (int32_t it = 0;; ++it) {
@@ -865,6 +937,51 @@ int mf_refine(const mf_plan *Pc, const double *elem_mats, const double *b, doubl
   std::snprintf(buf, sizeof buf, "refinement stopped after %d corrections at relres %.3e > tol %.3e",
                 max_it, rr, tol);
   return fail(MF_ENOCONV, buf);
+}
+
+int mf_refine(const mf_plan *Pc, const double *elem_mats, const double *b, double *x,
+              int32_t nrhs, double tol, int32_t max_it, int32_t *its, double *relres,
+              void *hip_stream) {
+  mf_plan *P = const_cast<mf_plan *>(Pc);
+  if (!P || !elem_mats || !b || !x) return fail(MF_EINVAL, "null argument");
+  if (nrhs < 1 || max_it < 0 || !(tol >= 0)) return fail(MF_EINVAL, "bad nrhs, max_it or tol");
+  if (!P->factored) return fail(MF_ESTATE, "no valid factorization: call mf_factor first");
+  int rc;
+  if ((rc = mf_solve(P, b, x, nrhs, 0, hip_stream))) return rc;
+  return refine_loop(P, elem_mats, b, x, nrhs, tol, max_it, its, relres, hip_stream);
+}
+
+int mf_factor_refine(mf_plan *P, const double *elem_mats, int32_t precision, const double *b,
+                     double *x, int32_t nrhs, double tol, int32_t max_it, int32_t *its,
+                     double *relres, void *hip_stream) {
+  if (!P || !elem_mats || !b || !x) return fail(MF_EINVAL, "null argument");
+  if (precision != MF_FP64 && precision != MF_SCHUR_FP32 && precision != MF_SCHUR_BF16)
+    return fail(MF_EINVAL, "unknown precision " + std::to_string(precision));
+  if (nrhs < 1 || max_it < 0 || !(tol >= 0)) return fail(MF_EINVAL, "bad nrhs, max_it or tol");
+  int rc = ensure_uploaded(P);
+  if (rc) return rc;
+  if ((rc = grow(P, P->d_ycb, P->ycb_cap, (size_t)std::max<int64_t>(1, P->hp.sum_c) * nrhs)))
+    return rc;
+  hipStream_t s = (hipStream_t)hip_stream;
+  P->factored = false;
+  GraphKey key;
+  key.p0 = elem_mats;
+  key.p1 = b;
+  key.p2 = x;
+  key.a = precision;
+  key.b = nrhs;
+  rc = run_graphed(P, P->g_fsolve, 2, P->g_fsolve_next, key, s, [&](hipStream_t st) {
+    return launch_factor_solve(P, elem_mats, precision, b, x, nrhs, st);
+  });
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(P->h_status, P->d_status, mf::kStatusWords * sizeof(int),
+                        hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (P->h_status[0])
+    return fail(MF_EZERO_PIVOT, "zero or non-finite pivot in front " + std::to_string(P->h_status[1]) +
+                                    ", pivot " + std::to_string(P->h_status[2]));
+  P->factored = true;
+  return refine_loop(P, elem_mats, b, x, nrhs, tol, max_it, its, relres, hip_stream);
 }
 
 int mf_elem_grad(const mf_plan *P, const double *lam, const double *u, int32_t nrhs, double *gK,

@@ -56,7 +56,7 @@ struct Cost {
 };
 
 struct StepDev {
-  int64_t fronts = 0, p0 = 0, n = 0;
+  int64_t prec = 0, n = 0;         // panel records (d_panel) of the step's fronts
   int64_t update = 0, n_update = 0;
   int64_t trsm_items = 0;
   Cost trsm, upd;
@@ -84,7 +84,7 @@ struct LevelDev {
   double tri_coef = 0, tri_down_rhs_bytes = 0, tri_up_rhs_bytes = 0, tri_down_flops = 0,
          tri_up_flops = 0;
   double rect_coef = 0, rect_down_rhs_bytes = 0, rect_up_rhs_bytes = 0, rect_flops = 0;
-  // rectangular-part tasks (int4: front, first row, rows, 0)
+  // rectangular-part tasks (int4: the front's wave record, first row, rows, 0)
   int64_t rdown = 0, n_rdown = 0, rup = 0, n_rup = 0;
   bool split_down = false, split_up = false;   // rectangular part in its own launch
 };
@@ -105,9 +105,11 @@ struct Profiler {
 };
 
 struct GraphKey {
-  const void *p0 = nullptr, *p1 = nullptr;
+  const void *p0 = nullptr, *p1 = nullptr, *p2 = nullptr;
   int32_t a = -1, b = -1;
-  bool operator==(const GraphKey &o) const { return p0 == o.p0 && p1 == o.p1 && a == o.a && b == o.b; }
+  bool operator==(const GraphKey &o) const {
+    return p0 == o.p0 && p1 == o.p1 && p2 == o.p2 && a == o.a && b == o.b;
+  }
 };
 
 struct Graph {
@@ -139,11 +141,13 @@ struct mf_plan {
   int32_t *d_lists = nullptr;
   mf::GemmTask *d_tasks = nullptr;
   int4 *d_rect = nullptr;
+  mf::PanelRec *d_panel = nullptr;   // panel records of every step, class after class
   mf::WaveRec *d_wrec = nullptr;   // wave records of every class's front list, class after class
   double *d_store = nullptr;
   // inverses of the diagonal blocks of the fronts the block solves handle (see k_diag_inverse)
   double *d_dinv = nullptr;
   int64_t *d_dinv_off = nullptr;
+  std::vector<int64_t> h_dinv_off;   // host copy (wave records carry it)
   int2 *d_dinv_tasks = nullptr;
   int64_t n_dinv_tasks = 0;
   mfapi::Cost c_dinv;
@@ -159,8 +163,12 @@ struct mf_plan {
   std::vector<mfapi::LevelDev> lv;
   mfapi::Profiler prof;
   hipStream_t cap_stream = nullptr;
-  mfapi::Graph g_factor[2], g_solve[4];   // small caches, least recently captured evicted
-  int g_factor_next = 0, g_solve_next = 0;
+  // second stream of the overlapped factor + forward solve, and its per-class events
+  hipStream_t side_stream = nullptr;
+  std::vector<hipEvent_t> lvl_events;
+  std::vector<int64_t> dinv_lvl;        // [classes + 1] first diagonal-inverse task per class
+  mfapi::Graph g_factor[2], g_solve[4], g_fsolve[2];   // small caches, least recently captured evicted
+  int g_factor_next = 0, g_solve_next = 0, g_fsolve_next = 0;
 
   void drop_graphs() {
     for (auto &g : g_factor) {
@@ -168,6 +176,10 @@ struct mf_plan {
       g = mfapi::Graph();
     }
     for (auto &g : g_solve) {
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+      g = mfapi::Graph();
+    }
+    for (auto &g : g_fsolve) {
       if (g.exec) (void)hipGraphExecDestroy(g.exec);
       g = mfapi::Graph();
     }
@@ -180,6 +192,8 @@ struct mf_plan {
       (void)hipEventDestroy(r.b);
     }
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (side_stream) (void)hipStreamDestroy(side_stream);
+    for (hipEvent_t e : lvl_events) (void)hipEventDestroy(e);
     mfapi::dfree(d_desc);
     mfapi::dfree(d_front_idx);
     mfapi::dfree(d_inv_l);
@@ -191,6 +205,7 @@ struct mf_plan {
     mfapi::dfree(d_tasks);
     mfapi::dfree(d_rect);
     mfapi::dfree(d_wrec);
+    mfapi::dfree(d_panel);
     mfapi::dfree(d_store);
     mfapi::dfree(d_dinv);
     mfapi::dfree(d_dinv_off);

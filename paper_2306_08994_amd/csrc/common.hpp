@@ -58,38 +58,21 @@ struct GatherCtx {
   int na, nb;         // contribution-block sizes of the two sources (a leaf: npe, 0)
 };
 
-__device__ inline GatherCtx gather_ctx(const FrontDesc *__restrict__ fd, const FrontDesc &d,
-                                       const double *__restrict__ store,
-                                       const double *__restrict__ K, int npe) {
+// Extend-add sources of a front from its wave record: a leaf (no second source) reads its
+// element matrix.
+__device__ inline GatherCtx rec_gather_ctx(const WaveRec &r, const double *__restrict__ store,
+                                           const double *__restrict__ K) {
   GatherCtx g;
-  g.npe = npe;
-  g.ke = nullptr;
-  g.ca = g.cb = nullptr;
-  g.la = g.lb = 0;
-  g.na = g.nb = 0;
-  if (d.elem >= 0) {
-    g.ke = K + (int64_t)d.elem * npe * npe;
-    g.ca = g.ke;
-    g.la = g.na = npe;
-    return g;
-  }
-  const FrontDesc a = fd[d.left], b = fd[d.right];
-  if (passthrough(a)) {
-    g.ca = K + (int64_t)a.elem * npe * npe;
-    g.la = g.na = npe;
-  } else {
-    g.ca = store + a.store + (int64_t)a.k * a.m + a.k;
-    g.la = a.m;
-    g.na = a.m - a.k;
-  }
-  if (passthrough(b)) {
-    g.cb = K + (int64_t)b.elem * npe * npe;
-    g.lb = g.nb = npe;
-  } else {
-    g.cb = store + b.store + (int64_t)b.k * b.m + b.k;
-    g.lb = b.m;
-    g.nb = b.m - b.k;
-  }
+  const double *s0 = r.src[0] >= 0 ? store + r.src[0] : K + (-1 - r.src[0]);
+  const double *s1 = r.src[1] >= 0 ? store + r.src[1] : K + (-1 - r.src[1]);
+  g.npe = r.ld[0];
+  g.ke = r.n[1] > 0 ? nullptr : s0;
+  g.ca = s0;
+  g.la = r.ld[0];
+  g.na = r.n[0];
+  g.cb = r.n[1] > 0 ? s1 : nullptr;
+  g.lb = r.ld[1];
+  g.nb = r.n[1];
   return g;
 }
 

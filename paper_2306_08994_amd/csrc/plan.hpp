@@ -23,7 +23,7 @@ static_assert(sizeof(FrontDesc) == 48, "FrontDesc layout");
 // Per-front record of the one-wave-per-front kernels (the tiny factor route and the wave
 // solves), one per entry of a class's front list: everything the wave needs before its first
 // gather, so that the record (uniform, scalar loads), then the maps and the sources in one
-// round trip, are the whole dependency chain.  88 bytes.
+// round trip, are the whole dependency chain.  96 bytes.
 struct WaveRec {
   int64_t store;    // offset (doubles) of the front's m x m storage
   int64_t idx;      // offset into front_idx / inv_l / inv_r
@@ -31,23 +31,36 @@ struct WaveRec {
   int64_t src[2];   // extend-add sources: >= 0 offset (doubles) into the store of a child's CB
                     // (its (k, k) entry); < 0: -1 - offset of an element matrix in K
   int64_t ycb[2];   // first CB-buffer row of each child that passes one to the solve, else -1
+  int64_t dinv;     // offset of the front's diagonal-block inverses (block solves), else -1
   int32_t f;        // front id
   int32_t m, k;     // width and pivots
   int32_t ld[2];    // leading dimension of each source
   int32_t n[2];     // size of each (square) source, 0 = absent
   int32_t pad;
 };
-static_assert(sizeof(WaveRec) == 88, "WaveRec layout");
+static_assert(sizeof(WaveRec) == 96, "WaveRec layout");
 
 // One tile of a batched GEMM update  C[i0:i1, j0:j1] -= A[i0:i1, q0:q1] * B[q0:q1, j0:j1],
-// where A, B and C are all views of the same front storage (row-major, leading dimension m).
+// where A, B and C are all views of the same front storage (row-major, leading dimension ld,
+// at offset store), so that the task alone locates its operands.
 struct GemmTask {
-  int32_t front;
+  int64_t store;
+  int32_t ld;
   int32_t i0, i1, j0, j1;
   int32_t q0, q1;
-  int32_t pad;
+  int32_t front;
 };
-static_assert(sizeof(GemmTask) == 32, "GemmTask layout");
+static_assert(sizeof(GemmTask) == 40, "GemmTask layout");
+
+// One front of a panel step of the tiled route: everything the panel kernel needs in one
+// record.  24 bytes.
+struct PanelRec {
+  int64_t store;    // offset (doubles) of the front's storage
+  int32_t m, k;     // width and pivots
+  int32_t p0;       // first pivot of the panel
+  int32_t f;        // front id
+};
+static_assert(sizeof(PanelRec) == 24, "PanelRec layout");
 
 // Work of one panel step of the tiled (HBM-resident) path inside one class.
 struct PanelStep {

@@ -409,12 +409,11 @@ __device__ inline void block_matvec(const double *Ms, const double *W, int ldw, 
 // this kernel in the down sweep, before it in the up sweep).
 template <bool TRANS, bool FULL>
 __global__ void __launch_bounds__(256)
-k_solve_down_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ list, int nlist,
+k_solve_down_block(const WaveRec *__restrict__ recs, int nrec,
                    const double *__restrict__ store, const int32_t *__restrict__ front_idx,
                    const int32_t *__restrict__ inv_l, const int32_t *__restrict__ inv_r,
                    const double *b, double *x, double *__restrict__ ycb, int nrhs, int nc,
-                   int rmax, const double *__restrict__ dinv,
-                   const int64_t *__restrict__ dinv_off) {
+                   int rmax, const double *__restrict__ dinv) {
   extern __shared__ double sm[];
   const int ldw = (rmax + NBS) | 1;
   double *W = sm;
@@ -422,9 +421,8 @@ k_solve_down_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__
   double *T = Ms + NBS * (NBS + 1);
   double *Y = T + kTileRows * (NBS + 1);
   const int tid = threadIdx.x;
-  for (int li = blockIdx.x; li < nlist; li += gridDim.x) {
-    const int f = list[li];
-    const FrontDesc d = fd[f];
+  for (int li = blockIdx.x; li < nrec; li += gridDim.x) {
+    const WaveRec d = recs[li];
     const int m = d.m, k = d.k;
     const int rows = FULL ? m : k;          // rows this kernel solves for
     if (rows == 0) continue;
@@ -432,13 +430,9 @@ k_solve_down_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__
     const int32_t *il = inv_l + d.idx;
     const int32_t *ir = inv_r + d.idx;
     const double *F = store + d.store;
-    const double *dv = k > 0 ? dinv + dinv_off[f] : nullptr;
-    FrontDesc a = d, c = d;
-    if (d.elem < 0) {
-      a = fd[d.left];
-      c = fd[d.right];
-    }
-    const bool use_a = d.elem < 0 && !passthrough(a), use_c = d.elem < 0 && !passthrough(c);
+    const double *dv = k > 0 ? dinv + d.dinv : nullptr;
+    // children that pass a contribution block (a pass-through leaf passes none)
+    const bool use_a = d.ycb[0] >= 0, use_c = d.ycb[1] >= 0;
     for (int r0 = 0; r0 < nrhs; r0 += nc) {
       const int nr = min(nc, nrhs - r0);
       double mv[kInvPerThread], pre[kTileLoads];
@@ -452,8 +446,8 @@ k_solve_down_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__
         const int x0 = use_a ? il[i] : -1, y0 = use_c ? ir[i] : -1;
         for (int r = 0; r < nr; ++r) {
           double v = i < k ? b[gi * nrhs + r0 + r] : 0.0;
-          if (x0 >= 0) v += ycb[(a.cbrow + x0) * nrhs + r0 + r];
-          if (y0 >= 0) v += ycb[(c.cbrow + y0) * nrhs + r0 + r];
+          if (x0 >= 0) v += ycb[(d.ycb[0] + x0) * nrhs + r0 + r];
+          if (y0 >= 0) v += ycb[(d.ycb[1] + y0) * nrhs + r0 + r];
           W[r * ldw + i] = v;
         }
       }
@@ -495,10 +489,9 @@ k_solve_down_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__
 
 template <bool TRANS, bool FULL>
 __global__ void __launch_bounds__(256)
-k_solve_up_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ list, int nlist,
+k_solve_up_block(const WaveRec *__restrict__ recs, int nrec,
                  const double *__restrict__ store, const int32_t *__restrict__ front_idx,
-                 double *x, int nrhs, int nc, int rmax, const double *__restrict__ dinv,
-                 const int64_t *__restrict__ dinv_off) {
+                 double *x, int nrhs, int nc, int rmax, const double *__restrict__ dinv) {
   extern __shared__ double sm[];
   const int ldw = (rmax + NBS) | 1;
   double *W = sm;
@@ -506,15 +499,14 @@ k_solve_up_block(const FrontDesc *__restrict__ fd, const int32_t *__restrict__ l
   double *T = Ms + NBS * (NBS + 1);
   double *Y = T + kTileRows * (NBS + 1);
   const int tid = threadIdx.x;
-  for (int li = blockIdx.x; li < nlist; li += gridDim.x) {
-    const int f = list[li];
-    const FrontDesc d = fd[f];
+  for (int li = blockIdx.x; li < nrec; li += gridDim.x) {
+    const WaveRec d = recs[li];
     const int m = d.m, k = d.k;
     if (k == 0) continue;
     const int rows = FULL ? m : k;          // rows of W: the pivots (+ the CB values if FULL)
     const int32_t *idx = front_idx + d.idx;
     const double *F = store + d.store;
-    const double *dv = dinv + dinv_off[f];
+    const double *dv = dinv + d.dinv;
     const int plast = ((k - 1) / NBS) * NBS;
     const bool cb = FULL && k < m;
     for (int r0 = 0; r0 < nrhs; r0 += nc) {
@@ -588,25 +580,20 @@ constexpr int kRectLdv = kRectCols + 4;
 
 template <bool TRANS, bool UP>
 __global__ void __launch_bounds__(256)
-k_solve_rect(const FrontDesc *__restrict__ fd, const int4 *__restrict__ tasks,
+k_solve_rect(const WaveRec *__restrict__ recs, const int4 *__restrict__ tasks,
              const double *__restrict__ store, const int32_t *__restrict__ front_idx,
              const int32_t *__restrict__ inv_l, const int32_t *__restrict__ inv_r, double *x,
              double *ycb, int nrhs) {
   extern __shared__ double sm[];
   double *V = sm;
   const int4 tk = tasks[blockIdx.x];
-  const FrontDesc d = fd[tk.x];
+  const WaveRec d = recs[tk.x];
   const int m = d.m, k = d.k, row0 = tk.y, rows = tk.z;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, li = lane & 15, lk = lane >> 4;
   const int plo = UP ? k : 0, phi = UP ? m : k;
   const double *F = store + d.store;
   const int32_t *idx = front_idx + d.idx;
   const int arow = row0 + min(16 * wv + li, rows - 1);     // this lane's A-operand row
-  FrontDesc ca = d, cc = d;
-  if (!UP && d.elem < 0) {
-    ca = fd[d.left];
-    cc = fd[d.right];
-  }
   for (int r0 = 0; r0 < nrhs; r0 += 16) {
     const int nr = min(16, nrhs - r0), col = li;
     // the values the product is combined with, for this lane's four result entries
@@ -618,10 +605,12 @@ k_solve_rect(const FrontDesc *__restrict__ fd, const int4 *__restrict__ tasks,
       if (orow < rows && col < nr) {
         if (UP) {
           base[r] = x[(int64_t)idx[row] * nrhs + r0 + col];
-        } else if (d.elem < 0) {
-          const int xa = inv_l[d.idx + row], xc = inv_r[d.idx + row];
-          if (xa >= 0 && !passthrough(ca)) base[r] += ycb[(ca.cbrow + xa) * nrhs + r0 + col];
-          if (xc >= 0 && !passthrough(cc)) base[r] += ycb[(cc.cbrow + xc) * nrhs + r0 + col];
+        } else {
+          // children that pass a contribution block (none for a leaf or a pass-through leaf)
+          const int xa = d.ycb[0] >= 0 ? inv_l[d.idx + row] : -1;
+          const int xc = d.ycb[1] >= 0 ? inv_r[d.idx + row] : -1;
+          if (xa >= 0) base[r] += ycb[(d.ycb[0] + xa) * nrhs + r0 + col];
+          if (xc >= 0) base[r] += ycb[(d.ycb[1] + xc) * nrhs + r0 + col];
         }
       }
     }

@@ -167,6 +167,25 @@ class Plan:
                                     _stream()))
         return x.reshape(b.shape), int(its.value), float(rr.value)
 
+    def factor_refine(self, K, b, precision: str = "fp64", tol: float = 1e-12, max_it: int = 30,
+                      x=None):
+        """factor(K, precision) then refine(K, b) in one call, the first forward sweep overlapped
+        with the factorization (see mf_factor_refine); returns (x, corrections, relres)."""
+        import torch
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+        b2 = b if b.dim() == 2 else b.reshape(-1, 1)
+        nrhs = int(b2.shape[1])
+        x = torch.empty_like(b2) if x is None else x.reshape(self.n, nrhs)
+        its = ctypes.c_int32(0)
+        rr = ctypes.c_double(0.0)
+        self.factor_version += 1
+        check(_lib.load().mf_factor_refine(
+            self._h, _dev_ptr(K, "K", (self.n_elem, self.npe, self.npe)), PRECISIONS[precision],
+            _dev_ptr(b2, "b", (self.n, nrhs)), _dev_ptr(x, "x"), nrhs, float(tol), int(max_it),
+            ctypes.byref(its), ctypes.byref(rr), _stream()))
+        return x.reshape(b.shape), int(its.value), float(rr.value)
+
     def elem_grad(self, lam, u):
         import torch
         lam2 = lam if lam.dim() == 2 else lam.reshape(-1, 1)
