@@ -86,7 +86,8 @@ typedef struct {
  * CBs (a leaf: of its element's nodes).  Index list: pivots ascending, then CB ascending
  * (pivots first, Sec. 3.2).  Foata class (Sec. 3.3) = height above the leaves.
  * meshes: host array of n_mesh descriptors (read only during the call).
- * out: receives a new plan; release it with mf_destroy.
+ * out: receives a new plan; release it with mf_destroy.  The plan replays its per-class launch
+ * sequences as captured hipGraphs unless the environment holds MF_GRAPHS=0 when it is created.
  * Errors: MF_EINVAL (bad sizes, ids out of range, duplicate elem_ijk, unused node), MF_ENOMEM. */
 int mf_analyse(int32_t n_mesh, const mf_mesh *meshes, mf_plan **out);
 
@@ -183,6 +184,7 @@ int mf_refine(const mf_plan *plan, const double *elem_mats, const double *b, dou
  * on a second stream of the plan while the upper classes are still being factored; the
  * backward sweep and the refinement loop follow on hip_stream.  The same kernels in the same
  * per-class order as mf_factor then mf_refine, so x and the factors are identical to theirs.
+ * Launched eagerly (not as a captured graph), so that the two streams overlap.
  * Arguments and errors: those of mf_factor and mf_refine (MF_EZERO_PIVOT leaves no valid
  * factor and x unspecified).  Synchronizes hip_stream at least twice. */
 int mf_factor_refine(mf_plan *plan, const double *elem_mats, int32_t precision, const double *b,

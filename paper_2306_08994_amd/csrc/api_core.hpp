@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -105,11 +106,9 @@ struct Profiler {
 };
 
 struct GraphKey {
-  const void *p0 = nullptr, *p1 = nullptr, *p2 = nullptr;
+  const void *p0 = nullptr, *p1 = nullptr;
   int32_t a = -1, b = -1;
-  bool operator==(const GraphKey &o) const {
-    return p0 == o.p0 && p1 == o.p1 && p2 == o.p2 && a == o.a && b == o.b;
-  }
+  bool operator==(const GraphKey &o) const { return p0 == o.p0 && p1 == o.p1 && a == o.a && b == o.b; }
 };
 
 struct Graph {
@@ -167,8 +166,8 @@ struct mf_plan {
   hipStream_t side_stream = nullptr;
   std::vector<hipEvent_t> lvl_events;
   std::vector<int64_t> dinv_lvl;        // [classes + 1] first diagonal-inverse task per class
-  mfapi::Graph g_factor[2], g_solve[4], g_fsolve[2];   // small caches, least recently captured evicted
-  int g_factor_next = 0, g_solve_next = 0, g_fsolve_next = 0;
+  mfapi::Graph g_factor[2], g_solve[4];   // small caches, least recently captured evicted
+  int g_factor_next = 0, g_solve_next = 0;
 
   void drop_graphs() {
     for (auto &g : g_factor) {
@@ -176,10 +175,6 @@ struct mf_plan {
       g = mfapi::Graph();
     }
     for (auto &g : g_solve) {
-      if (g.exec) (void)hipGraphExecDestroy(g.exec);
-      g = mfapi::Graph();
-    }
-    for (auto &g : g_fsolve) {
       if (g.exec) (void)hipGraphExecDestroy(g.exec);
       g = mfapi::Graph();
     }

@@ -221,11 +221,18 @@ k_assemble(const WaveRec *__restrict__ recs, double *__restrict__ store,
   __syncthreads();
   const GatherCtx g = rec_gather_ctx(d, store, K);
   double *F = store + d.store;
-  const int i1 = min(i0 + 4, m);
-  for (int i = i0; i < i1; ++i) {
-    const int li = sl[i], ri = sr[i];
-    for (int j = threadIdx.x; j < m; j += 256)
-      F[(int64_t)i * m + j] = gather_entry(g, li, sl[j], ri, sr[j]);
+  // per column of this thread: the strip's four entries gathered together, then stored
+  for (int j = threadIdx.x; j < m; j += 256) {
+    const int lj = sl[j], rj = sr[j];
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = min(i0 + u, m - 1);
+      v[u] = gather_entry(g, sl[i], lj, sr[i], rj);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i0 + u < m) F[(int64_t)(i0 + u) * m + j] = v[u];
   }
 }
 

@@ -54,6 +54,10 @@ constexpr int kWaveRows = 64;
 
 // Loads n values v[u] = src[u * stride], u < n, eight independent loads at a time, into
 // dst[u * dstride] (LDS).
+// Right-hand-side columns gathered per batch: the loads of a batch are issued together before
+// any of them is used (a loop of load-then-store waits for every load in turn).
+constexpr int kRhsBatch = 8;
+
 __device__ inline void copy_strided(const double *__restrict__ src, int64_t stride, int n,
                                     double *dst, int dstride) {
   for (int u0 = 0; u0 < n; u0 += 8) {
@@ -103,11 +107,21 @@ k_solve_down_wave(const WaveRec *__restrict__ recs, int nrec,
     for (int r0 = 0; r0 < nrhs; r0 += nc) {
       const int nr = min(nc, nrhs - r0);
       if (i < m)
-        for (int r = 0; r < nr; ++r) {
-          double v = i < k ? b[gi * nrhs + r0 + r] : 0.0;
-          if (xa >= 0) v += ycb[(d.ycb[0] + xa) * nrhs + r0 + r];
-          if (xc >= 0) v += ycb[(d.ycb[1] + xc) * nrhs + r0 + r];
-          W[i * nr + r] = v;
+        for (int rb = 0; rb < nr; rb += kRhsBatch) {     // loads of a batch in flight together
+          double v[kRhsBatch];
+#pragma unroll
+          for (int u = 0; u < kRhsBatch; ++u) {
+            const int r = rb + u;
+            v[u] = 0.0;
+            if (r < nr) {
+              if (i < k) v[u] = b[gi * nrhs + r0 + r];
+              if (xa >= 0) v[u] += ycb[(d.ycb[0] + xa) * nrhs + r0 + r];
+              if (xc >= 0) v[u] += ycb[(d.ycb[1] + xc) * nrhs + r0 + r];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < kRhsBatch; ++u)
+            if (rb + u < nr) W[i * nr + rb + u] = v[u];
         }
       wave_sync();
       for (int p = 0; p < k; ++p) {
@@ -158,7 +172,14 @@ k_solve_up_wave(const WaveRec *__restrict__ recs, int nrec,
     for (int r0 = 0; r0 < nrhs; r0 += nc) {
       const int nr = min(nc, nrhs - r0);
       if (j < m)
-        for (int r = 0; r < nr; ++r) W[j * nr + r] = x[gj * nrhs + r0 + r];
+        for (int rb = 0; rb < nr; rb += kRhsBatch) {
+          double v[kRhsBatch];
+#pragma unroll
+          for (int u = 0; u < kRhsBatch; ++u) v[u] = rb + u < nr ? x[gj * nrhs + r0 + rb + u] : 0.0;
+#pragma unroll
+          for (int u = 0; u < kRhsBatch; ++u)
+            if (rb + u < nr) W[j * nr + rb + u] = v[u];
+        }
       wave_sync();
       // the already-final CB unknowns applied to the pivot rows
       for (int t = lane; t < k * nr; t += 64) {
@@ -201,36 +222,57 @@ k_diag_inverse(const FrontDesc *__restrict__ fd, const int2 *__restrict__ tasks,
                const double *__restrict__ store, const int64_t *__restrict__ dinv_off,
                double *__restrict__ dinv) {
   __shared__ double Bs[4][NBS][NBS + 1];
+  __shared__ double Rs[4][NBS];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   double(*B)[NBS + 1] = Bs[wv];
+  double *rdg = Rs[wv];
   const int j = lane & (NBS - 1);
   for (int t = blockIdx.x * 4 + wv; t < ntasks; t += gridDim.x * 4) {
     const int2 tk = tasks[t];
     const FrontDesc d = fd[tk.x];
     const int p0 = tk.y, pb = min(NBS, d.k - p0);
     const double *F = store + d.store + (int64_t)p0 * d.m + p0;
-    for (int e = lane; e < NBS * NBS; e += 64) {
-      const int i = e / NBS, c = e % NBS;
-      B[i][c] = (i < pb && c < pb) ? F[(int64_t)i * d.m + c] : (i == c ? 1.0 : 0.0);
+    // the block's 16 entries per lane loaded together, then staged (one round trip)
+    double v[NBS * NBS / 64];
+#pragma unroll
+    for (int u = 0; u < NBS * NBS / 64; ++u) {
+      const int e = lane + 64 * u, i = e / NBS, c = e % NBS;
+      v[u] = (i < pb && c < pb) ? F[(int64_t)i * d.m + c] : (i == c ? 1.0 : 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < NBS * NBS / 64; ++u) {
+      const int e = lane + 64 * u;
+      B[e / NBS][e % NBS] = v[u];
     }
     wave_sync();
+    if (lane < NBS) rdg[lane] = 1.0 / B[lane][lane];   // the pivots' reciprocals, all at once
+    wave_sync();
+    // substitutions with two partial sums per row (half the dependent chain of one sum)
     double z[NBS];
     if (lane < NBS) {
 #pragma unroll
       for (int i = 0; i < NBS; ++i) {          // L z = e_j
-        double s = (i == j) ? 1.0 : 0.0;
+        double s0 = (i == j) ? 1.0 : 0.0, s1 = 0.0;
 #pragma unroll
-        for (int p = 0; p < i; ++p) s -= B[i][p] * z[p];
-        z[i] = s / B[i][i];
+        for (int p = 0; p + 1 < i; p += 2) {
+          s0 -= B[i][p] * z[p];
+          s1 -= B[i][p + 1] * z[p + 1];
+        }
+        if (i & 1) s0 -= B[i][i - 1] * z[i - 1];
+        z[i] = (s0 + s1) * rdg[i];
       }
     } else {
 #pragma unroll
       for (int i = NBS - 1; i >= 0; --i) {     // U z = e_j, unit diagonal
-        double s = (i == j) ? 1.0 : 0.0;
+        double s0 = (i == j) ? 1.0 : 0.0, s1 = 0.0;
 #pragma unroll
-        for (int p = i + 1; p < NBS; ++p) s -= B[i][p] * z[p];
-        z[i] = s;
+        for (int p = i + 1; p + 1 < NBS; p += 2) {
+          s0 -= B[i][p] * z[p];
+          s1 -= B[i][p + 1] * z[p + 1];
+        }
+        if ((NBS - 1 - i) & 1) s0 -= B[i][NBS - 1] * z[NBS - 1];
+        z[i] = s0 + s1;
       }
     }
     double *out = dinv + dinv_off[tk.x] + (int64_t)(p0 / NBS) * 2 * NBS * NBS +
@@ -444,11 +486,21 @@ k_solve_down_block(const WaveRec *__restrict__ recs, int nrec,
       for (int i = tid; i < rows; i += 256) {
         const int64_t gi = idx[i];
         const int x0 = use_a ? il[i] : -1, y0 = use_c ? ir[i] : -1;
-        for (int r = 0; r < nr; ++r) {
-          double v = i < k ? b[gi * nrhs + r0 + r] : 0.0;
-          if (x0 >= 0) v += ycb[(d.ycb[0] + x0) * nrhs + r0 + r];
-          if (y0 >= 0) v += ycb[(d.ycb[1] + y0) * nrhs + r0 + r];
-          W[r * ldw + i] = v;
+        for (int rb = 0; rb < nr; rb += kRhsBatch) {     // loads of a batch in flight together
+          double v[kRhsBatch];
+#pragma unroll
+          for (int u = 0; u < kRhsBatch; ++u) {
+            const int r = rb + u;
+            v[u] = 0.0;
+            if (r < nr) {
+              if (i < k) v[u] = b[gi * nrhs + r0 + r];
+              if (x0 >= 0) v[u] += ycb[(d.ycb[0] + x0) * nrhs + r0 + r];
+              if (y0 >= 0) v[u] += ycb[(d.ycb[1] + y0) * nrhs + r0 + r];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < kRhsBatch; ++u)
+            if (rb + u < nr) W[(rb + u) * ldw + i] = v[u];
         }
       }
       for (int t = tid; t < NBS * nr; t += 256) W[(t / NBS) * ldw + rows + t % NBS] = 0.0;
@@ -519,7 +571,14 @@ k_solve_up_block(const WaveRec *__restrict__ recs, int nrec,
         tile_load<TRANS>(F, m, 0, plast, plast, tid, pre);
       for (int i = tid; i < rows; i += 256) {
         const int64_t gi = idx[i];
-        for (int r = 0; r < nr; ++r) W[r * ldw + i] = x[gi * nrhs + r0 + r];
+        for (int rb = 0; rb < nr; rb += kRhsBatch) {
+          double v[kRhsBatch];
+#pragma unroll
+          for (int u = 0; u < kRhsBatch; ++u) v[u] = rb + u < nr ? x[gi * nrhs + r0 + rb + u] : 0.0;
+#pragma unroll
+          for (int u = 0; u < kRhsBatch; ++u)
+            if (rb + u < nr) W[(rb + u) * ldw + i] = v[u];
+        }
       }
       for (int t = tid; t < NBS * nr; t += 256) W[(t / NBS) * ldw + rows + t % NBS] = 0.0;
       if (cb) {
@@ -661,13 +720,33 @@ k_residual(const int64_t *__restrict__ nptr, const int32_t *__restrict__ nelem,
   if (t >= n * nrhs) return;
   const int64_t v = t / nrhs;
   const int c = (int)(t - v * nrhs);
+  // the same sum in the same order, with the loads of a batch of (element, node) pairs and of
+  // eight element columns issued together rather than one dependent chain per term
   double s = 0.0;
-  for (int64_t q = nptr[v]; q < nptr[v + 1]; ++q) {
-    const int32_t ea = nelem[q];
-    const int32_t e = ea / npe, a = ea - (ea / npe) * npe;
-    const double *Ke = K + ((int64_t)e * npe + a) * npe;
-    const int32_t *ce = conn + (int64_t)e * npe;
-    for (int bb = 0; bb < npe; ++bb) s += Ke[bb] * x[(int64_t)ce[bb] * nrhs + c];
+  const int64_t q0 = nptr[v], nq = nptr[v + 1] - q0;
+  for (int64_t qb = 0; qb < nq; qb += 4) {
+    int32_t ea[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) ea[u] = qb + u < nq ? nelem[q0 + qb + u] : 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (qb + u >= nq) break;
+      const int32_t e = ea[u] / npe, a = ea[u] - (ea[u] / npe) * npe;
+      const double *Ke = K + ((int64_t)e * npe + a) * npe;
+      const int32_t *ce = conn + (int64_t)e * npe;
+      for (int b0 = 0; b0 < npe; b0 += 8) {
+        double kv[8], xv[8];
+#pragma unroll
+        for (int w = 0; w < 8; ++w) {
+          const bool in = b0 + w < npe;
+          kv[w] = in ? Ke[b0 + w] : 0.0;
+          xv[w] = in ? x[(int64_t)ce[b0 + w] * nrhs + c] : 0.0;
+        }
+#pragma unroll
+        for (int w = 0; w < 8; ++w)
+          if (b0 + w < npe) s += kv[w] * xv[w];
+      }
+    }
   }
   r[t] = b[t] - s;
 }

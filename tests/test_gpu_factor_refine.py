@@ -1,8 +1,8 @@
 """mf_factor_refine: the factorization and the refined solve in one call, with the forward sweep
 of the first solve overlapped with the factorization on a second stream.  The same kernels run
 in the same per-class order as mf_factor followed by mf_refine, so the factors and x must be
-bit-identical to those two calls (eager and graph-replayed), and the refined solution meets the
-residual bar against the oracle's operator."""
+bit-identical to those two calls (replayed from their captured graphs or launched eagerly), and
+the refined solution meets the residual bar against the oracle's operator."""
 import numpy as np
 import pytest
 
@@ -44,7 +44,7 @@ def test_equals_factor_then_refine(case, prec):
     plan, K, b = _plan(p, tuning)
     ref_plan, _, _ = _plan(p, tuning)
     x = torch.empty_like(b)
-    for rep in range(3):                          # first call captures, later ones replay
+    for rep in range(3):                          # repeated calls on the same buffers
         Kr = (K * (1.0 + 0.5 * rep)).contiguous()
         ref_plan.factor(Kr, prec)
         xr, itr, rrr = ref_plan.refine(Kr, b, tol=1e-12, max_it=30)
@@ -61,11 +61,11 @@ def test_equals_factor_then_refine(case, prec):
         plan.solve(b)                             # eager work between the replays
 
 
-def test_eager_equals_graph():
+def test_equals_profiled_run():
     import torch
     p, tuning = _problem("2d-tiled")
     plan, K, b = _plan(p, tuning)
-    plan.profile(True)                            # launches run eagerly, streams and events alike
+    plan.profile(True)                            # every launch bracketed by events
     xe, ite, rre = plan.factor_refine(K, b)
     xe = xe.clone()
     plan.profile(False)
