@@ -125,17 +125,24 @@ k_panel_trsm(const PanelRec *__restrict__ recs, double *__restrict__ store,
                      nact == 1);
   __syncthreads();
   if (has) {
+    // each step reads its row (column) of D into registers first, the reads issued together,
+    // then its products: one LDS round trip per step, overlapped with the previous step
+    double dr[NB];
     if (colitem) {
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
+#pragma unroll
+        for (int r = 0; r < q; ++r) dr[r] = D[q][r];
+        const double rq = rd[q];
+        __builtin_amdgcn_sched_barrier(0);
         double s0 = v[q], s1 = 0.0;
 #pragma unroll
         for (int r = 0; r + 1 < q; r += 2) {
-          s0 -= D[q][r] * v[r];
-          s1 -= D[q][r + 1] * v[r + 1];
+          s0 -= dr[r] * v[r];
+          s1 -= dr[r + 1] * v[r + 1];
         }
-        if (q & 1) s0 -= D[q][q - 1] * v[q - 1];
-        v[q] = (s0 + s1) * rd[q];
+        if (q & 1) s0 -= dr[q - 1] * v[q - 1];
+        v[q] = (s0 + s1) * rq;
       }
       if (pb == NB) {
 #pragma unroll
@@ -148,13 +155,16 @@ k_panel_trsm(const PanelRec *__restrict__ recs, double *__restrict__ store,
     } else {
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
+#pragma unroll
+        for (int r = 0; r < q; ++r) dr[r] = D[r][q];
+        __builtin_amdgcn_sched_barrier(0);
         double s0 = v[q], s1 = 0.0;
 #pragma unroll
         for (int r = 0; r + 1 < q; r += 2) {
-          s0 -= v[r] * D[r][q];
-          s1 -= v[r + 1] * D[r + 1][q];
+          s0 -= v[r] * dr[r];
+          s1 -= v[r + 1] * dr[r + 1];
         }
-        if (q & 1) s0 -= v[q - 1] * D[q - 1][q];
+        if (q & 1) s0 -= v[q - 1] * dr[q - 1];
         v[q] = s0 + s1;
       }
       if (pb == NB) {

@@ -225,8 +225,11 @@ k_diag_inverse(const FrontDesc *__restrict__ fd, const int2 *__restrict__ tasks,
   __shared__ double Rs[4][NBS];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
-  double(*B)[NBS + 1] = Bs[wv];
-  double *rdg = Rs[wv];
+  // LDS base in a vector register (threadIdx-derived), so every block entry is an immediate
+  // offset from it instead of a separately materialized uniform address
+  const int wl = threadIdx.x >> 6;
+  double(*B)[NBS + 1] = Bs[wl];
+  double *rdg = Rs[wl];
   const int j = lane & (NBS - 1);
   for (int t = blockIdx.x * 4 + wv; t < ntasks; t += gridDim.x * 4) {
     const int2 tk = tasks[t];
@@ -248,30 +251,39 @@ k_diag_inverse(const FrontDesc *__restrict__ fd, const int2 *__restrict__ tasks,
     wave_sync();
     if (lane < NBS) rdg[lane] = 1.0 / B[lane][lane];   // the pivots' reciprocals, all at once
     wave_sync();
-    // substitutions with two partial sums per row (half the dependent chain of one sum)
+    // substitutions with two partial sums per row (half the dependent chain of one sum); each
+    // row of the block is read from LDS into registers as a whole (its reads issued together)
+    // before its products, so a row costs one LDS round trip rather than one per entry
     double z[NBS];
+    double br[NBS];
     if (lane < NBS) {
 #pragma unroll
       for (int i = 0; i < NBS; ++i) {          // L z = e_j
+#pragma unroll
+        for (int p = 0; p < i; ++p) br[p] = B[i][p];
+        __builtin_amdgcn_sched_barrier(0);     // the row's reads are issued before its products
         double s0 = (i == j) ? 1.0 : 0.0, s1 = 0.0;
 #pragma unroll
         for (int p = 0; p + 1 < i; p += 2) {
-          s0 -= B[i][p] * z[p];
-          s1 -= B[i][p + 1] * z[p + 1];
+          s0 -= br[p] * z[p];
+          s1 -= br[p + 1] * z[p + 1];
         }
-        if (i & 1) s0 -= B[i][i - 1] * z[i - 1];
+        if (i & 1) s0 -= br[i - 1] * z[i - 1];
         z[i] = (s0 + s1) * rdg[i];
       }
     } else {
 #pragma unroll
       for (int i = NBS - 1; i >= 0; --i) {     // U z = e_j, unit diagonal
+#pragma unroll
+        for (int p = i + 1; p < NBS; ++p) br[p] = B[i][p];
+        __builtin_amdgcn_sched_barrier(0);
         double s0 = (i == j) ? 1.0 : 0.0, s1 = 0.0;
 #pragma unroll
         for (int p = i + 1; p + 1 < NBS; p += 2) {
-          s0 -= B[i][p] * z[p];
-          s1 -= B[i][p + 1] * z[p + 1];
+          s0 -= br[p] * z[p];
+          s1 -= br[p + 1] * z[p + 1];
         }
-        if ((NBS - 1 - i) & 1) s0 -= B[i][NBS - 1] * z[NBS - 1];
+        if ((NBS - 1 - i) & 1) s0 -= br[NBS - 1] * z[NBS - 1];
         z[i] = s0 + s1;
       }
     }
@@ -634,6 +646,7 @@ k_solve_up_block(const WaveRec *__restrict__ recs, int nrec,
 // Right-hand sides in chunks of 16.  LDS: V (16 x kRectCols + 4).
 // ---------------------------------------------------------------------------------------------
 constexpr int kRectCols = 256;   // columns per group (64 MFMA steps of 4)
+static_assert(kRectCols == 256, "one staged column per thread of the rectangular kernel");
 constexpr int kRectRows = 64;    // output rows per task (4 waves x 16)
 constexpr int kRectLdv = kRectCols + 4;
 
@@ -681,11 +694,16 @@ k_solve_rect(const WaveRec *__restrict__ recs, const int4 *__restrict__ tasks,
         const int p = min(c0 + 4 * s + lk, phi - 1);
         av[s] = TRANS ? F[(int64_t)p * m + arow] : F[(int64_t)arow * m + p];
       }
+      // thread t stages column p = c0 + t of the group (kRectCols = 256 threads): its 16
+      // right-hand-side values, one contiguous row of x, loaded together
+      const int pv = c0 + tid;
+      const int64_t gp = pv < phi ? idx[pv] : 0;
+      double vv[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) vv[r] = (pv < phi && r < nr) ? x[gp * nrhs + r0 + r] : 0.0;
       __syncthreads();          // the previous group's V is no longer read
-      for (int t = tid; t < 16 * kRectCols; t += 256) {
-        const int r = t / kRectCols, q = t - (t / kRectCols) * kRectCols, p = c0 + q;
-        V[r * kRectLdv + q] = (p < phi && r < nr) ? x[(int64_t)idx[p] * nrhs + r0 + r] : 0.0;
-      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) V[r * kRectLdv + tid] = vv[r];
       __syncthreads();
 #pragma unroll
       for (int s = 0; s < kRectCols / 4; ++s)
