@@ -702,8 +702,11 @@ int run_graphed(mf_plan *P, Graph *cache, int n_cache, int &next, const GraphKey
 
 // Column 2-norms of up to two [n][nrhs] device arrays with one host synchronisation.
 constexpr int64_t kNormRows = 512;   // rows per partial sum
+// a1_ready: a1's partial sums are already in place (launched earlier on a stream that s has
+// joined), so only a0's are computed here.
 int col_norms(mf_plan *P, const double *a0, const double *a1, int64_t n, int32_t nrhs,
-              hipStream_t s, std::vector<double> *out0, std::vector<double> *out1) {
+              hipStream_t s, std::vector<double> *out0, std::vector<double> *out1,
+              bool a1_ready = false) {
   const int64_t rows_per = kNormRows;
   const int64_t blocks = std::max<int64_t>(1, (n + rows_per - 1) / rows_per);
   const size_t per = (size_t)blocks * nrhs;
@@ -719,7 +722,7 @@ int col_norms(mf_plan *P, const double *a0, const double *a1, int64_t n, int32_t
   double *dpart = P->d_work + 2 * (size_t)n * nrhs;   // tail of the refinement workspace
   hipLaunchKernelGGL(mf::k_colsq_partial, dim3((unsigned)blocks), dim3(256), 0, s, a0, n, nrhs,
                      rows_per, dpart);
-  if (a1)
+  if (a1 && !a1_ready)
     hipLaunchKernelGGL(mf::k_colsq_partial, dim3((unsigned)blocks), dim3(256), 0, s, a1, n, nrhs,
                        rows_per, dpart + per);
   HIPCHK(hipGetLastError());
@@ -907,9 +910,11 @@ int mf_residual(const mf_plan *P, const double *elem_mats, const double *x, cons
 }
 
 // The refinement loop from x = the direct solution: residual, norms, corrections.
+// check_status: the factorization's pivot status was copied to h_status on hip_stream ahead of
+// the first residual; it is checked after the first synchronization (no separate wait for it).
 static int refine_loop(mf_plan *P, const double *elem_mats, const double *b, double *x,
                        int32_t nrhs, double tol, int32_t max_it, int32_t *its, double *relres,
-                       void *hip_stream) {
+                       void *hip_stream, bool check_status = false, bool b_ready = false) {
   hipStream_t s = (hipStream_t)hip_stream;
   const int64_t n = P->hp.n;
   const size_t nn = (size_t)n * nrhs;
@@ -921,7 +926,13 @@ static int refine_loop(mf_plan *P, const double *elem_mats, const double *b, dou
   double rr = 0.0;
   for (int32_t it = 0;; ++it) {
     if ((rc = mf_residual(P, elem_mats, x, b, r, nrhs, hip_stream))) return rc;
-    if ((rc = col_norms(P, r, it == 0 ? b : nullptr, n, nrhs, s, &rn, &bn))) return rc;
+    if ((rc = col_norms(P, r, it == 0 ? b : nullptr, n, nrhs, s, &rn, &bn, b_ready))) return rc;
+    if (check_status && it == 0 && P->h_status[0]) {
+      P->factored = false;
+      return fail(MF_EZERO_PIVOT, "zero or non-finite pivot in front " +
+                                      std::to_string(P->h_status[1]) + ", pivot " +
+                                      std::to_string(P->h_status[2]));
+    }
     rr = 0.0;
     for (int c = 0; c < nrhs; ++c) {
       const double q = bn[c] > 0 ? rn[c] / bn[c] : (rn[c] > 0 ? INFINITY : 0.0);
@@ -970,15 +981,26 @@ int mf_factor_refine(mf_plan *P, const double *elem_mats, int32_t precision, con
   // launched eagerly: the two streams overlap only when each launch is issued to its own
   // stream (a captured graph of the same fork/join replays its branches one after the other
   // on this platform -- measured: no overlap, 3 % slower than the sequential calls)
+  {
+    // the norms of b do not depend on the factorization: their partial sums run first on the
+    // plan's second stream, which the caller's stream joins before the backward sweep
+    const int64_t n = P->hp.n;
+    const size_t nn = (size_t)n * nrhs;
+    const int64_t blocks = std::max<int64_t>(1, (n + kNormRows - 1) / kNormRows);
+    const size_t parts = (size_t)blocks * nrhs;
+    if ((rc = grow(P, P->d_work, P->work_cap, 2 * nn + 2 * parts))) return rc;
+    HIPCHK(hipEventRecord(P->lvl_events[P->lv.size() + 1], s));
+    HIPCHK(hipStreamWaitEvent(P->side_stream, P->lvl_events[P->lv.size() + 1], 0));
+    hipLaunchKernelGGL(mf::k_colsq_partial, dim3((unsigned)blocks), dim3(256), 0, P->side_stream, b, n,
+                       nrhs, kNormRows, P->d_work + 2 * nn + parts);
+    HIPCHK(hipGetLastError());
+  }
   if ((rc = launch_factor_solve(P, elem_mats, precision, b, x, nrhs, s))) return rc;
+  // the pivot status travels with the first residual's norms: one synchronization for both
   HIPCHK(hipMemcpyAsync(P->h_status, P->d_status, mf::kStatusWords * sizeof(int),
                         hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  if (P->h_status[0])
-    return fail(MF_EZERO_PIVOT, "zero or non-finite pivot in front " + std::to_string(P->h_status[1]) +
-                                    ", pivot " + std::to_string(P->h_status[2]));
-  P->factored = true;
-  return refine_loop(P, elem_mats, b, x, nrhs, tol, max_it, its, relres, hip_stream);
+  P->factored = true;     // withdrawn by refine_loop if the status reports a bad pivot
+  return refine_loop(P, elem_mats, b, x, nrhs, tol, max_it, its, relres, hip_stream, true, true);
 }
 
 int mf_elem_grad(const mf_plan *P, const double *lam, const double *u, int32_t nrhs, double *gK,
