@@ -43,7 +43,6 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ inline bool passthrough(const FrontDesc &c) { return c.elem >= 0 && c.k == 0; }
 
 __global__ void k_clear_status(int *st) {
   if (threadIdx.x < kStatusWords) st[threadIdx.x] = 0;

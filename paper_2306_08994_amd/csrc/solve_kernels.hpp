@@ -22,28 +22,6 @@
 
 namespace mf {
 
-template <bool TRANS>
-__device__ inline double cdown(const double *F, int64_t m, int i, int p) {
-  return TRANS ? F[p * m + i] : F[i * m + p];
-}
-template <bool TRANS>
-__device__ inline double cup(const double *F, int64_t m, int q, int p) {
-  return TRANS ? F[p * m + q] : F[q * m + p];
-}
-
-// Down-sweep gather of W rows [0, m) for right-hand-side columns r0 .. r0+nr-1.
-__device__ inline double down_gather(const FrontDesc &d, const FrontDesc &a, const FrontDesc &c,
-                                     const int32_t *idx, const int32_t *il, const int32_t *ir,
-                                     const double *b, const double *ycb, int nrhs, int i, int col) {
-  double v = i < d.k ? b[(int64_t)idx[i] * nrhs + col] : 0.0;
-  if (d.elem < 0) {
-    const int x = il[i], y = ir[i];
-    if (x >= 0 && !passthrough(a)) v += ycb[(a.cbrow + x) * nrhs + col];
-    if (y >= 0 && !passthrough(c)) v += ycb[(c.cbrow + y) * nrhs + col];
-  }
-  return v;
-}
-
 // ---------------------------------------------------------------------------------------------
 // One wave per front (fronts of width <= 64), four fronts per workgroup.  Lane i owns row i of
 // the front for every global access (coefficients, gathers, results), so each lane issues its
