@@ -647,9 +647,14 @@ int launch_factor_solve(mf_plan *P, const double *K, int prec, const double *b, 
   const size_t L = P->lv.size();
   hipLaunchKernelGGL(mf::k_clear_status, dim3(1), dim3(64), 0, s, P->d_status);
   int rc;
+  // every class of the factorization is issued first (the host issue of the second stream's
+  // work must not delay the factorization's short lower-class launches), then the second
+  // stream's per-class work, each class behind its event
   for (size_t l = 0; l < L; ++l) {
     if ((rc = factor_level(P, K, prec, l, s))) return rc;
     HIPCHK(hipEventRecord(P->lvl_events[l], s));
+  }
+  for (size_t l = 0; l < L; ++l) {
     HIPCHK(hipStreamWaitEvent(side, P->lvl_events[l], 0));
     dinv_launch(P, P->dinv_lvl[l], P->dinv_lvl[l + 1], side);
     solve_level(P, b, x, nrhs, false, true, l, side);
