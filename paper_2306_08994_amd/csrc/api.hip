@@ -705,42 +705,51 @@ int run_graphed(mf_plan *P, Graph *cache, int n_cache, int &next, const GraphKey
   return MF_OK;
 }
 
-// Column 2-norms of up to two [n][nrhs] device arrays with one host synchronisation.
-constexpr int64_t kNormRows = 512;   // rows per partial sum
-// a1_ready: a1's partial sums are already in place (launched earlier on a stream that s has
-// joined), so only a0's are computed here.
-int col_norms(mf_plan *P, const double *a0, const double *a1, int64_t n, int32_t nrhs,
-              hipStream_t s, std::vector<double> *out0, std::vector<double> *out1,
-              bool a1_ready = false) {
-  const int64_t rows_per = kNormRows;
-  const int64_t blocks = std::max<int64_t>(1, (n + rows_per - 1) / rows_per);
-  const size_t per = (size_t)blocks * nrhs;
-  const int cnt = a1 ? 2 : 1;
-  const size_t need = per * cnt;
+// Column 2-norms in the refinement loop, one host synchronisation per iteration.  The tail of
+// the refinement workspace holds per-block column sums of squares: the residual's (computed by
+// the residual kernel itself when nrhs divides 256, else by k_colsq_partial over kNormRows rows
+// per block), then those of b (kNormRows rows per block).
+constexpr int64_t kNormRows = 512;   // rows per partial sum of k_colsq_partial
+
+struct NormLayout {
+  bool fused;                        // residual kernel writes the residual's partial sums
+  int64_t r_blocks, b_blocks;
+  size_t r_parts, b_parts;           // doubles of each partial-sum array
+};
+
+NormLayout norm_layout(int64_t n, int32_t nrhs) {
+  NormLayout L;
+  L.fused = 256 % nrhs == 0;
+  L.r_blocks = L.fused ? std::max<int64_t>(1, (n * nrhs + 255) / 256)
+                       : std::max<int64_t>(1, (n + kNormRows - 1) / kNormRows);
+  L.b_blocks = std::max<int64_t>(1, (n + kNormRows - 1) / kNormRows);
+  L.r_parts = (size_t)L.r_blocks * nrhs;
+  L.b_parts = (size_t)L.b_blocks * nrhs;
+  return L;
+}
+
+// Sums the partials on the host: rn from the residual's, and bn from b's if want_b.
+int read_norms(mf_plan *P, const NormLayout &L, const double *dpart, int32_t nrhs, hipStream_t s,
+               bool want_b, std::vector<double> &rn, std::vector<double> &bn) {
+  const size_t need = L.r_parts + (want_b ? L.b_parts : 0);
   if (P->part_cap < need) {
     if (P->h_part) (void)hipHostFree(P->h_part);
     P->h_part = nullptr;
     P->part_cap = 0;
-    HIPCHK(hipHostMalloc((void **)&P->h_part, need * sizeof(double), hipHostMallocDefault));
-    P->part_cap = need;
+    HIPCHK(hipHostMalloc((void **)&P->h_part, (L.r_parts + L.b_parts) * sizeof(double),
+                         hipHostMallocDefault));
+    P->part_cap = L.r_parts + L.b_parts;
   }
-  double *dpart = P->d_work + 2 * (size_t)n * nrhs;   // tail of the refinement workspace
-  hipLaunchKernelGGL(mf::k_colsq_partial, dim3((unsigned)blocks), dim3(256), 0, s, a0, n, nrhs,
-                     rows_per, dpart);
-  if (a1 && !a1_ready)
-    hipLaunchKernelGGL(mf::k_colsq_partial, dim3((unsigned)blocks), dim3(256), 0, s, a1, n, nrhs,
-                       rows_per, dpart + per);
-  HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(P->h_part, dpart, need * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  std::vector<double> *outs[2] = {out0, out1};
-  for (int v = 0; v < cnt; ++v) {
-    std::vector<double> &o = *outs[v];
+  auto sum = [&](const double *h, int64_t blocks, std::vector<double> &o) {
     o.assign(nrhs, 0.0);
     for (int64_t bl = 0; bl < blocks; ++bl)
-      for (int c = 0; c < nrhs; ++c) o[c] += P->h_part[v * per + bl * nrhs + c];
+      for (int c = 0; c < nrhs; ++c) o[c] += h[bl * nrhs + c];
     for (int c = 0; c < nrhs; ++c) o[c] = std::sqrt(o[c]);
-  }
+  };
+  sum(P->h_part, L.r_blocks, rn);
+  if (want_b) sum(P->h_part + L.r_parts, L.b_blocks, bn);
   return MF_OK;
 }
 
@@ -909,7 +918,7 @@ int mf_residual(const mf_plan *P, const double *elem_mats, const double *x, cons
   const int64_t tot = H.n * nrhs;
   hipLaunchKernelGGL(mf::k_residual, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
                      (hipStream_t)hip_stream, P->d_nptr, P->d_nelem, P->d_conn, elem_mats, H.npe,
-                     H.n, x, b, r, nrhs);
+                     H.n, x, b, r, nrhs, (double *)nullptr);
   HIPCHK(hipGetLastError());
   return MF_OK;
 }
@@ -921,17 +930,28 @@ static int refine_loop(mf_plan *P, const double *elem_mats, const double *b, dou
                        int32_t nrhs, double tol, int32_t max_it, int32_t *its, double *relres,
                        void *hip_stream, bool check_status = false, bool b_ready = false) {
   hipStream_t s = (hipStream_t)hip_stream;
-  const int64_t n = P->hp.n;
+  const mf::HostPlan &H = P->hp;
+  const int64_t n = H.n;
   const size_t nn = (size_t)n * nrhs;
-  const size_t parts = (size_t)std::max<int64_t>(1, (n + kNormRows - 1) / kNormRows) * nrhs;
+  const NormLayout NL = norm_layout(n, nrhs);
   int rc;
-  if ((rc = grow(P, P->d_work, P->work_cap, 2 * nn + 2 * parts))) return rc;
+  if ((rc = grow(P, P->d_work, P->work_cap, 2 * nn + NL.r_parts + NL.b_parts))) return rc;
   double *r = P->d_work, *dx = P->d_work + nn;
+  double *rpart = P->d_work + 2 * nn, *bpart = rpart + NL.r_parts;
   std::vector<double> bn, rn;
   double rr = 0.0;
   for (int32_t it = 0;; ++it) {
-    if ((rc = mf_residual(P, elem_mats, x, b, r, nrhs, hip_stream))) return rc;
-    if ((rc = col_norms(P, r, it == 0 ? b : nullptr, n, nrhs, s, &rn, &bn, b_ready))) return rc;
+    hipLaunchKernelGGL(mf::k_residual, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s,
+                       P->d_nptr, P->d_nelem, P->d_conn, elem_mats, H.npe, n, x, b, r, nrhs,
+                       NL.fused ? rpart : (double *)nullptr);
+    if (!NL.fused)
+      hipLaunchKernelGGL(mf::k_colsq_partial, dim3((unsigned)NL.r_blocks), dim3(256), 0, s, r, n,
+                         nrhs, kNormRows, rpart);
+    if (it == 0 && !b_ready)
+      hipLaunchKernelGGL(mf::k_colsq_partial, dim3((unsigned)NL.b_blocks), dim3(256), 0, s, b, n,
+                         nrhs, kNormRows, bpart);
+    HIPCHK(hipGetLastError());
+    if ((rc = read_norms(P, NL, rpart, nrhs, s, it == 0, rn, bn))) return rc;
     if (check_status && it == 0 && P->h_status[0]) {
       P->factored = false;
       return fail(MF_EZERO_PIVOT, "zero or non-finite pivot in front " +
@@ -991,13 +1011,12 @@ int mf_factor_refine(mf_plan *P, const double *elem_mats, int32_t precision, con
     // plan's second stream, which the caller's stream joins before the backward sweep
     const int64_t n = P->hp.n;
     const size_t nn = (size_t)n * nrhs;
-    const int64_t blocks = std::max<int64_t>(1, (n + kNormRows - 1) / kNormRows);
-    const size_t parts = (size_t)blocks * nrhs;
-    if ((rc = grow(P, P->d_work, P->work_cap, 2 * nn + 2 * parts))) return rc;
+    const NormLayout NL = norm_layout(n, nrhs);
+    if ((rc = grow(P, P->d_work, P->work_cap, 2 * nn + NL.r_parts + NL.b_parts))) return rc;
     HIPCHK(hipEventRecord(P->lvl_events[P->lv.size() + 1], s));
     HIPCHK(hipStreamWaitEvent(P->side_stream, P->lvl_events[P->lv.size() + 1], 0));
-    hipLaunchKernelGGL(mf::k_colsq_partial, dim3((unsigned)blocks), dim3(256), 0, P->side_stream, b, n,
-                       nrhs, kNormRows, P->d_work + 2 * nn + parts);
+    hipLaunchKernelGGL(mf::k_colsq_partial, dim3((unsigned)NL.b_blocks), dim3(256), 0,
+                       P->side_stream, b, n, nrhs, kNormRows, P->d_work + 2 * nn + NL.r_parts);
     HIPCHK(hipGetLastError());
   }
   if ((rc = launch_factor_solve(P, elem_mats, precision, b, x, nrhs, s))) return rc;

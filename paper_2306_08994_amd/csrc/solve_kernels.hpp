@@ -707,44 +707,58 @@ k_solve_rect(const WaveRec *__restrict__ recs, const int4 *__restrict__ tasks,
 
 // r[v] = b[v] - sum over the (element, local node) pairs of v of K_e[a][:] x[conn_e]; the pairs
 // of each node are listed in ascending element order, so the result is deterministic.
+// part (may be null; requires nrhs | 256): the block's column sums of r^2, part[block][c] over
+// the block's 256 / nrhs nodes, added in a fixed order.
 __global__ void __launch_bounds__(256)
 k_residual(const int64_t *__restrict__ nptr, const int32_t *__restrict__ nelem,
            const int32_t *__restrict__ conn, const double *__restrict__ K, int npe, int64_t n,
            const double *__restrict__ x, const double *__restrict__ b, double *__restrict__ r,
-           int nrhs) {
+           int nrhs, double *__restrict__ part) {
+  __shared__ double red[256];
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t >= n * nrhs) return;
-  const int64_t v = t / nrhs;
-  const int c = (int)(t - v * nrhs);
-  // the same sum in the same order, with the loads of a batch of (element, node) pairs and of
-  // eight element columns issued together rather than one dependent chain per term
-  double s = 0.0;
-  const int64_t q0 = nptr[v], nq = nptr[v + 1] - q0;
-  for (int64_t qb = 0; qb < nq; qb += 4) {
-    int32_t ea[4];
+  double rv = 0.0;
+  if (t < n * nrhs) {
+    const int64_t v = t / nrhs;
+    const int c = (int)(t - v * nrhs);
+    // the same sum in the same order, with the loads of a batch of (element, node) pairs and
+    // of eight element columns issued together rather than one dependent chain per term
+    double s = 0.0;
+    const int64_t q0 = nptr[v], nq = nptr[v + 1] - q0;
+    for (int64_t qb = 0; qb < nq; qb += 4) {
+      int32_t ea[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) ea[u] = qb + u < nq ? nelem[q0 + qb + u] : 0;
+      for (int u = 0; u < 4; ++u) ea[u] = qb + u < nq ? nelem[q0 + qb + u] : 0;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (qb + u >= nq) break;
-      const int32_t e = ea[u] / npe, a = ea[u] - (ea[u] / npe) * npe;
-      const double *Ke = K + ((int64_t)e * npe + a) * npe;
-      const int32_t *ce = conn + (int64_t)e * npe;
-      for (int b0 = 0; b0 < npe; b0 += 8) {
-        double kv[8], xv[8];
+      for (int u = 0; u < 4; ++u) {
+        if (qb + u >= nq) break;
+        const int32_t e = ea[u] / npe, a = ea[u] - (ea[u] / npe) * npe;
+        const double *Ke = K + ((int64_t)e * npe + a) * npe;
+        const int32_t *ce = conn + (int64_t)e * npe;
+        for (int b0 = 0; b0 < npe; b0 += 8) {
+          double kv[8], xv[8];
 #pragma unroll
-        for (int w = 0; w < 8; ++w) {
-          const bool in = b0 + w < npe;
-          kv[w] = in ? Ke[b0 + w] : 0.0;
-          xv[w] = in ? x[(int64_t)ce[b0 + w] * nrhs + c] : 0.0;
+          for (int w = 0; w < 8; ++w) {
+            const bool in = b0 + w < npe;
+            kv[w] = in ? Ke[b0 + w] : 0.0;
+            xv[w] = in ? x[(int64_t)ce[b0 + w] * nrhs + c] : 0.0;
+          }
+#pragma unroll
+          for (int w = 0; w < 8; ++w)
+            if (b0 + w < npe) s += kv[w] * xv[w];
         }
-#pragma unroll
-        for (int w = 0; w < 8; ++w)
-          if (b0 + w < npe) s += kv[w] * xv[w];
       }
     }
+    rv = b[t] - s;
+    r[t] = rv;
   }
-  r[t] = b[t] - s;
+  if (!part) return;                  // uniform
+  red[threadIdx.x] = rv * rv;
+  __syncthreads();
+  if ((int)threadIdx.x < nrhs) {
+    double q = 0.0;
+    for (int j = threadIdx.x; j < 256; j += nrhs) q += red[j];
+    part[(int64_t)blockIdx.x * nrhs + threadIdx.x] = q;
+  }
 }
 
 // Per-column partial sums of squares: part[block][c] over rows block*rows_per .. .
