@@ -152,6 +152,57 @@ def cpu_baseline(runs=3):
             "host_nproc": os.cpu_count()}
 
 
+CPU_POOL_SNIPPET = r"""
+import json, os, sys, time
+sys.path.insert(0, %(root)r)
+import multiprocessing as mp
+import numpy as np
+from fixtures import config_problem
+from fixtures.mesh import Problem
+from oracle.tree import build_tree, front_flops
+from oracle.factor import factor, global_connectivity
+from oracle.solve import solve
+P = config_problem(4)
+NO, EO = P.node_offsets, P.elem_offsets
+
+def one(i):
+    sub = Problem(P.name, [P.meshes[i]], P.K[EO[i]:EO[i + 1]], P.b[NO[i]:NO[i + 1]],
+                  P.coef[EO[i]:EO[i + 1]], [P.S[i]], [P.M[i]])
+    tree = build_tree(sub.meshes)
+    conn = global_connectivity(sub)
+    fac_f, sol_f, _ = front_flops(tree)
+    fac = factor(tree, sub.K, conn)
+    solve(tree, fac, sub.b)
+    return fac_f + sub.nrhs * sol_f
+
+if __name__ == "__main__":
+    workers = %(workers)d
+    with mp.get_context("fork").Pool(workers) as pool:
+        t0 = time.perf_counter()
+        flops = sum(pool.map(one, range(len(P.meshes)), chunksize=1))
+        wall = time.perf_counter() - t0
+    print(json.dumps({"sec": wall, "flops": flops, "systems": len(P.meshes), "workers": workers}))
+"""
+
+
+def cpu_pool_baseline(workers=16):
+    """The 256-mesh batch on the host: the oracle (factor + solve) one mesh per task over a
+    process pool of `workers` single-threaded processes; wall clock of the whole batch."""
+    workers = max(1, min(workers, os.cpu_count() or 1))
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    code = CPU_POOL_SNIPPET % {"root": ROOT, "workers": workers}
+    res = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                         timeout=900)
+    if res.returncode != 0:
+        return {"error": res.stderr[-400:]}
+    r = json.loads(res.stdout.strip().splitlines()[-1])
+    return {"value": r["flops"] / r["sec"] / 1e9, "unit": "GFLOP/s", "cores": r["workers"],
+            "kind": "oracle",
+            "sample": f"the whole batch ({r['systems']} meshes): oracle factor + solve, one mesh "
+                      f"per task over {r['workers']} single-threaded processes, wall clock",
+            "ms_per_batch": r["sec"] * 1e3}
+
+
 def variant_mixed(steps, warmup):
     """3D Q1 32^3 (35,937 unknowns): FP64 vs FP32- and BF16-Schur factorizations, each refined
     in FP64 to a relative residual <= 1e-12; error against the FP64 solution reported."""
@@ -171,7 +222,6 @@ def variant_mixed(steps, warmup):
         out.setdefault("schedule", {})[prec] = plan.autotune(K, prec, reps=2)["chosen"]
 
         def step():
-
             return plan.factor_refine(K, b, prec, tol=1e-12, max_it=60, x=x)
         wall, dev, (xs, its, rr) = time_steps(step, steps, warmup)
         xs = xs.clone()
@@ -208,7 +258,6 @@ def variant_l2(steps, warmup):
         sched = plan.autotune(K, reps=2)["chosen"]
 
         def step():
-
             return plan.factor_refine(K, b, tol=1e-12, max_it=5, x=x)
         wall, dev, (_, its, rr) = time_steps(step, steps, warmup)
         t0 = time.perf_counter()
@@ -271,7 +320,6 @@ def variant_batched(steps, warmup):
         out.setdefault("schedule", {})[prec] = plan.autotune(K, prec, reps=2)["chosen"]
 
         def step():
-
             return plan.factor_refine(K, b, prec, tol=1e-12, max_it=30, x=x)
         wall, dev, (xs, its, rr) = time_steps(step, steps, warmup)
         xs = xs.clone()
@@ -391,6 +439,8 @@ def main():
         vs = max(3, args.steps // 4)
         out["mixed_precision_3d"] = variant_mixed(vs, 2)
         out["batched_256_meshes"] = variant_batched(vs, 2)
+        if not args.no_cpu_baseline:
+            out["batched_256_meshes"]["cpu_oracle_pool"] = cpu_pool_baseline()
         out["l2_projection_p123"] = variant_l2(vs, 2)
         out["tree_of_table3"] = variant_table3(vs, 2)
     if not args.no_cpu_baseline:
