@@ -334,23 +334,27 @@ k_gemm_update(const GemmTask *__restrict__ tasks, double *__restrict__ store) {
         for (int b = 0; b < QB; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
     } else {
+      // every operand of the slab read from LDS first (reads issued together), then the MFMAs
+      T av[KT / 4][QB], bv[KT / 4][QB];
 #pragma unroll
       for (int s = 0; s < KT / 4; ++s) {
-        T av[QB], bv[QB];
 #pragma unroll
-        for (int a = 0; a < QB; ++a) av[a] = As[HALF * wr + 16 * a + li][4 * s + lk];
+        for (int a = 0; a < QB; ++a) av[s][a] = As[HALF * wr + 16 * a + li][4 * s + lk];
 #pragma unroll
-        for (int b = 0; b < QB; ++b) bv[b] = Bs[HALF * wc + 16 * b + li][4 * s + lk];
+        for (int b = 0; b < QB; ++b) bv[s][b] = Bs[HALF * wc + 16 * b + li][4 * s + lk];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int s = 0; s < KT / 4; ++s)
 #pragma unroll
         for (int a = 0; a < QB; ++a)
 #pragma unroll
           for (int b = 0; b < QB; ++b) {
             if constexpr (PREC == 0)
-              acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+              acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s][a], bv[s][b], acc[a][b], 0, 0, 0);
             else
-              acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+              acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s][a], bv[s][b], acc[a][b], 0, 0, 0);
           }
-      }
     }
     __syncthreads();
   }

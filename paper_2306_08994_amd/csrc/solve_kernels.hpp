@@ -369,15 +369,21 @@ __device__ inline void tile_apply_mfma(const double *T, const double *X, int ldx
   for (int cb = 0; cb < nr; cb += 16) {
     v4d acc[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
     const int col = cb + li;
+    // every operand of the block's products read from LDS first (reads issued together), then
+    // the dependent MFMA chain -- not one LDS round trip per product
+    double bv[NBS / 4], av[2][NBS / 4];
 #pragma unroll
     for (int s = 0; s < NBS / 4; ++s) {
-      const double bv = col < nr ? X[col * ldx + 4 * s + lk] : 0.0;
+      bv[s] = col < nr ? X[col * ldx + 4 * s + lk] : 0.0;
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        const double av = T[(32 * wv + 16 * a + li) * (NBS + 1) + 4 * s + lk];
-        acc[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[a], 0, 0, 0);
-      }
+      for (int a = 0; a < 2; ++a) av[a][s] = T[(32 * wv + 16 * a + li) * (NBS + 1) + 4 * s + lk];
     }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int s = 0; s < NBS / 4; ++s)
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+        acc[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a][s], bv[s], acc[a], 0, 0, 0);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -421,12 +427,16 @@ __device__ inline void block_matvec(const double *Ms, const double *W, int ldw, 
   for (int cb = 16 * (wv >> 1); cb < nr; cb += 32) {
     v4d acc = {0.0, 0.0, 0.0, 0.0};
     const int col = cb + li;
+    double bv[NBS / 4], av[NBS / 4];          // operands first, then the MFMA chain
 #pragma unroll
     for (int s = 0; s < NBS / 4; ++s) {
-      const double bv = col < nr ? W[col * ldw + p0 + 4 * s + lk] : 0.0;
-      const double av = Ms[(16 * a + li) * (NBS + 1) + 4 * s + lk];
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+      bv[s] = col < nr ? W[col * ldw + p0 + 4 * s + lk] : 0.0;
+      av[s] = Ms[(16 * a + li) * (NBS + 1) + 4 * s + lk];
     }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int s = 0; s < NBS / 4; ++s)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[s], acc, 0, 0, 0);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int q = 16 * a + 4 * r + lk;
@@ -683,9 +693,18 @@ k_solve_rect(const WaveRec *__restrict__ recs, const int4 *__restrict__ tasks,
 #pragma unroll
       for (int r = 0; r < 16; ++r) V[r * kRectLdv + tid] = vv[r];
       __syncthreads();
+      // the B operands in chunks of 16 steps, each chunk's reads issued together (and
+      // overlapping the previous chunk's products), then its MFMA chain
 #pragma unroll
-      for (int s = 0; s < kRectCols / 4; ++s)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], V[col * kRectLdv + 4 * s + lk], acc, 0, 0, 0);
+      for (int c = 0; c < kRectCols / 4; c += 16) {
+        double vb[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) vb[u] = V[col * kRectLdv + 4 * (c + u) + lk];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[c + u], vb[u], acc, 0, 0, 0);
+      }
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
