@@ -654,8 +654,14 @@ int launch_factor_solve(mf_plan *P, const double *K, int prec, const double *b, 
     if ((rc = factor_level(P, K, prec, l, s))) return rc;
     HIPCHK(hipEventRecord(P->lvl_events[l], s));
   }
+  // the second stream starts once the lower classes, whose launches fill the chip, are factored:
+  // from the first class with fronts on the tiled route, the factorization is latency-bound and
+  // leaves most of the chip to the forward sweep
+  size_t start = 0;
+  while (start + 1 < L && P->lv[start].n_large == 0) ++start;
   for (size_t l = 0; l < L; ++l) {
-    HIPCHK(hipStreamWaitEvent(side, P->lvl_events[l], 0));
+    if (l == 0 || l >= start)
+      HIPCHK(hipStreamWaitEvent(side, P->lvl_events[std::max(l, start)], 0));
     dinv_launch(P, P->dinv_lvl[l], P->dinv_lvl[l + 1], side);
     solve_level(P, b, x, nrhs, false, true, l, side);
   }
