@@ -115,3 +115,26 @@ def test_full_size_equals_factor_then_refine():
         torch.testing.assert_close(xg, xr, rtol=0, atol=0)
     assert (its, rr) == (itr, rrr) and rr <= 1e-12
     assert G.relres(p, conn, xg.cpu().numpy()) <= 1e-12
+
+
+def test_plan_without_graphs_equals_graph_replay(monkeypatch):
+    """MF_GRAPHS=0 at plan creation: the same launch sequences issued eagerly give the same bits
+    as the captured graphs (factor, solve, transposed solve)."""
+    import torch
+    p, tuning = _problem("2d-tiled")
+    graphed, K, b = _plan(p, tuning)
+    monkeypatch.setenv("MF_GRAPHS", "0")
+    eager, _, _ = _plan(p, tuning)
+    for plan in (graphed, eager):
+        for _ in range(2):                        # the second call replays a captured graph
+            plan.factor(K)
+    Lg, Ug = graphed.export_factors()
+    Le, Ue = eager.export_factors()
+    for f in range(len(Lg)):
+        np.testing.assert_array_equal(Lg[f], Le[f])
+        np.testing.assert_array_equal(Ug[f], Ue[f])
+    for tr in (False, True):
+        xg = graphed.solve(b, transpose=tr)
+        xg = graphed.solve(b, transpose=tr).clone()
+        xe = eager.solve(b, transpose=tr)
+        torch.testing.assert_close(xg, xe, rtol=0, atol=0)
