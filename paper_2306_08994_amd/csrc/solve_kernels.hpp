@@ -676,11 +676,15 @@ k_solve_rect(const WaveRec *__restrict__ recs, const int4 *__restrict__ tasks,
     }
     v4d acc = {0.0, 0.0, 0.0, 0.0};
     for (int c0 = plo; c0 < phi; c0 += kRectCols) {
+      // MFMA steps of 4 columns that hold data in this group (the last group is usually
+      // partial): chunks of 16 steps beyond them are neither loaded nor multiplied
+      const int nst = min(kRectCols / 4, (phi - c0 + 3) / 4);
       double av[kRectCols / 4];
 #pragma unroll
       for (int s = 0; s < kRectCols / 4; ++s) {
         const int p = min(c0 + 4 * s + lk, phi - 1);
-        av[s] = TRANS ? F[(int64_t)p * m + arow] : F[(int64_t)arow * m + p];
+        av[s] = 0.0;
+        if ((s & ~15) < nst) av[s] = TRANS ? F[(int64_t)p * m + arow] : F[(int64_t)arow * m + p];
       }
       // thread t stages column p = c0 + t of the group (kRectCols = 256 threads): its 16
       // right-hand-side values, one contiguous row of x, loaded together
@@ -697,6 +701,7 @@ k_solve_rect(const WaveRec *__restrict__ recs, const int4 *__restrict__ tasks,
       // overlapping the previous chunk's products), then its MFMA chain
 #pragma unroll
       for (int c = 0; c < kRectCols / 4; c += 16) {
+        if (c >= nst) break;      // uniform
         double vb[16];
 #pragma unroll
         for (int u = 0; u < 16; ++u) vb[u] = V[col * kRectLdv + 4 * (c + u) + lk];
