@@ -857,10 +857,10 @@ int mf_task_trace(const mf_plan *P, mf_trace_info *out, int64_t *hist, int64_t c
 int mf_set_tuning(mf_plan *P, int32_t small_max_m, int32_t nb, int32_t fused_max_m, int32_t tile) {
   if (!P) return fail(MF_EINVAL, "null plan");
   if (tile != 0 && tile != 32 && tile != 64) return fail(MF_EINVAL, "tile must be 32 or 64");
-  if (tile > 0) P->tune.tile = tile;
   if (small_max_m < 0) return fail(MF_EINVAL, "small_max_m must be >= 0");
   if (nb != 0 && nb != 16 && nb != 32 && nb != 64) return fail(MF_EINVAL, "nb must be 16, 32 or 64");
   if (fused_max_m < -1) return fail(MF_EINVAL, "fused_max_m must be >= -1");
+  if (tile > 0) P->tune.tile = tile;
   if (small_max_m > 0) P->tune.small_max_m = small_max_m;
   if (nb > 0) P->tune.nb = nb;
   if (fused_max_m == -1) P->tune.fused_max_m = 0;
