@@ -351,9 +351,12 @@ int ensure_uploaded(mf_plan *P) {
     HIPCHK(hipHostMalloc((void **)&P->h_status, mf::kStatusWords * sizeof(int), hipHostMallocDefault));
   if (!P->cap_stream) HIPCHK(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
   if (!P->side_stream) HIPCHK(hipStreamCreateWithFlags(&P->side_stream, hipStreamNonBlocking));
+  // events that only order the plan's two streams on this device: no system-scope fence (the
+  // device-scope release of the recorded work is what the other stream needs; the host never
+  // waits on them), which removes a stall of the recording stream at every record
   while (P->lvl_events.size() < H.levels.size() + 2) {
     hipEvent_t e;
-    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming | hipEventDisableSystemFence));
     P->lvl_events.push_back(e);
   }
   // raise the dynamic-LDS limit of the kernels that size LDS per launch (best effort)
@@ -650,15 +653,16 @@ int launch_factor_solve(mf_plan *P, const double *K, int prec, const double *b, 
   // every class of the factorization is issued first (the host issue of the second stream's
   // work must not delay the factorization's short lower-class launches), then the second
   // stream's per-class work, each class behind its event
-  for (size_t l = 0; l < L; ++l) {
-    if ((rc = factor_level(P, K, prec, l, s))) return rc;
-    HIPCHK(hipEventRecord(P->lvl_events[l], s));
-  }
   // the second stream starts once the lower classes, whose launches fill the chip, are factored:
   // from the first class with fronts on the tiled route, the factorization is latency-bound and
-  // leaves most of the chip to the forward sweep
+  // leaves most of the chip to the forward sweep.  Only the classes it waits for record an
+  // event (each record stalls the caller's stream for a few microseconds).
   size_t start = 0;
   while (start + 1 < L && P->lv[start].n_large == 0) ++start;
+  for (size_t l = 0; l < L; ++l) {
+    if ((rc = factor_level(P, K, prec, l, s))) return rc;
+    if (l >= start) HIPCHK(hipEventRecord(P->lvl_events[l], s));
+  }
   for (size_t l = 0; l < L; ++l) {
     if (l == 0 || l >= start)
       HIPCHK(hipStreamWaitEvent(side, P->lvl_events[std::max(l, start)], 0));
