@@ -179,10 +179,14 @@ k_panel_trsm(const PanelRec *__restrict__ recs, double *__restrict__ store,
   }
   if (nact > 1 && threadIdx.x < 64) {
     // every thread of this workgroup is past its reads of the diagonal block (the LU consumed
-    // them before the barrier); count this workgroup and store the block if it is the last
+    // them before the barrier); count this workgroup and store the block if it is the last.
+    // Relaxed: the only order needed is each workgroup's reads (complete, their values used
+    // before the barrier) before the last one's stores (issued only after the count returned),
+    // and no data passes through the counter -- an acquire/release here would write back and
+    // invalidate the whole L2 around every increment.
     int prev = 0;
     if (threadIdx.x == 0)
-      prev = __hip_atomic_fetch_add(arrive + f, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      prev = __hip_atomic_fetch_add(arrive + f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     prev = __builtin_amdgcn_readlane(prev, 0);
     if (prev == nact - 1) {
       const int lane = threadIdx.x;
