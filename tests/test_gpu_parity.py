@@ -101,6 +101,28 @@ def test_residual_and_elem_grad_kernels():
     np.testing.assert_allclose(gK, oadj.elem_grad(conn, lam, x), rtol=1e-13, atol=1e-13)
 
 
+@pytest.mark.parametrize("nrhs", [1, 2, 3, 8, 12])
+def test_residual_and_refinement_norms(nrhs):
+    """The residual kernel and, when nrhs divides 256, its per-block column sums of r^2 that the
+    refinement's norms add up (else a separate column-norm kernel computes them): r against the
+    oracle's, and the relative residual the refinement reports for a system it does not solve
+    exactly (factored with K, residual with 1.01 K, so relres = 1e-2) against the oracle's
+    relative residual of the returned x."""
+    import torch
+    from oracle import residual as ores
+    p = _rd((9, 7), seed=6, nrhs=nrhs)
+    plan, K, b = _setup(p)
+    conn = np.concatenate([m.conn for m in p.meshes]).astype(np.int64)
+    x = np.random.default_rng(7).normal(size=p.b.shape)
+    r = plan.residual(K, torch.from_numpy(x).to(b.device), b).cpu().numpy()
+    np.testing.assert_allclose(r, ores.residual(p.K, conn, x, p.b), rtol=1e-13, atol=1e-13)
+    plan.factor(K)
+    xs, its, rr = plan.refine((1.01 * K).contiguous(), b, tol=1.0, max_it=0)
+    ro = ores.relres(1.01 * p.K, conn, xs.cpu().numpy(), p.b)
+    assert its == 0 and ro > 1e-6
+    assert abs(rr - ro) <= 1e-10 * ro, (rr, ro)
+
+
 def test_batched_equals_unbatched():
     import torch
     from paper_2306_08994_amd import Plan
