@@ -128,6 +128,9 @@ void level_costs(const mf::HostPlan &H, const mf::LevelSchedule &S, LevelDev &D,
 
 }  // namespace
 
+// Classes with fewer rectangular-part slabs of 64 rows than this use slabs of 16 (quarter form).
+constexpr int64_t kRectQuarterBelow = 256;
+
 // Fronts of a class whose widest front is above this take the workgroup-per-front block solves.
 constexpr int kWaveSolveMaxM = 64;
 // Largest (m - k) k of a class from which its rectangular part is a launch of its own.
@@ -230,7 +233,18 @@ int ensure_uploaded(mf_plan *P) {
     // rectangular part is large (measured on the 256 x 256 grid: from c k = 16K down, 8K up)
     D.split_down = ckmax >= kSplitDownCK;
     D.split_up = ckmax >= kSplitUpCK;
-    const int32_t sd = mf::kRectRows, su = mf::kRectRows;
+    // slabs of 64 rows, or of 16 (the quarter form) where a class has too few slabs of 64 to
+    // occupy the chip
+    int64_t n64_down = 0, n64_up = 0;
+    for (size_t i = 0; i < S.all.size(); ++i) {
+      const mf::FrontDesc &d = H.desc[S.all[i]];
+      n64_down += (d.m - d.k + mf::kRectRows - 1) / mf::kRectRows;
+      if (d.m > d.k) n64_up += (d.k + mf::kRectRows - 1) / mf::kRectRows;
+    }
+    D.rect_q_down = n64_down < kRectQuarterBelow;
+    D.rect_q_up = n64_up < kRectQuarterBelow;
+    const int32_t sd = D.rect_q_down ? mf::kRectRowsQ : mf::kRectRows;
+    const int32_t su = D.rect_q_up ? mf::kRectRowsQ : mf::kRectRows;
     D.rdown = (int64_t)rect.size();
     if (D.split_down)
       for (size_t i = 0; i < S.all.size(); ++i) {
@@ -593,7 +607,8 @@ void solve_level(mf_plan *P, const double *b, double *x, int32_t nrhs, bool tran
         const int grid = std::min(n, gridcap);
         const int64_t nt = down ? D.n_rdown : D.n_rup;
         const int4 *rt = P->d_rect + (down ? D.rdown : D.rup);
-        const size_t rlds = (size_t)16 * mf::kRectLdv * 8;
+        const bool rq = down ? D.rect_q_down : D.rect_q_up;
+        const size_t rlds = ((size_t)16 * mf::kRectLdv + (rq ? 4 * 64 * 4 : 0)) * 8;
 #define MF_DOWN_BLOCK(TR, FU)                                                                   \
   LAUNCH(K_DOWN_BLOCK, ct, (mf::k_solve_down_block<TR, FU>), dim3(grid), dim3(256), lds, s,     \
          rec, n, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, b, x, P->d_ycb,            \
@@ -601,9 +616,14 @@ void solve_level(mf_plan *P, const double *b, double *x, int32_t nrhs, bool tran
 #define MF_UP_BLOCK(TR, FU)                                                                     \
   LAUNCH(K_UP_BLOCK, ct, (mf::k_solve_up_block<TR, FU>), dim3(grid), dim3(256), lds, s,         \
          rec, n, P->d_store, P->d_front_idx, x, nrhs, nc, rmax, P->d_dinv)
-#define MF_RECT(KIND, TR, UP)                                                                   \
-  LAUNCH(KIND, cr, (mf::k_solve_rect<TR, UP>), dim3((unsigned)nt), dim3(256), rlds, s,          \
+#define MF_RECT_Q(KIND, TR, UP, Q)                                                              \
+  LAUNCH(KIND, cr, (mf::k_solve_rect<TR, UP, Q>), dim3((unsigned)nt), dim3(256), rlds, s,       \
          P->d_wrec, rt, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, x, P->d_ycb, nrhs)
+#define MF_RECT(KIND, TR, UP)                                                                   \
+  do {                                                                                          \
+    if (rq) MF_RECT_Q(KIND, TR, UP, true);                                                      \
+    else MF_RECT_Q(KIND, TR, UP, false);                                                        \
+  } while (0)
         if (down) {
           if (split) {
             if (trans) MF_DOWN_BLOCK(true, false); else MF_DOWN_BLOCK(false, false);
@@ -626,6 +646,7 @@ void solve_level(mf_plan *P, const double *b, double *x, int32_t nrhs, bool tran
 #undef MF_DOWN_BLOCK
 #undef MF_UP_BLOCK
 #undef MF_RECT
+#undef MF_RECT_Q
       }
     }
   }

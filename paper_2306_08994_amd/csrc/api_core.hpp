@@ -88,6 +88,7 @@ struct LevelDev {
   // rectangular-part tasks (int4: the front's wave record, first row, rows, 0)
   int64_t rdown = 0, n_rdown = 0, rup = 0, n_rup = 0;
   bool split_down = false, split_up = false;   // rectangular part in its own launch
+  bool rect_q_down = false, rect_q_up = false; // ... in slabs of 16 rows (quarter form)
 };
 
 struct ProfRec {

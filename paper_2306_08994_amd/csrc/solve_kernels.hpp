@@ -636,9 +636,14 @@ k_solve_up_block(const WaveRec *__restrict__ recs, int nrec,
 constexpr int kRectCols = 256;   // columns per group (64 MFMA steps of 4)
 static_assert(kRectCols == 256, "one staged column per thread of the rectangular kernel");
 constexpr int kRectRows = 64;    // output rows per task (4 waves x 16)
+constexpr int kRectRowsQ = 16;   // output rows per task of the quarter form
 constexpr int kRectLdv = kRectCols + 4;
 
-template <bool TRANS, bool UP>
+// Q (quarter form, for classes with too few tasks of kRectRows to spread over the chip): a task
+// is a slab of 16 rows, and wave w multiplies the w-th quarter (16 MFMA steps) of every column
+// group; the four partial products are added in wave order through LDS (after V: 4 x 64 x 4
+// doubles) and wave 0 stores.
+template <bool TRANS, bool UP, bool Q = false>
 __global__ void __launch_bounds__(256)
 k_solve_rect(const WaveRec *__restrict__ recs, const int4 *__restrict__ tasks,
              const double *__restrict__ store, const int32_t *__restrict__ front_idx,
@@ -653,14 +658,17 @@ k_solve_rect(const WaveRec *__restrict__ recs, const int4 *__restrict__ tasks,
   const int plo = UP ? k : 0, phi = UP ? m : k;
   const double *F = store + d.store;
   const int32_t *idx = front_idx + d.idx;
-  const int arow = row0 + min(16 * wv + li, rows - 1);     // this lane's A-operand row
+  const int wrow = Q ? 0 : 16 * wv;                          // this wave's first output row
+  const int arow = row0 + min(wrow + li, rows - 1);          // this lane's A-operand row
+  constexpr int NS = Q ? kRectCols / 16 : kRectCols / 4;     // MFMA steps per wave and group
+  const int s0 = Q ? 16 * wv : 0;                            // this wave's first step
   for (int r0 = 0; r0 < nrhs; r0 += 16) {
     const int nr = min(16, nrhs - r0), col = li;
     // the values the product is combined with, for this lane's four result entries
     double base[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int orow = 16 * wv + 4 * r + lk, row = row0 + orow;
+      const int orow = wrow + 4 * r + lk, row = row0 + orow;
       base[r] = 0.0;
       if (orow < rows && col < nr) {
         if (UP) {
@@ -679,12 +687,12 @@ k_solve_rect(const WaveRec *__restrict__ recs, const int4 *__restrict__ tasks,
       // MFMA steps of 4 columns that hold data in this group (the last group is usually
       // partial): chunks of 16 steps beyond them are neither loaded nor multiplied
       const int nst = min(kRectCols / 4, (phi - c0 + 3) / 4);
-      double av[kRectCols / 4];
+      double av[NS];
 #pragma unroll
-      for (int s = 0; s < kRectCols / 4; ++s) {
-        const int p = min(c0 + 4 * s + lk, phi - 1);
+      for (int s = 0; s < NS; ++s) {
+        const int p = min(c0 + 4 * (s0 + s) + lk, phi - 1);
         av[s] = 0.0;
-        if ((s & ~15) < nst) av[s] = TRANS ? F[(int64_t)p * m + arow] : F[(int64_t)arow * m + p];
+        if (((s0 + s) & ~15) < nst) av[s] = TRANS ? F[(int64_t)p * m + arow] : F[(int64_t)arow * m + p];
       }
       // thread t stages column p = c0 + t of the group (kRectCols = 256 threads): its 16
       // right-hand-side values, one contiguous row of x, loaded together
@@ -700,21 +708,31 @@ k_solve_rect(const WaveRec *__restrict__ recs, const int4 *__restrict__ tasks,
       // the B operands in chunks of 16 steps, each chunk's reads issued together (and
       // overlapping the previous chunk's products), then its MFMA chain
 #pragma unroll
-      for (int c = 0; c < kRectCols / 4; c += 16) {
-        if (c >= nst) break;      // uniform
+      for (int c = 0; c < NS; c += 16) {
+        if (s0 + c >= nst) break;      // wave-uniform
         double vb[16];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) vb[u] = V[col * kRectLdv + 4 * (c + u) + lk];
+        for (int u = 0; u < 16; ++u) vb[u] = V[col * kRectLdv + 4 * (s0 + c + u) + lk];
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int u = 0; u < 16; ++u)
           acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[c + u], vb[u], acc, 0, 0, 0);
       }
     }
+    if constexpr (Q) {
+      double *Red = V + 16 * kRectLdv;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Red[(wv * 64 + lane) * 4 + r] = acc[r];
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        acc[r] = ((Red[lane * 4 + r] + Red[(64 + lane) * 4 + r]) + Red[(128 + lane) * 4 + r]) +
+                 Red[(192 + lane) * 4 + r];
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int orow = 16 * wv + 4 * r + lk, row = row0 + orow;
-      if (orow < rows && col < nr) {
+      const int orow = wrow + 4 * r + lk, row = row0 + orow;
+      if ((!Q || wv == 0) && orow < rows && col < nr) {
         if (UP)
           x[(int64_t)idx[row] * nrhs + r0 + col] = base[r] - acc[r];
         else

@@ -85,6 +85,23 @@ def test_solve_parity(shape, smax, nrhs, fused):
     torch.testing.assert_close(bb, torch.from_numpy(x).to(bb.device), rtol=0, atol=0)
 
 
+@pytest.mark.parametrize("nrhs", [3, 20])
+def test_solve_parity_split_rectangular_parts(nrhs):
+    """A 3D mesh whose upper classes solve the rectangular parts of their fronts in launches of
+    their own (c k >= 8K up, >= 16K down), with few enough slabs to take the 16-row quarter form;
+    20 right-hand sides span two chunks of 16.  Solve and transposed solve against the oracle."""
+    p = _rd((16, 16, 12), seed=2, nrhs=nrhs)
+    tree, conn, fac = G.oracle_factor(p)
+    ms = np.diff(tree.front_ptr)
+    ck = (ms - tree.npiv) * tree.npiv
+    assert ck.max() >= 16384 and (ck >= 8192).sum() >= 4
+    plan, K, b = _setup(p)
+    plan.factor(K)
+    for trans in (False, True):
+        x = plan.solve(b, transpose=trans).cpu().numpy()
+        assert G.rel_err(x, G.oracle_solve(tree, fac, p.b, trans)) <= G.TOL_SOLVE, trans
+
+
 def test_residual_and_elem_grad_kernels():
     import torch
     from oracle import adjoint as oadj
