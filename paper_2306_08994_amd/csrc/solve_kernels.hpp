@@ -188,9 +188,10 @@ k_solve_up_wave(const WaveRec *__restrict__ recs, int nrec,
 // as one matrix-vector product instead of NBS dependent substitution steps.  For a front f with
 // k > 0, dinv + dinv_off[f] holds ceil(k / NBS) pairs of NBS x NBS row-major blocks: inv(L_BB)
 // (lower, pivots on the diagonal), then inv(U_BB) (unit upper); a ragged last block is padded
-// with the identity.  One wave per (front, block) task: lanes 0..NBS-1 form the columns of
-// inv(L_BB) by forward substitution, lanes NBS..2NBS-1 those of inv(U_BB) by back substitution,
-// each column in registers against the block staged in LDS.
+// with the identity.  A workgroup takes four (front, block) tasks at a time: each wave stages
+// one block in LDS, then the even waves form the columns of inv(L_BB) by forward substitution
+// and the odd waves those of inv(U_BB) by back substitution, NBS lanes per block (two blocks
+// per wave), each column in registers.
 // ---------------------------------------------------------------------------------------------
 constexpr int NBS = 32;
 static_assert(2 * NBS == 64, "one wave forms both inverses of a block");
@@ -203,38 +204,52 @@ k_diag_inverse(const FrontDesc *__restrict__ fd, const int2 *__restrict__ tasks,
   __shared__ double Rs[4][NBS];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
-  // LDS base in a vector register (threadIdx-derived), so every block entry is an immediate
-  // offset from it instead of a separately materialized uniform address
-  const int wl = threadIdx.x >> 6;
-  double(*B)[NBS + 1] = Bs[wl];
-  double *rdg = Rs[wl];
+  // the task this lane substitutes for (of the group's four): waves 0, 1 take tasks 0 and 1
+  // (lanes 0..NBS-1, NBS..2NBS-1), waves 2, 3 tasks 2 and 3; even waves form inv(L), odd waves
+  // inv(U), so no wave runs both substitutions one after the other.  LDS bases in vector
+  // registers (threadIdx-derived): every block entry is an immediate offset from them.
+  const int tl = ((threadIdx.x >> 6) & ~1) + (lane >> 5);
+  const bool upper = wv & 1;
+  double(*Bw)[NBS + 1] = Bs[threadIdx.x >> 6];
+  double(*B)[NBS + 1] = Bs[tl];
+  const double *rdg = Rs[tl];
   const int j = lane & (NBS - 1);
-  for (int t = blockIdx.x * 4 + wv; t < ntasks; t += gridDim.x * 4) {
-    const int2 tk = tasks[t];
-    const FrontDesc d = fd[tk.x];
-    const int p0 = tk.y, pb = min(NBS, d.k - p0);
-    const double *F = store + d.store + (int64_t)p0 * d.m + p0;
-    // the block's 16 entries per lane loaded together, then staged (one round trip)
-    double v[NBS * NBS / 64];
+  static_assert(2 * NBS == 64, "two blocks per wave");
+  for (int g0 = blockIdx.x * 4; g0 < ntasks; g0 += gridDim.x * 4) {   // uniform
+    // wave w stages task g0 + w: the block's 16 entries per lane loaded together, then stored
+    if (g0 + wv < ntasks) {
+      const int2 tk = tasks[g0 + wv];
+      const FrontDesc d = fd[tk.x];
+      const int p0 = tk.y, pb = min(NBS, d.k - p0);
+      const double *F = store + d.store + (int64_t)p0 * d.m + p0;
+      double v[NBS * NBS / 64];
 #pragma unroll
-    for (int u = 0; u < NBS * NBS / 64; ++u) {
-      const int e = lane + 64 * u, i = e / NBS, c = e % NBS;
-      v[u] = (i < pb && c < pb) ? F[(int64_t)i * d.m + c] : (i == c ? 1.0 : 0.0);
-    }
+      for (int u = 0; u < NBS * NBS / 64; ++u) {
+        const int e = lane + 64 * u, i = e / NBS, c = e % NBS;
+        v[u] = (i < pb && c < pb) ? F[(int64_t)i * d.m + c] : (i == c ? 1.0 : 0.0);
+      }
 #pragma unroll
-    for (int u = 0; u < NBS * NBS / 64; ++u) {
-      const int e = lane + 64 * u;
-      B[e / NBS][e % NBS] = v[u];
+      for (int u = 0; u < NBS * NBS / 64; ++u) {
+        const int e = lane + 64 * u;
+        Bw[e / NBS][e % NBS] = v[u];
+      }
+      wave_sync();
+      if (lane < NBS) Rs[wv][lane] = 1.0 / Bw[lane][lane];   // the pivots' reciprocals
     }
-    wave_sync();
-    if (lane < NBS) rdg[lane] = 1.0 / B[lane][lane];   // the pivots' reciprocals, all at once
-    wave_sync();
+    __syncthreads();
+    const bool act = g0 + tl < ntasks;
+    int2 tko = make_int2(0, 0);
+    int64_t off = 0;
+    if (act) {
+      tko = tasks[g0 + tl];
+      off = dinv_off[tko.x];
+    }
     // substitutions with two partial sums per row (half the dependent chain of one sum); each
     // row of the block is read from LDS into registers as a whole (its reads issued together)
     // before its products, so a row costs one LDS round trip rather than one per entry
     double z[NBS];
     double br[NBS];
-    if (lane < NBS) {
+    if (!upper) {
 #pragma unroll
       for (int i = 0; i < NBS; ++i) {          // L z = e_j
 #pragma unroll
@@ -265,11 +280,12 @@ k_diag_inverse(const FrontDesc *__restrict__ fd, const int2 *__restrict__ tasks,
         z[i] = s0 + s1;
       }
     }
-    double *out = dinv + dinv_off[tk.x] + (int64_t)(p0 / NBS) * 2 * NBS * NBS +
-                  (lane < NBS ? 0 : NBS * NBS);
+    if (act) {
+      double *out = dinv + off + (int64_t)(tko.y / NBS) * 2 * NBS * NBS + (upper ? NBS * NBS : 0);
 #pragma unroll
-    for (int i = 0; i < NBS; ++i) out[i * NBS + j] = z[i];
-    wave_sync();
+      for (int i = 0; i < NBS; ++i) out[i * NBS + j] = z[i];
+    }
+    __syncthreads();                           // the blocks are restaged by the next group
   }
 }
 
