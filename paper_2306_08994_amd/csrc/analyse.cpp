@@ -438,7 +438,8 @@ void build_schedule(HostPlan &P, const Tuning &t) {
         PanelStep &S = L.steps[s];
         S.fronts.push_back(f);
         S.p0.push_back(p0);
-        S.trsm_items = std::max<int64_t>(S.trsm_items, 2 * (int64_t)(d.m - pe));
+        // columns, then rows from the next multiple of 64 (see k_panel_trsm)
+        S.trsm_items = std::max<int64_t>(S.trsm_items, (int64_t)((d.m - pe + 63) & ~63) + (d.m - pe));
         // fully-summed region still to update: rows [pe,k) x cols [pe,m) and rows [k,m) x cols [pe,k)
         add_tiles(S.update, f, pe, d.k, pe, d.k, p0, pe);
         add_tiles(S.update, f, pe, d.k, d.k, d.m, p0, pe);

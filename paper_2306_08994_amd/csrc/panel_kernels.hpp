@@ -82,7 +82,10 @@ __device__ __noinline__ bool wave_diag_lu_call(double *F, int64_t m, int pb, dou
 // diagonal block at (p0, p0) itself (wave 0, in LDS), then its threads solve against it:
 //   U12 = L11^{-1} A12 column by column (rows p0..pe-1, columns pe..m-1),
 //   L21 = A21 U11^{-1} row by row       (rows pe..m-1, columns p0..pe-1).
-// grid = (item chunks of 256, fronts), at least one chunk; item t < m-pe is a column, else a row.
+// grid = (item chunks of 256, fronts), at least one chunk; with r = m - pe, item t < r is a
+// column and item t in [R, R + r) a row, R = r rounded up to a multiple of 64: every wave holds
+// only columns or only rows (a wave holding both ran the two substitutions one after the other).
+// The host sizes the chunks by the widest front's R + r.
 // Positions beyond pb load clamped (finite) values; the identity padding of D keeps them out of
 // the first pb results, and only those are stored.
 // The factored diagonal block overwrites the block that the other workgroups of the front read,
@@ -99,15 +102,15 @@ k_panel_trsm(const PanelRec *__restrict__ recs, double *__restrict__ store,
   const PanelRec d = recs[blockIdx.y];
   const int f = d.f, p0 = d.p0;
   const int m = d.m, pb = min(NB, d.k - p0), pe = p0 + pb;
-  const int rest = m - pe;
+  const int rest = m - pe, rpad = (rest + 63) & ~63;
   const int item = blockIdx.x * 256 + threadIdx.x;
-  if (blockIdx.x > 0 && (int)(blockIdx.x * 256) >= 2 * rest) return;   // idle (uniform)
+  if (blockIdx.x > 0 && (int)(blockIdx.x * 256) >= rpad + rest) return;   // idle (uniform)
   double *F = store + d.store;
   // this thread's column (item < rest) or row, loaded before the diagonal block is factored so
   // that the load latency overlaps the factorization
-  const bool has = item < 2 * rest, colitem = item < rest;
+  const bool colitem = item < rest, has = colitem || (item >= rpad && item < rpad + rest);
   double *cp = F + (int64_t)p0 * m + pe + item;
-  double *row = F + (int64_t)(pe + item - rest) * m + p0;
+  double *row = F + (int64_t)(pe + item - rpad) * m + p0;
   double v[NB];
   if (has) {
     if (colitem) {
@@ -119,7 +122,7 @@ k_panel_trsm(const PanelRec *__restrict__ recs, double *__restrict__ store,
     }
   }
   // workgroups that take part (the others returned above): at least one
-  const int nact = max(1, (2 * rest + 255) / 256);
+  const int nact = max(1, (rpad + rest + 255) / 256);
   if (threadIdx.x < 64)
     wave_diag_lu<NB>(F + (int64_t)p0 * m + p0, m, pb, D, rd, threadIdx.x, f, p0, status,
                      nact == 1);

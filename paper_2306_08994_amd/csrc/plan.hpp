@@ -67,7 +67,7 @@ struct PanelStep {
   std::vector<int32_t> fronts;     // fronts that still have pivots at this step
   std::vector<int32_t> p0;         // first pivot of the panel per front
   std::vector<GemmTask> update;    // trailing update restricted to the fully-summed region
-  int64_t trsm_items = 0;          // max over fronts of (rows + columns) of the two panels
+  int64_t trsm_items = 0;          // max over fronts of the panel kernel's items (columns, rows)
 };
 
 struct LevelSchedule {
