@@ -137,19 +137,38 @@ def cpu_baseline(runs=3):
     if res.returncode != 0:
         return {"error": res.stderr[-400:]}
     r = json.loads(res.stdout.strip().splitlines()[-1])
-    model = ""
-    try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                model = line.split(":", 1)[1].strip()
-                break
-    except OSError:
-        pass
     return {"value": r["flops"] / r["sec"] / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
             "sample": f"the full step workload (256x256 Q1, 8 RHS): oracle factor + solve, median of "
                       f"{runs} runs, single thread (OMP/OPENBLAS/MKL_NUM_THREADS=1)",
-            "ms_per_system": r["sec"] * 1e3, "relres": r["relres"], "host_cpu": model,
+            "ms_per_system": r["sec"] * 1e3, "relres": r["relres"], "host_cpu": host_cpu(),
             "host_nproc": os.cpu_count()}
+
+
+def host_cpu():
+    """The host processor as lscpu names it (model name, family / model / stepping, sockets,
+    cores, threads, clock), with /proc/cpuinfo as the fallback."""
+    out = {}
+    try:
+        res = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=30)
+        for line in res.stdout.splitlines():
+            if ":" not in line:
+                continue
+            k, v = (t.strip() for t in line.split(":", 1))
+            if k in ("Model name", "CPU family", "Model", "Stepping", "Socket(s)",
+                     "Core(s) per socket", "Thread(s) per core", "CPU(s)", "CPU max MHz",
+                     "Hypervisor vendor", "L3 cache"):
+                out[k] = v
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if "Model name" not in out:
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    out["Model name"] = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+    return out
 
 
 CPU_POOL_SNIPPET = r"""
@@ -203,7 +222,17 @@ def cpu_pool_baseline(workers=16):
             "ms_per_batch": r["sec"] * 1e3}
 
 
-def variant_mixed(steps, warmup):
+def schedule(plan, K, prec, tuning):
+    """The schedule of a run: `tuning` (tile,fused_max_m,nb,small_max_m) if given, else the
+    autotuner's choice on this workload and precision."""
+    if tuning:
+        t_, f_, nb_, sm_ = (int(v) for v in tuning.split(","))
+        plan.set_tuning(sm_, nb_, f_ if f_ > 0 else -1, t_)
+        return {"tile": t_, "fused_max_m": f_, "nb": nb_, "small_max_m": sm_, "given": True}
+    return plan.autotune(K, prec, reps=2)["chosen"]
+
+
+def variant_mixed(steps, warmup, precs=("fp64", "fp32", "bf16"), tuning=None):
     """3D Q1 32^3 (35,937 unknowns): FP64 vs FP32- and BF16-Schur factorizations, each refined
     in FP64 to a relative residual <= 1e-12; error against the FP64 solution reported."""
     import torch
@@ -218,8 +247,8 @@ def variant_mixed(steps, warmup):
     out = {"workload": "3D Q1 32x32x32 reaction-diffusion, k~lognormal(0,1), 1 RHS",
            "n": plan.n, "max_front": plan.info["max_m"]}
     ref = None
-    for prec in ("fp64", "fp32", "bf16"):
-        out.setdefault("schedule", {})[prec] = plan.autotune(K, prec, reps=2)["chosen"]
+    for prec in precs:
+        out.setdefault("schedule", {})[prec] = schedule(plan, K, prec, tuning)
 
         def step():
             return plan.factor_refine(K, b, prec, tol=1e-12, max_it=60, x=x)
@@ -301,7 +330,7 @@ def variant_table3(steps, warmup):
             "schedule": sched}
 
 
-def variant_batched(steps, warmup):
+def variant_batched(steps, warmup, precs=("fp64", "fp32"), tuning=None):
     """256 independent 2D advection-diffusion meshes (sides 32..128) in one batch: every class
     of all meshes in one launch sequence; FP64 and FP32-Schur, refined to 1e-12."""
     import torch
@@ -316,8 +345,8 @@ def variant_batched(steps, warmup):
     out = {"workload": "256 2D Q1 advection-diffusion meshes, sides U{32..128}, 1 RHS",
            "n": plan.n, "systems": len(p.meshes), "fronts": plan.info["n_fronts"]}
     ref = None
-    for prec in ("fp64", "fp32"):
-        out.setdefault("schedule", {})[prec] = plan.autotune(K, prec, reps=2)["chosen"]
+    for prec in precs:
+        out.setdefault("schedule", {})[prec] = schedule(plan, K, prec, tuning)
 
         def step():
             return plan.factor_refine(K, b, prec, tol=1e-12, max_it=30, x=x)
@@ -343,6 +372,11 @@ def main():
                     help="tile,fused_max_m,nb,small_max_m: use this schedule instead of autotuning "
                          "(fused_max_m 0 = fused route off), e.g. for counter runs, where the "
                          "serialised dispatches distort the autotuner's timings")
+    ap.add_argument("--variant", default="all",
+                    choices=["all", "main", "mixed", "batched", "l2", "table3"],
+                    help="run one workload only and print its JSON (main: the 256x256 step)")
+    ap.add_argument("--precs", default=None,
+                    help="comma-separated precisions of the mixed / batched variants")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="run a few steps and a 1 GiB device copy (HBM counter calibration) only")
     args = ap.parse_args()
@@ -355,6 +389,17 @@ def main():
 
     from fixtures import config_problem
     from paper_2306_08994_amd import Plan
+
+    if args.variant in ("mixed", "batched", "l2", "table3"):
+        kw = {}
+        if args.variant in ("mixed", "batched"):
+            kw["tuning"] = args.tuning
+            if args.precs:
+                kw["precs"] = tuple(args.precs.split(","))
+        fn = {"mixed": variant_mixed, "batched": variant_batched, "l2": variant_l2,
+              "table3": variant_table3}[args.variant]
+        print(json.dumps({"variant": args.variant, **fn(args.steps, args.warmup, **kw)}))
+        return
 
     dev = torch.device("cuda:0")
     p = config_problem(2)
@@ -435,7 +480,7 @@ def main():
                          flops_per_launch=top["flops"] / top["launches"]),
         "kernels": rep["kernels"],
     }
-    if not args.no_variants:
+    if not args.no_variants and args.variant == "all":
         vs = max(3, args.steps // 4)
         out["mixed_precision_3d"] = variant_mixed(vs, 2)
         out["batched_256_meshes"] = variant_batched(vs, 2)

@@ -160,12 +160,12 @@ int mf_factor(mf_plan *plan, const double *elem_mats, int32_t precision, void *h
  * forward substitution leaves -> root, backward substitution root -> leaves (Sec. 1.1).
  * b, x: device [n][nrhs] FP64 (may alias).  Asynchronous on hip_stream.
  * Errors: MF_ESTATE (no valid factor), MF_EINVAL, MF_ENOMEM, MF_EHIP. */
-int mf_solve(const mf_plan *plan, const double *b, double *x, int32_t nrhs, int32_t transpose,
+int mf_solve(mf_plan *plan, const double *b, double *x, int32_t nrhs, int32_t transpose,
              void *hip_stream);
 
 /* r = b - A x with A applied element by element (A = sum_e P_e^T K_e P_e), FP64.
  * elem_mats device [n_elem][npe][npe]; x, b, r device [n][nrhs].  Asynchronous. */
-int mf_residual(const mf_plan *plan, const double *elem_mats, const double *x, const double *b,
+int mf_residual(mf_plan *plan, const double *elem_mats, const double *x, const double *b,
                 double *r, int32_t nrhs, void *hip_stream);
 
 /* Iterative refinement in FP64: x = solve(b); repeat r = b - A x, x += solve(r) until
@@ -174,7 +174,7 @@ int mf_residual(const mf_plan *plan, const double *elem_mats, const double *x, c
  * relres (host, may be NULL) the final relative residual.  Synchronizes hip_stream once per
  * iteration.  Errors: MF_ENOCONV (tolerance not met; x holds the last iterate), MF_ESTATE,
  * MF_EINVAL, MF_ENOMEM, MF_EHIP. */
-int mf_refine(const mf_plan *plan, const double *elem_mats, const double *b, double *x,
+int mf_refine(mf_plan *plan, const double *elem_mats, const double *b, double *x,
               int32_t nrhs, double tol, int32_t max_it, int32_t *its, double *relres,
               void *hip_stream);
 
@@ -194,7 +194,7 @@ int mf_factor_refine(mf_plan *plan, const double *elem_mats, int32_t precision, 
 /* Adjoint element gradient: gK[e][a][b] = -sum_r lam[conn_e[a]][r] * u[conn_e[b]][r], the
  * derivative of a loss through A = sum_e P_e^T K_e P_e given lam = A^{-T} dL/du.
  * lam, u device [n][nrhs]; gK device [n_elem][npe][npe].  Asynchronous. */
-int mf_elem_grad(const mf_plan *plan, const double *lam, const double *u, int32_t nrhs,
+int mf_elem_grad(mf_plan *plan, const double *lam, const double *u, int32_t nrhs,
                  double *gK, void *hip_stream);
 
 /* Copies the factors to host buffers sized from mf_info, front after front in id order:

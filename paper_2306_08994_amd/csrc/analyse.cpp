@@ -182,6 +182,8 @@ std::string analyse(int32_t n_mesh, const int32_t *dims, const int32_t *npes,
 
   int64_t node_off = 0, elem_off = 0, front_off = 0;
   std::vector<int32_t> owner, cnt, pivs, pos_l, pos_r;
+  P.mesh_front_ptr.assign(1, 0);
+  P.mesh_node_ptr.assign(1, 0);
   for (int32_t mi = 0; mi < n_mesh; ++mi) {
     const int64_t nn = n_nodes[mi], ne = n_elems[mi];
     const int32_t *conn = conns[mi];
@@ -341,6 +343,8 @@ std::string analyse(int32_t n_mesh, const int32_t *dims, const int32_t *npes,
     node_off += nn;
     elem_off += ne;
     front_off += Fm;
+    P.mesh_front_ptr.push_back(front_off);
+    P.mesh_node_ptr.push_back(node_off);
   }
   // offsets, counts
   int64_t store = 0, cbrow = 0;

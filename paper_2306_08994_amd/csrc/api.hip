@@ -131,6 +131,9 @@ void level_costs(const mf::HostPlan &H, const mf::LevelSchedule &S, LevelDev &D,
 // Classes with fewer rectangular-part slabs of 64 rows than this use slabs of 16 (quarter form).
 constexpr int64_t kRectQuarterBelow = 256;
 
+// Launches that put one front per grid row cap the rows here and take the rest grid-stride.
+constexpr int64_t kMaxGridY = 65535;
+
 // Fronts of a class whose widest front is above this take the workgroup-per-front block solves.
 constexpr int kWaveSolveMaxM = 64;
 // Largest (m - k) k of a class from which its rectangular part is a launch of its own.
@@ -395,6 +398,25 @@ int ensure_uploaded(mf_plan *P) {
   return MF_OK;
 }
 
+// Message of a bad pivot reported by the kernels: the front and pivot, the mesh they belong to,
+// the front's id within that mesh and the pivot's node (global id and id within the mesh).
+std::string pivot_message(const mf_plan *P, int32_t f, int32_t p) {
+  const mf::HostPlan &H = P->hp;
+  std::string msg = "zero or non-finite pivot in front " + std::to_string(f) + ", pivot " +
+                    std::to_string(p);
+  if (f < 0 || f >= H.F) return msg;
+  const auto it = std::upper_bound(H.mesh_front_ptr.begin(), H.mesh_front_ptr.end(), (int64_t)f);
+  const int64_t mi = (int64_t)(it - H.mesh_front_ptr.begin()) - 1;
+  msg += " (mesh " + std::to_string(mi) + ", front " + std::to_string(f - H.mesh_front_ptr[mi]) +
+         " of that mesh";
+  if (p >= 0 && p < H.desc[f].k) {
+    const int32_t v = H.front_idx[H.front_ptr[f] + p];
+    msg += ", node " + std::to_string(v) + " = node " + std::to_string(v - H.mesh_node_ptr[mi]) +
+           " of that mesh";
+  }
+  return msg + ")";
+}
+
 int grow(mf_plan *P, double *&buf, size_t &cap, size_t doubles) {
   if (cap >= doubles && buf) return MF_OK;
   P->drop_graphs();   // captured launches may hold the old pointer
@@ -467,9 +489,10 @@ int factor_level(mf_plan *P, const double *K, int prec, size_t l, hipStream_t s)
     }
     if (D.n_large) {
       LAUNCH(K_ASSEMBLE, D.c_assemble, mf::k_assemble,
-             dim3((D.large_max_m + 3) / 4, (unsigned)D.n_large), dim3(256),
-             (size_t)2 * D.large_max_m * sizeof(int), s,
-             P->d_wrec + D.rall + D.n_tiny + D.n_small, P->d_store, P->d_inv_l, P->d_inv_r, K);
+             dim3((D.large_max_m + 3) / 4, (unsigned)std::min<int64_t>(D.n_large, kMaxGridY)),
+             dim3(256), (size_t)2 * D.large_max_m * sizeof(int), s,
+             P->d_wrec + D.rall + D.n_tiny + D.n_small, (int)D.n_large, P->d_store, P->d_inv_l,
+             P->d_inv_r, K);
       if (D.n_fused) {
         const size_t lds = (size_t)(32 * 33 + 32 + 32 * mf::FP_MAXM) * sizeof(double);
         LAUNCH(K_FUSED, D.c_fused, mf::k_front_panels<32>, dim3((unsigned)D.n_fused),
@@ -477,19 +500,20 @@ int factor_level(mf_plan *P, const double *K, int prec, size_t l, hipStream_t s)
                P->d_store, P->d_status);
       }
       for (const StepDev &st : D.steps) {
-        const dim3 gt((unsigned)std::max<int64_t>(1, (st.trsm_items + 255) / 256), (unsigned)st.n);
+        const dim3 gt((unsigned)std::max<int64_t>(1, (st.trsm_items + 255) / 256),
+                      (unsigned)std::min<int64_t>(st.n, kMaxGridY));
         const mf::PanelRec *pr = P->d_panel + st.prec;
         switch (P->tune.nb) {
           case 16:
-            LAUNCH(K_TRSM, st.trsm, mf::k_panel_trsm<16>, gt, dim3(256), 0, s, pr, P->d_store, P->d_status,
+            LAUNCH(K_TRSM, st.trsm, mf::k_panel_trsm<16>, gt, dim3(256), 0, s, pr, (int)st.n, P->d_store, P->d_status,
                    P->d_arrive);
             break;
           case 64:
-            LAUNCH(K_TRSM, st.trsm, mf::k_panel_trsm<64>, gt, dim3(256), 0, s, pr, P->d_store, P->d_status,
+            LAUNCH(K_TRSM, st.trsm, mf::k_panel_trsm<64>, gt, dim3(256), 0, s, pr, (int)st.n, P->d_store, P->d_status,
                    P->d_arrive);
             break;
           default:
-            LAUNCH(K_TRSM, st.trsm, mf::k_panel_trsm<32>, gt, dim3(256), 0, s, pr, P->d_store, P->d_status,
+            LAUNCH(K_TRSM, st.trsm, mf::k_panel_trsm<32>, gt, dim3(256), 0, s, pr, (int)st.n, P->d_store, P->d_status,
                    P->d_arrive);
         }
         if (st.n_update) {
@@ -913,16 +937,13 @@ int mf_factor(mf_plan *P, const double *elem_mats, int32_t precision, void *hip_
   HIPCHK(hipMemcpyAsync(P->h_status, P->d_status, mf::kStatusWords * sizeof(int),
                         hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  if (P->h_status[0])
-    return fail(MF_EZERO_PIVOT, "zero or non-finite pivot in front " + std::to_string(P->h_status[1]) +
-                                    ", pivot " + std::to_string(P->h_status[2]));
+  if (P->h_status[0]) return fail(MF_EZERO_PIVOT, pivot_message(P, P->h_status[1], P->h_status[2]));
   P->factored = true;
   return MF_OK;
 }
 
-int mf_solve(const mf_plan *Pc, const double *b, double *x, int32_t nrhs, int32_t transpose,
+int mf_solve(mf_plan *P, const double *b, double *x, int32_t nrhs, int32_t transpose,
              void *hip_stream) {
-  mf_plan *P = const_cast<mf_plan *>(Pc);
   if (!P || !b || !x) return fail(MF_EINVAL, "null argument");
   if (nrhs < 1) return fail(MF_EINVAL, "nrhs must be >= 1");
   if (transpose != 0 && transpose != 1) return fail(MF_EINVAL, "transpose must be 0 or 1");
@@ -939,11 +960,11 @@ int mf_solve(const mf_plan *Pc, const double *b, double *x, int32_t nrhs, int32_
                      [&](hipStream_t st) { return launch_solve(P, b, x, nrhs, transpose != 0, st); });
 }
 
-int mf_residual(const mf_plan *P, const double *elem_mats, const double *x, const double *b,
+int mf_residual(mf_plan *P, const double *elem_mats, const double *x, const double *b,
                 double *r, int32_t nrhs, void *hip_stream) {
   if (!P || !elem_mats || !x || !b || !r) return fail(MF_EINVAL, "null argument");
   if (nrhs < 1) return fail(MF_EINVAL, "nrhs must be >= 1");
-  int rc = ensure_uploaded(const_cast<mf_plan *>(P));
+  int rc = ensure_uploaded(P);
   if (rc) return rc;
   const mf::HostPlan &H = P->hp;
   const int64_t tot = H.n * nrhs;
@@ -985,9 +1006,7 @@ static int refine_loop(mf_plan *P, const double *elem_mats, const double *b, dou
     if ((rc = read_norms(P, NL, rpart, nrhs, s, it == 0, rn, bn))) return rc;
     if (check_status && it == 0 && P->h_status[0]) {
       P->factored = false;
-      return fail(MF_EZERO_PIVOT, "zero or non-finite pivot in front " +
-                                      std::to_string(P->h_status[1]) + ", pivot " +
-                                      std::to_string(P->h_status[2]));
+      return fail(MF_EZERO_PIVOT, pivot_message(P, P->h_status[1], P->h_status[2]));
     }
     rr = 0.0;
     for (int c = 0; c < nrhs; ++c) {
@@ -1009,10 +1028,9 @@ static int refine_loop(mf_plan *P, const double *elem_mats, const double *b, dou
   return fail(MF_ENOCONV, buf);
 }
 
-int mf_refine(const mf_plan *Pc, const double *elem_mats, const double *b, double *x,
+int mf_refine(mf_plan *P, const double *elem_mats, const double *b, double *x,
               int32_t nrhs, double tol, int32_t max_it, int32_t *its, double *relres,
               void *hip_stream) {
-  mf_plan *P = const_cast<mf_plan *>(Pc);
   if (!P || !elem_mats || !b || !x) return fail(MF_EINVAL, "null argument");
   if (nrhs < 1 || max_it < 0 || !(tol >= 0)) return fail(MF_EINVAL, "bad nrhs, max_it or tol");
   if (!P->factored) return fail(MF_ESTATE, "no valid factorization: call mf_factor first");
@@ -1058,11 +1076,11 @@ int mf_factor_refine(mf_plan *P, const double *elem_mats, int32_t precision, con
   return refine_loop(P, elem_mats, b, x, nrhs, tol, max_it, its, relres, hip_stream, true, true);
 }
 
-int mf_elem_grad(const mf_plan *P, const double *lam, const double *u, int32_t nrhs, double *gK,
+int mf_elem_grad(mf_plan *P, const double *lam, const double *u, int32_t nrhs, double *gK,
                  void *hip_stream) {
   if (!P || !lam || !u || !gK) return fail(MF_EINVAL, "null argument");
   if (nrhs < 1) return fail(MF_EINVAL, "nrhs must be >= 1");
-  int rc = ensure_uploaded(const_cast<mf_plan *>(P));
+  int rc = ensure_uploaded(P);
   if (rc) return rc;
   const mf::HostPlan &H = P->hp;
   const int64_t tot = H.n_elem * H.npe * H.npe;

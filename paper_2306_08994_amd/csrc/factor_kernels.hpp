@@ -201,38 +201,42 @@ k_factor_small(const WaveRec *__restrict__ recs, int nrec, double *__restrict__ 
 // tiled path
 // ---------------------------------------------------------------------------------------------
 
-// Extend-add into the front's storage.  grid = (row strips of 4, fronts).
+// Extend-add into the front's storage.  grid = (row strips of 4, fronts); the fronts beyond
+// gridDim.y are taken grid-stride.
 __global__ void __launch_bounds__(256)
-k_assemble(const WaveRec *__restrict__ recs, double *__restrict__ store,
+k_assemble(const WaveRec *__restrict__ recs, int nrec, double *__restrict__ store,
            const int32_t *__restrict__ inv_l, const int32_t *__restrict__ inv_r,
            const double *__restrict__ K) {
   extern __shared__ int smaps[];      // the front's column maps: left, then right
-  const WaveRec d = recs[blockIdx.y];
-  const int m = d.m;
-  const int i0 = blockIdx.x * 4;
-  if (i0 >= m) return;                // uniform per workgroup
-  const int32_t *il = inv_l + d.idx;
-  const int32_t *ir = inv_r + d.idx;
-  int *sl = smaps, *sr = smaps + m;
-  for (int j = threadIdx.x; j < m; j += 256) {
-    sl[j] = il[j];
-    sr[j] = ir[j];
-  }
-  __syncthreads();
-  const GatherCtx g = rec_gather_ctx(d, store, K);
-  double *F = store + d.store;
-  // per column of this thread: the strip's four entries gathered together, then stored
-  for (int j = threadIdx.x; j < m; j += 256) {
-    const int lj = sl[j], rj = sr[j];
-    double v[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int i = min(i0 + u, m - 1);
-      v[u] = gather_entry(g, sl[i], lj, sr[i], rj);
+  for (int fi = blockIdx.y; fi < nrec; fi += gridDim.y) {
+    const WaveRec d = recs[fi];
+    const int m = d.m;
+    const int i0 = blockIdx.x * 4;
+    if (i0 >= m) continue;              // uniform per workgroup
+    const int32_t *il = inv_l + d.idx;
+    const int32_t *ir = inv_r + d.idx;
+    int *sl = smaps, *sr = smaps + m;
+    __syncthreads();                    // the previous front's maps are no longer read
+    for (int j = threadIdx.x; j < m; j += 256) {
+      sl[j] = il[j];
+      sr[j] = ir[j];
     }
+    __syncthreads();
+    const GatherCtx g = rec_gather_ctx(d, store, K);
+    double *F = store + d.store;
+    // per column of this thread: the strip's four entries gathered together, then stored
+    for (int j = threadIdx.x; j < m; j += 256) {
+      const int lj = sl[j], rj = sr[j];
+      double v[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (i0 + u < m) F[(int64_t)(i0 + u) * m + j] = v[u];
+      for (int u = 0; u < 4; ++u) {
+        const int i = min(i0 + u, m - 1);
+        v[u] = gather_entry(g, sl[i], lj, sr[i], rj);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (i0 + u < m) F[(int64_t)(i0 + u) * m + j] = v[u];
+    }
   }
 }
 

@@ -95,109 +95,112 @@ __device__ __noinline__ bool wave_diag_lu_call(double *F, int64_t m, int pb, dou
 // the block and resets the counter to zero for the next panel step.
 template <int NB>
 __global__ void __launch_bounds__(256)
-k_panel_trsm(const PanelRec *__restrict__ recs, double *__restrict__ store,
+k_panel_trsm(const PanelRec *__restrict__ recs, int nrec, double *__restrict__ store,
              int *__restrict__ status, int *__restrict__ arrive) {
   __shared__ double D[NB][NB + 1];
   __shared__ double rd[NB];
-  const PanelRec d = recs[blockIdx.y];
-  const int f = d.f, p0 = d.p0;
-  const int m = d.m, pb = min(NB, d.k - p0), pe = p0 + pb;
-  const int rest = m - pe, rpad = (rest + 63) & ~63;
-  const int item = blockIdx.x * 256 + threadIdx.x;
-  if (blockIdx.x > 0 && (int)(blockIdx.x * 256) >= rpad + rest) return;   // idle (uniform)
-  double *F = store + d.store;
-  // this thread's column (item < rest) or row, loaded before the diagonal block is factored so
-  // that the load latency overlaps the factorization
-  const bool colitem = item < rest, has = colitem || (item >= rpad && item < rpad + rest);
-  double *cp = F + (int64_t)p0 * m + pe + item;
-  double *row = F + (int64_t)(pe + item - rpad) * m + p0;
-  double v[NB];
-  if (has) {
-    if (colitem) {
+  for (int fi = blockIdx.y; fi < nrec; fi += gridDim.y) {
+    const PanelRec d = recs[fi];
+    const int f = d.f, p0 = d.p0;
+    const int m = d.m, pb = min(NB, d.k - p0), pe = p0 + pb;
+    const int rest = m - pe, rpad = (rest + 63) & ~63;
+    const int item = blockIdx.x * 256 + threadIdx.x;
+    if (blockIdx.x > 0 && (int)(blockIdx.x * 256) >= rpad + rest) continue;   // idle (uniform)
+    __syncthreads();   // the previous front's diagonal block in D is no longer read
+    double *F = store + d.store;
+    // this thread's column (item < rest) or row, loaded before the diagonal block is factored so
+    // that the load latency overlaps the factorization
+    const bool colitem = item < rest, has = colitem || (item >= rpad && item < rpad + rest);
+    double *cp = F + (int64_t)p0 * m + pe + item;
+    double *row = F + (int64_t)(pe + item - rpad) * m + p0;
+    double v[NB];
+    if (has) {
+      if (colitem) {
 #pragma unroll
-      for (int q = 0; q < NB; ++q) v[q] = cp[(int64_t)min(q, pb - 1) * m];
-    } else {
-#pragma unroll
-      for (int q = 0; q < NB; ++q) v[q] = row[min(q, pb - 1)];
-    }
-  }
-  // workgroups that take part (the others returned above): at least one
-  const int nact = max(1, (rpad + rest + 255) / 256);
-  if (threadIdx.x < 64)
-    wave_diag_lu<NB>(F + (int64_t)p0 * m + p0, m, pb, D, rd, threadIdx.x, f, p0, status,
-                     nact == 1);
-  __syncthreads();
-  if (has) {
-    // each step reads its row (column) of D into registers first, the reads issued together,
-    // then its products: one LDS round trip per step, overlapped with the previous step
-    double dr[NB];
-    if (colitem) {
-#pragma unroll
-      for (int q = 0; q < NB; ++q) {
-#pragma unroll
-        for (int r = 0; r < q; ++r) dr[r] = D[q][r];
-        const double rq = rd[q];
-        __builtin_amdgcn_sched_barrier(0);
-        double s0 = v[q], s1 = 0.0;
-#pragma unroll
-        for (int r = 0; r + 1 < q; r += 2) {
-          s0 -= dr[r] * v[r];
-          s1 -= dr[r + 1] * v[r + 1];
-        }
-        if (q & 1) s0 -= dr[q - 1] * v[q - 1];
-        v[q] = (s0 + s1) * rq;
-      }
-      if (pb == NB) {
-#pragma unroll
-        for (int q = 0; q < NB; ++q) cp[(int64_t)q * m] = v[q];
+        for (int q = 0; q < NB; ++q) v[q] = cp[(int64_t)min(q, pb - 1) * m];
       } else {
 #pragma unroll
-        for (int q = 0; q < NB; ++q)
-          if (q < pb) cp[(int64_t)q * m] = v[q];
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < NB; ++q) {
-#pragma unroll
-        for (int r = 0; r < q; ++r) dr[r] = D[r][q];
-        __builtin_amdgcn_sched_barrier(0);
-        double s0 = v[q], s1 = 0.0;
-#pragma unroll
-        for (int r = 0; r + 1 < q; r += 2) {
-          s0 -= v[r] * dr[r];
-          s1 -= v[r + 1] * dr[r + 1];
-        }
-        if (q & 1) s0 -= v[q - 1] * dr[q - 1];
-        v[q] = s0 + s1;
-      }
-      if (pb == NB) {
-#pragma unroll
-        for (int q = 0; q < NB; ++q) row[q] = v[q];
-      } else {
-#pragma unroll
-        for (int q = 0; q < NB; ++q)
-          if (q < pb) row[q] = v[q];
+        for (int q = 0; q < NB; ++q) v[q] = row[min(q, pb - 1)];
       }
     }
-  }
-  if (nact > 1 && threadIdx.x < 64) {
-    // every thread of this workgroup is past its reads of the diagonal block (the LU consumed
-    // them before the barrier); count this workgroup and store the block if it is the last.
-    // Relaxed: the only order needed is each workgroup's reads (complete, their values used
-    // before the barrier) before the last one's stores (issued only after the count returned),
-    // and no data passes through the counter -- an acquire/release here would write back and
-    // invalidate the whole L2 around every increment.
-    int prev = 0;
-    if (threadIdx.x == 0)
-      prev = __hip_atomic_fetch_add(arrive + f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    prev = __builtin_amdgcn_readlane(prev, 0);
-    if (prev == nact - 1) {
-      const int lane = threadIdx.x;
-      if (lane < pb) {
-        double *dst = F + (int64_t)p0 * m + p0 + lane;
-        for (int i = 0; i < pb; ++i) dst[(int64_t)i * m] = D[i][lane];
+    // workgroups that take part (the others skip the front above): at least one
+    const int nact = max(1, (rpad + rest + 255) / 256);
+    if (threadIdx.x < 64)
+      wave_diag_lu<NB>(F + (int64_t)p0 * m + p0, m, pb, D, rd, threadIdx.x, f, p0, status,
+                       nact == 1);
+    __syncthreads();
+    if (has) {
+      // each step reads its row (column) of D into registers first, the reads issued together,
+      // then its products: one LDS round trip per step, overlapped with the previous step
+      double dr[NB];
+      if (colitem) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+#pragma unroll
+          for (int r = 0; r < q; ++r) dr[r] = D[q][r];
+          const double rq = rd[q];
+          __builtin_amdgcn_sched_barrier(0);
+          double s0 = v[q], s1 = 0.0;
+#pragma unroll
+          for (int r = 0; r + 1 < q; r += 2) {
+            s0 -= dr[r] * v[r];
+            s1 -= dr[r + 1] * v[r + 1];
+          }
+          if (q & 1) s0 -= dr[q - 1] * v[q - 1];
+          v[q] = (s0 + s1) * rq;
+        }
+        if (pb == NB) {
+#pragma unroll
+          for (int q = 0; q < NB; ++q) cp[(int64_t)q * m] = v[q];
+        } else {
+#pragma unroll
+          for (int q = 0; q < NB; ++q)
+            if (q < pb) cp[(int64_t)q * m] = v[q];
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+#pragma unroll
+          for (int r = 0; r < q; ++r) dr[r] = D[r][q];
+          __builtin_amdgcn_sched_barrier(0);
+          double s0 = v[q], s1 = 0.0;
+#pragma unroll
+          for (int r = 0; r + 1 < q; r += 2) {
+            s0 -= v[r] * dr[r];
+            s1 -= v[r + 1] * dr[r + 1];
+          }
+          if (q & 1) s0 -= v[q - 1] * dr[q - 1];
+          v[q] = s0 + s1;
+        }
+        if (pb == NB) {
+#pragma unroll
+          for (int q = 0; q < NB; ++q) row[q] = v[q];
+        } else {
+#pragma unroll
+          for (int q = 0; q < NB; ++q)
+            if (q < pb) row[q] = v[q];
+        }
       }
-      if (lane == 0) __hip_atomic_store(arrive + f, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (nact > 1 && threadIdx.x < 64) {
+      // every thread of this workgroup is past its reads of the diagonal block (the LU consumed
+      // them before the barrier); count this workgroup and store the block if it is the last.
+      // Relaxed: the only order needed is each workgroup's reads (complete, their values used
+      // before the barrier) before the last one's stores (issued only after the count returned),
+      // and no data passes through the counter -- an acquire/release here would write back and
+      // invalidate the whole L2 around every increment.
+      int prev = 0;
+      if (threadIdx.x == 0)
+        prev = __hip_atomic_fetch_add(arrive + f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      prev = __builtin_amdgcn_readlane(prev, 0);
+      if (prev == nact - 1) {
+        const int lane = threadIdx.x;
+        if (lane < pb) {
+          double *dst = F + (int64_t)p0 * m + p0 + lane;
+          for (int i = 0; i < pb; ++i) dst[(int64_t)i * m] = D[i][lane];
+        }
+        if (lane == 0) __hip_atomic_store(arrive + f, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
   }
 }

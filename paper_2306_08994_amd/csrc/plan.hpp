@@ -95,6 +95,7 @@ struct HostPlan {
   std::vector<int32_t> front_idx;  // [sum m]
   std::vector<int32_t> inv_l, inv_r;  // [sum m] child CB position (leaf: local node in inv_l)
   std::vector<FrontDesc> desc;
+  std::vector<int64_t> mesh_front_ptr, mesh_node_ptr;   // [n_mesh+1] first front / node of a mesh
   int32_t height = 0, max_m = 0, max_k = 0;
   int64_t store_doubles = 0, sum_c = 0, sum_mk = 0;
   double factor_flops = 0, solve_flops = 0, sum_cb2 = 0;

@@ -197,6 +197,22 @@ def test_mixed_precision_refines_to_fp64(prec):
     print(f"{prec}: factor deviation {err_factor:.2e}, {its} corrections, relres {rr:.2e}")
 
 
+def test_zero_pivot_message_names_mesh_and_node():
+    from paper_2306_08994_amd import MFError
+    from paper_2306_08994_amd import _lib
+    p = config_problem(4, n_mesh=3, side_range=(2, 6))
+    plan, K, b = _setup(p)
+    Kbad = K.clone()
+    Kbad[int(p.elem_offsets[2]), 0, 0] = 0.0     # node 0 of mesh 2: its corner, a leaf pivot
+    with pytest.raises(MFError) as ei:
+        plan.factor(Kbad)
+    assert ei.value.code == _lib.MF_EZERO_PIVOT
+    msg = str(ei.value)
+    assert "mesh 2" in msg and "= node 0 of that mesh" in msg, msg
+    assert f"node {int(p.node_offsets[2])} " in msg, msg
+    plan.factor(K)                                 # recovers
+
+
 def test_error_paths():
     import torch
     from paper_2306_08994_amd import MFError, Plan
