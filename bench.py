@@ -171,6 +171,84 @@ def host_cpu():
     return out
 
 
+ORACLE_SOLVE_SNIPPET = r"""
+import json, sys, time
+sys.path.insert(0, %(root)r)
+import numpy as np
+from fixtures import config_problem
+from oracle.tree import build_tree, front_flops
+from oracle.factor import factor, global_connectivity
+from oracle.solve import solve
+from oracle.residual import relres
+p = config_problem(%(cfg)d)
+tree = build_tree(p.meshes)
+conn = global_connectivity(p)
+fac_f, sol_f, _ = front_flops(tree)
+t0 = time.perf_counter()
+fac = factor(tree, p.K, conn)
+t1 = time.perf_counter()
+x = solve(tree, fac, p.b)
+t2 = time.perf_counter()
+np.save(%(out)r, x)
+print(json.dumps({"sec_factor": t1 - t0, "sec_solve": t2 - t1, "flops": fac_f + p.nrhs * sol_f,
+                  "relres": relres(p.K, conn, x, p.b)}))
+"""
+
+
+def oracle_solution(cfg):
+    """The oracle's solution of workload `cfg`, computed once on one host thread, and the time
+    it took: (x, summary) or (None, {"error": ...})."""
+    import tempfile
+    import numpy as np
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    with tempfile.TemporaryDirectory() as td:
+        path = os.path.join(td, "x.npy")
+        code = ORACLE_SOLVE_SNIPPET % {"root": ROOT, "cfg": cfg, "out": path}
+        res = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True,
+                             text=True, timeout=900)
+        if res.returncode != 0:
+            return None, {"error": res.stderr[-400:]}
+        r = json.loads(res.stdout.strip().splitlines()[-1])
+        x = np.load(path)
+    sec = r["sec_factor"] + r["sec_solve"]
+    return x, {"value": r["flops"] / sec / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+               "sample": "one run of the oracle's factor + solve of this workload, single thread",
+               "ms_per_system": sec * 1e3, "ms_factor": r["sec_factor"] * 1e3,
+               "relres": r["relres"]}
+
+
+def err_vs(x, xo):
+    """max over right-hand sides of ||x - x_O||_2 / ||x_O||_2 (x a device tensor)."""
+    import numpy as np
+    xh = x.detach().cpu().numpy().reshape(xo.shape[0], -1)
+    xo2 = xo.reshape(xo.shape[0], -1)
+    return float(np.max(np.linalg.norm(xh - xo2, axis=0) / np.linalg.norm(xo2, axis=0)))
+
+
+PEAK_TFS = {"fp64": FP64_PEAK_TFS, "fp32": FP32_PEAK_TFS, "bf16": BF16_PEAK_TFS}
+
+
+def schur_roofline(plan, step, prec):
+    """The Schur-complement GEMM launches of one step timed with events: algorithmic flops
+    (2 k c^2 per front) over their summed duration, against the MFMA peak of the precision
+    they run in."""
+    plan.profile(True)
+    step()
+    _sync()
+    rep = plan.profile_report()
+    plan.profile(False)
+    k = next((k for k in rep["kernels"] if k["name"] == "gemm_schur"), None)
+    if k is None:
+        return None
+    ach = k["flops"] / (k["ms"] / 1e3) / 1e12
+    peak = PEAK_TFS[prec]
+    return {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+            "launches": k["launches"], "ms_per_step": k["ms"],
+            "flops_per_launch": k["flops"] / k["launches"],
+            "bytes_per_launch": k["bytes"] / k["launches"],
+            "attainable_tfs": min(peak, k["flops"] / k["bytes"] * HBM_PEAK_GBS / 1e3)}
+
+
 CPU_POOL_SNIPPET = r"""
 import json, os, sys, time
 sys.path.insert(0, %(root)r)
@@ -191,53 +269,73 @@ def one(i):
     conn = global_connectivity(sub)
     fac_f, sol_f, _ = front_flops(tree)
     fac = factor(tree, sub.K, conn)
-    solve(tree, fac, sub.b)
-    return fac_f + sub.nrhs * sol_f
+    x = solve(tree, fac, sub.b)
+    return fac_f + sub.nrhs * sol_f, x
 
 if __name__ == "__main__":
     workers = %(workers)d
     with mp.get_context("fork").Pool(workers) as pool:
         t0 = time.perf_counter()
-        flops = sum(pool.map(one, range(len(P.meshes)), chunksize=1))
+        res = pool.map(one, range(len(P.meshes)), chunksize=1)
         wall = time.perf_counter() - t0
-    print(json.dumps({"sec": wall, "flops": flops, "systems": len(P.meshes), "workers": workers}))
+    np.save(%(out)r, np.concatenate([r[1] for r in res]))
+    print(json.dumps({"sec": wall, "flops": sum(r[0] for r in res), "systems": len(P.meshes),
+                      "workers": workers}))
 """
 
 
 def cpu_pool_baseline(workers=16):
     """The 256-mesh batch on the host: the oracle (factor + solve) one mesh per task over a
-    process pool of `workers` single-threaded processes; wall clock of the whole batch."""
+    process pool of `workers` single-threaded processes; wall clock of the whole batch.
+    Returns (the oracle's solution of the batch, summary)."""
+    import tempfile
+    import numpy as np
     workers = max(1, min(workers, os.cpu_count() or 1))
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    code = CPU_POOL_SNIPPET % {"root": ROOT, "workers": workers}
-    res = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
-                         timeout=900)
-    if res.returncode != 0:
-        return {"error": res.stderr[-400:]}
-    r = json.loads(res.stdout.strip().splitlines()[-1])
-    return {"value": r["flops"] / r["sec"] / 1e9, "unit": "GFLOP/s", "cores": r["workers"],
-            "kind": "oracle",
-            "sample": f"the whole batch ({r['systems']} meshes): oracle factor + solve, one mesh "
-                      f"per task over {r['workers']} single-threaded processes, wall clock",
-            "ms_per_batch": r["sec"] * 1e3}
+    with tempfile.TemporaryDirectory() as td:
+        path = os.path.join(td, "x.npy")
+        code = CPU_POOL_SNIPPET % {"root": ROOT, "workers": workers, "out": path}
+        res = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True,
+                             text=True, timeout=900)
+        if res.returncode != 0:
+            return None, {"error": res.stderr[-400:]}
+        r = json.loads(res.stdout.strip().splitlines()[-1])
+        x = np.load(path)
+    return x, {"value": r["flops"] / r["sec"] / 1e9, "unit": "GFLOP/s", "cores": r["workers"],
+               "kind": "oracle",
+               "sample": f"the whole batch ({r['systems']} meshes): oracle factor + solve, one "
+                         f"mesh per task over {r['workers']} single-threaded processes, wall clock",
+               "ms_per_batch": r["sec"] * 1e3}
 
 
 def schedule(plan, K, prec, tuning):
     """The schedule of a run: `tuning` (tile,fused_max_m,nb,small_max_m) if given, else the
     autotuner's choice on this workload and precision."""
     if tuning:
-        t_, f_, nb_, sm_ = (int(v) for v in tuning.split(","))
-        plan.set_tuning(sm_, nb_, f_ if f_ > 0 else -1, t_)
-        return {"tile": t_, "fused_max_m": f_, "nb": nb_, "small_max_m": sm_, "given": True}
+        return given_schedule(plan, tuning)
     return plan.autotune(K, prec, reps=2)["chosen"]
 
 
-def variant_mixed(steps, warmup, precs=("fp64", "fp32", "bf16"), tuning=None):
+def given_schedule(plan, tuning):
+    """tile,fused_max_m,nb,small_max_m[,persistent] (fused_max_m 0: fused route off;
+    persistent 1 / 0: persistent class launches on / off, default on)."""
+    v = [int(x) for x in tuning.split(",")]
+    t_, f_, nb_, sm_ = v[:4]
+    pers = v[4] if len(v) > 4 else 1
+    plan.set_tuning(sm_, nb_, f_ if f_ > 0 else -1, t_, 1 if pers else -1)
+    return {"persistent": pers, "tile": t_, "fused_max_m": f_, "nb": nb_, "small_max_m": sm_,
+            "given": True}
+
+
+def variant_mixed(steps, warmup, precs=("fp64", "fp32", "bf16"), tuning=None, oracle=True):
     """3D Q1 32^3 (35,937 unknowns): FP64 vs FP32- and BF16-Schur factorizations, each refined
-    in FP64 to a relative residual <= 1e-12; error against the FP64 solution reported."""
+    in FP64 to a relative residual <= 1e-12; the error of each against the oracle's solution
+    (computed once on the host, timed: the oracle leg of this workload) and against the GPU's
+    FP64 solution; the Schur GEMMs' fraction of their precision's MFMA peak."""
     import torch
     from fixtures import config_problem
     from paper_2306_08994_amd import Plan
+    xo, oleg = oracle_solution(3) if oracle else (None, None)
     p = config_problem(3)
     plan = Plan(p.meshes)
     K = torch.from_numpy(p.K).cuda()
@@ -264,7 +362,10 @@ def variant_mixed(steps, warmup, precs=("fp64", "fp32", "bf16"), tuning=None):
         tf = (time.perf_counter() - t0) / steps
         out[prec] = {"ms_per_system": wall * 1e3, "ms_factor": tf * 1e3,
                      "gflops": flops / wall / 1e9, "refine_corrections": its, "relres": rr,
-                     "err_vs_fp64": err}
+                     "err_vs_oracle": None if xo is None else err_vs(xs, xo),
+                     "err_vs_fp64": err, "roofline_schur": schur_roofline(plan, step, prec)}
+    if oleg is not None:
+        out["cpu_oracle"] = oleg
     return out
 
 
@@ -330,12 +431,16 @@ def variant_table3(steps, warmup):
             "schedule": sched}
 
 
-def variant_batched(steps, warmup, precs=("fp64", "fp32"), tuning=None):
+def variant_batched(steps, warmup, precs=("fp64", "fp32"), tuning=None, oracle=True):
     """256 independent 2D advection-diffusion meshes (sides 32..128) in one batch: every class
-    of all meshes in one launch sequence; FP64 and FP32-Schur, refined to 1e-12."""
+    of all meshes in one launch sequence; FP64 and FP32-Schur, refined to 1e-12.  The oracle
+    solves the batch on the host (one mesh per task over a process pool, timed): the error of
+    each variant against it, the whole batch's and the worst mesh's."""
+    import numpy as np
     import torch
     from fixtures import config_problem
     from paper_2306_08994_amd import Plan
+    xo, pool = cpu_pool_baseline() if oracle else (None, None)
     p = config_problem(4)
     plan = Plan(p.meshes)
     K = torch.from_numpy(p.K).cuda()
@@ -355,9 +460,19 @@ def variant_batched(steps, warmup, precs=("fp64", "fp32"), tuning=None):
         if ref is None:
             ref = xs
         err = float(torch.linalg.norm(xs - ref) / torch.linalg.norm(ref))
+        worst = None
+        if xo is not None:
+            xh = xs.cpu().numpy()
+            no = p.node_offsets
+            worst = max(float(np.linalg.norm(xh[no[i]:no[i + 1]] - xo[no[i]:no[i + 1]]) /
+                              np.linalg.norm(xo[no[i]:no[i + 1]])) for i in range(len(p.meshes)))
         out[prec] = {"ms_per_batch": wall * 1e3, "ms_per_system": wall * 1e3 / len(p.meshes),
                      "gflops": flops / wall / 1e9, "refine_corrections": its, "relres": rr,
-                     "err_vs_fp64": err}
+                     "err_vs_oracle": None if xo is None else err_vs(xs, xo),
+                     "err_vs_oracle_worst_mesh": worst,
+                     "err_vs_fp64": err, "roofline_schur": schur_roofline(plan, step, prec)}
+    if pool is not None:
+        out["cpu_oracle_pool"] = pool
     return out
 
 
@@ -369,8 +484,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--tuning", default=None,
-                    help="tile,fused_max_m,nb,small_max_m: use this schedule instead of autotuning "
-                         "(fused_max_m 0 = fused route off), e.g. for counter runs, where the "
+                    help="tile,fused_max_m,nb,small_max_m[,persistent]: use this schedule instead "
+                         "of autotuning (fused_max_m 0 = fused route off; persistent 0 = one launch "
+                         "per panel step), e.g. for counter runs, where the "
                          "serialised dispatches distort the autotuner's timings")
     ap.add_argument("--variant", default="all",
                     choices=["all", "main", "mixed", "batched", "l2", "table3"],
@@ -394,6 +510,7 @@ def main():
         kw = {}
         if args.variant in ("mixed", "batched"):
             kw["tuning"] = args.tuning
+            kw["oracle"] = not args.no_cpu_baseline
             if args.precs:
                 kw["precs"] = tuple(args.precs.split(","))
         fn = {"mixed": variant_mixed, "batched": variant_batched, "l2": variant_l2,
@@ -412,10 +529,7 @@ def main():
     info = plan.info
     nrhs = p.nrhs
     if args.tuning:
-        t_, f_, nb_, sm_ = (int(v) for v in args.tuning.split(","))
-        plan.set_tuning(sm_, nb_, f_ if f_ > 0 else -1, t_)
-        tuned = {"chosen": {"tile": t_, "fused_max_m": f_, "nb": nb_, "small_max_m": sm_,
-                            "given": True}}
+        tuned = {"chosen": given_schedule(plan, args.tuning)}
     else:
         tuned = plan.autotune(K, reps=3)      # schedule chosen on this workload, before timing
 
@@ -481,11 +595,9 @@ def main():
         "kernels": rep["kernels"],
     }
     if not args.no_variants and args.variant == "all":
-        vs = max(3, args.steps // 4)
-        out["mixed_precision_3d"] = variant_mixed(vs, 2)
-        out["batched_256_meshes"] = variant_batched(vs, 2)
-        if not args.no_cpu_baseline:
-            out["batched_256_meshes"]["cpu_oracle_pool"] = cpu_pool_baseline()
+        vs = args.steps
+        out["mixed_precision_3d"] = variant_mixed(vs, 2, oracle=not args.no_cpu_baseline)
+        out["batched_256_meshes"] = variant_batched(vs, 2, oracle=not args.no_cpu_baseline)
         out["l2_projection_p123"] = variant_l2(vs, 2)
         out["tree_of_table3"] = variant_table3(vs, 2)
     if not args.no_cpu_baseline:

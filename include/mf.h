@@ -127,20 +127,24 @@ int mf_task_trace(const mf_plan *plan, mf_trace_info *out, int64_t *hist, int64_
  *                (assembly, panel LU of nb pivots at a time, MFMA Schur GEMM).  It is clipped
  *                to what fits in one workgroup's LDS on the device.  0 keeps the current value.
  *   nb           panel width of the tiled path's separate panel launches: 16, 32 or 64.
- *                0 keeps the current value.
+ *                0 keeps the current value.  (The persistent route always uses 32.)
  *   fused_max_m  tiled fronts of width <= fused_max_m run all their panels (32 pivots each) in
  *                one workgroup, leaving only the Schur GEMM to a separate launch; wider fronts
  *                use one launch per panel step.  Clipped to 576; -1 disables the fused route;
- *                0 keeps the current value.
+ *                0 keeps the current value.  (Not used by the persistent route.)
  *   tile         output tile edge of the MFMA GEMMs: 32 or 64.  0 keeps the current value.
+ *   persistent   1: the tiled fronts of a Foata class run in one persistent launch whose
+ *                workgroups take the class's extend-add strips, panel chunks, update tiles
+ *                and Schur tiles in order and wait on per-front progress counters;
+ *                -1: one launch per kind of work and per panel step (the default); 0 keeps it.
  * Invalidates a previous factorization.  Errors: MF_EINVAL. */
 int mf_set_tuning(mf_plan *plan, int32_t small_max_m, int32_t nb, int32_t fused_max_m,
-                  int32_t tile);
+                  int32_t tile, int32_t persistent);
 
 /* Autotuner: factors elem_mats (device, as in mf_factor) under each candidate schedule that the
- * workload's front widths make relevant -- GEMM tile 64/32, fused route on/off, panel width
- * 32/64, LDS limit 128/64 -- times `reps` factorizations of each (host clock, median), keeps
- * the fastest and leaves the plan factored with it.  report (host, cap bytes, may be NULL)
+ * workload's front widths make relevant -- persistent class launches on/off, GEMM tile 64/32,
+ * fused route on/off, panel width 32/64, LDS limit 128/64 -- times `reps` factorizations of
+ * each (host clock, median), keeps the fastest and leaves the plan factored with it.  report (host, cap bytes, may be NULL)
  * receives a NUL-terminated JSON summary {"candidates": [...], "chosen": {...}}; needed (may
  * be NULL) its size.  Synchronizes hip_stream.  Errors: as mf_factor, MF_EINVAL. */
 int mf_autotune(mf_plan *plan, const double *elem_mats, int32_t precision, int32_t reps,

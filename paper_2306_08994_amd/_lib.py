@@ -63,7 +63,7 @@ def load():
         "mf_plan_export_tree": (c_int32, [P, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                           c_void_p]),
         "mf_task_trace": (c_int32, [P, POINTER(MfTraceInfo), c_void_p, c_int64, POINTER(c_int64)]),
-        "mf_set_tuning": (c_int32, [P, c_int32, c_int32, c_int32, c_int32]),
+        "mf_set_tuning": (c_int32, [P, c_int32, c_int32, c_int32, c_int32, c_int32]),
         "mf_autotune": (c_int32, [P, c_void_p, c_int32, c_int32, c_void_p, c_char_p, c_int64,
                                   POINTER(c_int64)]),
         "mf_factor": (c_int32, [P, c_void_p, c_int32, c_void_p]),

@@ -400,7 +400,9 @@ void build_schedule(HostPlan &P, const Tuning &t) {
     L.all.insert(L.all.end(), L.small.begin(), L.small.end());
     L.all.insert(L.all.end(), L.large.begin(), L.large.end());
   }
-  const int32_t nb = t.nb, T = t.tile;
+  // the persistent class launch runs every tiled front panel by panel, 32 pivots at a time
+  const int32_t nb = t.persistent ? 32 : t.nb, T = t.tile;
+  const int32_t fused_lim = t.persistent ? 0 : t.fused_max_m;
   auto add_tiles = [&](std::vector<GemmTask> &out, int32_t f, int32_t i0, int32_t i1, int32_t j0,
                        int32_t j1, int32_t q0, int32_t q1) {
     if (i0 >= i1 || j0 >= j1 || q0 >= q1) return;
@@ -423,7 +425,7 @@ void build_schedule(HostPlan &P, const Tuning &t) {
     int32_t max_steps = 0;
     for (int32_t f : L.large) {
       const FrontDesc &d = P.desc[f];
-      if (d.m <= t.fused_max_m) {
+      if (d.m <= fused_lim) {
         if (d.k > 0) {
           L.fused.push_back(f);
           L.fused_max_m = std::max(L.fused_max_m, d.m);
@@ -436,7 +438,7 @@ void build_schedule(HostPlan &P, const Tuning &t) {
     for (int32_t f : L.large) {
       const FrontDesc &d = P.desc[f];
       add_tiles(L.schur, f, d.k, d.m, d.k, d.m, 0, d.k);
-      if (d.m <= t.fused_max_m) continue;
+      if (d.m <= fused_lim) continue;
       for (int32_t s = 0; s * nb < d.k; ++s) {
         const int32_t p0 = s * nb, pe = std::min(p0 + nb, d.k);
         PanelStep &S = L.steps[s];

@@ -208,7 +208,7 @@ int ensure_uploaded(mf_plan *P) {
     D.schur = (int64_t)tasks.size();
     D.n_schur = (int64_t)S.schur.size();
     tasks.insert(tasks.end(), S.schur.begin(), S.schur.end());
-    level_costs(H, S, D, P->tune.nb);
+    level_costs(H, S, D, P->tune.persistent ? mf::kClassNB : P->tune.nb);
   }
   // wave records follow the class lists, class after class
   {
@@ -266,10 +266,121 @@ int ensure_uploaded(mf_plan *P) {
       }
     D.n_rup = (int64_t)rect.size() - D.rup;
   }
+  // persistent class launches: per class with tiled fronts, its task list in phase order
+  // (extend-add strips, then per panel step the chunks and the update tiles, then the Schur
+  // tiles) with the count of earlier-phase tasks of the same front that each task waits for
+  std::vector<mf::ClassTask> ctasks;
+  int64_t n_counters = 0;
+  if (P->tune.persistent) {
+    for (size_t l = 0; l < H.levels.size(); ++l) {
+      const mf::LevelSchedule &S = H.levels[l];
+      LevelDev &D = P->lv[l];
+      D.ctask = (int64_t)ctasks.size();
+      D.n_ctask = 0;
+      if (S.large.empty()) continue;
+      std::vector<int32_t> cidx(S.large.size()), done(S.large.size(), 0);
+      std::unordered_map<int32_t, int32_t> slot;
+      for (size_t i = 0; i < S.large.size(); ++i) {
+        cidx[i] = (int32_t)(n_counters++);
+        slot[S.large[i]] = (int32_t)i;
+      }
+      auto base = [&](int32_t f, int32_t type) {
+        const mf::FrontDesc &d = H.desc[f];
+        mf::ClassTask t;
+        std::memset(&t, 0, sizeof t);
+        t.store = d.store;
+        t.type = type;
+        t.f = f;
+        t.ci = cidx[slot[f]];
+        t.need = done[slot[f]];
+        t.m = d.m;
+        t.k = d.k;
+        return t;
+      };
+      std::vector<int32_t> phase(S.large.size(), 0);   // tasks of the current phase per front
+      auto close_phase = [&]() {
+        for (size_t i = 0; i < S.large.size(); ++i) {
+          done[i] += phase[i];
+          phase[i] = 0;
+        }
+      };
+      for (size_t i = 0; i < S.large.size(); ++i) {
+        const int32_t f = S.large[i];
+        const int32_t m = H.desc[f].m;
+        // strips of about 8K entries (rows in multiples of 4)
+        const int32_t rows = std::min(m, std::max(4, ((8192 / std::max(1, m)) + 3) & ~3));
+        for (int32_t r = 0; r < m; r += rows) {
+          mf::ClassTask t = base(f, mf::kTaskAssemble);
+          t.a = (int32_t)(D.rall + D.n_tiny + D.n_small + (int64_t)i);
+          t.b = r;
+          t.c = std::min(m, r + rows);
+          ctasks.push_back(t);
+          ++phase[i];
+        }
+      }
+      close_phase();
+      for (const mf::PanelStep &st : S.steps) {
+        for (size_t i = 0; i < st.fronts.size(); ++i) {
+          const int32_t f = st.fronts[i];
+          const mf::FrontDesc &d = H.desc[f];
+          const int32_t p0 = st.p0[i], pe = std::min(p0 + mf::kClassNB, d.k);
+          const int32_t nch = mf::panel_chunks(d.m, pe);
+          for (int32_t c = 0; c < nch; ++c) {
+            mf::ClassTask t = base(f, mf::kTaskPanel);
+            t.a = p0;
+            t.b = c;
+            t.c = nch;
+            ctasks.push_back(t);
+            ++phase[slot[f]];
+          }
+        }
+        close_phase();
+        for (const mf::GemmTask &g : st.update) {
+          mf::ClassTask t = base(g.front, mf::kTaskUpdate);
+          t.a = g.i0;
+          t.b = g.i1;
+          t.c = g.j0;
+          t.d = g.j1;
+          t.e = g.q0;
+          t.g = g.q1;
+          ctasks.push_back(t);
+          ++phase[slot[g.front]];
+        }
+        close_phase();
+      }
+      for (const mf::GemmTask &g : S.schur) {
+        mf::ClassTask t = base(g.front, mf::kTaskSchur);
+        t.a = g.i0;
+        t.b = g.i1;
+        t.c = g.j0;
+        t.d = g.j1;
+        t.e = g.q0;
+        t.g = g.q1;
+        ctasks.push_back(t);
+      }
+      D.n_ctask = (int64_t)ctasks.size() - D.ctask;
+      D.c_class.bytes = D.c_assemble.bytes + D.c_schur.bytes;
+      D.c_class.flops = D.c_assemble.flops + D.c_schur.flops;
+      for (const StepDev &sd : D.steps) {
+        D.c_class.bytes += sd.trsm.bytes + sd.upd.bytes;
+        D.c_class.flops += sd.trsm.flops + sd.upd.flops;
+      }
+    }
+    // ticket counters (one per class) precede the progress counters
+    for (size_t l = 0; l < H.levels.size(); ++l) P->lv[l].tick = (int32_t)l;
+  }
   int rc;
   if ((rc = upload(P->d_lists, lists)) || (rc = upload(P->d_tasks, tasks)) ||
-      (rc = upload(P->d_rect, rect)) || (rc = upload(P->d_panel, panel)))
+      (rc = upload(P->d_rect, rect)) || (rc = upload(P->d_panel, panel)) ||
+      (rc = upload(P->d_ctasks, ctasks)))
     return rc;
+  {
+    const int64_t nc = P->tune.persistent ? (int64_t)H.levels.size() + n_counters : 0;
+    dfree(P->d_ccnt);
+    P->n_ccnt = nc;
+    if (hipMalloc((void **)&P->d_ccnt, std::max<int64_t>(1, nc) * sizeof(int)) != hipSuccess)
+      return fail(MF_ENOMEM, "cannot allocate the class launches' counters");
+  }
   if (!P->static_up) {
     // node -> (element, local node) pairs in ascending element order, for the residual
     std::vector<int64_t> nptr(H.n + 1, 0);
@@ -394,6 +505,19 @@ int ensure_uploaded(mf_plan *P) {
   for (const void *fn : dyn)
     (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, P->max_shared);
   (void)hipGetLastError();
+  if (P->tune.persistent) {
+    // workgroups of a persistent class launch resident at once (the launch never needs more:
+    // it runs any number of tasks, and never waits for a workgroup that has not started)
+    int per_cu = 0, cus = 0;
+    int32_t mmax = 1;
+    for (const LevelDev &D : P->lv) mmax = std::max(mmax, D.large_max_m);
+    const size_t lds = mf::class_lds_bytes<2, 64>(mmax) > mf::class_lds_bytes<2, 32>(mmax)
+                           ? mf::class_lds_bytes<2, 64>(mmax) : mf::class_lds_bytes<2, 32>(mmax);
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, (const void *)mf::k_class_tiled<0, 64>, 256, lds));
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    P->class_blocks = std::max(1, per_cu) * std::max(1, cus);
+  }
   P->uploaded = true;
   return MF_OK;
 }
@@ -487,7 +611,28 @@ int factor_level(mf_plan *P, const double *K, int prec, size_t l, hipStream_t s)
              P->d_wrec + D.rall + D.n_tiny, (int)D.n_small, P->d_store, P->d_inv_l, P->d_inv_r, K,
              P->d_status, m);
     }
-    if (D.n_large) {
+    if (D.n_large && D.n_ctask) {
+      const size_t lds = P->tune.tile == 32 ? mf::class_lds_bytes<2, 32>(D.large_max_m)
+                                            : mf::class_lds_bytes<2, 64>(D.large_max_m);
+      const int grid = (int)std::min<int64_t>(D.n_ctask, P->class_blocks);
+      const mf::ClassTask *ct = P->d_ctasks + D.ctask;
+      int *tick = P->d_ccnt + D.tick;
+      int *cnt = P->d_ccnt + P->lv.size();
+#define MF_CLASS(PR, TI)                                                                       \
+  LAUNCH(K_CLASS, D.c_class, (mf::k_class_tiled<PR, TI>), dim3(grid), dim3(256), lds, s, ct,   \
+         (int)D.n_ctask, tick, cnt, P->d_wrec, P->d_store, P->d_inv_l, P->d_inv_r, K,          \
+         P->d_status, P->wait_ticks)
+      if (P->tune.tile == 32) {
+        if (prec == MF_SCHUR_FP32) MF_CLASS(1, 32);
+        else if (prec == MF_SCHUR_BF16) MF_CLASS(2, 32);
+        else MF_CLASS(0, 32);
+      } else {
+        if (prec == MF_SCHUR_FP32) MF_CLASS(1, 64);
+        else if (prec == MF_SCHUR_BF16) MF_CLASS(2, 64);
+        else MF_CLASS(0, 64);
+      }
+#undef MF_CLASS
+    } else if (D.n_large) {
       LAUNCH(K_ASSEMBLE, D.c_assemble, mf::k_assemble,
              dim3((D.large_max_m + 3) / 4, (unsigned)std::min<int64_t>(D.n_large, kMaxGridY)),
              dim3(256), (size_t)2 * D.large_max_m * sizeof(int), s,
@@ -557,8 +702,19 @@ void dinv_launch(mf_plan *P, int64_t lo, int64_t hi, hipStream_t s) {
          P->d_dinv_tasks + lo, (int)(hi - lo), P->d_store, P->d_dinv_off, P->d_dinv);
 }
 
+// Clears the status block (and the persistent class launches' counters) on s.
+void clear_status(mf_plan *P, hipStream_t s) {
+  if (P->n_ccnt > 0) {
+    const int grid = (int)std::min<int64_t>(1024, (P->n_ccnt + 255) / 256);
+    hipLaunchKernelGGL(mf::k_clear_status_counters, dim3(grid), dim3(256), 0, s, P->d_status,
+                       P->d_ccnt, P->n_ccnt);
+  } else {
+    hipLaunchKernelGGL(mf::k_clear_status, dim3(1), dim3(64), 0, s, P->d_status);
+  }
+}
+
 int launch_factor(mf_plan *P, const double *K, int prec, hipStream_t s) {
-  hipLaunchKernelGGL(mf::k_clear_status, dim3(1), dim3(64), 0, s, P->d_status);
+  clear_status(P, s);
   int rc;
   for (size_t l = 0; l < P->lv.size(); ++l)
     if ((rc = factor_level(P, K, prec, l, s))) return rc;
@@ -693,7 +849,7 @@ int launch_factor_solve(mf_plan *P, const double *K, int prec, const double *b, 
                         int32_t nrhs, hipStream_t s) {
   hipStream_t side = P->side_stream;
   const size_t L = P->lv.size();
-  hipLaunchKernelGGL(mf::k_clear_status, dim3(1), dim3(64), 0, s, P->d_status);
+  clear_status(P, s);
   int rc;
   // every class of the factorization is issued first (the host issue of the second stream's
   // work must not delay the factorization's short lower-class launches), then the second
@@ -848,6 +1004,12 @@ int mf_analyse(int32_t n_mesh, const mf_mesh *meshes, mf_plan **out) {
   // MF_GRAPHS=0 in the environment: launch sequences run eagerly instead of as captured graphs
   const char *g = std::getenv("MF_GRAPHS");
   P->use_graphs = !(g && std::strcmp(g, "0") == 0);
+  // MF_WAIT_LIMIT_US: bound of every device-side wait of the persistent class launches
+  // (default one second; a launch whose wait exceeds it is abandoned and reported)
+  if (const char *w = std::getenv("MF_WAIT_LIMIT_US")) {
+    const long long us = std::atoll(w);
+    if (us >= 0) P->wait_ticks = us * 100;   // the wait clock runs at 100 MHz
+  }
   *out = P;
   return MF_OK;
 }
@@ -903,13 +1065,16 @@ int mf_task_trace(const mf_plan *P, mf_trace_info *out, int64_t *hist, int64_t c
   return MF_OK;
 }
 
-int mf_set_tuning(mf_plan *P, int32_t small_max_m, int32_t nb, int32_t fused_max_m, int32_t tile) {
+int mf_set_tuning(mf_plan *P, int32_t small_max_m, int32_t nb, int32_t fused_max_m, int32_t tile,
+                  int32_t persistent) {
   if (!P) return fail(MF_EINVAL, "null plan");
+  if (persistent < -1 || persistent > 1) return fail(MF_EINVAL, "persistent must be -1, 0 or 1");
   if (tile != 0 && tile != 32 && tile != 64) return fail(MF_EINVAL, "tile must be 32 or 64");
   if (small_max_m < 0) return fail(MF_EINVAL, "small_max_m must be >= 0");
   if (nb != 0 && nb != 16 && nb != 32 && nb != 64) return fail(MF_EINVAL, "nb must be 16, 32 or 64");
   if (fused_max_m < -1) return fail(MF_EINVAL, "fused_max_m must be >= -1");
   if (tile > 0) P->tune.tile = tile;
+  if (persistent) P->tune.persistent = persistent > 0;
   if (small_max_m > 0) P->tune.small_max_m = small_max_m;
   if (nb > 0) P->tune.nb = nb;
   if (fused_max_m == -1) P->tune.fused_max_m = 0;
@@ -937,6 +1102,9 @@ int mf_factor(mf_plan *P, const double *elem_mats, int32_t precision, void *hip_
   HIPCHK(hipMemcpyAsync(P->h_status, P->d_status, mf::kStatusWords * sizeof(int),
                         hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  if (P->h_status[mf::kStatusAbort])
+    return fail(MF_EHIP, "a device-side wait of the factorization exceeded its limit; the "
+                         "launch was abandoned and the plan holds no valid factor");
   if (P->h_status[0]) return fail(MF_EZERO_PIVOT, pivot_message(P, P->h_status[1], P->h_status[2]));
   P->factored = true;
   return MF_OK;
@@ -1004,6 +1172,11 @@ static int refine_loop(mf_plan *P, const double *elem_mats, const double *b, dou
                          nrhs, kNormRows, bpart);
     HIPCHK(hipGetLastError());
     if ((rc = read_norms(P, NL, rpart, nrhs, s, it == 0, rn, bn))) return rc;
+    if (check_status && it == 0 && P->h_status[mf::kStatusAbort]) {
+      P->factored = false;
+      return fail(MF_EHIP, "a device-side wait of the factorization exceeded its limit; the "
+                           "launch was abandoned and the plan holds no valid factor");
+    }
     if (check_status && it == 0 && P->h_status[0]) {
       P->factored = false;
       return fail(MF_EZERO_PIVOT, pivot_message(P, P->h_status[1], P->h_status[2]));
@@ -1132,20 +1305,24 @@ int mf_autotune(mf_plan *P, const double *elem_mats, int32_t precision, int32_t 
   }
   std::vector<mf::Tuning> cands;
   const mf::Tuning base = P->tune;
-  for (int32_t tile : {64, 32})
-    for (int32_t fused : {mf::FP_MAXM, 0})
-      for (int32_t nb : {32, 64})
-        for (int32_t smax : {128, 64}) {
-          if (!wide && (tile != 64 || fused != mf::FP_MAXM || nb != 32)) continue;
-          if (fused == mf::FP_MAXM && nb != 32 && P->hp.max_m <= mf::FP_MAXM) continue;
-          if (!mid && smax != 128) continue;
-          mf::Tuning t = base;
-          t.tile = tile;
-          t.fused_max_m = fused;
-          t.nb = nb;
-          t.small_max_m = smax;
-          cands.push_back(t);
-        }
+  for (int32_t pers : {1, 0})
+    for (int32_t tile : {64, 32})
+      for (int32_t fused : {mf::FP_MAXM, 0})
+        for (int32_t nb : {32, 64})
+          for (int32_t smax : {128, 64}) {
+            // the persistent route has no fused form and a fixed panel width
+            if (pers && (fused != mf::FP_MAXM || nb != 32)) continue;
+            if (!wide && (tile != 64 || fused != mf::FP_MAXM || nb != 32)) continue;
+            if (fused == mf::FP_MAXM && nb != 32 && P->hp.max_m <= mf::FP_MAXM) continue;
+            if (!mid && smax != 128) continue;
+            mf::Tuning t = base;
+            t.persistent = pers;
+            t.tile = tile;
+            t.fused_max_m = pers ? 0 : fused;
+            t.nb = nb;
+            t.small_max_m = smax;
+            cands.push_back(t);
+          }
   std::string js = "{\"candidates\": [";
   double best = 1e300;
   mf::Tuning best_t = base;
@@ -1166,21 +1343,24 @@ int mf_autotune(mf_plan *P, const double *elem_mats, int32_t precision, int32_t 
       best = med;
       best_t = cands[c];
     }
-    char line[200];
+    char line[240];
     std::snprintf(line, sizeof line,
-                  "%s{\"tile\": %d, \"fused_max_m\": %d, \"nb\": %d, \"small_max_m\": %d, \"ms\": %.4f}",
-                  c ? ", " : "", cands[c].tile, cands[c].fused_max_m, cands[c].nb,
-                  P->tune.small_max_m, med);
+                  "%s{\"persistent\": %d, \"tile\": %d, \"fused_max_m\": %d, \"nb\": %d, "
+                  "\"small_max_m\": %d, \"ms\": %.4f}",
+                  c ? ", " : "", cands[c].persistent, cands[c].tile, cands[c].fused_max_m,
+                  cands[c].nb, P->tune.small_max_m, med);
     js += line;
   }
   P->tune = best_t;
   P->uploaded = false;
   P->factored = false;
   if ((rc = mf_factor(P, elem_mats, precision, hip_stream))) return rc;
-  char line[200];
+  char line[240];
   std::snprintf(line, sizeof line,
-                "], \"chosen\": {\"tile\": %d, \"fused_max_m\": %d, \"nb\": %d, \"small_max_m\": %d, \"ms\": %.4f}}",
-                P->tune.tile, P->tune.fused_max_m, P->tune.nb, P->tune.small_max_m, best);
+                "], \"chosen\": {\"persistent\": %d, \"tile\": %d, \"fused_max_m\": %d, "
+                "\"nb\": %d, \"small_max_m\": %d, \"ms\": %.4f}}",
+                P->tune.persistent, P->tune.tile, P->tune.fused_max_m, P->tune.nb,
+                P->tune.small_max_m, best);
   js += line;
   if (needed) *needed = (int64_t)js.size() + 1;
   if (report && cap > 0) {

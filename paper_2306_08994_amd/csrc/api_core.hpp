@@ -15,10 +15,12 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/mf.h"
 #include "common.hpp"
+#include "class_kernels.hpp"
 #include "factor_kernels.hpp"
 #include "trace.hpp"
 #include "plan.hpp"
@@ -43,12 +45,12 @@ inline int fail(int code, const std::string &msg) {
 enum Kind {
   K_TINY, K_SMALL, K_ASSEMBLE, K_FUSED, K_TRSM, K_GEMM_PANEL, K_GEMM_SCHUR,
   K_DOWN_WAVE, K_DOWN_BLOCK, K_UP_WAVE, K_UP_BLOCK, K_DOWN_RECT, K_UP_RECT, K_RESIDUAL,
-  K_DIAG_INV, K_OTHER, K_COUNT
+  K_DIAG_INV, K_CLASS, K_OTHER, K_COUNT
 };
 static const char *const kKindName[K_COUNT] = {
     "factor_tiny", "factor_small", "assemble", "front_panels", "panel_lu_trsm", "gemm_panel",
     "gemm_schur", "solve_down_wave", "solve_down_block", "solve_up_wave", "solve_up_block",
-    "solve_down_rect", "solve_up_rect", "residual", "diag_block_inverse", "other"};
+    "solve_down_rect", "solve_up_rect", "residual", "diag_block_inverse", "class_tiled", "other"};
 
 // Algorithmic traffic and work of one launch (bytes that must cross HBM at least once, flops
 // of the method's own operation count).
@@ -78,6 +80,10 @@ struct LevelDev {
   std::vector<StepDev> steps;
   int64_t schur = 0, n_schur = 0;
   Cost c_tiny, c_small, c_assemble, c_schur, c_fused;
+  // persistent launch of the class's tiled fronts: its tasks in d_ctasks, its ticket counter
+  int64_t ctask = 0, n_ctask = 0;
+  int32_t tick = 0;
+  Cost c_class;
   // solves: fixed (coefficient) bytes, bytes and flops per right-hand side; for the block
   // route split into the triangle (pivot block) and the rectangular (contribution) part
   double down_coef = 0, down_rhs_bytes = 0, down_rhs_flops = 0;
@@ -153,6 +159,13 @@ struct mf_plan {
   mfapi::Cost c_dinv;
   int *d_status = nullptr;
   int *d_arrive = nullptr;    // [F] arrival counters of the panel steps
+  // persistent class launches: task lists, and [classes] ticket counters followed by one
+  // progress counter per tiled front, cleared at the start of every factorization
+  mf::ClassTask *d_ctasks = nullptr;
+  int *d_ccnt = nullptr;
+  int64_t n_ccnt = 0;
+  int class_blocks = 0;       // workgroups of a persistent class launch resident at once
+  int64_t wait_ticks = 100000000;   // bound of a device-side wait (100 MHz clock ticks)
   int *h_status = nullptr;
   double *d_ycb = nullptr;
   size_t ycb_cap = 0;
@@ -208,6 +221,8 @@ struct mf_plan {
     mfapi::dfree(d_dinv_tasks);
     mfapi::dfree(d_status);
     mfapi::dfree(d_arrive);
+    mfapi::dfree(d_ctasks);
+    mfapi::dfree(d_ccnt);
     mfapi::dfree(d_ycb);
     mfapi::dfree(d_work);
     if (h_status) (void)hipHostFree(h_status);

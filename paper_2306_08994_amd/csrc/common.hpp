@@ -24,7 +24,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
-constexpr int kStatusWords = 4;   // [0] error flag, [1] front, [2] pivot
+constexpr int kStatusWords = 4;   // [0] bad-pivot flag, [1] front, [2] pivot, [3] wait abort
 
 __device__ inline void record_bad_pivot(int *st, int f, int p) {
   if (atomicCAS(st, 0, 1) == 0) {
@@ -46,6 +46,14 @@ __device__ inline void wave_sync() {
 
 __global__ void k_clear_status(int *st) {
   if (threadIdx.x < kStatusWords) st[threadIdx.x] = 0;
+}
+
+// Clears the status block and n counters (the persistent class launches' tickets and progress
+// counters) at the start of a factorization: a kernel, so that captured graphs replay it.
+__global__ void k_clear_status_counters(int *st, int *cnt, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < kStatusWords) st[i] = 0;
+  for (int64_t j = i; j < n; j += (int64_t)gridDim.x * blockDim.x) cnt[j] = 0;
 }
 
 // Sources of the extend-add of one front: its element matrix (a leaf), or its two children's

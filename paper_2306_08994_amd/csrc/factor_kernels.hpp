@@ -201,6 +201,44 @@ k_factor_small(const WaveRec *__restrict__ recs, int nrec, double *__restrict__ 
 // tiled path
 // ---------------------------------------------------------------------------------------------
 
+// Rows i0 .. i1-1 of the extend-add of one front into its storage, by a workgroup of 256
+// threads: the front's maps staged in LDS (smaps, 2 m ints), then per column of each thread the
+// strip's entries gathered four rows at a time and stored.  Begins and ends with a workgroup
+// barrier (smaps may be in use before and is free after).
+__device__ __forceinline__ void assemble_rows(const WaveRec &d, int i0, int i1,
+                                              double *__restrict__ store,
+                                              const int32_t *__restrict__ inv_l,
+                                              const int32_t *__restrict__ inv_r,
+                                              const double *__restrict__ K, int *smaps) {
+  const int m = d.m;
+  const int32_t *il = inv_l + d.idx;
+  const int32_t *ir = inv_r + d.idx;
+  int *sl = smaps, *sr = smaps + m;
+  __syncthreads();
+  for (int j = threadIdx.x; j < m; j += 256) {
+    sl[j] = il[j];
+    sr[j] = ir[j];
+  }
+  __syncthreads();
+  const GatherCtx g = rec_gather_ctx(d, store, K);
+  double *F = store + d.store;
+  for (int r0 = i0; r0 < i1; r0 += 4) {
+    for (int j = threadIdx.x; j < m; j += 256) {
+      const int lj = sl[j], rj = sr[j];
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = min(r0 + u, i1 - 1);
+        v[u] = gather_entry(g, sl[i], lj, sr[i], rj);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (r0 + u < i1) F[(int64_t)(r0 + u) * m + j] = v[u];
+    }
+  }
+  __syncthreads();
+}
+
 // Extend-add into the front's storage.  grid = (row strips of 4, fronts); the fronts beyond
 // gridDim.y are taken grid-stride.
 __global__ void __launch_bounds__(256)
@@ -210,33 +248,9 @@ k_assemble(const WaveRec *__restrict__ recs, int nrec, double *__restrict__ stor
   extern __shared__ int smaps[];      // the front's column maps: left, then right
   for (int fi = blockIdx.y; fi < nrec; fi += gridDim.y) {
     const WaveRec d = recs[fi];
-    const int m = d.m;
     const int i0 = blockIdx.x * 4;
-    if (i0 >= m) continue;              // uniform per workgroup
-    const int32_t *il = inv_l + d.idx;
-    const int32_t *ir = inv_r + d.idx;
-    int *sl = smaps, *sr = smaps + m;
-    __syncthreads();                    // the previous front's maps are no longer read
-    for (int j = threadIdx.x; j < m; j += 256) {
-      sl[j] = il[j];
-      sr[j] = ir[j];
-    }
-    __syncthreads();
-    const GatherCtx g = rec_gather_ctx(d, store, K);
-    double *F = store + d.store;
-    // per column of this thread: the strip's four entries gathered together, then stored
-    for (int j = threadIdx.x; j < m; j += 256) {
-      const int lj = sl[j], rj = sr[j];
-      double v[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int i = min(i0 + u, m - 1);
-        v[u] = gather_entry(g, sl[i], lj, sr[i], rj);
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (i0 + u < m) F[(int64_t)(i0 + u) * m + j] = v[u];
-    }
+    if (i0 >= d.m) continue;            // uniform per workgroup
+    assemble_rows(d, i0, min(i0 + 4, d.m), store, inv_l, inv_r, K, smaps);
   }
 }
 
@@ -258,19 +272,28 @@ template <>
 struct GemmCfg<2> { typedef __bf16 T; static constexpr int KT = 32; };
 
 template <int PREC, int TILE>
-__global__ void __launch_bounds__(256)
-k_gemm_update(const GemmTask *__restrict__ tasks, double *__restrict__ store) {
+struct GemmLds {
   typedef typename GemmCfg<PREC>::T T;
   // inner-dimension slab: 32 at TILE 32 (a panel update is one slab), else the type's depth
-  constexpr int KT = TILE == 32 ? 32 : GemmCfg<PREC>::KT;
-  constexpr int APAD = (PREC == 2) ? 8 : 1;
+  static constexpr int KT = TILE == 32 ? 32 : GemmCfg<PREC>::KT;
+  static constexpr int APAD = (PREC == 2) ? 8 : 1;
+  T As[TILE][KT + APAD];
+  T Bs[TILE][KT + APAD];        // stored transposed: Bs[col][k]
+};
+
+// One tile task of the GEMM update, by a workgroup of 256 threads (4 waves) with its operand
+// staging in `sm` (LDS); every slab ends with a workgroup barrier, so sm is free on return.
+template <int PREC, int TILE>
+__device__ __forceinline__ void gemm_tile(const GemmTask &tk, double *__restrict__ store,
+                                          GemmLds<PREC, TILE> &sm) {
+  typedef typename GemmCfg<PREC>::T T;
+  constexpr int KT = GemmLds<PREC, TILE>::KT;
   constexpr int QB = TILE / 32;            // 16 x 16 MFMA blocks per wave and dimension
   constexpr int HALF = TILE / 2;           // each wave owns a HALF x HALF quadrant
   constexpr int EA = TILE * KT / 256;      // staged elements of A (and of B) per thread
   static_assert(TILE == 32 || TILE == 64, "tile");
-  __shared__ T As[TILE][KT + APAD];
-  __shared__ T Bs[TILE][KT + APAD];        // stored transposed: Bs[col][k]
-  const GemmTask tk = tasks[blockIdx.x];
+  auto &As = sm.As;
+  auto &Bs = sm.Bs;
   const int64_t ld = tk.ld;
   double *F = store + tk.store;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -374,6 +397,13 @@ k_gemm_update(const GemmTask *__restrict__ tasks, double *__restrict__ store) {
         const int gj = j0 + HALF * wc + 16 * b + li;
         if (gi < tk.i1 && gj < tk.j1) F[gi * ld + gj] = cv[a][b][r] - (double)acc[a][b][r];
       }
+}
+
+template <int PREC, int TILE>
+__global__ void __launch_bounds__(256)
+k_gemm_update(const GemmTask *__restrict__ tasks, double *__restrict__ store) {
+  __shared__ GemmLds<PREC, TILE> sm;
+  gemm_tile<PREC, TILE>(tasks[blockIdx.x], store, sm);
 }
 
 }  // namespace mf

@@ -93,6 +93,127 @@ __device__ __noinline__ bool wave_diag_lu_call(double *F, int64_t m, int pb, dou
 // chip at once), so the store is left to the workgroup that arrives last: each workgroup counts
 // itself in arrive[f] once its copy is loaded, and the one that sees every other arrival stores
 // the block and resets the counter to zero for the next panel step.
+// Number of 256-item chunks (workgroups) of a panel step of a front: r = m - pe columns, then
+// r rows from the next multiple of 64 (at least one chunk).
+__device__ __host__ inline int panel_chunks(int m, int pe) {
+  const int rest = m - pe, rpad = (rest + 63) & ~63;
+  return (rpad + rest + 255) / 256 > 1 ? (rpad + rest + 255) / 256 : 1;
+}
+
+// Chunk `chunk` of the panel step (p0 .. pe-1) of one front by a workgroup of 256 threads: the
+// loads of its columns / rows, the diagonal-block LU by wave 0 into D / rd (LDS; stored to F
+// only if writeback_diag), the two triangular solves and their stores.  Ends after a workgroup
+// barrier that follows every thread's reads of D, with the solves' stores issued.
+template <int NB>
+__device__ __forceinline__ void panel_chunk(const PanelRec &d, int chunk, double *__restrict__ store,
+                                            int *__restrict__ status, double (*D)[NB + 1],
+                                            double *rd, bool writeback_diag) {
+  const int f = d.f, p0 = d.p0;
+  const int m = d.m, pb = min(NB, d.k - p0), pe = p0 + pb;
+  const int rest = m - pe, rpad = (rest + 63) & ~63;
+  const int item = chunk * 256 + threadIdx.x;
+  double *F = store + d.store;
+  // this thread's column (item < rest) or row, loaded before the diagonal block is factored so
+  // that the load latency overlaps the factorization
+  const bool colitem = item < rest, has = colitem || (item >= rpad && item < rpad + rest);
+  double *cp = F + (int64_t)p0 * m + pe + item;
+  double *row = F + (int64_t)(pe + item - rpad) * m + p0;
+  double v[NB];
+  if (has) {
+    if (colitem) {
+#pragma unroll
+      for (int q = 0; q < NB; ++q) v[q] = cp[(int64_t)min(q, pb - 1) * m];
+    } else {
+#pragma unroll
+      for (int q = 0; q < NB; ++q) v[q] = row[min(q, pb - 1)];
+    }
+  }
+  if (threadIdx.x < 64)
+    wave_diag_lu<NB>(F + (int64_t)p0 * m + p0, m, pb, D, rd, threadIdx.x, f, p0, status,
+                     writeback_diag);
+  __syncthreads();
+  if (has) {
+    // each step reads its row (column) of D into registers first, the reads issued together,
+    // then its products: one LDS round trip per step, overlapped with the previous step
+    double dr[NB];
+    if (colitem) {
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+#pragma unroll
+        for (int r = 0; r < q; ++r) dr[r] = D[q][r];
+        const double rq = rd[q];
+        __builtin_amdgcn_sched_barrier(0);
+        double s0 = v[q], s1 = 0.0;
+#pragma unroll
+        for (int r = 0; r + 1 < q; r += 2) {
+          s0 -= dr[r] * v[r];
+          s1 -= dr[r + 1] * v[r + 1];
+        }
+        if (q & 1) s0 -= dr[q - 1] * v[q - 1];
+        v[q] = (s0 + s1) * rq;
+      }
+      if (pb == NB) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) cp[(int64_t)q * m] = v[q];
+      } else {
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+          if (q < pb) cp[(int64_t)q * m] = v[q];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+#pragma unroll
+        for (int r = 0; r < q; ++r) dr[r] = D[r][q];
+        __builtin_amdgcn_sched_barrier(0);
+        double s0 = v[q], s1 = 0.0;
+#pragma unroll
+        for (int r = 0; r + 1 < q; r += 2) {
+          s0 -= v[r] * dr[r];
+          s1 -= v[r + 1] * dr[r + 1];
+        }
+        if (q & 1) s0 -= v[q - 1] * dr[q - 1];
+        v[q] = s0 + s1;
+      }
+      if (pb == NB) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) row[q] = v[q];
+      } else {
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+          if (q < pb) row[q] = v[q];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// The factored pb x pb diagonal block of panel p0 from LDS D into the front (wave 0's lanes).
+template <int NB>
+__device__ __forceinline__ void store_diag_block(const PanelRec &d, double *__restrict__ store,
+                                                 double (*D)[NB + 1], int lane) {
+  const int pb = min(NB, d.k - d.p0);
+  if (lane < pb) {
+    double *dst = store + d.store + (int64_t)d.p0 * d.m + d.p0 + lane;
+    for (int i = 0; i < pb; ++i) dst[(int64_t)i * d.m] = D[i][lane];
+  }
+}
+
+// Panel step of the fronts wider than the fused route: every workgroup factors the pb x pb
+// diagonal block at (p0, p0) itself (wave 0, in LDS), then its threads solve against it:
+//   U12 = L11^{-1} A12 column by column (rows p0..pe-1, columns pe..m-1),
+//   L21 = A21 U11^{-1} row by row       (rows pe..m-1, columns p0..pe-1).
+// grid = (item chunks of 256, fronts; fronts beyond gridDim.y grid-stride), at least one chunk;
+// with r = m - pe, item t < r is a column and item t in [R, R + r) a row, R = r rounded up to a
+// multiple of 64: every wave holds only columns or only rows (a wave holding both ran the two
+// substitutions one after the other).  The host sizes the chunks by the widest front's R + r.
+// Positions beyond pb load clamped (finite) values; the identity padding of D keeps them out of
+// the first pb results, and only those are stored.
+// The factored diagonal block overwrites the block that the other workgroups of the front read,
+// and a workgroup may start only after another has finished (more workgroups than fit on the
+// chip at once), so the store is left to the workgroup that arrives last: each workgroup counts
+// itself in arrive[f] once its copy is loaded, and the one that sees every other arrival stores
+// the block and resets the counter to zero for the next panel step.
 template <int NB>
 __global__ void __launch_bounds__(256)
 k_panel_trsm(const PanelRec *__restrict__ recs, int nrec, double *__restrict__ store,
@@ -101,87 +222,9 @@ k_panel_trsm(const PanelRec *__restrict__ recs, int nrec, double *__restrict__ s
   __shared__ double rd[NB];
   for (int fi = blockIdx.y; fi < nrec; fi += gridDim.y) {
     const PanelRec d = recs[fi];
-    const int f = d.f, p0 = d.p0;
-    const int m = d.m, pb = min(NB, d.k - p0), pe = p0 + pb;
-    const int rest = m - pe, rpad = (rest + 63) & ~63;
-    const int item = blockIdx.x * 256 + threadIdx.x;
-    if (blockIdx.x > 0 && (int)(blockIdx.x * 256) >= rpad + rest) continue;   // idle (uniform)
-    __syncthreads();   // the previous front's diagonal block in D is no longer read
-    double *F = store + d.store;
-    // this thread's column (item < rest) or row, loaded before the diagonal block is factored so
-    // that the load latency overlaps the factorization
-    const bool colitem = item < rest, has = colitem || (item >= rpad && item < rpad + rest);
-    double *cp = F + (int64_t)p0 * m + pe + item;
-    double *row = F + (int64_t)(pe + item - rpad) * m + p0;
-    double v[NB];
-    if (has) {
-      if (colitem) {
-#pragma unroll
-        for (int q = 0; q < NB; ++q) v[q] = cp[(int64_t)min(q, pb - 1) * m];
-      } else {
-#pragma unroll
-        for (int q = 0; q < NB; ++q) v[q] = row[min(q, pb - 1)];
-      }
-    }
-    // workgroups that take part (the others skip the front above): at least one
-    const int nact = max(1, (rpad + rest + 255) / 256);
-    if (threadIdx.x < 64)
-      wave_diag_lu<NB>(F + (int64_t)p0 * m + p0, m, pb, D, rd, threadIdx.x, f, p0, status,
-                       nact == 1);
-    __syncthreads();
-    if (has) {
-      // each step reads its row (column) of D into registers first, the reads issued together,
-      // then its products: one LDS round trip per step, overlapped with the previous step
-      double dr[NB];
-      if (colitem) {
-#pragma unroll
-        for (int q = 0; q < NB; ++q) {
-#pragma unroll
-          for (int r = 0; r < q; ++r) dr[r] = D[q][r];
-          const double rq = rd[q];
-          __builtin_amdgcn_sched_barrier(0);
-          double s0 = v[q], s1 = 0.0;
-#pragma unroll
-          for (int r = 0; r + 1 < q; r += 2) {
-            s0 -= dr[r] * v[r];
-            s1 -= dr[r + 1] * v[r + 1];
-          }
-          if (q & 1) s0 -= dr[q - 1] * v[q - 1];
-          v[q] = (s0 + s1) * rq;
-        }
-        if (pb == NB) {
-#pragma unroll
-          for (int q = 0; q < NB; ++q) cp[(int64_t)q * m] = v[q];
-        } else {
-#pragma unroll
-          for (int q = 0; q < NB; ++q)
-            if (q < pb) cp[(int64_t)q * m] = v[q];
-        }
-      } else {
-#pragma unroll
-        for (int q = 0; q < NB; ++q) {
-#pragma unroll
-          for (int r = 0; r < q; ++r) dr[r] = D[r][q];
-          __builtin_amdgcn_sched_barrier(0);
-          double s0 = v[q], s1 = 0.0;
-#pragma unroll
-          for (int r = 0; r + 1 < q; r += 2) {
-            s0 -= v[r] * dr[r];
-            s1 -= v[r + 1] * dr[r + 1];
-          }
-          if (q & 1) s0 -= v[q - 1] * dr[q - 1];
-          v[q] = s0 + s1;
-        }
-        if (pb == NB) {
-#pragma unroll
-          for (int q = 0; q < NB; ++q) row[q] = v[q];
-        } else {
-#pragma unroll
-          for (int q = 0; q < NB; ++q)
-            if (q < pb) row[q] = v[q];
-        }
-      }
-    }
+    const int nact = panel_chunks(d.m, d.p0 + min(NB, d.k - d.p0));
+    if ((int)blockIdx.x >= nact) continue;   // idle chunk of a narrower front (uniform)
+    panel_chunk<NB>(d, blockIdx.x, store, status, D, rd, nact == 1);
     if (nact > 1 && threadIdx.x < 64) {
       // every thread of this workgroup is past its reads of the diagonal block (the LU consumed
       // them before the barrier); count this workgroup and store the block if it is the last.
@@ -191,15 +234,12 @@ k_panel_trsm(const PanelRec *__restrict__ recs, int nrec, double *__restrict__ s
       // invalidate the whole L2 around every increment.
       int prev = 0;
       if (threadIdx.x == 0)
-        prev = __hip_atomic_fetch_add(arrive + f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        prev = __hip_atomic_fetch_add(arrive + d.f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       prev = __builtin_amdgcn_readlane(prev, 0);
       if (prev == nact - 1) {
-        const int lane = threadIdx.x;
-        if (lane < pb) {
-          double *dst = F + (int64_t)p0 * m + p0 + lane;
-          for (int i = 0; i < pb; ++i) dst[(int64_t)i * m] = D[i][lane];
-        }
-        if (lane == 0) __hip_atomic_store(arrive + f, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        store_diag_block<NB>(d, store, D, threadIdx.x);
+        if (threadIdx.x == 0)
+          __hip_atomic_store(arrive + d.f, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
   }

@@ -62,6 +62,23 @@ struct PanelRec {
 };
 static_assert(sizeof(PanelRec) == 24, "PanelRec layout");
 
+// One task of the persistent launch of a class's tiled fronts (see k_class_tiled): a strip of
+// the extend-add, a chunk of a panel step, a tile of a panel's trailing update or a tile of the
+// Schur update, with the value of its front's progress counter it must wait for.  56 bytes.
+enum : int32_t { kTaskAssemble = 0, kTaskPanel = 1, kTaskUpdate = 2, kTaskSchur = 3 };
+struct ClassTask {
+  int64_t store;    // offset (doubles) of the front's storage
+  int32_t type;     // kTask*
+  int32_t f;        // front id
+  int32_t ci;       // the front's progress counter
+  int32_t need;     // counter value (tasks of the front's earlier phases) to wait for
+  int32_t m, k;     // width and pivots
+  // assemble: wave record, first row, end row; panel: first pivot, chunk, chunks of the step;
+  // update / Schur tile: i0, i1, j0, j1, q0, q1 (as GemmTask)
+  int32_t a, b, c, d, e, g;
+};
+static_assert(sizeof(ClassTask) == 56, "ClassTask layout");
+
 // Work of one panel step of the tiled (HBM-resident) path inside one class.
 struct PanelStep {
   std::vector<int32_t> fronts;     // fronts that still have pivots at this step
@@ -109,6 +126,7 @@ struct Tuning {
   int32_t nb = 32;             // panel width of the tiled path
   int32_t fused_max_m = 576;   // tiled fronts up to this width run all panels in one workgroup
   int32_t tile = 64;           // GEMM output tile edge
+  int32_t persistent = 0;      // tiled fronts of a class in one persistent launch (panel width 32)
 };
 
 // Builds the tree and front structure; returns an error message or "" on success.

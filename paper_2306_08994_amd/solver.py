@@ -106,11 +106,13 @@ class Plan:
                 "front_levels_order_dependencies": bool(info.levels_order_dependencies),
                 "hist": hist.reshape(-1, 4)}
 
-    def set_tuning(self, small_max_m: int = 0, nb: int = 0, fused_max_m: int = 0, tile: int = 0):
-        """See mf_set_tuning: 0 keeps a value; fused_max_m=-1 disables the fused panel route."""
+    def set_tuning(self, small_max_m: int = 0, nb: int = 0, fused_max_m: int = 0, tile: int = 0,
+                   persistent: int = 0):
+        """See mf_set_tuning: 0 keeps a value; fused_max_m=-1 disables the fused panel route;
+        persistent=1 / -1 switches the persistent class launches on / off."""
         self.factor_version += 1
         check(_lib.load().mf_set_tuning(self._h, int(small_max_m), int(nb), int(fused_max_m),
-                                        int(tile)))
+                                        int(tile), int(persistent)))
 
     def autotune(self, K, precision: str = "fp64", reps: int = 3) -> dict:
         """Times the relevant schedule candidates on K, keeps the fastest (see mf_autotune)."""

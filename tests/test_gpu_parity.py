@@ -13,13 +13,13 @@ from tests import gpu_common as G
 pytestmark = pytest.mark.gpu
 
 
-def _setup(problem, small_max_m=0, nb=0, fused=0, tile=0):
+def _setup(problem, small_max_m=0, nb=0, fused=0, tile=0, persistent=0):
     import torch
     from paper_2306_08994_amd import Plan
     dev = G.torch_dev()
     plan = Plan(problem.meshes)
-    if small_max_m or nb or fused or tile:
-        plan.set_tuning(small_max_m, nb, fused, tile)
+    if small_max_m or nb or fused or tile or persistent:
+        plan.set_tuning(small_max_m, nb, fused, tile, persistent)
     K = torch.from_numpy(problem.K).to(dev)
     b = torch.from_numpy(problem.b).to(dev)
     return plan, K, b
@@ -50,11 +50,38 @@ TILED = [((64, 48), 8, 16, -1, 0), ((96, 80), 24, 32, -1, 32), ((70, 53), 40, 64
          ((14, 11, 9), 24, 32, 0, 32), ((20, 20, 20), 0, 0, 0, 0), ((20, 20, 20), 0, 64, 0, 32)]
 
 
+# every case on the route of one launch per panel step (persistent -1), and each distinct
+# (shape, LDS limit, tile) on the persistent class launches (panel width 32, no fused route)
+TILED_PERSISTENT = sorted({(shape, smax, tile) for shape, smax, _, _, tile in TILED})
+
+
 @pytest.mark.parametrize("shape,smax,nb,fused,tile", TILED)
 def test_factor_tiled_path(shape, smax, nb, fused, tile):
     p = _rd(shape, seed=1)
     tree, conn, fac = G.oracle_factor(p)
-    plan, K, b = _setup(p, smax, nb, fused, tile)
+    plan, K, b = _setup(p, smax, nb, fused, tile, persistent=-1)
+    plan.factor(K)
+    Ls, Us = plan.export_factors()
+    ms = np.diff(tree.front_ptr)
+    assert ms.max() > 64 and (ms > smax).sum() > 0   # several tiles on the tiled path
+    assert G.factor_violation(Ls, Us, fac) <= G.TOL_FACTOR
+
+
+@pytest.mark.parametrize("shape,smax,tile", TILED_PERSISTENT)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_factor_persistent_class_launch(shape, smax, tile, prec):
+    """The tiled fronts of each class in one persistent launch: extend-add strips, panel
+    chunks, update tiles and Schur tiles ordered by per-front counters.  FP64 entry by entry
+    against the oracle; the FP32-Schur factor refines to the oracle's solution."""
+    p = _rd(shape, seed=1)
+    tree, conn, fac = G.oracle_factor(p)
+    plan, K, b = _setup(p, smax, 0, 0, tile, persistent=1)
+    if prec == "fp32":
+        plan.factor(K, "fp32")
+        x, its, rr = plan.refine(K, b, tol=1e-12, max_it=20)
+        assert rr <= 1e-12
+        assert G.rel_err(x.cpu().numpy(), G.oracle_solve(tree, fac, p.b)) <= 1e-9
+        return
     plan.factor(K)
     Ls, Us = plan.export_factors()
     ms = np.diff(tree.front_ptr)
@@ -195,6 +222,29 @@ def test_mixed_precision_refines_to_fp64(prec):
     assert G.relres(p, conn, xn) <= 1e-12
     assert G.rel_err(xn, xo) <= 1e-9
     print(f"{prec}: factor deviation {err_factor:.2e}, {its} corrections, relres {rr:.2e}")
+
+
+def test_persistent_launch_wait_limit_abandons_and_recovers(monkeypatch):
+    """A bound of zero on the persistent class launch's device-side waits (set from the host
+    before the plan is made): the first task that has to wait gives up, every other workgroup
+    leaves, the launch ends normally and the factorization reports the abort; a plan with the
+    default bound then factors the same matrix."""
+    from paper_2306_08994_amd import MFError
+    from paper_2306_08994_amd import _lib
+    p = _rd((20, 20, 20), seed=1)
+    monkeypatch.setenv("MF_WAIT_LIMIT_US", "0")
+    plan, K, b = _setup(p, 40, 0, 0, 0, persistent=1)
+    monkeypatch.delenv("MF_WAIT_LIMIT_US")
+    with pytest.raises(MFError) as ei:
+        plan.factor(K)
+    assert ei.value.code == _lib.MF_EHIP and "exceeded its limit" in str(ei.value)
+    with pytest.raises(MFError) as ei:
+        plan.solve(b)
+    assert ei.value.code == _lib.MF_ESTATE
+    plan2, _, _ = _setup(p, 40, 0, 0, 0, persistent=1)
+    plan2.factor(K)
+    x, its, rr = plan2.refine(K, b, tol=1e-12, max_it=5)
+    assert rr <= 1e-12
 
 
 def test_zero_pivot_message_names_mesh_and_node():
