@@ -167,6 +167,25 @@ int mf_factor(mf_plan *plan, const double *elem_mats, int32_t precision, void *h
 int mf_solve(mf_plan *plan, const double *b, double *x, int32_t nrhs, int32_t transpose,
              void *hip_stream);
 
+/* Largest scratch of mf_solve_noalloc, in doubles (64 MiB): the sum of contribution-block
+ * widths of the plan times nrhs must not exceed it (the 256 x 256 Q1 grid: 901,042 x 8 RHS). */
+#define MF_NOALLOC_SCRATCH_DOUBLES 8388608
+
+/* mf_solve for callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same kernels and results as mf_solve,
+ * launched eagerly on hip_stream, with no hipMalloc, hipFree or other allocation in the call.
+ * Its only workspace, the per-front contribution blocks of the right-hand sides (sum of CB
+ * widths x nrhs doubles), lives in a static device array of MF_NOALLOC_SCRATCH_DOUBLES doubles
+ * that each GPU holds until the process ends; its device address is looked up once per device
+ * (on the first call with that device current).  Every call on one GPU shares that array, so
+ * calls that overlap on one GPU (two streams, two threads, two plans) race: order them.  The
+ * plan must already be factored (mf_factor allocates what the solve reads), and the plan's
+ * device must be current.  b, x: device [n][nrhs] FP64 (may alias).  Asynchronous.
+ * Errors: MF_EINVAL (nrhs too large for the scratch, bad arguments), MF_ESTATE (no valid
+ * factor), MF_EHIP. */
+int mf_solve_noalloc(mf_plan *plan, const double *b, double *x, int32_t nrhs, int32_t transpose,
+                     void *hip_stream);
+
 /* r = b - A x with A applied element by element (A = sum_e P_e^T K_e P_e), FP64.
  * elem_mats device [n_elem][npe][npe]; x, b, r device [n][nrhs].  Asynchronous. */
 int mf_residual(mf_plan *plan, const double *elem_mats, const double *x, const double *b,

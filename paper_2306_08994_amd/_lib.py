@@ -10,12 +10,13 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmf.so")
 
 MF_OK, MF_EINVAL, MF_ENOMEM, MF_EZERO_PIVOT, MF_EHIP, MF_ENOCONV, MF_ESTATE = 0, -1, -2, -3, -4, -5, -6
 MF_FP64, MF_SCHUR_FP32, MF_SCHUR_BF16 = 0, 1, 2
+MF_NOALLOC_SCRATCH_DOUBLES = 8388608     # include/mf.h
 ERROR_NAMES = {MF_EINVAL: "MF_EINVAL", MF_ENOMEM: "MF_ENOMEM", MF_EZERO_PIVOT: "MF_EZERO_PIVOT",
                MF_EHIP: "MF_EHIP", MF_ENOCONV: "MF_ENOCONV", MF_ESTATE: "MF_ESTATE"}
 
 EXPORTED = ["mf_analyse", "mf_plan_info", "mf_plan_export_tree", "mf_task_trace", "mf_set_tuning",
             "mf_autotune",
-            "mf_factor", "mf_solve",
+            "mf_factor", "mf_solve", "mf_solve_noalloc",
             "mf_residual", "mf_refine", "mf_factor_refine", "mf_elem_grad", "mf_export_factors", "mf_profile",
             "mf_profile_report", "mf_destroy", "mf_last_error"]
 
@@ -68,6 +69,7 @@ def load():
                                   POINTER(c_int64)]),
         "mf_factor": (c_int32, [P, c_void_p, c_int32, c_void_p]),
         "mf_solve": (c_int32, [P, c_void_p, c_void_p, c_int32, c_int32, c_void_p]),
+        "mf_solve_noalloc": (c_int32, [P, c_void_p, c_void_p, c_int32, c_int32, c_void_p]),
         "mf_residual": (c_int32, [P, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
         "mf_refine": (c_int32, [P, c_void_p, c_void_p, c_void_p, c_int32, c_double, c_int32,
                                 POINTER(c_int32), dp, c_void_p]),

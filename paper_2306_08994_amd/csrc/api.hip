@@ -2,6 +2,7 @@
 #include "api_core.hpp"
 
 #include <chrono>
+#include <mutex>
 
 namespace mfapi {
 
@@ -731,9 +732,10 @@ int chunk(const mf_plan *P, int32_t nrhs, int64_t fixed_doubles, int64_t per_col
   return nc;
 }
 
-// The launches of class l of the forward (down) or backward sweep.
+// The launches of class l of the forward (down) or backward sweep; ycb holds the per-front
+// contribution blocks of the right-hand sides ([sum of CB widths][nrhs] doubles).
 void solve_level(mf_plan *P, const double *b, double *x, int32_t nrhs, bool trans, bool down,
-                 size_t l, hipStream_t s) {
+                 size_t l, hipStream_t s, double *ycb) {
   const int gridcap = 16384;
   {
     {
@@ -755,11 +757,11 @@ void solve_level(mf_plan *P, const double *b, double *x, int32_t nrhs, bool tran
         const int grid = (int)std::min<int64_t>((n + 3) / 4, gridcap);
         if (down && trans)
           LAUNCH(K_DOWN_WAVE, c, mf::k_solve_down_wave<true>, dim3(grid), dim3(256), lds, s, rec,
-                 n, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, b, x, P->d_ycb, nrhs, nc,
+                 n, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, b, x, ycb, nrhs, nc,
                  mmax, cld, ldsw);
         else if (down)
           LAUNCH(K_DOWN_WAVE, c, mf::k_solve_down_wave<false>, dim3(grid), dim3(256), lds, s, rec,
-                 n, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, b, x, P->d_ycb, nrhs, nc,
+                 n, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, b, x, ycb, nrhs, nc,
                  mmax, cld, ldsw);
         else if (trans)
           LAUNCH(K_UP_WAVE, c, mf::k_solve_up_wave<true>, dim3(grid), dim3(256), lds, s, rec,
@@ -791,14 +793,14 @@ void solve_level(mf_plan *P, const double *b, double *x, int32_t nrhs, bool tran
         const size_t rlds = ((size_t)16 * mf::kRectLdv + (rq ? 4 * 64 * 4 : 0)) * 8;
 #define MF_DOWN_BLOCK(TR, FU)                                                                   \
   LAUNCH(K_DOWN_BLOCK, ct, (mf::k_solve_down_block<TR, FU>), dim3(grid), dim3(256), lds, s,     \
-         rec, n, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, b, x, P->d_ycb,            \
+         rec, n, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, b, x, ycb,            \
          nrhs, nc, rmax, P->d_dinv)
 #define MF_UP_BLOCK(TR, FU)                                                                     \
   LAUNCH(K_UP_BLOCK, ct, (mf::k_solve_up_block<TR, FU>), dim3(grid), dim3(256), lds, s,         \
          rec, n, P->d_store, P->d_front_idx, x, nrhs, nc, rmax, P->d_dinv)
 #define MF_RECT_Q(KIND, TR, UP, Q)                                                              \
   LAUNCH(KIND, cr, (mf::k_solve_rect<TR, UP, Q>), dim3((unsigned)nt), dim3(256), rlds, s,       \
-         P->d_wrec, rt, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, x, P->d_ycb, nrhs)
+         P->d_wrec, rt, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, x, ycb, nrhs)
 #define MF_RECT(KIND, TR, UP)                                                                   \
   do {                                                                                          \
     if (rq) MF_RECT_Q(KIND, TR, UP, true);                                                      \
@@ -832,9 +834,10 @@ void solve_level(mf_plan *P, const double *b, double *x, int32_t nrhs, bool tran
   }
 }
 
-int launch_solve(mf_plan *P, const double *b, double *x, int32_t nrhs, bool trans, hipStream_t s) {
-  for (size_t l = 0; l < P->lv.size(); ++l) solve_level(P, b, x, nrhs, trans, true, l, s);
-  for (size_t l = P->lv.size(); l-- > 0;) solve_level(P, b, x, nrhs, trans, false, l, s);
+int launch_solve(mf_plan *P, const double *b, double *x, int32_t nrhs, bool trans, hipStream_t s,
+                 double *ycb) {
+  for (size_t l = 0; l < P->lv.size(); ++l) solve_level(P, b, x, nrhs, trans, true, l, s, ycb);
+  for (size_t l = P->lv.size(); l-- > 0;) solve_level(P, b, x, nrhs, trans, false, l, s, ycb);
   HIPCHK(hipGetLastError());
   return MF_OK;
 }
@@ -868,11 +871,11 @@ int launch_factor_solve(mf_plan *P, const double *K, int prec, const double *b, 
     if (l == 0 || l >= start)
       HIPCHK(hipStreamWaitEvent(side, P->lvl_events[std::max(l, start)], 0));
     dinv_launch(P, P->dinv_lvl[l], P->dinv_lvl[l + 1], side);
-    solve_level(P, b, x, nrhs, false, true, l, side);
+    solve_level(P, b, x, nrhs, false, true, l, side, P->d_ycb);
   }
   HIPCHK(hipEventRecord(P->lvl_events[L], side));
   HIPCHK(hipStreamWaitEvent(s, P->lvl_events[L], 0));
-  for (size_t l = L; l-- > 0;) solve_level(P, b, x, nrhs, false, false, l, s);
+  for (size_t l = L; l-- > 0;) solve_level(P, b, x, nrhs, false, false, l, s, P->d_ycb);
   HIPCHK(hipGetLastError());
   return MF_OK;
 }
@@ -964,6 +967,38 @@ int read_norms(mf_plan *P, const NormLayout &L, const double *dpart, int32_t nrh
   return MF_OK;
 }
 
+}  // namespace mfapi
+
+// Scratch of the allocation-free solve (mf_solve_noalloc): the per-front contribution blocks of
+// the right-hand sides.  One copy per GPU the library runs on, held until the process ends.
+// Host code never passes `scratch` itself to a kernel (on the host the name is only a stand-in
+// for the symbol): the device address is taken once per device with hipGetSymbolAddress.
+static __device__ __align__(256) double scratch[MF_NOALLOC_SCRATCH_DOUBLES];
+
+namespace mfapi {
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kScratchDevices] = {};
+
+// Device address of `scratch` on the current device, looked up on the first call per device.
+int scratch_address(double **out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kScratchDevices)
+    return fail(MF_EINVAL, "device " + std::to_string(dev) + " beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(MF_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<double *>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return MF_OK;
+}
+}  // namespace
 }  // namespace mfapi
 
 using namespace mfapi;
@@ -1125,7 +1160,32 @@ int mf_solve(mf_plan *P, const double *b, double *x, int32_t nrhs, int32_t trans
   key.a = nrhs;
   key.b = transpose;
   return run_graphed(P, P->g_solve, 4, P->g_solve_next, key, (hipStream_t)hip_stream,
-                     [&](hipStream_t st) { return launch_solve(P, b, x, nrhs, transpose != 0, st); });
+                     [&](hipStream_t st) { return launch_solve(P, b, x, nrhs, transpose != 0, st, P->d_ycb); });
+}
+
+int mf_solve_noalloc(mf_plan *P, const double *b, double *x, int32_t nrhs, int32_t transpose,
+                     void *hip_stream) {
+  if (!P || !b || !x) return fail(MF_EINVAL, "null argument");
+  if (nrhs < 1) return fail(MF_EINVAL, "nrhs must be >= 1");
+  if (transpose != 0 && transpose != 1) return fail(MF_EINVAL, "transpose must be 0 or 1");
+  if (!P->factored) return fail(MF_ESTATE, "no valid factorization: call mf_factor first");
+  const int64_t need = std::max<int64_t>(1, P->hp.sum_c) * (int64_t)nrhs;
+  if (need > (int64_t)MF_NOALLOC_SCRATCH_DOUBLES)
+    return fail(MF_EINVAL, "mf_solve_noalloc needs " + std::to_string(need) +
+                               " doubles of scratch (sum of contribution-block widths " +
+                               std::to_string(P->hp.sum_c) + " x nrhs " + std::to_string(nrhs) +
+                               "), above its limit of " +
+                               std::to_string((int64_t)MF_NOALLOC_SCRATCH_DOUBLES));
+  double *ycb = nullptr;
+  int rc;
+  if ((rc = scratch_address(&ycb))) return rc;
+  // the same kernels as mf_solve, launched eagerly (no graph: instantiating one allocates), and
+  // without the per-launch timing events of a profiled plan
+  const bool prof = P->prof.on;
+  P->prof.on = false;
+  rc = launch_solve(P, b, x, nrhs, transpose != 0, (hipStream_t)hip_stream, ycb);
+  P->prof.on = prof;
+  return rc;
 }
 
 int mf_residual(mf_plan *P, const double *elem_mats, const double *x, const double *b,

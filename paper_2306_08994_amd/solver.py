@@ -145,6 +145,18 @@ class Plan:
         check(_lib.load().mf_solve(self._h, pb, px, nrhs, int(bool(transpose)), _stream()))
         return x.reshape(b.shape)
 
+    def solve_noalloc(self, b, out, transpose: bool = False):
+        """mf_solve_noalloc: the solve without any device allocation in the call (the output
+        buffer `out` is the caller's); its workspace is the library's static scratch."""
+        b2 = b if b.dim() == 2 else b.reshape(-1, 1)
+        nrhs = int(b2.shape[1])
+        pb = _dev_ptr(b2, "b", (self.n, nrhs))
+        x = out.reshape(self.n, nrhs)
+        px = _dev_ptr(x, "x", (self.n, nrhs))
+        check(_lib.load().mf_solve_noalloc(self._h, pb, px, nrhs, int(bool(transpose)),
+                                           _stream()))
+        return out
+
     def residual(self, K, x, b):
         import torch
         b2 = b if b.dim() == 2 else b.reshape(-1, 1)
