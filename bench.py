@@ -366,6 +366,11 @@ def variant_mixed(steps, warmup, precs=("fp64", "fp32", "bf16"), tuning=None, or
                      "err_vs_fp64": err, "roofline_schur": schur_roofline(plan, step, prec)}
     if oleg is not None:
         out["cpu_oracle"] = oleg
+    if "fp64" in out:
+        for prec in precs:
+            if prec in out and prec != "fp64":
+                out[prec]["speedup_vs_fp64"] = out["fp64"]["ms_per_system"] / out[prec]["ms_per_system"]
+                out[prec]["factor_speedup_vs_fp64"] = out["fp64"]["ms_factor"] / out[prec]["ms_factor"]
     return out
 
 
@@ -473,7 +478,75 @@ def variant_batched(steps, warmup, precs=("fp64", "fp32"), tuning=None, oracle=T
                      "err_vs_fp64": err, "roofline_schur": schur_roofline(plan, step, prec)}
     if pool is not None:
         out["cpu_oracle_pool"] = pool
+    out["one_mesh_at_a_time"] = unbatched(p, steps=3)
+    if "fp64" in out:
+        for prec in precs:
+            if prec in out and prec != "fp64":
+                out[prec]["speedup_vs_fp64"] = out["fp64"]["ms_per_batch"] / out[prec]["ms_per_batch"]
     return out
+
+
+def unbatched(p, steps=3):
+    """The same 256 meshes with one plan per mesh, factored and solved one after another (FP64,
+    the same step and schedule defaults): what the batched class launches are compared with."""
+    import torch
+    from paper_2306_08994_amd import Plan
+    NO, EO = p.node_offsets, p.elem_offsets
+    plans = []
+    for i in range(len(p.meshes)):
+        plan = Plan([p.meshes[i]])
+        K = torch.from_numpy(p.K[EO[i]:EO[i + 1]]).cuda()
+        b = torch.from_numpy(p.b[NO[i]:NO[i + 1]]).cuda()
+        plans.append((plan, K, b, torch.empty_like(b)))
+
+    def step():
+        for plan, K, b, x in plans:
+            plan.factor_refine(K, b, tol=1e-12, max_it=30, x=x)
+    wall, _, _ = time_steps(step, steps, 1)
+    return {"ms_per_batch": wall * 1e3, "ms_per_system": wall * 1e3 / len(plans),
+            "note": "one plan per mesh, factor_refine called mesh after mesh (FP64)"}
+
+
+def calibration_copies():
+    """Device-to-device copies of known sizes (8 KiB .. 1 GiB, three each, in that order) after
+    the measured launches: the HBM counters of a plain copy of each size calibrate the counter
+    readings of kernels with few workgroups as well as of ones that fill the chip."""
+    import torch
+    sizes = [1 << 13, 1 << 16, 1 << 19, 1 << 23, 1 << 30]
+    for nbytes in sizes:
+        src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        _sync()
+        for _ in range(3):
+            dst.copy_(src)
+        _sync()
+        del src, dst
+    return sizes
+
+
+def pmc_probe_variant(variant, prec, tuning):
+    """Counter runs of the 3D or the batched workload: the schedule (given or autotuned), one
+    profiled factorization to count launches, three plain factorizations, then the calibration
+    copies."""
+    import torch
+    from fixtures import config_problem
+    from paper_2306_08994_amd import Plan
+    p = config_problem(3 if variant == "mixed" else 4)
+    plan = Plan(p.meshes)
+    K = torch.from_numpy(p.K).cuda()
+    sched = schedule(plan, K, prec, tuning)
+    plan.factor(K, prec)
+    plan.profile(True)
+    plan.factor(K, prec)
+    _sync()
+    per = {k["name"]: k["launches"] for k in plan.profile_report()["kernels"]}
+    plan.profile(False)
+    for _ in range(3):
+        plan.factor(K, prec)
+    _sync()
+    return {"pmc_probe": True, "variant": variant, "precision": prec, "plain_factorizations": 3,
+            "launches_per_factorization": per, "schedule": sched,
+            "copy_bytes": calibration_copies()}
 
 
 def main():
@@ -506,6 +579,10 @@ def main():
     from fixtures import config_problem
     from paper_2306_08994_amd import Plan
 
+    if args.pmc_probe and args.variant in ("mixed", "batched"):
+        print(json.dumps(pmc_probe_variant(args.variant, (args.precs or "fp64").split(",")[0],
+                                           args.tuning)))
+        return
     if args.variant in ("mixed", "batched", "l2", "table3"):
         kw = {}
         if args.variant in ("mixed", "batched"):
@@ -550,12 +627,8 @@ def main():
         plan.profile(False)
         for _ in range(3):
             step()
-        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)   # 1 GiB
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        _sync()
-        print(json.dumps({"pmc_probe": True, "copy_bytes": src.numel() * 8, "plain_steps": 3,
+        copies = calibration_copies()
+        print(json.dumps({"pmc_probe": True, "copy_bytes": copies, "plain_steps": 3,
                           "launches_per_step": per_step, "schedule": tuned["chosen"]}))
         return
     t_step, t_dev, (_, its, rr) = time_steps(step, args.steps, args.warmup)
@@ -572,6 +645,12 @@ def main():
     rep = plan.profile_report()
     plan.profile(False)
     top, roof = roofline_of(rep)
+    factor_kinds = {"factor_tiny", "factor_small", "assemble", "front_panels", "panel_lu_trsm",
+                    "gemm_panel", "gemm_schur", "class_tiled"}
+    launches = {"factor": sum(k["launches"] for k in rep["kernels"] if k["name"] in factor_kinds),
+                "solve_and_inverses": sum(k["launches"] for k in rep["kernels"]
+                                          if k["name"] not in factor_kinds)}
+    launches = {k: v / args.steps for k, v in launches.items()}
 
     out = {
         "metric": "factor+solve GFLOP/s at relres<=1e-12 (FP64 multifrontal, 256x256 Q1, 8 RHS)",
@@ -593,6 +672,9 @@ def main():
                          bytes_per_launch=top["bytes"] / top["launches"],
                          flops_per_launch=top["flops"] / top["launches"]),
         "kernels": rep["kernels"],
+        "launches_per_step": dict(launches, classes=info["height"] + 1,
+                                  note="the plan's kernel launches per step; the residual, norm "
+                                       "and status-clearing launches (4-5 per step) not included"),
     }
     if not args.no_variants and args.variant == "all":
         vs = args.steps

@@ -137,16 +137,30 @@ int mf_task_trace(const mf_plan *plan, mf_trace_info *out, int64_t *hist, int64_
  *                workgroups take the class's extend-add strips, panel chunks, update tiles
  *                and Schur tiles in order and wait on per-front progress counters;
  *                -1: one launch per kind of work and per panel step (the default); 0 keeps it.
+ * The values apply to every class (a per-class schedule chosen by mf_autotune is dropped).
  * Invalidates a previous factorization.  Errors: MF_EINVAL. */
 int mf_set_tuning(mf_plan *plan, int32_t small_max_m, int32_t nb, int32_t fused_max_m,
                   int32_t tile, int32_t persistent);
 
+/* Per-class schedule: params (host) holds n_class = height + 1 rows of five values, one row per
+ * Foata class in order -- small_max_m (>= 1), nb (16, 32, 64), fused_max_m (0 = off, clipped to
+ * 576), tile (32, 64), persistent (0, 1), each meaning what it does in mf_set_tuning, for the
+ * fronts of that class only.  n_class = 0 drops a per-class schedule (mf_set_tuning's values
+ * then apply to every class).  This is the form mf_autotune chooses ("classes" of its report).
+ * Invalidates a previous factorization.  Errors: MF_EINVAL (wrong class count, bad value). */
+int mf_set_class_tuning(mf_plan *plan, int32_t n_class, const int32_t *params);
+
 /* Autotuner: factors elem_mats (device, as in mf_factor) under each candidate schedule that the
  * workload's front widths make relevant -- persistent class launches on/off, GEMM tile 64/32,
- * fused route on/off, panel width 32/64, LDS limit 128/64 -- times `reps` factorizations of
- * each (host clock, median), keeps the fastest and leaves the plan factored with it.  report (host, cap bytes, may be NULL)
- * receives a NUL-terminated JSON summary {"candidates": [...], "chosen": {...}}; needed (may
- * be NULL) its size.  Synchronizes hip_stream.  Errors: as mf_factor, MF_EINVAL. */
+ * fused route on/off, panel width 32/64, LDS limit 128/64 -- timing `reps` factorizations of
+ * each as a whole (host clock, median) and each Foata class's launches on their own (device
+ * events on the launch stream, mean).  Every class then takes the candidate under which its
+ * launches were fastest; the per-class schedule is kept if the whole factorization under it is
+ * faster than under the best single candidate, else that candidate is kept for every class.
+ * Leaves the plan factored with the kept schedule.  report (host, cap bytes, may be NULL)
+ * receives a NUL-terminated JSON summary {"candidates": [{..., "ms", "class_ms": [...]}],
+ * "chosen": {"mode": "per_class" | "global", "ms", ..., "classes": [...]}}; needed (may be NULL)
+ * its size.  Synchronizes hip_stream.  Errors: as mf_factor, MF_EINVAL. */
 int mf_autotune(mf_plan *plan, const double *elem_mats, int32_t precision, int32_t reps,
                 void *hip_stream, char *report, int64_t cap, int64_t *needed);
 

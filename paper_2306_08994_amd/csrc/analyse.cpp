@@ -369,16 +369,17 @@ std::string analyse(int32_t n_mesh, const int32_t *dims, const int32_t *npes,
   }
   P.store_doubles = store;
   P.sum_c = cbrow;
-  build_schedule(P, Tuning());
+  build_schedule(P, std::vector<Tuning>(P.height + 1, Tuning()));
   return "";
 }
 
-void build_schedule(HostPlan &P, const Tuning &t) {
+void build_schedule(HostPlan &P, const std::vector<Tuning> &tl) {
   P.levels.assign(P.height + 1, LevelSchedule());
   for (int64_t f = 0; f < P.F; ++f) {
     const FrontDesc &d = P.desc[f];
     if (d.elem >= 0 && d.k == 0) continue;   // pass-through leaf: read directly by its parent
     LevelSchedule &L = P.levels[d.level];
+    const Tuning &t = tl[d.level];
     L.max_m = std::max(L.max_m, d.m);
     L.max_k = std::max(L.max_k, d.k);
     if (d.m <= std::min(t.tiny_max_m, t.small_max_m)) {
@@ -401,8 +402,7 @@ void build_schedule(HostPlan &P, const Tuning &t) {
     L.all.insert(L.all.end(), L.large.begin(), L.large.end());
   }
   // the persistent class launch runs every tiled front panel by panel, 32 pivots at a time
-  const int32_t nb = t.persistent ? 32 : t.nb, T = t.tile;
-  const int32_t fused_lim = t.persistent ? 0 : t.fused_max_m;
+  int32_t T = 64;
   auto add_tiles = [&](std::vector<GemmTask> &out, int32_t f, int32_t i0, int32_t i1, int32_t j0,
                        int32_t j1, int32_t q0, int32_t q1) {
     if (i0 >= i1 || j0 >= j1 || q0 >= q1) return;
@@ -421,7 +421,12 @@ void build_schedule(HostPlan &P, const Tuning &t) {
         out.push_back(g);
       }
   };
-  for (auto &L : P.levels) {
+  for (size_t l = 0; l < P.levels.size(); ++l) {
+    LevelSchedule &L = P.levels[l];
+    const Tuning &t = tl[l];
+    const int32_t nb = t.persistent ? 32 : t.nb;
+    const int32_t fused_lim = t.persistent ? 0 : t.fused_max_m;
+    T = t.tile;
     int32_t max_steps = 0;
     for (int32_t f : L.large) {
       const FrontDesc &d = P.desc[f];
@@ -435,6 +440,7 @@ void build_schedule(HostPlan &P, const Tuning &t) {
       }
     }
     L.steps.assign(max_steps, PanelStep());
+    L.lookahead = !t.persistent && nb == 32;
     for (int32_t f : L.large) {
       const FrontDesc &d = P.desc[f];
       add_tiles(L.schur, f, d.k, d.m, d.k, d.m, 0, d.k);
@@ -446,10 +452,22 @@ void build_schedule(HostPlan &P, const Tuning &t) {
         S.p0.push_back(p0);
         // columns, then rows from the next multiple of 64 (see k_panel_trsm)
         S.trsm_items = std::max<int64_t>(S.trsm_items, (int64_t)((d.m - pe + 63) & ~63) + (d.m - pe));
-        // fully-summed region still to update: rows [pe,k) x cols [pe,m) and rows [k,m) x cols [pe,k)
-        add_tiles(S.update, f, pe, d.k, pe, d.k, p0, pe);
-        add_tiles(S.update, f, pe, d.k, d.k, d.m, p0, pe);
-        add_tiles(S.update, f, d.k, d.m, pe, d.k, p0, pe);
+        // fully-summed region still to update by this panel: rows [pe,k) x cols [pe,m) and rows
+        // [k,m) x cols [pe,k); in the look-ahead form the next step's launch does it beyond the
+        // next panel (its own rows and columns the next panel updates itself)
+        if (L.lookahead) {
+          if (pe < d.k) {
+            PanelStep &N = L.steps[s + 1];
+            const int32_t pn = std::min(pe + nb, d.k);
+            add_tiles(N.prev_update, f, pn, d.k, pn, d.k, p0, pe);
+            add_tiles(N.prev_update, f, pn, d.k, d.k, d.m, p0, pe);
+            add_tiles(N.prev_update, f, d.k, d.m, pn, d.k, p0, pe);
+          }
+        } else {
+          add_tiles(S.update, f, pe, d.k, pe, d.k, p0, pe);
+          add_tiles(S.update, f, pe, d.k, d.k, d.m, p0, pe);
+          add_tiles(S.update, f, d.k, d.m, pe, d.k, p0, pe);
+        }
       }
     }
   }

@@ -48,12 +48,39 @@ Cost front_factor_cost(const mf::HostPlan &H, int32_t f) {
   return c;
 }
 
+// Length of the union of half-open intervals.
+double union_length(std::vector<std::pair<int32_t, int32_t>> v) {
+  std::sort(v.begin(), v.end());
+  double len = 0;
+  int32_t hi = INT32_MIN;
+  for (const auto &iv : v) {
+    const int32_t lo = std::max(iv.first, hi);
+    if (iv.second > lo) len += iv.second - lo;
+    hi = std::max(hi, iv.second);
+  }
+  return len;
+}
+
+// Algorithmic cost of a set of GEMM update tiles C -= A B: per front (and inner range), the
+// output entries read and written once, and each operand row of A and column of B read once
+// over the inner dimension -- not the operand re-reads of the tiling.
 Cost gemm_cost(const std::vector<mf::GemmTask> &ts) {
   Cost c;
-  for (const auto &t : ts) {
-    const double ni = t.i1 - t.i0, nj = t.j1 - t.j0, nq = t.q1 - t.q0;
-    c.flops += 2 * ni * nj * nq;
-    c.bytes += 8 * (2 * ni * nj + ni * nq + nq * nj);
+  std::unordered_map<int64_t, std::vector<size_t>> by_front;
+  for (size_t i = 0; i < ts.size(); ++i) by_front[((int64_t)ts[i].front << 20) ^ ts[i].q0].push_back(i);
+  for (const auto &kv : by_front) {
+    std::vector<std::pair<int32_t, int32_t>> rows, cols;
+    double out = 0, nq = 0;
+    for (size_t i : kv.second) {
+      const mf::GemmTask &t = ts[i];
+      const double ni = t.i1 - t.i0, nj = t.j1 - t.j0;
+      nq = t.q1 - t.q0;
+      c.flops += 2 * ni * nj * nq;
+      out += ni * nj;
+      rows.emplace_back(t.i0, t.i1);
+      cols.emplace_back(t.j0, t.j1);
+    }
+    c.bytes += 8 * (2 * out + (union_length(rows) + union_length(cols)) * nq);
   }
   return c;
 }
@@ -92,8 +119,14 @@ void level_costs(const mf::HostPlan &H, const mf::LevelSchedule &S, LevelDev &D,
       const double rest = d.m - st.p0[i] - pb;
       sd.trsm.bytes += 8 * (2 * pb * pb + 4 * rest * pb);
       sd.trsm.flops += elim_flops((int32_t)pb, (int32_t)pb) + 2 * rest * pb * pb;
+      if (S.lookahead && st.p0[i] > 0) {
+        // the previous panel's update of this panel's rows and columns: its L and U entries
+        // of them read once, 2 nb flops per entry of the panel's rows and columns
+        sd.trsm.bytes += 8 * (nb * (2 * rest + 2 * pb));
+        sd.trsm.flops += 2.0 * nb * pb * (2 * rest + pb);
+      }
     }
-    sd.upd = gemm_cost(st.update);
+    sd.upd = gemm_cost(S.lookahead ? st.prev_update : st.update);
   }
   D.c_schur = gemm_cost(S.schur);
   for (int32_t f : S.all) {
@@ -155,9 +188,17 @@ int ensure_uploaded(mf_plan *P) {
   mf::HostPlan &H = P->hp;
   // widest front whose padded square fits in one workgroup's LDS
   int32_t mm = 1;
-  while (((int64_t)(mm + 1) * ((mm + 1) | 1) + (mm + 1)) * 8 <= P->max_shared) ++mm;
+  while (mf::small_lds_doubles(mm + 1) * 8 <= P->max_shared) ++mm;
   P->tune.small_max_m = std::min<int32_t>(P->tune.small_max_m, mm);
-  mf::build_schedule(H, P->tune);
+  // the schedule of each class: its own entry if the autotuner chose one, else the plan's
+  P->eff.assign(H.height + 1, P->tune);
+  if (P->ctune.size() == P->eff.size()) P->eff = P->ctune;
+  bool any_persistent = false;
+  for (mf::Tuning &t : P->eff) {
+    t.small_max_m = std::min<int32_t>(t.small_max_m, mm);
+    any_persistent = any_persistent || t.persistent;
+  }
+  mf::build_schedule(H, P->eff);
   std::vector<int32_t> lists;
   std::vector<mf::GemmTask> tasks;
   std::vector<mf::PanelRec> panel;
@@ -203,13 +244,22 @@ int ensure_uploaded(mf_plan *P) {
       sd.update = (int64_t)tasks.size();
       sd.n_update = (int64_t)st.update.size();
       tasks.insert(tasks.end(), st.update.begin(), st.update.end());
+      sd.prev_update = (int64_t)tasks.size();
+      sd.n_prev_update = (int64_t)st.prev_update.size();
+      tasks.insert(tasks.end(), st.prev_update.begin(), st.prev_update.end());
+      for (size_t i = 0; i < st.fronts.size(); ++i) {
+        const mf::FrontDesc &d = H.desc[st.fronts[i]];
+        sd.la_chunks = std::max(sd.la_chunks,
+                                mf::lookahead_chunks(d.m, std::min(st.p0[i] + mf::LA_NB, d.k)));
+      }
       sd.trsm_items = st.trsm_items;
       D.steps.push_back(sd);
     }
+    D.lookahead = S.lookahead;
     D.schur = (int64_t)tasks.size();
     D.n_schur = (int64_t)S.schur.size();
     tasks.insert(tasks.end(), S.schur.begin(), S.schur.end());
-    level_costs(H, S, D, P->tune.persistent ? mf::kClassNB : P->tune.nb);
+    level_costs(H, S, D, P->eff[l].persistent ? mf::kClassNB : P->eff[l].nb);
   }
   // wave records follow the class lists, class after class
   {
@@ -272,13 +322,13 @@ int ensure_uploaded(mf_plan *P) {
   // tiles) with the count of earlier-phase tasks of the same front that each task waits for
   std::vector<mf::ClassTask> ctasks;
   int64_t n_counters = 0;
-  if (P->tune.persistent) {
+  if (any_persistent) {
     for (size_t l = 0; l < H.levels.size(); ++l) {
       const mf::LevelSchedule &S = H.levels[l];
       LevelDev &D = P->lv[l];
       D.ctask = (int64_t)ctasks.size();
       D.n_ctask = 0;
-      if (S.large.empty()) continue;
+      if (S.large.empty() || !P->eff[l].persistent) continue;
       std::vector<int32_t> cidx(S.large.size()), done(S.large.size(), 0);
       std::unordered_map<int32_t, int32_t> slot;
       for (size_t i = 0; i < S.large.size(); ++i) {
@@ -376,7 +426,7 @@ int ensure_uploaded(mf_plan *P) {
       (rc = upload(P->d_ctasks, ctasks)))
     return rc;
   {
-    const int64_t nc = P->tune.persistent ? (int64_t)H.levels.size() + n_counters : 0;
+    const int64_t nc = any_persistent ? (int64_t)H.levels.size() + n_counters : 0;
     dfree(P->d_ccnt);
     P->n_ccnt = nc;
     if (hipMalloc((void **)&P->d_ccnt, std::max<int64_t>(1, nc) * sizeof(int)) != hipSuccess)
@@ -506,7 +556,7 @@ int ensure_uploaded(mf_plan *P) {
   for (const void *fn : dyn)
     (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, P->max_shared);
   (void)hipGetLastError();
-  if (P->tune.persistent) {
+  if (any_persistent) {
     // workgroups of a persistent class launch resident at once (the launch never needs more:
     // it runs any number of tasks, and never waits for a workgroup that has not started)
     int per_cu = 0, cus = 0;
@@ -571,7 +621,7 @@ struct Scope {
       return;
     }
     (void)hipEventRecord(b, s);
-    P->prof.recs.push_back(ProfRec{kind, a, b, cost});
+    P->prof.recs.push_back(ProfRec{kind, P->prof.cur_class, a, b, cost});
   }
 };
 
@@ -583,8 +633,10 @@ struct Scope {
 
 // The launches of class l of the factorization.
 int factor_level(mf_plan *P, const double *K, int prec, size_t l, hipStream_t s) {
+  P->prof.cur_class = (int)l;
   {
     const LevelDev &D = P->lv[l];
+    const mf::Tuning &T = P->eff[l];
     if (D.n_tiny) {
       const int m = D.tiny_max_m;
       const int ldsw = m * (m | 1) + m;           // front + 2m int maps
@@ -606,14 +658,14 @@ int factor_level(mf_plan *P, const double *K, int prec, size_t l, hipStream_t s)
     }
     if (D.n_small) {
       const int m = D.small_max_m;
-      const size_t lds = ((size_t)m * (m | 1) + m) * sizeof(double);
+      const size_t lds = (size_t)mf::small_lds_doubles(m) * sizeof(double);
       const int grid = (int)std::min<int64_t>(D.n_small, 16384);
       LAUNCH(K_SMALL, D.c_small, mf::k_factor_small, dim3(grid), dim3(mf::SM_THREADS), lds, s,
              P->d_wrec + D.rall + D.n_tiny, (int)D.n_small, P->d_store, P->d_inv_l, P->d_inv_r, K,
              P->d_status, m);
     }
     if (D.n_large && D.n_ctask) {
-      const size_t lds = P->tune.tile == 32 ? mf::class_lds_bytes<2, 32>(D.large_max_m)
+      const size_t lds = T.tile == 32 ? mf::class_lds_bytes<2, 32>(D.large_max_m)
                                             : mf::class_lds_bytes<2, 64>(D.large_max_m);
       const int grid = (int)std::min<int64_t>(D.n_ctask, P->class_blocks);
       const mf::ClassTask *ct = P->d_ctasks + D.ctask;
@@ -623,7 +675,7 @@ int factor_level(mf_plan *P, const double *K, int prec, size_t l, hipStream_t s)
   LAUNCH(K_CLASS, D.c_class, (mf::k_class_tiled<PR, TI>), dim3(grid), dim3(256), lds, s, ct,   \
          (int)D.n_ctask, tick, cnt, P->d_wrec, P->d_store, P->d_inv_l, P->d_inv_r, K,          \
          P->d_status, P->wait_ticks)
-      if (P->tune.tile == 32) {
+      if (T.tile == 32) {
         if (prec == MF_SCHUR_FP32) MF_CLASS(1, 32);
         else if (prec == MF_SCHUR_BF16) MF_CLASS(2, 32);
         else MF_CLASS(0, 32);
@@ -645,11 +697,28 @@ int factor_level(mf_plan *P, const double *K, int prec, size_t l, hipStream_t s)
                dim3(mf::FP_THREADS), lds, s, P->d_desc, P->d_lists + D.fused, (int)D.n_fused,
                P->d_store, P->d_status);
       }
-      for (const StepDev &st : D.steps) {
+      if (D.lookahead) {
+        for (const StepDev &st : D.steps) {
+          Cost c;
+          c.bytes = st.trsm.bytes + st.upd.bytes;
+          c.flops = st.trsm.flops + st.upd.flops;
+          const int64_t nblk = st.n * (int64_t)st.la_chunks + st.n_prev_update;
+          const mf::PanelRec *pr = P->d_panel + st.prec;
+          const mf::GemmTask *t = P->d_tasks + st.prev_update;
+          if (T.tile == 32)
+            LAUNCH(K_PANEL_LA, c, mf::k_panel_lookahead<32>, dim3((unsigned)nblk), dim3(256), 0, s,
+                   pr, (int)st.n, st.la_chunks, t, P->d_store, P->d_status, P->d_arrive);
+          else
+            LAUNCH(K_PANEL_LA, c, mf::k_panel_lookahead<64>, dim3((unsigned)nblk), dim3(256), 0, s,
+                   pr, (int)st.n, st.la_chunks, t, P->d_store, P->d_status, P->d_arrive);
+        }
+      }
+      for (size_t si = 0; si < (D.lookahead ? 0 : D.steps.size()); ++si) {
+        const StepDev &st = D.steps[si];
         const dim3 gt((unsigned)std::max<int64_t>(1, (st.trsm_items + 255) / 256),
                       (unsigned)std::min<int64_t>(st.n, kMaxGridY));
         const mf::PanelRec *pr = P->d_panel + st.prec;
-        switch (P->tune.nb) {
+        switch (T.nb) {
           case 16:
             LAUNCH(K_TRSM, st.trsm, mf::k_panel_trsm<16>, gt, dim3(256), 0, s, pr, (int)st.n, P->d_store, P->d_status,
                    P->d_arrive);
@@ -665,7 +734,7 @@ int factor_level(mf_plan *P, const double *K, int prec, size_t l, hipStream_t s)
         if (st.n_update) {
           const dim3 g((unsigned)st.n_update);
           const mf::GemmTask *t = P->d_tasks + st.update;
-          if (P->tune.tile == 32)
+          if (T.tile == 32)
             LAUNCH(K_GEMM_PANEL, st.upd, (mf::k_gemm_update<0, 32>), g, dim3(256), 0, s, t, P->d_store);
           else
             LAUNCH(K_GEMM_PANEL, st.upd, (mf::k_gemm_update<0, 64>), g, dim3(256), 0, s, t, P->d_store);
@@ -674,7 +743,7 @@ int factor_level(mf_plan *P, const double *K, int prec, size_t l, hipStream_t s)
       if (D.n_schur) {
         const mf::GemmTask *t = P->d_tasks + D.schur;
         const dim3 g((unsigned)D.n_schur);
-        const bool t32 = P->tune.tile == 32;
+        const bool t32 = T.tile == 32;
         if (prec == MF_SCHUR_FP32) {
           if (t32) LAUNCH(K_GEMM_SCHUR, D.c_schur, (mf::k_gemm_update<1, 32>), g, dim3(256), 0, s, t, P->d_store);
           else LAUNCH(K_GEMM_SCHUR, D.c_schur, (mf::k_gemm_update<1, 64>), g, dim3(256), 0, s, t, P->d_store);
@@ -688,6 +757,7 @@ int factor_level(mf_plan *P, const double *K, int prec, size_t l, hipStream_t s)
       }
     }
   }
+  P->prof.cur_class = -1;
   return MF_OK;
 }
 
@@ -1114,7 +1184,39 @@ int mf_set_tuning(mf_plan *P, int32_t small_max_m, int32_t nb, int32_t fused_max
   if (nb > 0) P->tune.nb = nb;
   if (fused_max_m == -1) P->tune.fused_max_m = 0;
   else if (fused_max_m > 0) P->tune.fused_max_m = std::min(fused_max_m, mf::FP_MAXM);
+  P->ctune.clear();         // one schedule for every class again
   P->uploaded = false;      // the schedule is rebuilt at the next device call
+  P->factored = false;
+  P->drop_graphs();
+  return MF_OK;
+}
+
+int mf_set_class_tuning(mf_plan *P, int32_t n_class, const int32_t *params) {
+  if (!P) return fail(MF_EINVAL, "null plan");
+  const int32_t nc = P->hp.height + 1;
+  if (n_class == 0) {
+    P->ctune.clear();
+  } else {
+    if (n_class != nc || !params)
+      return fail(MF_EINVAL, "expected " + std::to_string(nc) + " classes of 5 values");
+    std::vector<mf::Tuning> ct(nc, P->tune);
+    for (int32_t l = 0; l < nc; ++l) {
+      const int32_t *q = params + 5 * l;
+      const int32_t smax = q[0], nb = q[1], fused = q[2], tile = q[3], pers = q[4];
+      if (smax < 1) return fail(MF_EINVAL, "small_max_m must be >= 1 (class " + std::to_string(l) + ")");
+      if (nb != 16 && nb != 32 && nb != 64) return fail(MF_EINVAL, "nb must be 16, 32 or 64");
+      if (fused < 0) return fail(MF_EINVAL, "fused_max_m must be >= 0");
+      if (tile != 32 && tile != 64) return fail(MF_EINVAL, "tile must be 32 or 64");
+      if (pers != 0 && pers != 1) return fail(MF_EINVAL, "persistent must be 0 or 1");
+      ct[l].small_max_m = smax;
+      ct[l].nb = nb;
+      ct[l].fused_max_m = std::min(fused, mf::FP_MAXM);
+      ct[l].tile = tile;
+      ct[l].persistent = pers;
+    }
+    P->ctune = ct;
+  }
+  P->uploaded = false;
   P->factored = false;
   P->drop_graphs();
   return MF_OK;
@@ -1383,45 +1485,98 @@ int mf_autotune(mf_plan *P, const double *elem_mats, int32_t precision, int32_t 
             t.small_max_m = smax;
             cands.push_back(t);
           }
-  std::string js = "{\"candidates\": [";
-  double best = 1e300;
-  mf::Tuning best_t = base;
-  for (size_t c = 0; c < cands.size(); ++c) {
-    P->tune = cands[c];
+  const size_t ncls = P->hp.levels.size();
+  // host-clock median of `reps` factorizations under the plan's current schedule
+  auto timed = [&](double &med) -> int {
+    int r;
     P->uploaded = false;
     P->factored = false;
-    if ((rc = mf_factor(P, elem_mats, precision, hip_stream))) return rc;   // warm-up + capture
+    if ((r = mf_factor(P, elem_mats, precision, hip_stream))) return r;   // warm-up + capture
     std::vector<double> ts;
-    for (int32_t r = 0; r < reps; ++r) {
+    for (int32_t i = 0; i < reps; ++i) {
       const auto t0 = std::chrono::steady_clock::now();
-      if ((rc = mf_factor(P, elem_mats, precision, hip_stream))) return rc;
+      if ((r = mf_factor(P, elem_mats, precision, hip_stream))) return r;
       ts.push_back(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
     }
     std::sort(ts.begin(), ts.end());
-    const double med = ts[ts.size() / 2];
-    if (med < best) {
-      best = med;
-      best_t = cands[c];
+    med = ts[ts.size() / 2];
+    return MF_OK;
+  };
+  // per candidate: the whole factorization (host clock), then each class's launches timed with
+  // device events on the stream they run on (summed over the class, averaged over reps)
+  std::vector<double> tglob(cands.size());
+  std::vector<std::vector<double>> tcls(cands.size(), std::vector<double>(ncls, 0.0));
+  const Profiler saved = P->prof;
+  P->prof = Profiler();
+  for (size_t c = 0; c < cands.size(); ++c) {
+    P->tune = cands[c];
+    P->ctune.clear();
+    if ((rc = timed(tglob[c]))) return rc;
+    P->prof.on = true;
+    for (int32_t i = 0; i < reps; ++i)
+      if ((rc = mf_factor(P, elem_mats, precision, hip_stream))) return rc;
+    for (auto &r : P->prof.recs) {
+      float ms = 0;
+      HIPCHK(hipEventSynchronize(r.b));
+      HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+      if (r.cls >= 0 && (size_t)r.cls < ncls) tcls[c][r.cls] += ms / reps;
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
     }
-    char line[240];
-    std::snprintf(line, sizeof line,
-                  "%s{\"persistent\": %d, \"tile\": %d, \"fused_max_m\": %d, \"nb\": %d, "
-                  "\"small_max_m\": %d, \"ms\": %.4f}",
-                  c ? ", " : "", cands[c].persistent, cands[c].tile, cands[c].fused_max_m,
-                  cands[c].nb, P->tune.small_max_m, med);
-    js += line;
+    P->prof = Profiler();
   }
-  P->tune = best_t;
+  P->prof = saved;
+  size_t cb = 0;
+  for (size_t c = 1; c < cands.size(); ++c)
+    if (tglob[c] < tglob[cb]) cb = c;
+  // each class takes the candidate under which its own launches were fastest
+  std::vector<size_t> pick(ncls, cb);
+  for (size_t l = 0; l < ncls; ++l)
+    for (size_t c = 0; c < cands.size(); ++c)
+      if (tcls[c][l] < tcls[pick[l]][l]) pick[l] = c;
+  P->tune = cands[cb];
+  P->ctune.assign(ncls, cands[cb]);
+  for (size_t l = 0; l < ncls; ++l) P->ctune[l] = cands[pick[l]];
+  double tmix = 0;
+  if ((rc = timed(tmix))) return rc;
+  const bool per_class = tmix < tglob[cb];
+  if (!per_class) P->ctune.clear();
   P->uploaded = false;
   P->factored = false;
   if ((rc = mf_factor(P, elem_mats, precision, hip_stream))) return rc;
-  char line[240];
-  std::snprintf(line, sizeof line,
-                "], \"chosen\": {\"persistent\": %d, \"tile\": %d, \"fused_max_m\": %d, "
-                "\"nb\": %d, \"small_max_m\": %d, \"ms\": %.4f}}",
-                P->tune.persistent, P->tune.tile, P->tune.fused_max_m, P->tune.nb,
-                P->tune.small_max_m, best);
-  js += line;
+  auto tune_js = [](const mf::Tuning &t) {
+    char b[160];
+    std::snprintf(b, sizeof b, "\"persistent\": %d, \"tile\": %d, \"fused_max_m\": %d, \"nb\": %d, "
+                               "\"small_max_m\": %d", t.persistent, t.tile, t.fused_max_m, t.nb,
+                  t.small_max_m);
+    return std::string(b);
+  };
+  std::string js = "{\"candidates\": [";
+  for (size_t c = 0; c < cands.size(); ++c) {
+    char b[64];
+    std::snprintf(b, sizeof b, ", \"ms\": %.4f, \"class_ms\": [", tglob[c]);
+    js += (c ? ", {" : "{") + tune_js(cands[c]) + b;
+    for (size_t l = 0; l < ncls; ++l) {
+      std::snprintf(b, sizeof b, "%s%.4f", l ? ", " : "", tcls[c][l]);
+      js += b;
+    }
+    js += "]}";
+  }
+  js += "], \"chosen\": {\"mode\": \"";
+  js += per_class ? "per_class" : "global";
+  {
+    char b[160];
+    std::snprintf(b, sizeof b, "\", \"ms\": %.4f, \"best_global_ms\": %.4f, \"per_class_ms\": %.4f, ",
+                  per_class ? tmix : tglob[cb], tglob[cb], tmix);
+    js += b;
+  }
+  js += tune_js(cands[cb]) + ", \"classes\": [";
+  for (size_t l = 0; l < ncls; ++l) {
+    char b[48];
+    std::snprintf(b, sizeof b, ", \"class_ms\": %.4f}", tcls[pick[l]][l]);
+    js += (l ? ", {" : "{") + tune_js(cands[pick[l]]) + b;
+  }
+  js += "]}}";
   if (needed) *needed = (int64_t)js.size() + 1;
   if (report && cap > 0) {
     const size_t n = std::min<size_t>((size_t)cap - 1, js.size());

@@ -45,12 +45,13 @@ inline int fail(int code, const std::string &msg) {
 enum Kind {
   K_TINY, K_SMALL, K_ASSEMBLE, K_FUSED, K_TRSM, K_GEMM_PANEL, K_GEMM_SCHUR,
   K_DOWN_WAVE, K_DOWN_BLOCK, K_UP_WAVE, K_UP_BLOCK, K_DOWN_RECT, K_UP_RECT, K_RESIDUAL,
-  K_DIAG_INV, K_CLASS, K_OTHER, K_COUNT
+  K_DIAG_INV, K_CLASS, K_PANEL_LA, K_OTHER, K_COUNT
 };
 static const char *const kKindName[K_COUNT] = {
     "factor_tiny", "factor_small", "assemble", "front_panels", "panel_lu_trsm", "gemm_panel",
     "gemm_schur", "solve_down_wave", "solve_down_block", "solve_up_wave", "solve_up_block",
-    "solve_down_rect", "solve_up_rect", "residual", "diag_block_inverse", "class_tiled", "other"};
+    "solve_down_rect", "solve_up_rect", "residual", "diag_block_inverse", "class_tiled",
+    "panel_lookahead", "other"};
 
 // Algorithmic traffic and work of one launch (bytes that must cross HBM at least once, flops
 // of the method's own operation count).
@@ -62,6 +63,10 @@ struct StepDev {
   int64_t prec = 0, n = 0;         // panel records (d_panel) of the step's fronts
   int64_t update = 0, n_update = 0;
   int64_t trsm_items = 0;
+  // look-ahead form: the previous panel's update tiles beyond this panel (d_tasks), and the
+  // chunks per front of the panel part (the widest front's)
+  int64_t prev_update = 0, n_prev_update = 0;
+  int32_t la_chunks = 0;
   Cost trsm, upd;
 };
 
@@ -84,6 +89,7 @@ struct LevelDev {
   int64_t ctask = 0, n_ctask = 0;
   int32_t tick = 0;
   Cost c_class;
+  bool lookahead = false;      // panel steps in the look-ahead form
   // solves: fixed (coefficient) bytes, bytes and flops per right-hand side; for the block
   // route split into the triangle (pivot block) and the rectangular (contribution) part
   double down_coef = 0, down_rhs_bytes = 0, down_rhs_flops = 0;
@@ -99,12 +105,14 @@ struct LevelDev {
 
 struct ProfRec {
   int kind;
+  int cls;          // Foata class of the launch (-1: not a class's launch)
   hipEvent_t a, b;
   Cost cost;
 };
 
 struct Profiler {
   bool on = false;
+  int cur_class = -1;     // class whose launches are being issued
   std::vector<ProfRec> recs;
   double ms[K_COUNT] = {0};
   double bytes[K_COUNT] = {0};
@@ -133,7 +141,9 @@ void dfree(T *&p) {
 
 struct mf_plan {
   mf::HostPlan hp;
-  mf::Tuning tune;
+  mf::Tuning tune;                  // schedule of every class without an entry of its own
+  std::vector<mf::Tuning> ctune;    // per-class schedule (empty: `tune` for every class)
+  std::vector<mf::Tuning> eff;      // the schedule in use, per class (set at upload)
   int device = -1;
   bool uploaded = false;     // schedule (front lists, GEMM tasks) on the device
   bool static_up = false;    // tree arrays and factor storage on the device

@@ -135,59 +135,120 @@ k_factor_tiny(const WaveRec *__restrict__ recs, int nrec, double *__restrict__ s
 }
 
 // ---------------------------------------------------------------------------------------------
-// small: one workgroup of SM_THREADS per front, the whole front resident in LDS.  Thread t owns
-// column j = t mod m of the rows i = g, g + G, ... with g = t div m and G = SM_THREADS div m
-// groups.  At pivot p every owner of column j > p forms U[p][j] = F[p][j] / F[p][p] itself
-// (the division task) and subtracts F[i][p] U[p][j] from its rows i > p; the scaled row p is
-// stored one step later (nothing reads row p then), so one barrier per pivot orders the steps.
+// small: one workgroup of SM_THREADS per front, the whole front resident in LDS, eliminated in
+// panels of SM_NB pivots (Table 2's division, multiplication and subtraction tasks, blocked):
+//   1. wave 0 factors the pb x pb diagonal block (register resident, readlane broadcasts);
+//   2. one thread per column solves U12 = L11^{-1} A12 (the division tasks of the panel's rows
+//      and their updates inside the panel), one thread per row solves L21 = A21 U11^{-1};
+//   3. the trailing matrix (the rest of the fully summed part and the contribution block) takes
+//      the panel's multiplications and subtractions at once, A22 -= L21 U12, as 16 x 16 blocks
+//      of v_mfma_f64_16x16x4f64 with operands and results in LDS.
+// Three barriers per panel instead of one per pivot, and one LDS read and write of each trailing
+// entry per panel instead of per pivot.  LDS: front (m rows of m|1) | D (NB x NB+1) | rd (NB) |
+// extend-add maps (2 m ints).
 // ---------------------------------------------------------------------------------------------
 constexpr int SM_THREADS = 512;
+constexpr int SM_NB = 8;
+
+__host__ __device__ inline int64_t small_lds_doubles(int m) {
+  return (int64_t)m * (m | 1) + SM_NB * (SM_NB + 1) + SM_NB + m;
+}
 
 __global__ void __launch_bounds__(SM_THREADS)
 k_factor_small(const WaveRec *__restrict__ recs, int nrec, double *__restrict__ store,
                const int32_t *__restrict__ inv_l, const int32_t *__restrict__ inv_r,
                const double *__restrict__ K, int *__restrict__ status, int mmax) {
+  constexpr int NB = SM_NB;
   extern __shared__ double sh[];
-  int *ma = reinterpret_cast<int *>(sh + (size_t)mmax * (mmax | 1));   // 2 * mmax ints
+  double(*D)[NB + 1] = reinterpret_cast<double(*)[NB + 1]>(sh + (size_t)mmax * (mmax | 1));
+  double *rd = sh + (size_t)mmax * (mmax | 1) + NB * (NB + 1);
+  int *ma = reinterpret_cast<int *>(rd + NB);   // 2 * mmax ints
   int *mb = ma + mmax;
-  const int tid = threadIdx.x;
-  for (int li = blockIdx.x; li < nrec; li += gridDim.x) {
-    const WaveRec d = recs[li];
+  __shared__ int s_bad;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int li = lane & 15, lk = lane >> 4;
+  for (int fi = blockIdx.x; fi < nrec; fi += gridDim.x) {
+    const WaveRec d = recs[fi];
     const int m = d.m, k = d.k, ld = m | 1;
-    const int32_t *il = inv_l + d.idx;
-    const int32_t *ir = inv_r + d.idx;
     const GatherCtx g = rec_gather_ctx(d, store, K);
-    scatter_assemble(g, il, ir, m, ld, sh, ma, mb, tid, SM_THREADS,
+    if (tid == 0) s_bad = 0;
+    scatter_assemble(g, inv_l + d.idx, inv_r + d.idx, m, ld, sh, ma, mb, tid, SM_THREADS,
                      [] __device__() { __syncthreads(); });
-    const int G = SM_THREADS / m;            // row groups per column (m <= SM_THREADS)
-    const int j = tid % m, grp = tid / m;
-    const bool owner = grp < G;
-    double u_prev = 0.0;
-    int p = 0;
-    for (; p < k; ++p) {
-      const double piv = sh[p * ld + p];
-      if (!good_pivot(piv)) {
-        if (tid == 0) record_bad_pivot(status, d.f, p);
-        break;
-      }
-      double u = 0.0;
-      if (owner && j > p) {
-        u = sh[p * ld + j] / piv;
-        int i = p + 1 + grp;
-        for (; i + G < m; i += 2 * G) {
-          const double c0 = sh[i * ld + p], c1 = sh[(i + G) * ld + p];
-          sh[i * ld + j] -= c0 * u;
-          sh[(i + G) * ld + j] -= c1 * u;
+    for (int p0 = 0; p0 < k; p0 += NB) {
+      const int pb = min(NB, k - p0), pe = p0 + pb, rest = m - pe;
+      // 1. the diagonal block, factored in registers and written back in place
+      if (wv == 0 && !wave_diag_lu<NB>(sh + p0 * ld + p0, ld, pb, D, rd, lane, d.f, p0, status))
+        if (lane == 0) s_bad = 1;
+      __syncthreads();
+      if (s_bad) break;                                     // uniform
+      // 2. U12 columns (items t < rest) and L21 rows (items from the next multiple of 64, so
+      //    that no wave holds both kinds); positions beyond pb meet the identity padding of D
+      const int rpad = (rest + 63) & ~63;
+      for (int t = tid; t < rpad + rest; t += SM_THREADS) {
+        if (t < rest) {
+          double *cp = sh + p0 * ld + pe + t;
+          double v[NB];
+#pragma unroll
+          for (int q = 0; q < NB; ++q) v[q] = cp[min(q, pb - 1) * ld];
+#pragma unroll
+          for (int q = 0; q < NB; ++q) {
+            double a = v[q];
+#pragma unroll
+            for (int r = 0; r < q; ++r) a -= D[q][r] * v[r];
+            v[q] = a * rd[q];
+          }
+#pragma unroll
+          for (int q = 0; q < NB; ++q)
+            if (q < pb) cp[q * ld] = v[q];
+        } else if (t >= rpad) {
+          double *row = sh + (pe + t - rpad) * ld + p0;
+          double v[NB];
+#pragma unroll
+          for (int q = 0; q < NB; ++q) v[q] = row[min(q, pb - 1)];
+#pragma unroll
+          for (int q = 0; q < NB; ++q) {
+            double a = v[q];
+#pragma unroll
+            for (int r = 0; r < q; ++r) a -= v[r] * D[r][q];
+            v[q] = a;
+          }
+#pragma unroll
+          for (int q = 0; q < NB; ++q)
+            if (q < pb) row[q] = v[q];
         }
-        if (i < m) sh[i * ld + j] -= sh[i * ld + p] * u;
       }
-      // deferred store of the scaled row p-1 (its owner group is (p-1) mod G)
-      if (owner && p > 0 && j > p - 1 && (p - 1) % G == grp) sh[(p - 1) * ld + j] = u_prev;
-      u_prev = u;
+      __syncthreads();
+      // 3. A22 -= L21 U12 over the rest x rest trailing matrix, one 16 x 16 block per wave at a
+      //    time: A operand lane l = L21[row l%16][q = l/16 + 4s] (negated), B operand lane l =
+      //    U12[q = l/16 + 4s][col l%16], result lane l register r at row 4r + l/16, col l%16
+      const int nbk = (rest + 15) >> 4;
+      for (int blk = wv; blk < nbk * nbk; blk += SM_THREADS / 64) {
+        const int bi = blk / nbk, bj = blk - bi * nbk;
+        const int r0 = pe + 16 * bi, c0 = pe + 16 * bj;
+        const int col = c0 + li;
+        v4d acc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = r0 + 4 * r + lk;
+          acc[r] = (row < m && col < m) ? sh[row * ld + col] : 0.0;
+        }
+        const int arow = r0 + li;
+#pragma unroll
+        for (int s = 0; s < NB / 4; ++s) {
+          const int q = 4 * s + lk;
+          const double a = (q < pb && arow < m) ? -sh[arow * ld + p0 + q] : 0.0;
+          const double b = (q < pb && col < m) ? sh[(p0 + q) * ld + col] : 0.0;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = r0 + 4 * r + lk;
+          if (row < m && col < m) sh[row * ld + col] = acc[r];
+        }
+      }
       __syncthreads();
     }
-    if (owner && p > 0 && p == k && j > p - 1 && (p - 1) % G == grp) sh[(p - 1) * ld + j] = u_prev;
-    __syncthreads();
     double *out = store + d.store;
     for (int t = tid; t < m * m; t += SM_THREADS) {
       const int i = t / m, jj = t - (t / m) * m;
@@ -404,6 +465,227 @@ __global__ void __launch_bounds__(256)
 k_gemm_update(const GemmTask *__restrict__ tasks, double *__restrict__ store) {
   __shared__ GemmLds<PREC, TILE> sm;
   gemm_tile<PREC, TILE>(tasks[blockIdx.x], store, sm);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Panel step in the look-ahead form (panel width 32): one launch per step does
+//   A. per front, the panel p0 .. pe-1.  Its rows and columns -- the diagonal block, the U12
+//      columns and the L21 rows -- first take the previous panel's trailing update
+//      (F -= L U over the previous 32 pivots, Table 2's multiplications and subtractions of
+//      those pivots); then the diagonal block is factored and the columns and rows are solved
+//      against it, as in k_panel_trsm;
+//   B. the previous panel's trailing update of the rest of the fully summed region (rows and
+//      columns from pe on), as GEMM tiles in the workgroups after the A chunks.
+// A and B write disjoint entries and read only entries that are final when the launch starts, so
+// one launch does the work of a panel launch and an update launch: one launch and two
+// inter-kernel gaps less per step on the dependency chain of a front.
+// An A chunk is 256 threads: wave 0 stages and factors the diagonal block, waves 1-3 hold 192
+// items (item t < rest a U12 column, t in [R, R + rest) an L21 row, R = rest rounded up to 64,
+// so that no wave holds both kinds).
+// ---------------------------------------------------------------------------------------------
+constexpr int LA_NB = 32;
+constexpr int LA_ITEMS = 192;
+
+__device__ __host__ inline int lookahead_chunks(int m, int pe) {
+  const int rest = m - pe, rpad = (rest + 63) & ~63;
+  const int c = (rpad + rest + LA_ITEMS - 1) / LA_ITEMS;
+  return c > 1 ? c : 1;
+}
+
+template <int TILE>
+union LookaheadLds {
+  struct {
+    double D[LA_NB][LA_NB + 1];     // factored diagonal block (identity padding beyond pb)
+    double rd[LA_NB];               // reciprocals of its pivots
+    double Dg[LA_NB][LA_NB + 1];    // the diagonal block as loaded, then updated
+    double Lp[LA_NB][LA_NB + 1];    // Lp[i][q] = F[p0 + i][p0 - 32 + q]: previous panel's L rows
+    double UpT[LA_NB][LA_NB + 1];   // UpT[j][q] = F[p0 - 32 + q][p0 + j]: its U columns
+  } a;
+  GemmLds<0, TILE> g;
+};
+
+template <int TILE>
+__global__ void __launch_bounds__(256)
+k_panel_lookahead(const PanelRec *__restrict__ recs, int nrec, int cmax,
+                  const GemmTask *__restrict__ tiles, double *__restrict__ store,
+                  int *__restrict__ status, int *__restrict__ arrive) {
+  constexpr int NB = LA_NB;
+  __shared__ LookaheadLds<TILE> sm;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t na = (int64_t)nrec * cmax;
+  if ((int64_t)blockIdx.x >= na) {                       // B: a tile of the previous update
+    gemm_tile<0, TILE>(tiles[blockIdx.x - na], store, sm.g);
+    return;
+  }
+  const int fi = (int)(blockIdx.x / cmax), chunk = (int)(blockIdx.x - (int64_t)fi * cmax);
+  const PanelRec d = recs[fi];
+  const int m = d.m, p0 = d.p0, pb = min(NB, d.k - p0), pe = p0 + pb;
+  const int nact = lookahead_chunks(m, pe);
+  if (chunk >= nact) return;                             // idle chunk of a narrower front
+  const bool prev = p0 > 0;                              // every panel but the last is NB wide
+  const int rest = m - pe, rpad = (rest + 63) & ~63;
+  double *F = store + d.store;
+  // this thread's item: a U12 column (entries F[p0 + q][j], stride m) or an L21 row (entries
+  // F[i][p0 + q], stride 1), at 32-bit element offset io from the front's (uniform) base
+  const int item = chunk * LA_ITEMS + tid - 64;
+  const bool colitem = wv > 0 && item < rest;
+  const bool has = colitem || (wv > 0 && item >= rpad && item < rpad + rest);
+  const int st = colitem ? m : 1;
+  const uint32_t io = colitem ? p0 * m + pe + item : (pe + item - rpad) * m + p0;
+  double v[NB];
+  // the diagonal block and the previous panel's blocks of this panel, staged in LDS by waves
+  // 1-3, every load issued before the first store (rows and columns beyond pb clamped: finite
+  // values that the identity padding of the factored block keeps out of the results)
+  if (wv > 0) {
+    constexpr int U = (NB * NB + LA_ITEMS - 1) / LA_ITEMS;
+    double a0[U], a1[U], a2[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = tid - 64 + LA_ITEMS * u;
+      const int i = t >> 5, j = t & (NB - 1), ic = min(i, pb - 1), jc = min(j, pb - 1);
+      if (t < NB * NB) {
+        a0[u] = F[(p0 + ic) * m + p0 + jc];
+        if (prev) {
+          a1[u] = F[(p0 + ic) * m + p0 - NB + j];
+          a2[u] = F[(p0 - NB + i) * m + p0 + jc];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = tid - 64 + LA_ITEMS * u;
+      const int i = t >> 5, j = t & (NB - 1);
+      if (t < NB * NB) {
+        sm.a.Dg[i][j] = a0[u];
+        if (prev) {
+          sm.a.Lp[i][j] = a1[u];
+          sm.a.UpT[j][i] = a2[u];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // every workgroup of the front has its copy of the diagonal block once it is past the barrier
+  // above: count it (relaxed, as in k_panel_trsm); the last one stores the factored block
+  int arrived = 0;
+  if (nact > 1 && tid == 0)
+    arrived = __hip_atomic_fetch_add(arrive + d.f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (prev) {
+    // the previous panel's update of the diagonal block first (the factorization waits for it),
+    // one 16 x 16 block per wave on MFMA: A operand lane l = -Lp[row l%16][q], B operand lane l
+    // = U[q][col l%16], q = 4 s + l/16; result lane l register r at row 4r + l/16, column l%16
+    const int li = lane & 15, lk = lane >> 4, bi = wv >> 1, bj = wv & 1;
+    v4d acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = sm.a.Dg[16 * bi + 4 * r + lk][16 * bj + li];
+#pragma unroll
+    for (int q = 0; q < NB / 4; ++q)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-sm.a.Lp[16 * bi + li][4 * q + lk],
+                                                 sm.a.UpT[16 * bj + li][4 * q + lk], acc, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sm.a.Dg[16 * bi + 4 * r + lk][16 * bj + li] = acc[r];
+    __syncthreads();
+  }
+  if (wv == 0) {
+    wave_diag_lu<NB>(&sm.a.Dg[0][0], NB + 1, pb, sm.a.D, sm.a.rd, lane, d.f, p0, status, false);
+  } else if (has) {
+    // while wave 0 factors the block: this item's entries in this panel (v) and in the
+    // previous one (w) -- loaded here, after the barriers, which wait for every outstanding
+    // load -- and the previous panel's update of them, v[q] -= sum_r Lp[q][r] w[r] for a
+    // column, v[q] -= sum_r w[r] U[r][q] for a row
+    double w[NB];
+    if (colitem) {
+#pragma unroll
+      for (int q = 0; q < NB; ++q) v[q] = F[io + (uint32_t)(min(q, pb - 1) * m)];
+      if (prev) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) w[q] = F[io + (uint32_t)((q - NB) * m)];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NB; ++q) v[q] = F[io + (uint32_t)min(q, pb - 1)];
+      if (prev) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) w[q] = F[io + (uint32_t)(q - NB)];
+      }
+    }
+    if (prev && colitem) {
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        double s0 = v[q], s1 = 0.0;
+#pragma unroll
+        for (int r = 0; r < NB; r += 2) {
+          s0 -= sm.a.Lp[q][r] * w[r];
+          s1 -= sm.a.Lp[q][r + 1] * w[r + 1];
+        }
+        v[q] = s0 + s1;
+      }
+    } else if (prev) {
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        double s0 = v[q], s1 = 0.0;
+#pragma unroll
+        for (int r = 0; r < NB; r += 2) {
+          s0 -= sm.a.UpT[q][r] * w[r];
+          s1 -= sm.a.UpT[q][r + 1] * w[r + 1];
+        }
+        v[q] = s0 + s1;
+      }
+    }
+  }
+  __syncthreads();
+  if (has) {
+    // substitution against the factored block: a column solves L11 u = v (pivots on the
+    // diagonal: v[q] = (v[q] - sum_{r<q} D[q][r] v[r]) / D[q][q]), a row solves l U11 = v (unit
+    // diagonal: v[q] -= sum_{r<q} v[r] D[r][q]); each step reads its entries of D into
+    // registers first, the reads issued together
+    double dr[NB];
+    if (colitem) {
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+#pragma unroll
+        for (int r = 0; r < q; ++r) dr[r] = sm.a.D[q][r];
+        const double rq = sm.a.rd[q];
+        __builtin_amdgcn_sched_barrier(0);
+        double s0 = v[q], s1 = 0.0;
+#pragma unroll
+        for (int r = 0; r + 1 < q; r += 2) {
+          s0 -= dr[r] * v[r];
+          s1 -= dr[r + 1] * v[r + 1];
+        }
+        if (q & 1) s0 -= dr[q - 1] * v[q - 1];
+        v[q] = (s0 + s1) * rq;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+#pragma unroll
+        for (int r = 0; r < q; ++r) dr[r] = sm.a.D[r][q];
+        __builtin_amdgcn_sched_barrier(0);
+        double s0 = v[q], s1 = 0.0;
+#pragma unroll
+        for (int r = 0; r + 1 < q; r += 2) {
+          s0 -= dr[r] * v[r];
+          s1 -= dr[r + 1] * v[r + 1];
+        }
+        if (q & 1) s0 -= dr[q - 1] * v[q - 1];
+        v[q] = s0 + s1;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+      if (q < pb) F[io + (uint32_t)(q * st)] = v[q];
+  } else if (wv == 0) {
+    // the factored diagonal block: by the only workgroup of the front, or by the one that
+    // arrived last (every other one has staged the block by now)
+    const int last = __builtin_amdgcn_readlane(arrived, 0) == nact - 1;
+    if (nact == 1 || last) {
+      store_diag_block<NB>(d, store, sm.a.D, lane);
+      if (nact > 1 && lane == 0)
+        __hip_atomic_store(arrive + d.f, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
 }
 
 }  // namespace mf

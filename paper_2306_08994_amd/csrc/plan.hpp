@@ -84,6 +84,10 @@ struct PanelStep {
   std::vector<int32_t> fronts;     // fronts that still have pivots at this step
   std::vector<int32_t> p0;         // first pivot of the panel per front
   std::vector<GemmTask> update;    // trailing update restricted to the fully-summed region
+  // look-ahead form (panel width 32): the previous panel's trailing update beyond this panel,
+  // run by the same launch as this panel (which applies the previous panel's update to its own
+  // rows and columns itself); `update` is then empty
+  std::vector<GemmTask> prev_update;
   int64_t trsm_items = 0;          // max over fronts of the panel kernel's items (columns, rows)
 };
 
@@ -97,6 +101,7 @@ struct LevelSchedule {
   std::vector<int32_t> fused;      // large fronts whose panels run in one workgroup
   int32_t fused_max_m = 0;
   std::vector<PanelStep> steps;    // panel steps of the large fronts that are not fused
+  bool lookahead = false;          // steps in the look-ahead form (see PanelStep)
   std::vector<GemmTask> schur;     // C22 -= L21 U12 tiles of the large fronts
   std::vector<int32_t> all;        // every front of the class that the solve visits
   int32_t max_m = 0, max_k = 0;
@@ -134,7 +139,8 @@ std::string analyse(int32_t n_mesh, const int32_t *dims, const int32_t *npes,
                     const int64_t *n_nodes, const int64_t *n_elem,
                     const int32_t *const *conns, const int32_t *const *ijks, HostPlan &out);
 
-// (Re)builds the per-class schedule for the given tuning.
-void build_schedule(HostPlan &p, const Tuning &t);
+// (Re)builds the per-class schedule: class l routes and blocks its fronts by t[l] (t holds one
+// entry per class, height + 1).
+void build_schedule(HostPlan &p, const std::vector<Tuning> &t);
 
 }  // namespace mf

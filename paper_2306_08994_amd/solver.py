@@ -114,6 +114,19 @@ class Plan:
         check(_lib.load().mf_set_tuning(self._h, int(small_max_m), int(nb), int(fused_max_m),
                                         int(tile), int(persistent)))
 
+    def set_class_tuning(self, classes):
+        """Per-class schedule (see mf_set_class_tuning): one dict per Foata class with keys
+        small_max_m, nb, fused_max_m, tile, persistent (e.g. autotune()["chosen"]["classes"]);
+        an empty list drops it."""
+        self.factor_version += 1
+        if not classes:
+            check(_lib.load().mf_set_class_tuning(self._h, 0, None))
+            return
+        keys = ("small_max_m", "nb", "fused_max_m", "tile", "persistent")
+        arr = np.ascontiguousarray([[int(c[k]) for k in keys] for c in classes], dtype=np.int32)
+        check(_lib.load().mf_set_class_tuning(self._h, len(classes),
+                                              ctypes.c_void_p(arr.ctypes.data)))
+
     def autotune(self, K, precision: str = "fp64", reps: int = 3) -> dict:
         """Times the relevant schedule candidates on K, keeps the fastest (see mf_autotune)."""
         import json

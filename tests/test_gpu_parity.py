@@ -301,10 +301,50 @@ def test_autotune_keeps_a_correct_schedule():
     plan, K, b = _setup(p)
     rep = plan.autotune(K, reps=1)
     assert len(rep["candidates"]) >= 2 and "chosen" in rep
+    ncls = int(plan.info["height"]) + 1
+    assert all(len(c["class_ms"]) == ncls for c in rep["candidates"])
+    assert rep["chosen"]["mode"] in ("per_class", "global") and len(rep["chosen"]["classes"]) == ncls
     Ls, Us = plan.export_factors()              # autotune leaves the plan factored
     assert G.factor_violation(Ls, Us, fac) <= G.TOL_FACTOR
     x = plan.solve(b).cpu().numpy()
     assert G.rel_err(x, G.oracle_solve(tree, fac, p.b)) <= G.TOL_SOLVE
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_per_class_schedule(prec):
+    """Every class on a schedule of its own: LDS limits, panel widths, fused route, GEMM tiles
+    and the persistent launch alternate from class to class.  FP64 entry by entry against the
+    oracle; FP32-Schur refined to the oracle's solution."""
+    from paper_2306_08994_amd import MFError
+    p = _rd((12, 12, 12), seed=2)
+    tree, conn, fac = G.oracle_factor(p)
+    plan, K, b = _setup(p)
+    ncls = int(plan.info["height"]) + 1
+    menu = [dict(small_max_m=40, nb=16, fused_max_m=0, tile=32, persistent=0),
+            dict(small_max_m=128, nb=64, fused_max_m=0, tile=64, persistent=0),
+            dict(small_max_m=24, nb=32, fused_max_m=0, tile=64, persistent=1),
+            dict(small_max_m=64, nb=32, fused_max_m=576, tile=32, persistent=0)]
+    classes = [menu[l % len(menu)] for l in range(ncls)]
+    plan.set_class_tuning(classes)
+    ms = np.diff(tree.front_ptr)
+    assert ms.max() > 128
+    if prec == "fp32":
+        plan.factor(K, "fp32")
+        x, its, rr = plan.refine(K, b, tol=1e-12, max_it=20)
+        assert rr <= 1e-12
+        assert G.rel_err(x.cpu().numpy(), G.oracle_solve(tree, fac, p.b)) <= 1e-9
+    else:
+        plan.factor(K)
+        Ls, Us = plan.export_factors()
+        assert G.factor_violation(Ls, Us, fac) <= G.TOL_FACTOR
+        x = plan.solve(b).cpu().numpy()
+        assert G.rel_err(x, G.oracle_solve(tree, fac, p.b)) <= G.TOL_SOLVE
+    with pytest.raises(MFError):
+        plan.set_class_tuning(classes[:-1])      # one class short
+    plan.set_class_tuning([])                    # back to one schedule for every class
+    plan.factor(K)
+    Ls, Us = plan.export_factors()
+    assert G.factor_violation(Ls, Us, fac) <= G.TOL_FACTOR
 
 
 # Quadratic and cubic elements: larger leaves that eliminate interior unknowns, fronts built
