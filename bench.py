@@ -67,6 +67,7 @@ KIND_SOURCE = {
     "gemm_schur": "factor_kernels.hpp", "solve_down_wave": "solve_kernels.hpp",
     "solve_down_block": "solve_kernels.hpp", "solve_up_wave": "solve_kernels.hpp",
     "solve_up_block": "solve_kernels.hpp", "diag_block_inverse": "solve_kernels.hpp",
+    "panel_lookahead": "factor_kernels.hpp", "class_tiled": "class_kernels.hpp",
 }
 TRAFFIC_TAG = re.compile(r"<!-- traffic kind=(\S+) source=(\S+) sha256=([0-9a-f]{64}) "
                          r"bytes_per_launch=([0-9.eE+]+) -->")
@@ -646,7 +647,7 @@ def main():
     plan.profile(False)
     top, roof = roofline_of(rep)
     factor_kinds = {"factor_tiny", "factor_small", "assemble", "front_panels", "panel_lu_trsm",
-                    "gemm_panel", "gemm_schur", "class_tiled"}
+                    "gemm_panel", "gemm_schur", "class_tiled", "panel_lookahead"}
     launches = {"factor": sum(k["launches"] for k in rep["kernels"] if k["name"] in factor_kinds),
                 "solve_and_inverses": sum(k["launches"] for k in rep["kernels"]
                                           if k["name"] not in factor_kinds)}

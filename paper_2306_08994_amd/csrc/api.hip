@@ -160,6 +160,79 @@ void level_costs(const mf::HostPlan &H, const mf::LevelSchedule &S, LevelDev &D,
 }
 
 
+// Appends the tiles of one GEMM launch in an order that keeps tiles sharing operands on one
+// XCD.  Workgroups are dispatched to the 8 XCDs round robin (workgroup b on XCD b mod 8), each
+// XCD with its own L2: a front's tile grid is cut into 8 blocks of tile rows x tile columns (2 x
+// 4, 4 x 2, 1 x 8 or 8 x 1, the closest to square), one per XCD, so each XCD reads a half or a
+// quarter of the front's L21 rows and U12 columns instead of all of them; a front of fewer than
+// 32 tiles goes whole to the least loaded XCD.  Slot t of the launch (workgroup first + t) gets
+// a tile of XCD (first + t) mod 8 while that XCD has tiles left.  Tiles of a launch are
+// independent, so the order changes only where they run.
+void append_xcd_ordered(std::vector<mf::GemmTask> &out, const std::vector<mf::GemmTask> &ts,
+                        int64_t first) {
+  constexpr int X = 8;
+  if (ts.size() < 2 * X) {
+    out.insert(out.end(), ts.begin(), ts.end());
+    return;
+  }
+  std::vector<std::vector<size_t>> q(X);
+  std::vector<int64_t> load(X, 0);
+  size_t i = 0;
+  while (i < ts.size()) {
+    size_t j = i;
+    while (j < ts.size() && ts[j].front == ts[i].front && ts[j].q0 == ts[i].q0) ++j;
+    const size_t n = j - i;
+    if (n < 32) {
+      const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      for (size_t t = i; t < j; ++t) q[x].push_back(t);
+      load[x] += (int64_t)n;
+    } else {
+      std::vector<int32_t> rows, cols;
+      for (size_t t = i; t < j; ++t) {
+        rows.push_back(ts[t].i0);
+        cols.push_back(ts[t].j0);
+      }
+      std::sort(rows.begin(), rows.end());
+      rows.erase(std::unique(rows.begin(), rows.end()), rows.end());
+      std::sort(cols.begin(), cols.end());
+      cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+      // pa x pb = 8 blocks, pa (tile-row groups) chosen closest to square blocks
+      int pa = 1;
+      double best = 1e30;
+      for (int a : {1, 2, 4, 8}) {
+        const double r = ((double)rows.size() / a) / ((double)cols.size() / (X / a));
+        const double dev = std::fabs(std::log(r));
+        if (dev < best) {
+          best = dev;
+          pa = a;
+        }
+      }
+      const int pb = X / pa;
+      for (size_t t = i; t < j; ++t) {
+        const int64_t ri = std::lower_bound(rows.begin(), rows.end(), ts[t].i0) - rows.begin();
+        const int64_t ci = std::lower_bound(cols.begin(), cols.end(), ts[t].j0) - cols.begin();
+        const int x = (int)(ri * pa / (int64_t)rows.size()) * pb + (int)(ci * pb / (int64_t)cols.size());
+        q[x].push_back(t);
+        ++load[x];
+      }
+    }
+    i = j;
+  }
+  std::vector<size_t> head(X, 0);
+  for (size_t t = 0; t < ts.size(); ++t) {
+    int x = (int)((first + (int64_t)t) % X);
+    if (head[x] == q[x].size()) {   // this XCD's tiles are used up: take from the fullest one
+      size_t most = 0;
+      for (int y = 0; y < X; ++y)
+        if (q[y].size() - head[y] > most) {
+          most = q[y].size() - head[y];
+          x = y;
+        }
+    }
+    out.push_back(ts[q[x][head[x]++]]);
+  }
+}
+
 }  // namespace
 
 // Classes with fewer rectangular-part slabs of 64 rows than this use slabs of 16 (quarter form).
@@ -241,24 +314,25 @@ int ensure_uploaded(mf_plan *P) {
         r.f = st.fronts[i];
         panel.push_back(r);
       }
-      sd.update = (int64_t)tasks.size();
-      sd.n_update = (int64_t)st.update.size();
-      tasks.insert(tasks.end(), st.update.begin(), st.update.end());
-      sd.prev_update = (int64_t)tasks.size();
-      sd.n_prev_update = (int64_t)st.prev_update.size();
-      tasks.insert(tasks.end(), st.prev_update.begin(), st.prev_update.end());
       for (size_t i = 0; i < st.fronts.size(); ++i) {
         const mf::FrontDesc &d = H.desc[st.fronts[i]];
         sd.la_chunks = std::max(sd.la_chunks,
                                 mf::lookahead_chunks(d.m, std::min(st.p0[i] + mf::LA_NB, d.k)));
       }
+      sd.update = (int64_t)tasks.size();
+      sd.n_update = (int64_t)st.update.size();
+      append_xcd_ordered(tasks, st.update, 0);
+      sd.prev_update = (int64_t)tasks.size();
+      sd.n_prev_update = (int64_t)st.prev_update.size();
+      // the update tiles follow the panel's workgroups in the same launch
+      append_xcd_ordered(tasks, st.prev_update, sd.n * (int64_t)sd.la_chunks);
       sd.trsm_items = st.trsm_items;
       D.steps.push_back(sd);
     }
     D.lookahead = S.lookahead;
     D.schur = (int64_t)tasks.size();
     D.n_schur = (int64_t)S.schur.size();
-    tasks.insert(tasks.end(), S.schur.begin(), S.schur.end());
+    append_xcd_ordered(tasks, S.schur, 0);
     level_costs(H, S, D, P->eff[l].persistent ? mf::kClassNB : P->eff[l].nb);
   }
   // wave records follow the class lists, class after class
