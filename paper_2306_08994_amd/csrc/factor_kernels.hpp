@@ -335,8 +335,9 @@ struct GemmCfg<2> { typedef __bf16 T; static constexpr int KT = 32; };
 template <int PREC, int TILE>
 struct GemmLds {
   typedef typename GemmCfg<PREC>::T T;
-  // inner-dimension slab: 32 at TILE 32 (a panel update is one slab), else the type's depth
-  static constexpr int KT = TILE == 32 ? 32 : GemmCfg<PREC>::KT;
+  // inner-dimension slab: 32 (a panel update is one slab; a 64 x 64 tile does 32 MFMA k-steps
+  // per wave between two barriers)
+  static constexpr int KT = 32;
   static constexpr int APAD = (PREC == 2) ? 8 : 1;
   T As[TILE][KT + APAD];
   T Bs[TILE][KT + APAD];        // stored transposed: Bs[col][k]
@@ -422,27 +423,32 @@ __device__ __forceinline__ void gemm_tile(const GemmTask &tk, double *__restrict
         for (int b = 0; b < QB; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
     } else {
-      // every operand of the slab read from LDS first (reads issued together), then the MFMAs
-      T av[KT / 4][QB], bv[KT / 4][QB];
+      // the operands of S k-steps read from LDS first (reads issued together), then their
+      // MFMAs; S bounds the registers the staged operands take (16 / (QB * QB) k-steps)
+      constexpr int S = (QB == 1) ? KT / 4 : 4;
 #pragma unroll
-      for (int s = 0; s < KT / 4; ++s) {
+      for (int s0 = 0; s0 < KT / 4; s0 += S) {
+        T av[S][QB], bv[S][QB];
 #pragma unroll
-        for (int a = 0; a < QB; ++a) av[s][a] = As[HALF * wr + 16 * a + li][4 * s + lk];
+        for (int s = 0; s < S; ++s) {
 #pragma unroll
-        for (int b = 0; b < QB; ++b) bv[s][b] = Bs[HALF * wc + 16 * b + li][4 * s + lk];
+          for (int a = 0; a < QB; ++a) av[s][a] = As[HALF * wr + 16 * a + li][4 * (s0 + s) + lk];
+#pragma unroll
+          for (int b = 0; b < QB; ++b) bv[s][b] = Bs[HALF * wc + 16 * b + li][4 * (s0 + s) + lk];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+          for (int a = 0; a < QB; ++a)
+#pragma unroll
+            for (int b = 0; b < QB; ++b) {
+              if constexpr (PREC == 0)
+                acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s][a], bv[s][b], acc[a][b], 0, 0, 0);
+              else
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s][a], bv[s][b], acc[a][b], 0, 0, 0);
+            }
       }
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int s = 0; s < KT / 4; ++s)
-#pragma unroll
-        for (int a = 0; a < QB; ++a)
-#pragma unroll
-          for (int b = 0; b < QB; ++b) {
-            if constexpr (PREC == 0)
-              acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s][a], bv[s][b], acc[a][b], 0, 0, 0);
-            else
-              acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s][a], bv[s][b], acc[a][b], 0, 0, 0);
-          }
     }
     __syncthreads();
   }
