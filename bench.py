@@ -365,6 +365,15 @@ def variant_mixed(steps, warmup, precs=("fp64", "fp32", "bf16"), tuning=None, or
                      "gflops": flops / wall / 1e9, "refine_corrections": its, "relres": rr,
                      "err_vs_oracle": None if xo is None else err_vs(xs, xo),
                      "err_vs_fp64": err, "roofline_schur": schur_roofline(plan, step, prec)}
+        if prec != "fp64":
+            # the same factorization refined by GMRES (FP64, preconditioned by the factors)
+            def step_gmres():
+                plan.factor(K, prec)
+                return plan.refine_gmres(K, b, tol=1e-12, max_it=60, restart=20, x=x)
+            gw, _, (xg, gits, grr) = time_steps(step_gmres, steps, warmup)
+            out[prec]["gmres"] = {"ms_per_system": gw * 1e3, "gflops": flops / gw / 1e9,
+                                  "arnoldi_steps": gits, "relres": grr,
+                                  "err_vs_oracle": None if xo is None else err_vs(xg, xo)}
     if oleg is not None:
         out["cpu_oracle"] = oleg
     if "fp64" in out:

@@ -215,6 +215,22 @@ int mf_refine(mf_plan *plan, const double *elem_mats, const double *b, double *x
               int32_t nrhs, double tol, int32_t max_it, int32_t *its, double *relres,
               void *hip_stream);
 
+/* Refinement by GMRES in FP64, preconditioned by the stored factors (GMRES-IR): x = solve(b);
+ * then restarted cycles of right-preconditioned GMRES on A x = b (one Krylov basis of at most
+ * `restart` vectors per right-hand side, classical Gram-Schmidt applied twice, Givens
+ * rotations on the host), each Arnoldi step one solve with the stored factors and one
+ * element-by-element FP64 product with A; every cycle ends with the true FP64 residual, and the
+ * iteration stops once max_r ||b_r - A x_r||_2 / ||b_r||_2 <= tol.  For factors whose Schur
+ * updates ran in BF16 or FP32 (mf_factor with MF_SCHUR_BF16 / MF_SCHUR_FP32), where plain
+ * refinement (mf_refine) converges slowly.  max_it bounds the Arnoldi steps; its (host, may be
+ * NULL) receives the steps taken, relres (host, may be NULL) the final relative residual.
+ * elem_mats, b, x as in mf_refine (b and x must not alias).  Synchronizes hip_stream several
+ * times per step.  Errors: MF_ENOCONV (x holds the last iterate), MF_ESTATE, MF_EINVAL
+ * (restart outside 1..64), MF_ENOMEM, MF_EHIP. */
+int mf_refine_gmres(mf_plan *plan, const double *elem_mats, const double *b, double *x,
+                    int32_t nrhs, double tol, int32_t max_it, int32_t restart, int32_t *its,
+                    double *relres, void *hip_stream);
+
 /* mf_factor followed by mf_refine in one call, with the forward substitution of the first
  * solve overlapped with the factorization: class l of the forward sweep depends only on classes
  * <= l of the factorization (the elimination tree orders it, Sec. 2.4 / Sec. 3.3), so it runs

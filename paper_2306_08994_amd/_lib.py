@@ -18,7 +18,7 @@ EXPORTED = ["mf_analyse", "mf_plan_info", "mf_plan_export_tree", "mf_task_trace"
             "mf_set_class_tuning",
             "mf_autotune",
             "mf_factor", "mf_solve", "mf_solve_noalloc",
-            "mf_residual", "mf_refine", "mf_factor_refine", "mf_elem_grad", "mf_export_factors", "mf_profile",
+            "mf_residual", "mf_refine", "mf_refine_gmres", "mf_factor_refine", "mf_elem_grad", "mf_export_factors", "mf_profile",
             "mf_profile_report", "mf_destroy", "mf_last_error"]
 
 
@@ -75,6 +75,8 @@ def load():
         "mf_residual": (c_int32, [P, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
         "mf_refine": (c_int32, [P, c_void_p, c_void_p, c_void_p, c_int32, c_double, c_int32,
                                 POINTER(c_int32), dp, c_void_p]),
+        "mf_refine_gmres": (c_int32, [P, c_void_p, c_void_p, c_void_p, c_int32, c_double, c_int32,
+                                      c_int32, POINTER(c_int32), dp, c_void_p]),
         "mf_factor_refine": (c_int32, [P, c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_double,
                                        c_int32, POINTER(c_int32), dp, c_void_p]),
         "mf_elem_grad": (c_int32, [P, c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),

@@ -1448,6 +1448,178 @@ int mf_refine(mf_plan *P, const double *elem_mats, const double *b, double *x,
   return refine_loop(P, elem_mats, b, x, nrhs, tol, max_it, its, relres, hip_stream);
 }
 
+int mf_refine_gmres(mf_plan *P, const double *elem_mats, const double *b, double *x,
+                    int32_t nrhs, double tol, int32_t max_it, int32_t restart, int32_t *its,
+                    double *relres, void *hip_stream) {
+  if (!P || !elem_mats || !b || !x) return fail(MF_EINVAL, "null argument");
+  if (nrhs < 1 || max_it < 0 || !(tol >= 0)) return fail(MF_EINVAL, "bad nrhs, max_it or tol");
+  if (restart < 1 || restart > 64) return fail(MF_EINVAL, "restart must be in 1..64");
+  if (!P->factored) return fail(MF_ESTATE, "no valid factorization: call mf_factor first");
+  hipStream_t s = (hipStream_t)hip_stream;
+  const mf::HostPlan &H = P->hp;
+  const int64_t n = H.n;
+  const int m = restart;
+  const size_t nn = (size_t)n * nrhs;
+  const NormLayout NL = norm_layout(n, nrhs);
+  const int64_t dblocks = std::max<int64_t>(1, (n + kNormRows - 1) / kNormRows);
+  const size_t ndots = (size_t)dblocks * (m + 1) * nrhs;
+  const size_t total = (size_t)(2 * m + 3) * nn + ndots + NL.r_parts + NL.b_parts + (size_t)(m + 1) * nrhs;
+  int rc;
+  if ((rc = grow(P, P->d_kry, P->kry_cap, total))) return rc;
+  if ((rc = grow(P, P->d_ycb, P->ycb_cap, (size_t)std::max<int64_t>(1, H.sum_c) * nrhs))) return rc;
+  const size_t hneed = std::max(ndots, (size_t)(m + 1) * nrhs) + (size_t)(m + 1) * nrhs;
+  if (P->hkry_cap < hneed) {
+    if (P->h_kry) (void)hipHostFree(P->h_kry);
+    P->h_kry = nullptr;
+    P->hkry_cap = 0;
+    HIPCHK(hipHostMalloc((void **)&P->h_kry, hneed * sizeof(double), hipHostMallocDefault));
+    P->hkry_cap = hneed;
+  }
+  double *V = P->d_kry;                       // m + 1 basis blocks
+  double *Z = V + (size_t)(m + 1) * nn;       // m preconditioned basis blocks
+  double *t = Z + (size_t)m * nn;             // -A z
+  double *zero = t + nn;
+  double *dpart = zero + nn;
+  double *rpart = dpart + ndots, *bpart = rpart + NL.r_parts;
+  double *coef = bpart + NL.b_parts;
+  double *h_dots = P->h_kry, *h_coef = P->h_kry + std::max(ndots, (size_t)(m + 1) * nrhs);
+  HIPCHK(hipMemsetAsync(zero, 0, nn * sizeof(double), s));
+  const unsigned gblocks = (unsigned)((nn + 255) / 256);
+  auto upload = [&](size_t count) -> int {
+    HIPCHK(hipMemcpyAsync(coef, h_coef, count * sizeof(double), hipMemcpyHostToDevice, s));
+    return MF_OK;
+  };
+  // sums of the partial column dots of t with V_0 .. V_{nv-1}: d[i * nrhs + c]
+  auto dots = [&](int nv, std::vector<double> &d) -> int {
+    hipLaunchKernelGGL(mf::k_coldots_partial, dim3((unsigned)dblocks, (unsigned)nv), dim3(256), 0, s,
+                       V, (int64_t)nn, t, n, nrhs, kNormRows, dpart);
+    HIPCHK(hipGetLastError());
+    const size_t cnt = (size_t)dblocks * nv * nrhs;
+    HIPCHK(hipMemcpyAsync(h_dots, dpart, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    d.assign((size_t)nv * nrhs, 0.0);
+    for (int64_t bl = 0; bl < dblocks; ++bl)
+      for (size_t q = 0; q < (size_t)nv * nrhs; ++q) d[q] += h_dots[bl * nv * nrhs + q];
+    return MF_OK;
+  };
+  // x0 = M^-1 b with the stored (possibly narrow-Schur) factors
+  if ((rc = launch_solve(P, b, x, nrhs, false, s, P->d_ycb))) return rc;
+  std::vector<double> bn, rn, d, Hm, cs, sn, g, y;
+  double rr = INFINITY;
+  int32_t done_its = 0;
+  for (int outer = 0;; ++outer) {
+    // the true FP64 residual r = b - A x, into V_0, and its column norms
+    hipLaunchKernelGGL(mf::k_residual, dim3(gblocks), dim3(256), 0, s, P->d_nptr, P->d_nelem,
+                       P->d_conn, elem_mats, H.npe, n, x, b, V, nrhs,
+                       NL.fused ? rpart : (double *)nullptr);
+    if (!NL.fused)
+      hipLaunchKernelGGL(mf::k_colsq_partial, dim3((unsigned)NL.r_blocks), dim3(256), 0, s, V, n,
+                         nrhs, kNormRows, rpart);
+    if (outer == 0)
+      hipLaunchKernelGGL(mf::k_colsq_partial, dim3((unsigned)NL.b_blocks), dim3(256), 0, s, b, n,
+                         nrhs, kNormRows, bpart);
+    HIPCHK(hipGetLastError());
+    if ((rc = read_norms(P, NL, rpart, nrhs, s, outer == 0, rn, bn))) return rc;
+    rr = 0.0;
+    for (int c = 0; c < nrhs; ++c) {
+      const double q = bn[c] > 0 ? rn[c] / bn[c] : (rn[c] > 0 ? INFINITY : 0.0);
+      rr = std::max(rr, std::isnan(q) ? INFINITY : q);
+    }
+    if (its) *its = done_its;
+    if (relres) *relres = rr;
+    if (rr <= tol) return MF_OK;
+    if (done_its >= max_it || !std::isfinite(rr)) break;
+    // V_0 = r / ||r|| per column; Givens-rotated Hessenberg H (column-major per column c)
+    for (int c = 0; c < nrhs; ++c) h_coef[c] = rn[c] > 0 ? 1.0 / rn[c] : 0.0;
+    if ((rc = upload((size_t)nrhs))) return rc;
+    hipLaunchKernelGGL(mf::k_scale_cols, dim3(gblocks), dim3(256), 0, s, V, V, coef, n, nrhs);
+    Hm.assign((size_t)(m + 1) * m * nrhs, 0.0);
+    cs.assign((size_t)m * nrhs, 1.0);
+    sn.assign((size_t)m * nrhs, 0.0);
+    g.assign((size_t)(m + 1) * nrhs, 0.0);
+    for (int c = 0; c < nrhs; ++c) g[c] = rn[c];
+    auto h = [&](int i, int j, int c) -> double & { return Hm[((size_t)j * (m + 1) + i) * nrhs + c]; };
+    int j = 0;
+    while (j < m && done_its < max_it) {
+      double *Vj = V + (size_t)j * nn, *Zj = Z + (size_t)j * nn;
+      if ((rc = launch_solve(P, Vj, Zj, nrhs, false, s, P->d_ycb))) return rc;
+      hipLaunchKernelGGL(mf::k_residual, dim3(gblocks), dim3(256), 0, s, P->d_nptr, P->d_nelem,
+                         P->d_conn, elem_mats, H.npe, n, Zj, zero, t, nrhs, (double *)nullptr);
+      HIPCHK(hipGetLastError());
+      // w = A z_j = -t, orthogonalised against V_0 .. V_j by classical Gram-Schmidt, twice
+      for (int pass = 0; pass < 2; ++pass) {
+        if ((rc = dots(j + 1, d))) return rc;       // d_i = <t, V_i> = -<w, V_i>
+        for (int i = 0; i <= j; ++i)
+          for (int c = 0; c < nrhs; ++c) {
+            h(i, j, c) -= d[(size_t)i * nrhs + c];
+            h_coef[(size_t)i * nrhs + c] = -d[(size_t)i * nrhs + c];
+          }
+        if ((rc = upload((size_t)(j + 1) * nrhs))) return rc;
+        hipLaunchKernelGGL(mf::k_combine, dim3(gblocks), dim3(256), 0, s, t, V, (int64_t)nn, j + 1,
+                           coef, n, nrhs);
+      }
+      hipLaunchKernelGGL(mf::k_colsq_partial, dim3((unsigned)NL.b_blocks), dim3(256), 0, s, t, n,
+                         nrhs, kNormRows, dpart);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(h_dots, dpart, (size_t)NL.b_blocks * nrhs * sizeof(double),
+                            hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      std::vector<double> wn(nrhs, 0.0);
+      for (int64_t bl = 0; bl < NL.b_blocks; ++bl)
+        for (int c = 0; c < nrhs; ++c) wn[c] += h_dots[bl * nrhs + c];
+      double est = 0.0;
+      for (int c = 0; c < nrhs; ++c) {
+        wn[c] = std::sqrt(wn[c]);
+        h(j + 1, j, c) = wn[c];
+        h_coef[c] = wn[c] > 0 ? -1.0 / wn[c] : 0.0;       // V_{j+1} = w / ||w|| = -t / ||t||
+        // the column's earlier rotations, then a new one that zeroes h(j+1, j)
+        for (int i = 0; i < j; ++i) {
+          const double a = h(i, j, c), bb = h(i + 1, j, c);
+          const double ci = cs[(size_t)i * nrhs + c], si = sn[(size_t)i * nrhs + c];
+          h(i, j, c) = ci * a + si * bb;
+          h(i + 1, j, c) = -si * a + ci * bb;
+        }
+        const double a = h(j, j, c), bb = h(j + 1, j, c), r = std::hypot(a, bb);
+        const double cj = r > 0 ? a / r : 1.0, sj = r > 0 ? bb / r : 0.0;
+        cs[(size_t)j * nrhs + c] = cj;
+        sn[(size_t)j * nrhs + c] = sj;
+        h(j, j, c) = r;
+        h(j + 1, j, c) = 0.0;
+        const double gj = g[(size_t)j * nrhs + c];
+        g[(size_t)j * nrhs + c] = cj * gj;
+        g[(size_t)(j + 1) * nrhs + c] = -sj * gj;
+        const double q = bn[c] > 0 ? std::fabs(g[(size_t)(j + 1) * nrhs + c]) / bn[c] : 0.0;
+        est = std::max(est, q);
+      }
+      if ((rc = upload((size_t)nrhs))) return rc;
+      hipLaunchKernelGGL(mf::k_scale_cols, dim3(gblocks), dim3(256), 0, s, V + (size_t)(j + 1) * nn,
+                         t, coef, n, nrhs);
+      HIPCHK(hipGetLastError());
+      ++j;
+      ++done_its;
+      if (est <= 0.5 * tol) break;                       // the least-squares residual suffices
+    }
+    // y = R^-1 g per column (back substitution), then x += Z y
+    y.assign((size_t)j * nrhs, 0.0);
+    for (int c = 0; c < nrhs; ++c)
+      for (int i = j - 1; i >= 0; --i) {
+        double v = g[(size_t)i * nrhs + c];
+        for (int k = i + 1; k < j; ++k) v -= h(i, k, c) * y[(size_t)k * nrhs + c];
+        const double dg = h(i, i, c);
+        y[(size_t)i * nrhs + c] = dg != 0.0 ? v / dg : 0.0;
+      }
+    std::memcpy(h_coef, y.data(), y.size() * sizeof(double));
+    if ((rc = upload(y.size()))) return rc;
+    hipLaunchKernelGGL(mf::k_combine, dim3(gblocks), dim3(256), 0, s, x, Z, (int64_t)nn, j, coef, n,
+                       nrhs);
+    HIPCHK(hipGetLastError());
+  }
+  char buf[160];
+  std::snprintf(buf, sizeof buf, "GMRES refinement stopped after %d preconditioned steps at relres %.3e > tol %.3e",
+                done_its, rr, tol);
+  return fail(MF_ENOCONV, buf);
+}
+
 int mf_factor_refine(mf_plan *P, const double *elem_mats, int32_t precision, const double *b,
                      double *x, int32_t nrhs, double tol, int32_t max_it, int32_t *its,
                      double *relres, void *hip_stream) {

@@ -183,6 +183,10 @@ struct mf_plan {
   size_t work_cap = 0;
   double *h_part = nullptr;
   size_t part_cap = 0;
+  double *d_kry = nullptr;    // Krylov workspace of mf_refine_gmres
+  size_t kry_cap = 0;
+  double *h_kry = nullptr;    // pinned host staging of its dot products and coefficients
+  size_t hkry_cap = 0;
   std::vector<mfapi::LevelDev> lv;
   mfapi::Profiler prof;
   hipStream_t cap_stream = nullptr;
@@ -237,5 +241,7 @@ struct mf_plan {
     mfapi::dfree(d_work);
     if (h_status) (void)hipHostFree(h_status);
     if (h_part) (void)hipHostFree(h_part);
+    if (h_kry) (void)hipHostFree(h_kry);
+    mfapi::dfree(d_kry);
   }
 };

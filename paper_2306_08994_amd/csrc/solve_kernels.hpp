@@ -868,6 +868,68 @@ k_axpy(double *__restrict__ x, const double *__restrict__ dx, int64_t len) {
   if (t < len) x[t] += dx[t];
 }
 
+// Krylov kernels of the refinement with GMRES (FP64, [n][nrhs] blocks, one Krylov basis per
+// right-hand side): partial column dots of w with nv basis vectors, a linear combination of basis
+// vectors added to a block, and a column scaling.
+
+// part[(blk * nv + i) * nrhs + c] = sum over the rows of block blk of V_i[row][c] * w[row][c];
+// grid (row blocks of rows_per, nv).
+__global__ void __launch_bounds__(256)
+k_coldots_partial(const double *__restrict__ V, int64_t vstride, const double *__restrict__ w,
+                  int64_t n, int nrhs, int64_t rows_per, double *__restrict__ part) {
+  __shared__ double red[256];
+  const int nv = gridDim.y, i = blockIdx.y;
+  const double *a = V + (int64_t)i * vstride;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per;
+  const int64_t r1 = min(n, r0 + rows_per);
+  double *out = part + ((int64_t)blockIdx.x * nv + i) * nrhs;
+  if (256 % nrhs == 0) {
+    double s = 0.0;
+    for (int64_t e = r0 * nrhs + threadIdx.x; e < r1 * nrhs; e += 256) s += a[e] * w[e];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if ((int)threadIdx.x < nrhs) {
+      double t = 0.0;
+      for (int j = threadIdx.x; j < 256; j += nrhs) t += red[j];
+      out[threadIdx.x] = t;
+    }
+    return;
+  }
+  for (int c = 0; c < nrhs; ++c) {
+    double s = 0.0;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) s += a[r * nrhs + c] * w[r * nrhs + c];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+      if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[c] = red[0];
+    __syncthreads();
+  }
+}
+
+// y[row][c] += sum_{i < nv} coef[i * nrhs + c] * V_i[row][c]
+__global__ void __launch_bounds__(256)
+k_combine(double *__restrict__ y, const double *__restrict__ V, int64_t vstride, int nv,
+          const double *__restrict__ coef, int64_t n, int nrhs) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n * nrhs) return;
+  const int c = (int)(e % nrhs);
+  double s = y[e];
+  for (int i = 0; i < nv; ++i) s += coef[i * nrhs + c] * V[(int64_t)i * vstride + e];
+  y[e] = s;
+}
+
+// dst[row][c] = scale[c] * src[row][c]
+__global__ void __launch_bounds__(256)
+k_scale_cols(double *__restrict__ dst, const double *__restrict__ src,
+             const double *__restrict__ scale, int64_t n, int nrhs) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n * nrhs) return;
+  dst[e] = scale[e % nrhs] * src[e];
+}
+
 // gK[e][a][b] = -sum_r lam[conn_e[a]][r] u[conn_e[b]][r]
 __global__ void __launch_bounds__(256)
 k_elem_grad(const int32_t *__restrict__ conn, int64_t ne, int npe, const double *__restrict__ lam,

@@ -194,6 +194,21 @@ class Plan:
                                     _stream()))
         return x.reshape(b.shape), int(its.value), float(rr.value)
 
+    def refine_gmres(self, K, b, tol: float = 1e-12, max_it: int = 60, restart: int = 20, x=None):
+        """Solve with GMRES refinement in FP64 preconditioned by the stored factors (see
+        mf_refine_gmres); returns (x, Arnoldi steps, relres)."""
+        import torch
+        b2 = b if b.dim() == 2 else b.reshape(-1, 1)
+        nrhs = int(b2.shape[1])
+        x = torch.empty_like(b2) if x is None else x.reshape(self.n, nrhs)
+        its = ctypes.c_int32(0)
+        rr = ctypes.c_double(0.0)
+        check(_lib.load().mf_refine_gmres(
+            self._h, _dev_ptr(K, "K", (self.n_elem, self.npe, self.npe)),
+            _dev_ptr(b2, "b", (self.n, nrhs)), _dev_ptr(x, "x"), nrhs, float(tol), int(max_it),
+            int(restart), ctypes.byref(its), ctypes.byref(rr), _stream()))
+        return x.reshape(b.shape), int(its.value), float(rr.value)
+
     def factor_refine(self, K, b, precision: str = "fp64", tol: float = 1e-12, max_it: int = 30,
                       x=None):
         """factor(K, precision) then refine(K, b) in one call, the first forward sweep overlapped

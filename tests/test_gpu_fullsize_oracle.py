@@ -116,6 +116,23 @@ def test_3d_mixed_solution_matches_oracle(prec, max_it):
     print(f"3D {prec}: {its} corrections, relres {rr:.2e}, error vs oracle {err:.2e}")
 
 
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_3d_mixed_gmres_matches_oracle(prec):
+    """GMRES refinement preconditioned by the narrow-Schur factors reaches relres <= 1e-12 and
+    the oracle's solution, in fewer preconditioned steps than plain refinement needs."""
+    p, tree, conn, fac, xo = _oracle(3)
+    plan, K, b = _setup(p)
+    plan.factor(K, prec)
+    _, its_ir, _ = plan.refine(K, b, tol=1e-12, max_it=80)
+    x, its, rr = plan.refine_gmres(K, b, tol=1e-12, max_it=60, restart=20)
+    xn = x.cpu().numpy()
+    err = G.rel_err(xn, xo)
+    assert rr <= 1e-12 and G.relres(p, conn, xn) <= 1e-12
+    assert err <= TOL_MIXED_VS_ORACLE, err
+    assert its <= its_ir
+    print(f"3D {prec} GMRES: {its} steps (refinement: {its_ir}), relres {rr:.2e}, error {err:.2e}")
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_batch_solution_matches_oracle(prec):
     """The 256-mesh batch: sampled meshes solved by the oracle one by one against the batch's

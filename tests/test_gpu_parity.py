@@ -224,6 +224,31 @@ def test_mixed_precision_refines_to_fp64(prec):
     print(f"{prec}: factor deviation {err_factor:.2e}, {its} corrections, relres {rr:.2e}")
 
 
+@pytest.mark.parametrize("prec,nrhs", [("bf16", 3), ("bf16", 8), ("fp32", 1), ("fp64", 2)])
+def test_gmres_refinement(prec, nrhs):
+    """GMRES refinement (FP64, preconditioned by the stored factors) against the oracle's
+    solution; nrhs 3 takes the separate column-norm path, 8 the fused one."""
+    from paper_2306_08994_amd import MFError
+    from paper_2306_08994_amd import _lib
+    p = _rd((12, 12, 12), seed=4, nrhs=nrhs)
+    tree, conn, fac = G.oracle_factor(p)
+    plan, K, b = _setup(p, 40, 0, 0, 0, 0)
+    plan.factor(K, prec)
+    x, its, rr = plan.refine_gmres(K, b, tol=1e-12, max_it=60, restart=8)
+    xn = x.cpu().numpy()
+    assert rr <= 1e-12 and G.relres(p, conn, xn) <= 1e-12
+    assert G.rel_err(xn, G.oracle_solve(tree, fac, p.b)) <= 1e-9
+    if prec == "fp64":
+        assert its <= 1
+    with pytest.raises(MFError) as ei:
+        plan.refine_gmres(K, b, restart=0)
+    assert ei.value.code == _lib.MF_EINVAL
+    with pytest.raises(MFError) as ei:
+        plan.refine_gmres(K, b, tol=0.0, max_it=2)
+    assert ei.value.code == _lib.MF_ENOCONV
+    print(f"{prec} nrhs {nrhs}: {its} GMRES steps, relres {rr:.2e}")
+
+
 def test_persistent_launch_wait_limit_abandons_and_recovers(monkeypatch):
     """A bound of zero on the persistent class launch's device-side waits (set from the host
     before the plan is made): the first task that has to wait gives up, every other workgroup
