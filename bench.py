@@ -68,6 +68,8 @@ KIND_SOURCE = {
     "solve_down_block": "solve_kernels.hpp", "solve_up_wave": "solve_kernels.hpp",
     "solve_up_block": "solve_kernels.hpp", "diag_block_inverse": "solve_kernels.hpp",
     "panel_lookahead": "factor_kernels.hpp", "class_tiled": "class_kernels.hpp",
+    "factor_subtree": "factor_kernels.hpp", "solve_down_subtree": "solve_kernels.hpp",
+    "solve_up_subtree": "solve_kernels.hpp",
 }
 TRAFFIC_TAG = re.compile(r"<!-- traffic kind=(\S+) source=(\S+) sha256=([0-9a-f]{64}) "
                          r"bytes_per_launch=([0-9.eE+]+) -->")
@@ -317,15 +319,42 @@ def schedule(plan, K, prec, tuning):
     return plan.autotune(K, prec, reps=2)["chosen"]
 
 
+SUBTREE = None     # --subtree: (max_classes, min_units) of the bottom-subtree launches
+
+
+def new_plan(meshes):
+    """A plan of the meshes, with the --subtree setting if one was given."""
+    from paper_2306_08994_amd import Plan
+    plan = Plan(meshes)
+    if SUBTREE is not None:
+        plan.set_subtree_launch(*SUBTREE)
+    return plan
+
+
 def given_schedule(plan, tuning):
     """tile,fused_max_m,nb,small_max_m[,persistent] (fused_max_m 0: fused route off;
-    persistent 1 / 0: persistent class launches on / off, default on)."""
-    v = [int(x) for x in tuning.split(",")]
-    t_, f_, nb_, sm_ = v[:4]
-    pers = v[4] if len(v) > 4 else 1
-    plan.set_tuning(sm_, nb_, f_ if f_ > 0 else -1, t_, 1 if pers else -1)
-    return {"persistent": pers, "tile": t_, "fused_max_m": f_, "nb": nb_, "small_max_m": sm_,
-            "given": True}
+    persistent 1 / 0: persistent class launches on / off, default on); several such groups
+    separated by ';' give one schedule per Foata class, leaves first (the form of the
+    autotuner's per-class choice, e.g. to profile exactly that schedule)."""
+    groups = [g for g in tuning.split(";") if g.strip()]
+
+    def parse(g):
+        v = [int(x) for x in g.split(",")]
+        t_, f_, nb_, sm_ = v[:4]
+        pers = v[4] if len(v) > 4 else 1
+        return {"persistent": pers, "tile": t_, "fused_max_m": f_, "nb": nb_, "small_max_m": sm_}
+
+    if len(groups) > 1:
+        cls = [parse(g) for g in groups]
+        if len(cls) != plan.info["height"] + 1:
+            raise SystemExit(f"--tuning has {len(cls)} class groups, the plan has "
+                             f"{plan.info['height'] + 1} Foata classes")
+        plan.set_class_tuning([dict(c, persistent=1 if c["persistent"] else 0) for c in cls])
+        return {"mode": "per_class", "classes": cls, "given": True}
+    c = parse(groups[0])
+    plan.set_tuning(c["small_max_m"], c["nb"], c["fused_max_m"] if c["fused_max_m"] > 0 else -1,
+                    c["tile"], 1 if c["persistent"] else -1)
+    return dict(c, given=True)
 
 
 def variant_mixed(steps, warmup, precs=("fp64", "fp32", "bf16"), tuning=None, oracle=True):
@@ -335,10 +364,9 @@ def variant_mixed(steps, warmup, precs=("fp64", "fp32", "bf16"), tuning=None, or
     FP64 solution; the Schur GEMMs' fraction of their precision's MFMA peak."""
     import torch
     from fixtures import config_problem
-    from paper_2306_08994_amd import Plan
     xo, oleg = oracle_solution(3) if oracle else (None, None)
     p = config_problem(3)
-    plan = Plan(p.meshes)
+    plan = new_plan(p.meshes)
     K = torch.from_numpy(p.K).cuda()
     b = torch.from_numpy(p.b).cuda()
     x = torch.empty_like(b)
@@ -390,11 +418,10 @@ def variant_l2(steps, warmup):
     load vector; step = factor + solve + FP64 refinement to relres <= 1e-12."""
     import torch
     from fixtures import l2_workload
-    from paper_2306_08994_amd import Plan
     out = {"workload": "2D L2 projection (mass matrix), 299,209 unknowns, 1 RHS, FP64"}
     for deg in (1, 2, 3):
         p = l2_workload(deg)
-        plan = Plan(p.meshes)
+        plan = new_plan(p.meshes)
         K = torch.from_numpy(p.K).cuda()
         b = torch.from_numpy(p.b).cuda()
         x = torch.empty_like(b)
@@ -424,10 +451,9 @@ def variant_table3(steps, warmup):
     the tree's own operation count."""
     import torch
     from fixtures import config_problem
-    from paper_2306_08994_amd import Plan
     p = config_problem(2)
     p.meshes[0].ijk = None
-    plan = Plan(p.meshes)
+    plan = new_plan(p.meshes)
     K = torch.from_numpy(p.K).cuda()
     b = torch.from_numpy(p.b).cuda()
     x = torch.empty_like(b)
@@ -454,10 +480,9 @@ def variant_batched(steps, warmup, precs=("fp64", "fp32"), tuning=None, oracle=T
     import numpy as np
     import torch
     from fixtures import config_problem
-    from paper_2306_08994_amd import Plan
     xo, pool = cpu_pool_baseline() if oracle else (None, None)
     p = config_problem(4)
-    plan = Plan(p.meshes)
+    plan = new_plan(p.meshes)
     K = torch.from_numpy(p.K).cuda()
     b = torch.from_numpy(p.b).cuda()
     x = torch.empty_like(b)
@@ -500,11 +525,10 @@ def unbatched(p, steps=3):
     """The same 256 meshes with one plan per mesh, factored and solved one after another (FP64,
     the same step and schedule defaults): what the batched class launches are compared with."""
     import torch
-    from paper_2306_08994_amd import Plan
     NO, EO = p.node_offsets, p.elem_offsets
     plans = []
     for i in range(len(p.meshes)):
-        plan = Plan([p.meshes[i]])
+        plan = new_plan([p.meshes[i]])
         K = torch.from_numpy(p.K[EO[i]:EO[i + 1]]).cuda()
         b = torch.from_numpy(p.b[NO[i]:NO[i + 1]]).cuda()
         plans.append((plan, K, b, torch.empty_like(b)))
@@ -540,9 +564,8 @@ def pmc_probe_variant(variant, prec, tuning):
     copies."""
     import torch
     from fixtures import config_problem
-    from paper_2306_08994_amd import Plan
     p = config_problem(3 if variant == "mixed" else 4)
-    plan = Plan(p.meshes)
+    plan = new_plan(p.meshes)
     K = torch.from_numpy(p.K).cuda()
     sched = schedule(plan, K, prec, tuning)
     plan.factor(K, prec)
@@ -576,6 +599,9 @@ def main():
                     help="run one workload only and print its JSON (main: the 256x256 step)")
     ap.add_argument("--precs", default=None,
                     help="comma-separated precisions of the mixed / batched variants")
+    ap.add_argument("--subtree", default=None,
+                    help="max_classes[,min_units] of the bottom-subtree launches (0: per-class "
+                         "launches; default: the library's choice)")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="run a few steps and a 1 GiB device copy (HBM counter calibration) only")
     args = ap.parse_args()
@@ -587,7 +613,10 @@ def main():
     import torch
 
     from fixtures import config_problem
-    from paper_2306_08994_amd import Plan
+    global SUBTREE
+    if args.subtree:
+        v = [int(x) for x in args.subtree.split(",")]
+        SUBTREE = (v[0], v[1] if len(v) > 1 else 2048)
 
     if args.pmc_probe and args.variant in ("mixed", "batched"):
         print(json.dumps(pmc_probe_variant(args.variant, (args.precs or "fp64").split(",")[0],
@@ -608,7 +637,7 @@ def main():
     dev = torch.device("cuda:0")
     p = config_problem(2)
     t0 = time.perf_counter()
-    plan = Plan(p.meshes)
+    plan = new_plan(p.meshes)
     t_analyse = time.perf_counter() - t0
     K = torch.from_numpy(p.K).to(dev)
     b = torch.from_numpy(p.b).to(dev)
@@ -656,7 +685,7 @@ def main():
     plan.profile(False)
     top, roof = roofline_of(rep)
     factor_kinds = {"factor_tiny", "factor_small", "assemble", "front_panels", "panel_lu_trsm",
-                    "gemm_panel", "gemm_schur", "class_tiled", "panel_lookahead"}
+                    "gemm_panel", "gemm_schur", "class_tiled", "panel_lookahead", "factor_subtree"}
     launches = {"factor": sum(k["launches"] for k in rep["kernels"] if k["name"] in factor_kinds),
                 "solve_and_inverses": sum(k["launches"] for k in rep["kernels"]
                                           if k["name"] not in factor_kinds)}
@@ -682,6 +711,7 @@ def main():
                          bytes_per_launch=top["bytes"] / top["launches"],
                          flops_per_launch=top["flops"] / top["launches"]),
         "kernels": rep["kernels"],
+        "subtree_launch": plan.subtree_launch_info(),
         "launches_per_step": dict(launches, classes=info["height"] + 1,
                                   note="the plan's kernel launches per step; the residual, norm "
                                        "and status-clearing launches (4-5 per step) not included"),

@@ -150,6 +150,27 @@ int mf_set_tuning(mf_plan *plan, int32_t small_max_m, int32_t nb, int32_t fused_
  * Invalidates a previous factorization.  Errors: MF_EINVAL (wrong class count, bad value). */
 int mf_set_class_tuning(mf_plan *plan, int32_t n_class, const int32_t *params);
 
+/* Bottom-subtree launches (Sec. 3.3's class barrier kept inside a workgroup): the leading
+ * Foata classes whose fronts all take the one-wave-per-front routes (the tiny factor route,
+ * fronts up to 32 wide; the wave solves, up to 64) run as one launch of the factorization and
+ * one of each sweep instead of one per class.  The fronts of those classes split into units --
+ * a front whose parent lies above the fused classes, with all its descendants -- and one
+ * workgroup takes a unit class by class with a workgroup barrier between classes; the results
+ * are identical to the per-class launches.  max_classes: at most this many classes (-1: as many
+ * as the routes allow, 0 or 1: off, the default); min_units: the most classes that still give
+ * at least this many units are fused (default 2048, so that the launch fills the chip; >= 1).
+ * The factorization and the solves choose separately.  Off by default: a unit's classes run
+ * one after another inside its workgroup with fewer fronts per class than waves near its root,
+ * while the per-class launches keep every wave busy -- on the 2D and 3D trees measured the
+ * per-class launches are faster.  Takes effect at the next device call; invalidates a previous
+ * factorization.  Errors: MF_EINVAL. */
+int mf_set_subtree_launch(mf_plan *plan, int32_t max_classes, int64_t min_units);
+
+/* The bottom-subtree launches in use (uploads the plan's schedule first, see mf_factor):
+ * out (host, 4 values) = classes fused and units of the factorization, then of the solves
+ * (0 classes: per-class launches).  Errors: MF_EINVAL, MF_EHIP. */
+int mf_subtree_launch_info(mf_plan *plan, int64_t *out);
+
 /* Autotuner: factors elem_mats (device, as in mf_factor) under each candidate schedule that the
  * workload's front widths make relevant -- persistent class launches on/off, GEMM tile 64/32,
  * fused route on/off, panel width 32/64, LDS limit 128/64 -- timing `reps` factorizations of

@@ -393,6 +393,15 @@ void build_schedule(HostPlan &P, const std::vector<Tuning> &tl) {
       L.large_max_m = std::max(L.large_max_m, d.m);
     }
   }
+  // a class with at most as many tiny fronts as small ones runs them on the small route too:
+  // one launch for the class instead of two in sequence (the two routes' arithmetic is the
+  // same elimination; a few tiny fronts are not worth a launch of their own)
+  for (auto &L : P.levels) {
+    if (L.small.empty() || L.tiny.empty() || L.tiny.size() > L.small.size()) continue;
+    L.small.insert(L.small.begin(), L.tiny.begin(), L.tiny.end());
+    L.tiny.clear();
+    L.tiny_max_m = 0;
+  }
   // the solve's list of a class: the tiny fronts first (their wave records are then a prefix
   // of the class's records), then the rest; fronts of a class are independent
   for (auto &L : P.levels) {

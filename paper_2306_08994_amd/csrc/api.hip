@@ -246,6 +246,75 @@ constexpr int kWaveSolveMaxM = 64;
 // Largest (m - k) k of a class from which its rectangular part is a launch of its own.
 constexpr int64_t kSplitDownCK = 16384, kSplitUpCK = 8192;
 
+// Bottom subtrees of the first classes as one launch (see k_factor_subtree).  `eligible` is the
+// number of leading classes whose every front takes the route the subtree kernels run (the
+// tiny factor route, or the wave solves); of those, the most classes (at least two, at most
+// P->sub_max_classes) that still give P->sub_min_units units, so that the launch fills the chip
+// with units whose per-class front counts are small.  wpos[f]: front f's entry in `wrec`.
+int build_subtrees(mf_plan *P, SubtreeDev &S, int32_t eligible,
+                   const std::vector<mf::WaveRec> &wrec, const std::vector<int64_t> &wpos) {
+  const mf::HostPlan &H = P->hp;
+  dfree(S.d_rec);
+  dfree(S.d_ptr);
+  S = SubtreeDev();
+  int32_t lim = eligible;
+  if (P->sub_max_classes >= 0) lim = std::min(lim, P->sub_max_classes);
+  // units of ncls classes: fronts with a record, class < ncls, parent at or above ncls
+  auto is_root = [&](int64_t f, int32_t ncls) {
+    if (wpos[f] < 0 || H.level[f] >= ncls) return false;
+    const int32_t par = H.parent[f];
+    return par < 0 || H.level[par] >= ncls;
+  };
+  int32_t ncls = 0;
+  for (int32_t c = lim; c >= 2 && !ncls; --c) {
+    int64_t units = 0;
+    for (int64_t f = 0; f < H.F; ++f) units += is_root(f, c) ? 1 : 0;
+    if (units >= P->sub_min_units) ncls = c;
+  }
+  if (!ncls) return MF_OK;
+  std::vector<mf::WaveRec> rec;
+  std::vector<int32_t> ptr;
+  std::vector<std::vector<int32_t>> by_cls(ncls);
+  std::vector<int32_t> stack;
+  for (int64_t f = 0; f < H.F; ++f) {
+    if (!is_root(f, ncls)) continue;
+    for (auto &v : by_cls) v.clear();
+    stack.assign(1, (int32_t)f);
+    while (!stack.empty()) {
+      const int32_t g = stack.back();
+      stack.pop_back();
+      if (wpos[g] >= 0) by_cls[H.level[g]].push_back(g);
+      const mf::FrontDesc &d = H.desc[g];
+      if (d.left >= 0) stack.push_back(d.left);
+      if (d.right >= 0) stack.push_back(d.right);
+    }
+    for (int32_t c = 0; c < ncls; ++c) {
+      ptr.push_back((int32_t)rec.size());
+      for (int32_t g : by_cls[c]) rec.push_back(wrec[wpos[g]]);
+    }
+    ++S.nsub;
+  }
+  ptr.push_back((int32_t)rec.size());
+  S.ncls = ncls;
+  S.nrec = (int64_t)rec.size();
+  for (int32_t c = 0; c < ncls; ++c) {
+    const LevelDev &D = P->lv[c];
+    S.max_m = std::max(S.max_m, D.max_m);
+    S.max_k = std::max(S.max_k, D.max_k);
+    S.c_factor.bytes += D.c_tiny.bytes;
+    S.c_factor.flops += D.c_tiny.flops;
+    S.down_coef += D.down_coef;
+    S.down_rhs_bytes += D.down_rhs_bytes;
+    S.down_rhs_flops += D.down_rhs_flops;
+    S.up_coef += D.up_coef;
+    S.up_rhs_bytes += D.up_rhs_bytes;
+    S.up_rhs_flops += D.up_rhs_flops;
+  }
+  int rc;
+  if ((rc = upload(S.d_rec, rec)) || (rc = upload(S.d_ptr, ptr))) return rc;
+  return MF_OK;
+}
+
 int ensure_uploaded(mf_plan *P) {
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
@@ -258,6 +327,7 @@ int ensure_uploaded(mf_plan *P) {
   P->drop_graphs();
   P->device = dev;
   HIPCHK(hipDeviceGetAttribute(&P->max_shared, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  HIPCHK(hipDeviceGetAttribute(&P->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
   mf::HostPlan &H = P->hp;
   // widest front whose padded square fits in one workgroup's LDS
   int32_t mm = 1;
@@ -599,9 +669,27 @@ int ensure_uploaded(mf_plan *P) {
     }
   }
   if ((rc = upload(P->d_wrec, wrec))) return rc;
+  {
+    // bottom subtrees: the leading classes on the tiny factor route, and on the wave solves
+    std::vector<int64_t> wpos(H.F, -1);
+    int64_t w = 0;
+    for (const mf::LevelSchedule &S : H.levels)
+      for (int32_t f : S.all) wpos[f] = w++;
+    int32_t ef = 0, es = 0;
+    while (ef < (int32_t)H.levels.size() &&
+           H.levels[ef].tiny.size() == H.levels[ef].all.size())
+      ++ef;
+    while (es < (int32_t)H.levels.size() && H.levels[es].max_m <= kWaveSolveMaxM) ++es;
+    if ((rc = build_subtrees(P, P->sub_f, ef, wrec, wpos)) ||
+        (rc = build_subtrees(P, P->sub_s, es, wrec, wpos)))
+      return rc;
+  }
   if (!P->d_status) HIPCHK(hipMalloc((void **)&P->d_status, mf::kStatusWords * sizeof(int)));
-  if (!P->h_status)
-    HIPCHK(hipHostMalloc((void **)&P->h_status, mf::kStatusWords * sizeof(int), hipHostMallocDefault));
+  if (!P->h_status) {
+    HIPCHK(hipHostMalloc((void **)&P->h_status, mf::kStatusWords * sizeof(int),
+                         hipHostMallocMapped | hipHostMallocCoherent));
+    HIPCHK(hipHostGetDevicePointer((void **)&P->d_hstatus, P->h_status, 0));
+  }
   if (!P->cap_stream) HIPCHK(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
   if (!P->side_stream) HIPCHK(hipStreamCreateWithFlags(&P->side_stream, hipStreamNonBlocking));
   // events that only order the plan's two streams on this device: no system-scope fence (the
@@ -615,7 +703,8 @@ int ensure_uploaded(mf_plan *P) {
   // raise the dynamic-LDS limit of the kernels that size LDS per launch (best effort)
   const void *dyn[] = {(const void *)mf::k_factor_tiny<1>, (const void *)mf::k_factor_tiny<4>,
                        (const void *)mf::k_factor_tiny<9>, (const void *)mf::k_factor_tiny<16>,
-                       (const void *)mf::k_factor_small,
+                       (const void *)mf::k_factor_small<256>,
+                       (const void *)mf::k_factor_small<mf::SM_THREADS>,
                        (const void *)mf::k_assemble, (const void *)mf::k_front_panels<32>,
                        (const void *)mf::k_solve_down_wave<false>, (const void *)mf::k_solve_down_wave<true>,
                        (const void *)mf::k_solve_up_wave<false>, (const void *)mf::k_solve_up_wave<true>,
@@ -626,7 +715,13 @@ int ensure_uploaded(mf_plan *P) {
                        (const void *)mf::k_solve_up_block<false, false>,
                        (const void *)mf::k_solve_up_block<true, false>,
                        (const void *)mf::k_solve_up_block<false, true>,
-                       (const void *)mf::k_solve_up_block<true, true>};
+                       (const void *)mf::k_solve_up_block<true, true>,
+                       (const void *)mf::k_factor_subtree<1>, (const void *)mf::k_factor_subtree<4>,
+                       (const void *)mf::k_factor_subtree<9>, (const void *)mf::k_factor_subtree<16>,
+                       (const void *)mf::k_solve_down_subtree<false>,
+                       (const void *)mf::k_solve_down_subtree<true>,
+                       (const void *)mf::k_solve_up_subtree<false>,
+                       (const void *)mf::k_solve_up_subtree<true>};
   for (const void *fn : dyn)
     (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, P->max_shared);
   (void)hipGetLastError();
@@ -708,6 +803,27 @@ struct Scope {
 // The launches of class l of the factorization.
 int factor_level(mf_plan *P, const double *K, int prec, size_t l, hipStream_t s) {
   P->prof.cur_class = (int)l;
+  if ((int32_t)l < P->sub_f.ncls) {
+    // the bottom-subtree launch runs classes 0..ncls-1 (issued with class 0)
+    const mfapi::SubtreeDev &S = P->sub_f;
+    if (l == 0) {
+      const int m = S.max_m;
+      const int ldsw = m * (m | 1) + m;
+      const int grid = (int)std::min<int64_t>(S.nsub, 65535);
+      const size_t lds = (size_t)4 * ldsw * 8;
+      if (m > mf::kTinyMaxM) return fail(MF_EINVAL, "tiny route front wider than the kernel's limit");
+#define MF_SUB(U)                                                                                \
+  LAUNCH(K_SUB_FACTOR, S.c_factor, mf::k_factor_subtree<U>, dim3(grid), dim3(256), lds, s, S.d_rec, \
+         S.d_ptr, (int)S.nsub, S.ncls, P->d_store, P->d_inv_l, P->d_inv_r, K, P->d_status, ldsw, m)
+      if (m <= 8) MF_SUB(1);
+      else if (m <= 16) MF_SUB(4);
+      else if (m <= 24) MF_SUB(9);
+      else MF_SUB(16);
+#undef MF_SUB
+    }
+    P->prof.cur_class = -1;
+    return MF_OK;
+  }
   {
     const LevelDev &D = P->lv[l];
     const mf::Tuning &T = P->eff[l];
@@ -734,9 +850,15 @@ int factor_level(mf_plan *P, const double *K, int prec, size_t l, hipStream_t s)
       const int m = D.small_max_m;
       const size_t lds = (size_t)mf::small_lds_doubles(m) * sizeof(double);
       const int grid = (int)std::min<int64_t>(D.n_small, 16384);
-      LAUNCH(K_SMALL, D.c_small, mf::k_factor_small, dim3(grid), dim3(mf::SM_THREADS), lds, s,
-             P->d_wrec + D.rall + D.n_tiny, (int)D.n_small, P->d_store, P->d_inv_l, P->d_inv_r, K,
-             P->d_status, m);
+      // more fronts than compute units: smaller workgroups, more of them resident
+      if (D.n_small > P->n_cu)
+        LAUNCH(K_SMALL, D.c_small, mf::k_factor_small<256>, dim3(grid), dim3(256), lds, s,
+               P->d_wrec + D.rall + D.n_tiny, (int)D.n_small, P->d_store, P->d_inv_l, P->d_inv_r,
+               K, P->d_status, m);
+      else
+        LAUNCH(K_SMALL, D.c_small, mf::k_factor_small<mf::SM_THREADS>, dim3(grid),
+               dim3(mf::SM_THREADS), lds, s, P->d_wrec + D.rall + D.n_tiny, (int)D.n_small,
+               P->d_store, P->d_inv_l, P->d_inv_r, K, P->d_status, m);
     }
     if (D.n_large && D.n_ctask) {
       const size_t lds = T.tile == 32 ? mf::class_lds_bytes<2, 32>(D.large_max_m)
@@ -883,6 +1005,39 @@ void solve_level(mf_plan *P, const double *b, double *x, int32_t nrhs, bool tran
   const int gridcap = 16384;
   {
     {
+      if ((int32_t)l < P->sub_s.ncls) {
+        // the bottom-subtree launch of the sweep: issued with class 0 (down: the first class
+        // of the sweep, up: the last), it runs classes 0..ncls-1
+        const mfapi::SubtreeDev &S = P->sub_s;
+        if (l != 0) return;
+        Cost c;
+        c.bytes = (down ? S.down_coef : S.up_coef) + nrhs * (down ? S.down_rhs_bytes : S.up_rhs_bytes);
+        c.flops = nrhs * (down ? S.down_rhs_flops : S.up_rhs_flops);
+        const int mmax = std::max(1, S.max_m), kmax = std::max(1, S.max_k);
+        const int cld = kmax | 1;
+        const int64_t cdoubles = (int64_t)mmax * cld + mf::kWaveRows;
+        const int nc = chunk(P, nrhs, 4 * cdoubles, 4 * (int64_t)mmax);
+        const int ldsw = (int)(mmax * nc + cdoubles);
+        const size_t lds = (size_t)4 * ldsw * 8;
+        const int grid = (int)std::min<int64_t>(S.nsub, 65535);
+        if (down && trans)
+          LAUNCH(K_SUB_DOWN, c, mf::k_solve_down_subtree<true>, dim3(grid), dim3(256), lds, s,
+                 S.d_rec, S.d_ptr, (int)S.nsub, S.ncls, P->d_store, P->d_front_idx, P->d_inv_l,
+                 P->d_inv_r, b, x, ycb, nrhs, nc, mmax, cld, ldsw);
+        else if (down)
+          LAUNCH(K_SUB_DOWN, c, mf::k_solve_down_subtree<false>, dim3(grid), dim3(256), lds, s,
+                 S.d_rec, S.d_ptr, (int)S.nsub, S.ncls, P->d_store, P->d_front_idx, P->d_inv_l,
+                 P->d_inv_r, b, x, ycb, nrhs, nc, mmax, cld, ldsw);
+        else if (trans)
+          LAUNCH(K_SUB_UP, c, mf::k_solve_up_subtree<true>, dim3(grid), dim3(256), lds, s,
+                 S.d_rec, S.d_ptr, (int)S.nsub, S.ncls, P->d_store, P->d_front_idx, x, nrhs, nc,
+                 mmax, cld, ldsw);
+        else
+          LAUNCH(K_SUB_UP, c, mf::k_solve_up_subtree<false>, dim3(grid), dim3(256), lds, s,
+                 S.d_rec, S.d_ptr, (int)S.nsub, S.ncls, P->d_store, P->d_front_idx, x, nrhs, nc,
+                 mmax, cld, ldsw);
+        return;
+      }
       const LevelDev &D = P->lv[l];
       if (!D.n_all) return;
       Cost c;
@@ -992,31 +1147,59 @@ int launch_solve(mf_plan *P, const double *b, double *x, int32_t nrhs, bool tran
 // upper classes of the factorization occupy a fraction of the chip; the backward sweep follows
 // on s once both streams have joined.  The same kernels in the same per-class order as
 // launch_factor then launch_solve, so the results are identical.
+// Spacing of the second stream's joins among the classes below the first class with tiled
+// fronts (0: it starts at that class), and whether each join's forward-sweep work is issued
+// right after the factorization up to it (else after the whole factorization).  Measured on
+// the 256 x 256 workload: joins every 2 or 3 lower classes make the step 3-5 % slower (the
+// lower classes' forward sweep then competes with their factorization, which fills the chip,
+// and every join stalls the caller's stream); interleaved issue is within noise.
+constexpr int kSideStride = 0;
+constexpr bool kSideInterleave = false;
+
 int launch_factor_solve(mf_plan *P, const double *K, int prec, const double *b, double *x,
                         int32_t nrhs, hipStream_t s) {
   hipStream_t side = P->side_stream;
   const size_t L = P->lv.size();
   clear_status(P, s);
   int rc;
-  // every class of the factorization is issued first (the host issue of the second stream's
-  // work must not delay the factorization's short lower-class launches), then the second
-  // stream's per-class work, each class behind its event
-  // the second stream starts once the lower classes, whose launches fill the chip, are factored:
-  // from the first class with fronts on the tiled route, the factorization is latency-bound and
-  // leaves most of the chip to the forward sweep.  Only the classes it waits for record an
-  // event (each record stalls the caller's stream for a few microseconds).
+  // The second stream's class l needs the factorization of classes <= l.  It joins the
+  // caller's stream at "sync" classes: every class from the first one with tiled fronts (from
+  // there the factorization is latency-bound and leaves most of the chip to the forward sweep),
+  // and every kSideStride-th class below it, so that the lower classes' forward sweep overlaps
+  // the factorization of the middle classes instead of queueing behind the upper ones.  Each
+  // join costs an event record (a stall of a few microseconds on the caller's stream) and a
+  // wait, so the lower classes join in groups.
   size_t start = 0;
   while (start + 1 < L && P->lv[start].n_large == 0) ++start;
+  std::vector<char> sync(L, 0);
+  for (size_t l = start; l < L; ++l) sync[l] = 1;
+  if (kSideStride > 0)
+    for (size_t l = kSideStride - 1; l < start; l += kSideStride) sync[l] = 1;
+  sync[L - 1] = 1;
+  // a bottom-subtree forward sweep (issued with class 0) runs its classes 0..ncls-1 at once:
+  // it may start only after the factorization of all of them
+  if (P->sub_s.ncls > 1) {
+    for (size_t l = 0; l + 1 < (size_t)P->sub_s.ncls && l < L; ++l) sync[l] = 0;
+    sync[std::min(L, (size_t)P->sub_s.ncls) - 1] = 1;
+  }
+  size_t next_side = 0;   // first class of the forward sweep not yet issued
+  auto issue_side = [&](size_t upto) -> int {   // classes next_side .. upto behind event[upto]
+    HIPCHK(hipStreamWaitEvent(side, P->lvl_events[upto], 0));
+    for (; next_side <= upto; ++next_side) {
+      dinv_launch(P, P->dinv_lvl[next_side], P->dinv_lvl[next_side + 1], side);
+      solve_level(P, b, x, nrhs, false, true, next_side, side, P->d_ycb);
+    }
+    return MF_OK;
+  };
   for (size_t l = 0; l < L; ++l) {
     if ((rc = factor_level(P, K, prec, l, s))) return rc;
-    if (l >= start) HIPCHK(hipEventRecord(P->lvl_events[l], s));
+    if (!sync[l]) continue;
+    HIPCHK(hipEventRecord(P->lvl_events[l], s));
+    if (kSideInterleave && (rc = issue_side(l))) return rc;
   }
-  for (size_t l = 0; l < L; ++l) {
-    if (l == 0 || l >= start)
-      HIPCHK(hipStreamWaitEvent(side, P->lvl_events[std::max(l, start)], 0));
-    dinv_launch(P, P->dinv_lvl[l], P->dinv_lvl[l + 1], side);
-    solve_level(P, b, x, nrhs, false, true, l, side, P->d_ycb);
-  }
+  if (!kSideInterleave)
+    for (size_t l = 0; l < L; ++l)
+      if (sync[l] && (rc = issue_side(l))) return rc;
   HIPCHK(hipEventRecord(P->lvl_events[L], side));
   HIPCHK(hipStreamWaitEvent(s, P->lvl_events[L], 0));
   for (size_t l = L; l-- > 0;) solve_level(P, b, x, nrhs, false, false, l, s, P->d_ycb);
@@ -1086,28 +1269,68 @@ NormLayout norm_layout(int64_t n, int32_t nrhs) {
   return L;
 }
 
-// Sums the partials on the host: rn from the residual's, and bn from b's if want_b.
+// The residual's column norms rn (and b's, bn, if want_b) from their partial sums: summed on
+// the device and written, with the factorization's status words if with_status (into
+// h_status), to mapped host memory by one small kernel, whose last workgroup then writes a
+// sequence number there.  The host spins on that number for up to kSpinMicros (a wake-up from
+// a stream synchronization costs tens of microseconds per refinement step), checking the stream
+// for errors now and then, and falls back to a synchronization after that.
+constexpr double kSpinMicros = 2000.0;
+
 int read_norms(mf_plan *P, const NormLayout &L, const double *dpart, int32_t nrhs, hipStream_t s,
-               bool want_b, std::vector<double> &rn, std::vector<double> &bn) {
-  const size_t need = L.r_parts + (want_b ? L.b_parts : 0);
+               bool want_b, std::vector<double> &rn, std::vector<double> &bn,
+               bool with_status = false) {
+  const size_t need = 2 * (size_t)nrhs + 1;   // the sums, then the sequence number
   if (P->part_cap < need) {
     if (P->h_part) (void)hipHostFree(P->h_part);
     P->h_part = nullptr;
+    P->d_hpart = nullptr;
     P->part_cap = 0;
-    HIPCHK(hipHostMalloc((void **)&P->h_part, (L.r_parts + L.b_parts) * sizeof(double),
-                         hipHostMallocDefault));
-    P->part_cap = L.r_parts + L.b_parts;
+    HIPCHK(hipHostMalloc((void **)&P->h_part, need * sizeof(double),
+                         hipHostMallocMapped | hipHostMallocCoherent));
+    HIPCHK(hipHostGetDevicePointer((void **)&P->d_hpart, P->h_part, 0));
+    P->part_cap = need;
   }
-  HIPCHK(hipMemcpyAsync(P->h_part, dpart, need * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  auto sum = [&](const double *h, int64_t blocks, std::vector<double> &o) {
-    o.assign(nrhs, 0.0);
-    for (int64_t bl = 0; bl < blocks; ++bl)
-      for (int c = 0; c < nrhs; ++c) o[c] += h[bl * nrhs + c];
-    for (int c = 0; c < nrhs; ++c) o[c] = std::sqrt(o[c]);
-  };
-  sum(P->h_part, L.r_blocks, rn);
-  if (want_b) sum(P->h_part + L.r_parts, L.b_blocks, bn);
+  if (!P->d_pub_count) {
+    HIPCHK(hipMalloc((void **)&P->d_pub_count, sizeof(int)));
+    HIPCHK(hipMemset(P->d_pub_count, 0, sizeof(int)));
+  }
+  int *hseq = reinterpret_cast<int *>(P->h_part + 2 * (size_t)nrhs);
+  int *dseq = reinterpret_cast<int *>(P->d_hpart + 2 * (size_t)nrhs);
+  if (P->pub_seq == INT32_MAX) P->pub_seq = 0;
+  const int seq = ++P->pub_seq;
+  __atomic_store_n(hseq, 0, __ATOMIC_RELAXED);   // no stale value can match (seq >= 1)
+  const double *bpart = dpart + L.r_parts;
+  const int grid = nrhs * (want_b ? 2 : 1);
+  hipLaunchKernelGGL(mf::k_norm_publish, dim3(grid), dim3(256), 0, s, dpart, L.r_blocks, bpart,
+                     want_b ? L.b_blocks : (int64_t)0, nrhs,
+                     with_status ? (const int *)P->d_status : (const int *)nullptr, P->d_hpart,
+                     P->d_hstatus, P->d_pub_count, dseq, seq);
+  HIPCHK(hipGetLastError());
+  const auto t0 = std::chrono::steady_clock::now();
+  for (int64_t spins = 1;; ++spins) {
+    if (__atomic_load_n(hseq, __ATOMIC_ACQUIRE) == seq) break;
+    if (spins % 1024) continue;
+    const hipError_t e = hipStreamQuery(s);
+    if (e == hipSuccess) {
+      if (__atomic_load_n(hseq, __ATOMIC_ACQUIRE) == seq) break;
+      return fail(MF_EHIP, "the norm kernel completed without publishing its results");
+    }
+    if (e != hipErrorNotReady) return fail(MF_EHIP, std::string("hipStreamQuery: ") + hipGetErrorString(e));
+    if (std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count() >
+        kSpinMicros) {
+      HIPCHK(hipStreamSynchronize(s));
+      if (__atomic_load_n(hseq, __ATOMIC_ACQUIRE) != seq)
+        return fail(MF_EHIP, "the norm kernel completed without publishing its results");
+      break;
+    }
+  }
+  rn.assign(nrhs, 0.0);
+  for (int c = 0; c < nrhs; ++c) rn[c] = std::sqrt(P->h_part[c]);
+  if (want_b) {
+    bn.assign(nrhs, 0.0);
+    for (int c = 0; c < nrhs; ++c) bn[c] = std::sqrt(P->h_part[nrhs + c]);
+  }
   return MF_OK;
 }
 
@@ -1265,6 +1488,29 @@ int mf_set_tuning(mf_plan *P, int32_t small_max_m, int32_t nb, int32_t fused_max
   return MF_OK;
 }
 
+int mf_set_subtree_launch(mf_plan *P, int32_t max_classes, int64_t min_units) {
+  if (!P) return fail(MF_EINVAL, "null plan");
+  if (max_classes < -1) return fail(MF_EINVAL, "max_classes must be >= -1");
+  if (min_units < 1) return fail(MF_EINVAL, "min_units must be >= 1");
+  P->sub_max_classes = max_classes;
+  P->sub_min_units = min_units;
+  P->uploaded = false;
+  P->factored = false;
+  P->drop_graphs();
+  return MF_OK;
+}
+
+int mf_subtree_launch_info(mf_plan *P, int64_t *out) {
+  if (!P || !out) return fail(MF_EINVAL, "null argument");
+  const int rc = ensure_uploaded(P);
+  if (rc) return rc;
+  out[0] = P->sub_f.ncls;
+  out[1] = P->sub_f.nsub;
+  out[2] = P->sub_s.ncls;
+  out[3] = P->sub_s.nsub;
+  return MF_OK;
+}
+
 int mf_set_class_tuning(mf_plan *P, int32_t n_class, const int32_t *params) {
   if (!P) return fail(MF_EINVAL, "null plan");
   const int32_t nc = P->hp.height + 1;
@@ -1380,8 +1626,8 @@ int mf_residual(mf_plan *P, const double *elem_mats, const double *x, const doub
 }
 
 // The refinement loop from x = the direct solution: residual, norms, corrections.
-// check_status: the factorization's pivot status was copied to h_status on hip_stream ahead of
-// the first residual; it is checked after the first synchronization (no separate wait for it).
+// check_status: the factorization's pivot status is published to h_status with the first
+// residual's norms and checked after that synchronization (no separate wait for it).
 static int refine_loop(mf_plan *P, const double *elem_mats, const double *b, double *x,
                        int32_t nrhs, double tol, int32_t max_it, int32_t *its, double *relres,
                        void *hip_stream, bool check_status = false, bool b_ready = false) {
@@ -1407,7 +1653,8 @@ static int refine_loop(mf_plan *P, const double *elem_mats, const double *b, dou
       hipLaunchKernelGGL(mf::k_colsq_partial, dim3((unsigned)NL.b_blocks), dim3(256), 0, s, b, n,
                          nrhs, kNormRows, bpart);
     HIPCHK(hipGetLastError());
-    if ((rc = read_norms(P, NL, rpart, nrhs, s, it == 0, rn, bn))) return rc;
+    if ((rc = read_norms(P, NL, rpart, nrhs, s, it == 0, rn, bn, check_status && it == 0)))
+      return rc;
     if (check_status && it == 0 && P->h_status[mf::kStatusAbort]) {
       P->factored = false;
       return fail(MF_EHIP, "a device-side wait of the factorization exceeded its limit; the "
@@ -1637,22 +1884,20 @@ int mf_factor_refine(mf_plan *P, const double *elem_mats, int32_t precision, con
   // stream (a captured graph of the same fork/join replays its branches one after the other
   // on this platform -- measured: no overlap, 3 % slower than the sequential calls)
   {
-    // the norms of b do not depend on the factorization: their partial sums run first on the
-    // plan's second stream, which the caller's stream joins before the backward sweep
+    // the norms of b do not depend on the factorization: their partial sums run first, on the
+    // caller's stream (the first launches of a step find the device idle while the host issues
+    // them; a second stream would need an event and a wait, two more host calls)
     const int64_t n = P->hp.n;
     const size_t nn = (size_t)n * nrhs;
     const NormLayout NL = norm_layout(n, nrhs);
     if ((rc = grow(P, P->d_work, P->work_cap, 2 * nn + NL.r_parts + NL.b_parts))) return rc;
-    HIPCHK(hipEventRecord(P->lvl_events[P->lv.size() + 1], s));
-    HIPCHK(hipStreamWaitEvent(P->side_stream, P->lvl_events[P->lv.size() + 1], 0));
-    hipLaunchKernelGGL(mf::k_colsq_partial, dim3((unsigned)NL.b_blocks), dim3(256), 0,
-                       P->side_stream, b, n, nrhs, kNormRows, P->d_work + 2 * nn + NL.r_parts);
+    hipLaunchKernelGGL(mf::k_colsq_partial, dim3((unsigned)NL.b_blocks), dim3(256), 0, s, b, n,
+                       nrhs, kNormRows, P->d_work + 2 * nn + NL.r_parts);
     HIPCHK(hipGetLastError());
   }
   if ((rc = launch_factor_solve(P, elem_mats, precision, b, x, nrhs, s))) return rc;
-  // the pivot status travels with the first residual's norms: one synchronization for both
-  HIPCHK(hipMemcpyAsync(P->h_status, P->d_status, mf::kStatusWords * sizeof(int),
-                        hipMemcpyDeviceToHost, s));
+  // the pivot status travels with the first residual's norms (k_norm_publish): one
+  // synchronization for both
   P->factored = true;     // withdrawn by refine_loop if the status reports a bad pivot
   return refine_loop(P, elem_mats, b, x, nrhs, tol, max_it, its, relres, hip_stream, true, true);
 }

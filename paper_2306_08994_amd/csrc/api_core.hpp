@@ -45,13 +45,13 @@ inline int fail(int code, const std::string &msg) {
 enum Kind {
   K_TINY, K_SMALL, K_ASSEMBLE, K_FUSED, K_TRSM, K_GEMM_PANEL, K_GEMM_SCHUR,
   K_DOWN_WAVE, K_DOWN_BLOCK, K_UP_WAVE, K_UP_BLOCK, K_DOWN_RECT, K_UP_RECT, K_RESIDUAL,
-  K_DIAG_INV, K_CLASS, K_PANEL_LA, K_OTHER, K_COUNT
+  K_DIAG_INV, K_CLASS, K_PANEL_LA, K_SUB_FACTOR, K_SUB_DOWN, K_SUB_UP, K_OTHER, K_COUNT
 };
 static const char *const kKindName[K_COUNT] = {
     "factor_tiny", "factor_small", "assemble", "front_panels", "panel_lu_trsm", "gemm_panel",
     "gemm_schur", "solve_down_wave", "solve_down_block", "solve_up_wave", "solve_up_block",
     "solve_down_rect", "solve_up_rect", "residual", "diag_block_inverse", "class_tiled",
-    "panel_lookahead", "other"};
+    "panel_lookahead", "factor_subtree", "solve_down_subtree", "solve_up_subtree", "other"};
 
 // Algorithmic traffic and work of one launch (bytes that must cross HBM at least once, flops
 // of the method's own operation count).
@@ -103,6 +103,20 @@ struct LevelDev {
   bool rect_q_down = false, rect_q_up = false; // ... in slabs of 16 rows (quarter form)
 };
 
+// Bottom subtrees of the first ncls classes run as one launch (see k_factor_subtree): the wave
+// records unit after unit, class after class, and ptr[u * ncls + c] = first record of unit u's
+// class c.  ncls = 0: the classes run one launch each.
+struct SubtreeDev {
+  int32_t ncls = 0;
+  int64_t nsub = 0, nrec = 0;
+  mf::WaveRec *d_rec = nullptr;
+  int32_t *d_ptr = nullptr;
+  int32_t max_m = 0, max_k = 0;
+  Cost c_factor;                       // factor: the classes' tiny-route cost
+  double down_coef = 0, down_rhs_bytes = 0, down_rhs_flops = 0;   // solves: the classes' sums
+  double up_coef = 0, up_rhs_bytes = 0, up_rhs_flops = 0;
+};
+
 struct ProfRec {
   int kind;
   int cls;          // Foata class of the launch (-1: not a class's launch)
@@ -150,6 +164,7 @@ struct mf_plan {
   bool factored = false;
   bool use_graphs = true;
   int max_shared = 65536;
+  int n_cu = 256;             // compute units of the plan's device
   mf::FrontDesc *d_desc = nullptr;
   int32_t *d_front_idx = nullptr, *d_inv_l = nullptr, *d_inv_r = nullptr, *d_conn = nullptr;
   int64_t *d_nptr = nullptr;
@@ -181,13 +196,23 @@ struct mf_plan {
   size_t ycb_cap = 0;
   double *d_work = nullptr;
   size_t work_cap = 0;
-  double *h_part = nullptr;
+  double *h_part = nullptr;   // mapped host memory of the final norms (k_norm_publish)
+  double *d_hpart = nullptr;  // its device address
+  int *d_hstatus = nullptr;   // device address of h_status (mapped host memory)
+  int *d_pub_count = nullptr; // workgroups of k_norm_publish done (zero between launches)
+  int pub_seq = 0;            // sequence number of the last k_norm_publish
   size_t part_cap = 0;
   double *d_kry = nullptr;    // Krylov workspace of mf_refine_gmres
   size_t kry_cap = 0;
   double *h_kry = nullptr;    // pinned host staging of its dot products and coefficients
   size_t hkry_cap = 0;
   std::vector<mfapi::LevelDev> lv;
+  // bottom-subtree launches of the factorization and of the solves, and their settings: at most
+  // sub_max_classes classes (-1: as many as the routes allow; off by default: the per-class
+  // launches measured faster on the 2D and 3D workloads), units at least sub_min_units
+  mfapi::SubtreeDev sub_f, sub_s;
+  int32_t sub_max_classes = 0;
+  int64_t sub_min_units = 2048;
   mfapi::Profiler prof;
   hipStream_t cap_stream = nullptr;
   // second stream of the overlapped factor + forward solve, and its per-class events
@@ -228,6 +253,10 @@ struct mf_plan {
     mfapi::dfree(d_tasks);
     mfapi::dfree(d_rect);
     mfapi::dfree(d_wrec);
+    mfapi::dfree(sub_f.d_rec);
+    mfapi::dfree(sub_f.d_ptr);
+    mfapi::dfree(sub_s.d_rec);
+    mfapi::dfree(sub_s.d_ptr);
     mfapi::dfree(d_panel);
     mfapi::dfree(d_store);
     mfapi::dfree(d_dinv);
@@ -243,5 +272,6 @@ struct mf_plan {
     if (h_part) (void)hipHostFree(h_part);
     if (h_kry) (void)hipHostFree(h_kry);
     mfapi::dfree(d_kry);
+    mfapi::dfree(d_pub_count);
   }
 };

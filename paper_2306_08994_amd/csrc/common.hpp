@@ -101,6 +101,10 @@ template <bool ADD>
 __device__ inline void scatter_source(const double *__restrict__ src, int lda, int n,
                                       const int *map, int ld, double *sh, int t0, int nt) {
   const int nn = n * n;
+  if (nn == 0) return;
+  // (r, c) of entry t, advanced by nt entries per step without a division
+  const int dr = nt / n, dc = nt - dr * n;
+  int r = t0 / n, c = t0 - r * n;
   for (int tb = t0; tb < nn; tb += 4 * nt) {
     double v[4];
     int dst[4];
@@ -110,9 +114,14 @@ __device__ inline void scatter_source(const double *__restrict__ src, int lda, i
       dst[u] = -1;
       v[u] = 0.0;
       if (t < nn) {
-        const int r = t / n, c = t - (t / n) * n;
         v[u] = src[(int64_t)r * lda + c];
         dst[u] = map[r] * ld + map[c];
+      }
+      c += dc;
+      r += dr;
+      if (c >= n) {
+        c -= n;
+        ++r;
       }
     }
 #pragma unroll

@@ -76,8 +76,59 @@ __device__ __forceinline__ void scatter_staged(const double (&v)[U], int n, cons
   }
 }
 
-// U = ceil(mmax^2 / 64): the class's widest tiny front bounds every source (a child's CB and an
-// element matrix are never wider than the front they enter).
+// One tiny front, by one wave: the record's maps and both sources staged in registers, the
+// scatter into the LDS front sh (rows ld = m | 1 apart; ma / mb: 2 * mmax ints of map scratch),
+// the k pivot steps, the store of the front.  U = ceil(mmax^2 / 64): the widest front of the
+// launch bounds every source (a child's CB and an element matrix are never wider than the
+// front they enter).
+template <int U>
+__device__ __forceinline__ void tiny_front(const WaveRec r, int lane, double *sh, int *ma,
+                                           int *mb, double *store, const int32_t *inv_l,
+                                           const int32_t *inv_r, const double *K, int *status) {
+  const int m = r.m, k = r.k, ld = m | 1;
+  int xa = -1, xb = -1;
+  if (lane < m) {
+    xa = inv_l[r.idx + lane];
+    if (r.n[1] > 0) xb = inv_r[r.idx + lane];
+  }
+  double va[U], vb[U];
+  stage_source<U>(rec_source(r.src[0], store, K), r.ld[0], r.n[0], lane, va);
+  stage_source<U>(rec_source(r.src[1], store, K), r.ld[1], r.n[1], lane, vb);
+  for (int t = lane; t < m * ld; t += 64) sh[t] = 0.0;
+  if (xa >= 0) ma[xa] = lane;
+  if (xb >= 0) mb[xb] = lane;
+  wave_sync();
+  // the left source assigned, then the right one added: each front entry is summed left
+  // then right, as in the extend-add of the two children
+  scatter_staged<false, U>(va, r.n[0], ma, ld, sh, lane);
+  wave_sync();
+  scatter_staged<true, U>(vb, r.n[1], mb, ld, sh, lane);
+  wave_sync();
+  // pivot steps: lane (h, jj) owns column p + 1 + jj of the rows p + 1 + h, p + 3 + h, ...
+  // (m <= 32: one column per half-wave lane); its multiplier u = F[p][j] / piv stays in a
+  // register, written back to row p by the first half
+  const int jj = lane & 31, h = lane >> 5;
+  for (int p = 0; p < k; ++p) {
+    const double piv = sh[p * ld + p];
+    if (!good_pivot(piv)) {
+      if (lane == 0) record_bad_pivot(status, r.f, p);
+      break;
+    }
+    const int j = p + 1 + jj;
+    if (j < m) {
+      const double u = sh[p * ld + j] / piv;
+      if (h == 0) sh[p * ld + j] = u;
+#pragma unroll 4
+      for (int i = p + 1 + h; i < m; i += 2) sh[i * ld + j] -= sh[i * ld + p] * u;
+    }
+    wave_sync();
+  }
+  double *out = store + r.store;
+  if (jj < m)
+    for (int i = h; i < m; i += 2) out[i * m + jj] = sh[i * ld + jj];
+  wave_sync();
+}
+
 template <int U>
 __global__ void __launch_bounds__(256)
 k_factor_tiny(const WaveRec *__restrict__ recs, int nrec, double *__restrict__ store,
@@ -89,53 +140,45 @@ k_factor_tiny(const WaveRec *__restrict__ recs, int nrec, double *__restrict__ s
   double *sh = sm + wv * ldsw;
   int *ma = reinterpret_cast<int *>(sh + (ldsw - mmax));   // 2 * mmax ints after the front
   int *mb = ma + mmax;
-  for (int li = blockIdx.x * 4 + wv; li < nrec; li += gridDim.x * 4) {
-    const WaveRec r = recs[li];
-    const int m = r.m, k = r.k, ld = m | 1;
-    int xa = -1, xb = -1;
-    if (lane < m) {
-      xa = inv_l[r.idx + lane];
-      if (r.n[1] > 0) xb = inv_r[r.idx + lane];
+  for (int li = blockIdx.x * 4 + wv; li < nrec; li += gridDim.x * 4)
+    tiny_front<U>(recs[li], lane, sh, ma, mb, store, inv_l, inv_r, K, status);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Bottom subtrees: classes 0..ncls-1 of the tiny route in one launch.  A unit is a front of
+// class < ncls whose parent lies above that range (or a root), with all its descendants; one
+// workgroup takes a unit's fronts class by class, one front per wave, with a workgroup barrier
+// between classes.  Every child of a front is in the front's unit and was stored by the same
+// workgroup before the barrier, so the barrier between Foata classes (Sec. 3.3) holds inside
+// the unit without a launch per class.  Records unit after unit, class after class:
+// ptr[u * ncls + c] is the first record of unit u's class c (ptr[nsub * ncls] = the total).
+// Each front is the tiny route's arithmetic in the same order, so the results are identical.
+// ---------------------------------------------------------------------------------------------
+template <int U>
+__global__ void __launch_bounds__(256)
+k_factor_subtree(const WaveRec *__restrict__ recs, const int32_t *__restrict__ ptr, int nsub,
+                 int ncls, double *store, const int32_t *__restrict__ inv_l,
+                 const int32_t *__restrict__ inv_r, const double *__restrict__ K,
+                 int *__restrict__ status, int ldsw, int mmax) {
+  extern __shared__ double sm[];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  double *sh = sm + wv * ldsw;
+  int *ma = reinterpret_cast<int *>(sh + (ldsw - mmax));
+  int *mb = ma + mmax;
+  for (int u = blockIdx.x; u < nsub; u += gridDim.x) {
+    const int32_t *pu = ptr + (int64_t)u * ncls;
+    for (int c = 0; c < ncls; ++c) {
+      const int a = pu[c], e = pu[c + 1];
+      for (int li = a + wv; li < e; li += 4)
+        tiny_front<U>(recs[li], lane, sh, ma, mb, store, inv_l, inv_r, K, status);
+      __syncthreads();   // the class's fronts stored before the next class gathers them
     }
-    double va[U], vb[U];
-    stage_source<U>(rec_source(r.src[0], store, K), r.ld[0], r.n[0], lane, va);
-    stage_source<U>(rec_source(r.src[1], store, K), r.ld[1], r.n[1], lane, vb);
-    for (int t = lane; t < m * ld; t += 64) sh[t] = 0.0;
-    if (xa >= 0) ma[xa] = lane;
-    if (xb >= 0) mb[xb] = lane;
-    wave_sync();
-    // the left source assigned, then the right one added: each front entry is summed left
-    // then right, as in the extend-add of the two children
-    scatter_staged<false, U>(va, r.n[0], ma, ld, sh, lane);
-    wave_sync();
-    scatter_staged<true, U>(vb, r.n[1], mb, ld, sh, lane);
-    wave_sync();
-    for (int p = 0; p < k; ++p) {
-      const double piv = sh[p * ld + p];
-      if (!good_pivot(piv)) {
-        if (lane == 0) record_bad_pivot(status, r.f, p);
-        break;
-      }
-      for (int j = p + 1 + lane; j < m; j += 64) sh[p * ld + j] = sh[p * ld + j] / piv;
-      wave_sync();
-      const int rr = m - p - 1;
-      for (int t = lane; t < rr * rr; t += 64) {
-        const int i = p + 1 + t / rr, j = p + 1 + (t - (t / rr) * rr);
-        sh[i * ld + j] -= sh[i * ld + p] * sh[p * ld + j];
-      }
-      wave_sync();
-    }
-    double *out = store + r.store;
-    for (int t = lane; t < m * m; t += 64) {
-      const int i = t / m, j = t - (t / m) * m;
-      out[t] = sh[i * ld + j];
-    }
-    wave_sync();
   }
 }
 
 // ---------------------------------------------------------------------------------------------
-// small: one workgroup of SM_THREADS per front, the whole front resident in LDS, eliminated in
+// small: one workgroup of NT threads per front, the whole front resident in LDS, eliminated in
 // panels of SM_NB pivots (Table 2's division, multiplication and subtraction tasks, blocked):
 //   1. wave 0 factors the pb x pb diagonal block (register resident, readlane broadcasts);
 //   2. one thread per column solves U12 = L11^{-1} A12 (the division tasks of the panel's rows
@@ -145,16 +188,20 @@ k_factor_tiny(const WaveRec *__restrict__ recs, int nrec, double *__restrict__ s
 //      of v_mfma_f64_16x16x4f64 with operands and results in LDS.
 // Three barriers per panel instead of one per pivot, and one LDS read and write of each trailing
 // entry per panel instead of per pivot.  LDS: front (m rows of m|1) | D (NB x NB+1) | rd (NB) |
-// extend-add maps (2 m ints).
+// extend-add maps (2 m ints).  NT = 512 when a class has few fronts (each front's steps spread
+// over eight waves); 256 when it has more fronts than the chip has compute units, so that more
+// fronts are resident at once (the kernel's register use allows three waves per SIMD: one
+// 512-thread workgroup per compute unit, or three of 256).
 // ---------------------------------------------------------------------------------------------
-constexpr int SM_THREADS = 512;
+constexpr int SM_THREADS = 512;      // the larger workgroup of the small route
 constexpr int SM_NB = 8;
 
 __host__ __device__ inline int64_t small_lds_doubles(int m) {
   return (int64_t)m * (m | 1) + SM_NB * (SM_NB + 1) + SM_NB + m;
 }
 
-__global__ void __launch_bounds__(SM_THREADS)
+template <int NT>
+__global__ void __launch_bounds__(NT)
 k_factor_small(const WaveRec *__restrict__ recs, int nrec, double *__restrict__ store,
                const int32_t *__restrict__ inv_l, const int32_t *__restrict__ inv_r,
                const double *__restrict__ K, int *__restrict__ status, int mmax) {
@@ -173,7 +220,7 @@ k_factor_small(const WaveRec *__restrict__ recs, int nrec, double *__restrict__ 
     const int m = d.m, k = d.k, ld = m | 1;
     const GatherCtx g = rec_gather_ctx(d, store, K);
     if (tid == 0) s_bad = 0;
-    scatter_assemble(g, inv_l + d.idx, inv_r + d.idx, m, ld, sh, ma, mb, tid, SM_THREADS,
+    scatter_assemble(g, inv_l + d.idx, inv_r + d.idx, m, ld, sh, ma, mb, tid, NT,
                      [] __device__() { __syncthreads(); });
     for (int p0 = 0; p0 < k; p0 += NB) {
       const int pb = min(NB, k - p0), pe = p0 + pb, rest = m - pe;
@@ -185,7 +232,7 @@ k_factor_small(const WaveRec *__restrict__ recs, int nrec, double *__restrict__ 
       // 2. U12 columns (items t < rest) and L21 rows (items from the next multiple of 64, so
       //    that no wave holds both kinds); positions beyond pb meet the identity padding of D
       const int rpad = (rest + 63) & ~63;
-      for (int t = tid; t < rpad + rest; t += SM_THREADS) {
+      for (int t = tid; t < rpad + rest; t += NT) {
         if (t < rest) {
           double *cp = sh + p0 * ld + pe + t;
           double v[NB];
@@ -223,7 +270,7 @@ k_factor_small(const WaveRec *__restrict__ recs, int nrec, double *__restrict__ 
       //    time: A operand lane l = L21[row l%16][q = l/16 + 4s] (negated), B operand lane l =
       //    U12[q = l/16 + 4s][col l%16], result lane l register r at row 4r + l/16, col l%16
       const int nbk = (rest + 15) >> 4;
-      for (int blk = wv; blk < nbk * nbk; blk += SM_THREADS / 64) {
+      for (int blk = wv; blk < nbk * nbk; blk += NT / 64) {
         const int bi = blk / nbk, bj = blk - bi * nbk;
         const int r0 = pe + 16 * bi, c0 = pe + 16 * bj;
         const int col = c0 + li;
@@ -250,9 +297,18 @@ k_factor_small(const WaveRec *__restrict__ recs, int nrec, double *__restrict__ 
       __syncthreads();
     }
     double *out = store + d.store;
-    for (int t = tid; t < m * m; t += SM_THREADS) {
-      const int i = t / m, jj = t - (t / m) * m;
-      out[t] = sh[i * ld + jj];
+    {
+      const int di = NT / m, dj = NT - di * m;
+      int i = tid / m, jj = tid - i * m;
+      for (int t = tid; t < m * m; t += NT) {
+        out[t] = sh[i * ld + jj];
+        jj += dj;
+        i += di;
+        if (jj >= m) {
+          jj -= m;
+          ++i;
+        }
+      }
     }
     __syncthreads();
   }

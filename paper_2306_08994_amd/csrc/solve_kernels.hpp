@@ -48,6 +48,133 @@ __device__ inline void copy_strided(const double *__restrict__ src, int64_t stri
   }
 }
 
+// The down sweep of one front by one wave: W (mmax x nc), C (mmax rows of cld) and rdv (64)
+// are the wave's LDS.
+template <bool TRANS>
+__device__ __forceinline__ void down_wave_front(const WaveRec d, int lane, double *W, double *C,
+                                                double *rdv, const double *store,
+                                                const int32_t *front_idx, const int32_t *inv_l,
+                                                const int32_t *inv_r, const double *b, double *x,
+                                                double *ycb, int nrhs, int nc, int cld) {
+  const int m = d.m, k = d.k;
+  const double *F = store + d.store;
+  // children that pass a contribution block (a pass-through leaf passes none)
+  const bool use_a = d.ycb[0] >= 0, use_c = d.ycb[1] >= 0;
+  const int i = lane;                               // this lane's row
+  int64_t gi = 0;
+  int xa = -1, xc = -1;
+  if (i < m) {
+    gi = front_idx[d.idx + i];
+    if (use_a) xa = inv_l[d.idx + i];
+    if (use_c) xc = inv_r[d.idx + i];
+    const int np = min(i + 1, k);
+    if (TRANS)
+      copy_strided(F + i, m, np, C + i * cld, 1);            // U[p][i], p <= i
+    else
+      copy_strided(F + (int64_t)i * m, 1, np, C + i * cld, 1);   // L[i][p], p <= i
+  }
+  wave_sync();
+  if (i < k) rdv[i] = TRANS ? 1.0 : 1.0 / C[i * cld + i];
+  for (int r0 = 0; r0 < nrhs; r0 += nc) {
+    const int nr = min(nc, nrhs - r0);
+    if (i < m)
+      for (int rb = 0; rb < nr; rb += kRhsBatch) {     // loads of a batch in flight together
+        double v[kRhsBatch];
+#pragma unroll
+        for (int u = 0; u < kRhsBatch; ++u) {
+          const int r = rb + u;
+          v[u] = 0.0;
+          if (r < nr) {
+            if (i < k) v[u] = b[gi * nrhs + r0 + r];
+            if (xa >= 0) v[u] += ycb[(d.ycb[0] + xa) * nrhs + r0 + r];
+            if (xc >= 0) v[u] += ycb[(d.ycb[1] + xc) * nrhs + r0 + r];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kRhsBatch; ++u)
+          if (rb + u < nr) W[i * nr + rb + u] = v[u];
+      }
+    wave_sync();
+    // lane (la, lr): right-hand sides lr, lr + 64, ... of the rows la, la + rs, ... (rs rows
+    // per pass; one row and several sides per lane when nr >= 64)
+    const int rs = nr >= 64 ? 1 : 64 / nr, la = nr >= 64 ? 0 : lane / nr, lr = lane - la * nr;
+    const bool act = la < rs;
+    for (int p = 0; p < k; ++p) {
+      if (act)
+        for (int c = lr; c < nr; c += 64) {
+          const double wp = W[p * nr + c] * rdv[p];
+          for (int ii = p + 1 + la; ii < m; ii += rs) W[ii * nr + c] -= C[ii * cld + p] * wp;
+        }
+      wave_sync();
+    }
+    // pivot rows: y = w / L_pp (row p is final after step p); CB rows: the contribution block
+    if (i < k)
+      for (int r = 0; r < nr; ++r) x[gi * nrhs + r0 + r] = W[i * nr + r] * rdv[i];
+    else if (i < m)
+      for (int r = 0; r < nr; ++r) ycb[(d.cbrow + i - k) * nrhs + r0 + r] = W[i * nr + r];
+    wave_sync();
+  }
+}
+
+// The up sweep of one front by one wave (LDS as in down_wave_front; C column-major here).
+template <bool TRANS>
+__device__ __forceinline__ void up_wave_front(const WaveRec d, int lane, double *W, double *C,
+                                              double *rdv, const double *store,
+                                              const int32_t *front_idx, double *x, int nrhs,
+                                              int nc, int cld) {
+  const int m = d.m, k = d.k;
+  const double *F = store + d.store;
+  const int j = lane;                               // this lane's row / column
+  int64_t gj = 0;
+  if (j < m) {
+    gj = front_idx[d.idx + j];
+    const int nq = min(j + 1, k);
+    if (TRANS)
+      copy_strided(F + (int64_t)j * m, 1, nq, C + j * cld, 1);   // L[j][q], q <= j
+    else
+      copy_strided(F + j, m, nq, C + j * cld, 1);                // U[q][j], q <= j
+  }
+  wave_sync();
+  if (j < k) rdv[j] = TRANS ? 1.0 / C[j * cld + j] : 1.0;
+  for (int r0 = 0; r0 < nrhs; r0 += nc) {
+    const int nr = min(nc, nrhs - r0);
+    if (j < m)
+      for (int rb = 0; rb < nr; rb += kRhsBatch) {
+        double v[kRhsBatch];
+#pragma unroll
+        for (int u = 0; u < kRhsBatch; ++u) v[u] = rb + u < nr ? x[gj * nrhs + r0 + rb + u] : 0.0;
+#pragma unroll
+        for (int u = 0; u < kRhsBatch; ++u)
+          if (rb + u < nr) W[j * nr + rb + u] = v[u];
+      }
+    wave_sync();
+    // lane (la, lr): right-hand sides lr, lr + 64, ... of the rows la, la + rs, ... (rs rows
+    // per pass; one row and several sides per lane when nr >= 64)
+    const int rs = nr >= 64 ? 1 : 64 / nr, la = nr >= 64 ? 0 : lane / nr, lr = lane - la * nr;
+    const bool act = la < rs;
+    // the already-final CB unknowns applied to the pivot rows
+    if (act)
+      for (int p = la; p < k; p += rs)
+        for (int c = lr; c < nr; c += 64) {
+          double s = 0.0;
+          for (int jj = k; jj < m; ++jj) s += C[jj * cld + p] * W[jj * nr + c];
+          W[p * nr + c] -= s;
+        }
+    wave_sync();
+    for (int p = k - 1; p >= 0; --p) {
+      if (act)
+        for (int c = lr; c < nr; c += 64) {
+          const double wp = W[p * nr + c] * rdv[p];
+          for (int q = la; q < p; q += rs) W[q * nr + c] -= C[p * cld + q] * wp;
+        }
+      wave_sync();
+    }
+    if (j < k)
+      for (int r = 0; r < nr; ++r) x[gj * nrhs + r0 + r] = W[j * nr + r] * rdv[j];
+    wave_sync();
+  }
+}
+
 template <bool TRANS>
 __global__ void __launch_bounds__(256)
 k_solve_down_wave(const WaveRec *__restrict__ recs, int nrec,
@@ -61,63 +188,9 @@ k_solve_down_wave(const WaveRec *__restrict__ recs, int nrec,
   double *W = sm + wv * ldsw;
   double *C = W + mmax * nc;       // C[i * cld + p] = cd(i, p), p <= i, p < k
   double *rdv = C + mmax * cld;    // reciprocal of each pivot's diagonal coefficient
-  for (int li = blockIdx.x * 4 + wv; li < nrec; li += gridDim.x * 4) {
-    const WaveRec d = recs[li];
-    const int m = d.m, k = d.k;
-    const double *F = store + d.store;
-    // children that pass a contribution block (a pass-through leaf passes none)
-    const bool use_a = d.ycb[0] >= 0, use_c = d.ycb[1] >= 0;
-    const int i = lane;                               // this lane's row
-    int64_t gi = 0;
-    int xa = -1, xc = -1;
-    if (i < m) {
-      gi = front_idx[d.idx + i];
-      if (use_a) xa = inv_l[d.idx + i];
-      if (use_c) xc = inv_r[d.idx + i];
-      const int np = min(i + 1, k);
-      if (TRANS)
-        copy_strided(F + i, m, np, C + i * cld, 1);            // U[p][i], p <= i
-      else
-        copy_strided(F + (int64_t)i * m, 1, np, C + i * cld, 1);   // L[i][p], p <= i
-    }
-    wave_sync();
-    if (i < k) rdv[i] = TRANS ? 1.0 : 1.0 / C[i * cld + i];
-    for (int r0 = 0; r0 < nrhs; r0 += nc) {
-      const int nr = min(nc, nrhs - r0);
-      if (i < m)
-        for (int rb = 0; rb < nr; rb += kRhsBatch) {     // loads of a batch in flight together
-          double v[kRhsBatch];
-#pragma unroll
-          for (int u = 0; u < kRhsBatch; ++u) {
-            const int r = rb + u;
-            v[u] = 0.0;
-            if (r < nr) {
-              if (i < k) v[u] = b[gi * nrhs + r0 + r];
-              if (xa >= 0) v[u] += ycb[(d.ycb[0] + xa) * nrhs + r0 + r];
-              if (xc >= 0) v[u] += ycb[(d.ycb[1] + xc) * nrhs + r0 + r];
-            }
-          }
-#pragma unroll
-          for (int u = 0; u < kRhsBatch; ++u)
-            if (rb + u < nr) W[i * nr + rb + u] = v[u];
-        }
-      wave_sync();
-      for (int p = 0; p < k; ++p) {
-        const double rp = rdv[p];
-        for (int t = lane; t < (m - p - 1) * nr; t += 64) {
-          const int ii = p + 1 + t / nr, r = t - (t / nr) * nr;
-          W[ii * nr + r] -= C[ii * cld + p] * (W[p * nr + r] * rp);
-        }
-        wave_sync();
-      }
-      // pivot rows: y = w / L_pp (row p is final after step p); CB rows: the contribution block
-      if (i < k)
-        for (int r = 0; r < nr; ++r) x[gi * nrhs + r0 + r] = W[i * nr + r] * rdv[i];
-      else if (i < m)
-        for (int r = 0; r < nr; ++r) ycb[(d.cbrow + i - k) * nrhs + r0 + r] = W[i * nr + r];
-      wave_sync();
-    }
-  }
+  for (int li = blockIdx.x * 4 + wv; li < nrec; li += gridDim.x * 4)
+    down_wave_front<TRANS>(recs[li], lane, W, C, rdv, store, front_idx, inv_l, inv_r, b, x, ycb,
+                           nrhs, nc, cld);
 }
 
 template <bool TRANS>
@@ -131,53 +204,62 @@ k_solve_up_wave(const WaveRec *__restrict__ recs, int nrec,
   double *W = sm + wv * ldsw;
   double *C = W + mmax * nc;       // C[j * cld + q] = cu(q, j), q <= j, q < k  (column-major)
   double *rdv = C + mmax * cld;
-  for (int li = blockIdx.x * 4 + wv; li < nrec; li += gridDim.x * 4) {
-    const WaveRec d = recs[li];
-    const int m = d.m, k = d.k;
-    const double *F = store + d.store;
-    const int j = lane;                               // this lane's row / column
-    int64_t gj = 0;
-    if (j < m) {
-      gj = front_idx[d.idx + j];
-      const int nq = min(j + 1, k);
-      if (TRANS)
-        copy_strided(F + (int64_t)j * m, 1, nq, C + j * cld, 1);   // L[j][q], q <= j
-      else
-        copy_strided(F + j, m, nq, C + j * cld, 1);                // U[q][j], q <= j
+  for (int li = blockIdx.x * 4 + wv; li < nrec; li += gridDim.x * 4)
+    up_wave_front<TRANS>(recs[li], lane, W, C, rdv, store, front_idx, x, nrhs, nc, cld);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Bottom subtrees of the wave route in one launch per sweep (units and record order as for
+// k_factor_subtree): the down sweep takes a unit's classes 0..ncls-1 in turn, the up sweep
+// ncls-1..0, one front per wave, a workgroup barrier between classes.  The contribution blocks
+// a front gathers (down) and the ancestor values it reads (up) were written by this workgroup
+// before the barrier or by an earlier launch.  Per front the wave route's arithmetic, so the
+// results are identical to the per-class launches.
+// ---------------------------------------------------------------------------------------------
+template <bool TRANS>
+__global__ void __launch_bounds__(256)
+k_solve_down_subtree(const WaveRec *__restrict__ recs, const int32_t *__restrict__ ptr,
+                     int nsub, int ncls, const double *__restrict__ store,
+                     const int32_t *__restrict__ front_idx, const int32_t *__restrict__ inv_l,
+                     const int32_t *__restrict__ inv_r, const double *b, double *x, double *ycb,
+                     int nrhs, int nc, int mmax, int cld, int ldsw) {
+  extern __shared__ double sm[];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  double *W = sm + wv * ldsw;
+  double *C = W + mmax * nc;
+  double *rdv = C + mmax * cld;
+  for (int u = blockIdx.x; u < nsub; u += gridDim.x) {
+    const int32_t *pu = ptr + (int64_t)u * ncls;
+    for (int c = 0; c < ncls; ++c) {
+      const int a = pu[c], e = pu[c + 1];
+      for (int li = a + wv; li < e; li += 4)
+        down_wave_front<TRANS>(recs[li], lane, W, C, rdv, store, front_idx, inv_l, inv_r, b, x,
+                               ycb, nrhs, nc, cld);
+      __syncthreads();   // the class's contribution blocks written before the next class
     }
-    wave_sync();
-    if (j < k) rdv[j] = TRANS ? 1.0 / C[j * cld + j] : 1.0;
-    for (int r0 = 0; r0 < nrhs; r0 += nc) {
-      const int nr = min(nc, nrhs - r0);
-      if (j < m)
-        for (int rb = 0; rb < nr; rb += kRhsBatch) {
-          double v[kRhsBatch];
-#pragma unroll
-          for (int u = 0; u < kRhsBatch; ++u) v[u] = rb + u < nr ? x[gj * nrhs + r0 + rb + u] : 0.0;
-#pragma unroll
-          for (int u = 0; u < kRhsBatch; ++u)
-            if (rb + u < nr) W[j * nr + rb + u] = v[u];
-        }
-      wave_sync();
-      // the already-final CB unknowns applied to the pivot rows
-      for (int t = lane; t < k * nr; t += 64) {
-        const int p = t / nr, r = t - (t / nr) * nr;
-        double s = 0.0;
-        for (int jj = k; jj < m; ++jj) s += C[jj * cld + p] * W[jj * nr + r];
-        W[p * nr + r] -= s;
-      }
-      wave_sync();
-      for (int p = k - 1; p >= 0; --p) {
-        const double rp = rdv[p];
-        for (int t = lane; t < p * nr; t += 64) {
-          const int q = t / nr, r = t - (t / nr) * nr;
-          W[q * nr + r] -= C[p * cld + q] * (W[p * nr + r] * rp);
-        }
-        wave_sync();
-      }
-      if (j < k)
-        for (int r = 0; r < nr; ++r) x[gj * nrhs + r0 + r] = W[j * nr + r] * rdv[j];
-      wave_sync();
+  }
+}
+
+template <bool TRANS>
+__global__ void __launch_bounds__(256)
+k_solve_up_subtree(const WaveRec *__restrict__ recs, const int32_t *__restrict__ ptr, int nsub,
+                   int ncls, const double *__restrict__ store,
+                   const int32_t *__restrict__ front_idx, double *x, int nrhs, int nc, int mmax,
+                   int cld, int ldsw) {
+  extern __shared__ double sm[];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  double *W = sm + wv * ldsw;
+  double *C = W + mmax * nc;
+  double *rdv = C + mmax * cld;
+  for (int u = blockIdx.x; u < nsub; u += gridDim.x) {
+    const int32_t *pu = ptr + (int64_t)u * ncls;
+    for (int c = ncls - 1; c >= 0; --c) {
+      const int a = pu[c], e = pu[c + 1];
+      for (int li = a + wv; li < e; li += 4)
+        up_wave_front<TRANS>(recs[li], lane, W, C, rdv, store, front_idx, x, nrhs, nc, cld);
+      __syncthreads();   // the class's values written before its children read them
     }
   }
 }
@@ -816,6 +898,44 @@ k_residual(const int64_t *__restrict__ nptr, const int32_t *__restrict__ nelem,
     double q = 0.0;
     for (int j = threadIdx.x; j < 256; j += nrhs) q += red[j];
     part[(int64_t)blockIdx.x * nrhs + threadIdx.x] = q;
+  }
+}
+
+// The column sums of the partial sums of squares of the residual (and of b, bblocks > 0),
+// written with the factorization's status words (status non-null) straight into mapped host
+// memory: out[c] = sum over blocks of rpart[block][c], out[nrhs + c] the same of bpart.  One
+// workgroup per column and vector; each thread adds its blocks in ascending order, then a fixed
+// tree adds the threads: deterministic.  Each workgroup makes its writes visible to the host
+// and counts itself in *count; the last one resets the count and writes seq to *seq_out, after
+// which every value is readable by a host that sees seq.
+__global__ void __launch_bounds__(256)
+k_norm_publish(const double *__restrict__ rpart, int64_t rblocks,
+               const double *__restrict__ bpart, int64_t bblocks, int nrhs,
+               const int *__restrict__ status, double *out, int *out_status, int *count,
+               int *seq_out, int seq) {
+  __shared__ double red[256];
+  const int c = blockIdx.x % nrhs;
+  const bool isb = (int)blockIdx.x >= nrhs;
+  const double *part = isb ? bpart : rpart;
+  const int64_t nb = isb ? bblocks : rblocks;
+  double s = 0.0;
+  for (int64_t bl = threadIdx.x; bl < nb; bl += 256) s += part[bl * nrhs + c];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[blockIdx.x] = red[0];
+    if (blockIdx.x == 0 && status)
+      for (int w = 0; w < kStatusWords; ++w) out_status[w] = status[w];
+    __threadfence_system();
+    if (atomicAdd(count, 1) == (int)gridDim.x - 1) {
+      *count = 0;
+      __threadfence_system();
+      __hip_atomic_store(seq_out, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
   }
 }
 

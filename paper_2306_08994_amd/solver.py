@@ -14,7 +14,12 @@ PRECISIONS = {"fp64": _lib.MF_FP64, "fp32": _lib.MF_SCHUR_FP32, "bf16": _lib.MF_
 
 
 def _stream():
+    """The current HIP stream of the current device (its raw handle: building a Stream object
+    per call costs more than the rest of a call's marshalling)."""
     import torch
+    raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+    if raw is not None:
+        return ctypes.c_void_p(raw(torch.cuda.current_device()))
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
@@ -126,6 +131,20 @@ class Plan:
         arr = np.ascontiguousarray([[int(c[k]) for k in keys] for c in classes], dtype=np.int32)
         check(_lib.load().mf_set_class_tuning(self._h, len(classes),
                                               ctypes.c_void_p(arr.ctypes.data)))
+
+    def set_subtree_launch(self, max_classes: int = -1, min_units: int = 2048):
+        """Bottom-subtree launches (see mf_set_subtree_launch): at most max_classes leading
+        classes as one launch (-1: as the routes allow, 0 / 1: off, the library's default), with
+        >= min_units units."""
+        self.factor_version += 1
+        check(_lib.load().mf_set_subtree_launch(self._h, int(max_classes), int(min_units)))
+
+    def subtree_launch_info(self) -> dict:
+        """Classes fused and units of the factorization's and the solves' subtree launches."""
+        out = (ctypes.c_int64 * 4)()
+        check(_lib.load().mf_subtree_launch_info(self._h, out))
+        return {"factor_classes": out[0], "factor_units": out[1], "solve_classes": out[2],
+                "solve_units": out[3]}
 
     def autotune(self, K, precision: str = "fp64", reps: int = 3) -> dict:
         """Times the relevant schedule candidates on K, keeps the fastest (see mf_autotune)."""
