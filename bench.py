@@ -311,12 +311,21 @@ def cpu_pool_baseline(workers=16):
                "ms_per_batch": r["sec"] * 1e3}
 
 
+def tuning_arg(sched):
+    """The --tuning value that reproduces a chosen schedule (one group per class if per-class)."""
+    def grp(c):
+        return ",".join(str(int(c[k])) for k in ("tile", "fused_max_m", "nb", "small_max_m",
+                                                 "persistent"))
+    if sched.get("mode") == "per_class" and sched.get("classes"):
+        return ";".join(grp(c) for c in sched["classes"])
+    return grp(sched)
+
+
 def schedule(plan, K, prec, tuning):
     """The schedule of a run: `tuning` (tile,fused_max_m,nb,small_max_m) if given, else the
-    autotuner's choice on this workload and precision."""
-    if tuning:
-        return given_schedule(plan, tuning)
-    return plan.autotune(K, prec, reps=2)["chosen"]
+    autotuner's choice on this workload and precision; with its --tuning form."""
+    sched = given_schedule(plan, tuning) if tuning else plan.autotune(K, prec, reps=2)["chosen"]
+    return dict(sched, tuning_arg=tuning_arg(sched))
 
 
 SUBTREE = None     # --subtree: (max_classes, min_units) of the bottom-subtree launches
@@ -648,6 +657,7 @@ def main():
         tuned = {"chosen": given_schedule(plan, args.tuning)}
     else:
         tuned = plan.autotune(K, reps=3)      # schedule chosen on this workload, before timing
+    tuned["chosen"]["tuning_arg"] = tuning_arg(tuned["chosen"])
 
     def step():
         # factorization, the first solve with its forward sweep overlapped, FP64 residual check
