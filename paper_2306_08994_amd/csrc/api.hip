@@ -142,7 +142,7 @@ void level_costs(const mf::HostPlan &H, const mf::LevelSchedule &S, LevelDev &D,
     D.down_coef += 8 * (m * k - k * (k - 1) / 2);
     D.down_rhs_bytes += 8 * (k + ch + (m - k) + k);
     D.up_coef += 8 * (m * k - k * (k - 1) / 2);
-    D.up_rhs_bytes += 8 * (m + k);
+    if (d.k > 0) D.up_rhs_bytes += 8 * (m + k);   // a front without pivots has no up-sweep work
     for (int32_t p = 0; p < d.k; ++p) {
       D.down_rhs_flops += 1 + 2 * (m - p - 1);
       D.up_rhs_flops += 2 * (m - p - 1);
@@ -670,6 +670,19 @@ int ensure_uploaded(mf_plan *P) {
   }
   if ((rc = upload(P->d_wrec, wrec))) return rc;
   {
+    // the up sweep's wave records: a front without pivots computes nothing there (its rows are
+    // its ancestors' pivots), and the lower classes hold many of them (element-pair fronts)
+    std::vector<mf::WaveRec> wup;
+    int64_t w = 0;
+    for (size_t l = 0; l < H.levels.size(); ++l) {
+      P->lv[l].rwup = (int64_t)wup.size();
+      for (size_t i = 0; i < H.levels[l].all.size(); ++i, ++w)
+        if (wrec[w].k > 0) wup.push_back(wrec[w]);
+      P->lv[l].n_wup = (int64_t)wup.size() - P->lv[l].rwup;
+    }
+    if ((rc = upload(P->d_wrec_up, wup))) return rc;
+  }
+  {
     // bottom subtrees: the leading classes on the tiny factor route, and on the wave solves
     std::vector<int64_t> wpos(H.F, -1);
     int64_t w = 0;
@@ -1054,6 +1067,8 @@ void solve_level(mf_plan *P, const double *b, double *x, int32_t nrhs, bool tran
         const int ldsw = (int)(mmax * nc + cdoubles);
         const size_t lds = (size_t)4 * ldsw * 8;
         const int grid = (int)std::min<int64_t>((n + 3) / 4, gridcap);
+        const mf::WaveRec *rec_up = P->d_wrec_up + D.rwup;
+        const int grid_up = (int)std::min<int64_t>((D.n_wup + 3) / 4, gridcap);
         if (down && trans)
           LAUNCH(K_DOWN_WAVE, c, mf::k_solve_down_wave<true>, dim3(grid), dim3(256), lds, s, rec,
                  n, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, b, x, ycb, nrhs, nc,
@@ -1062,12 +1077,14 @@ void solve_level(mf_plan *P, const double *b, double *x, int32_t nrhs, bool tran
           LAUNCH(K_DOWN_WAVE, c, mf::k_solve_down_wave<false>, dim3(grid), dim3(256), lds, s, rec,
                  n, P->d_store, P->d_front_idx, P->d_inv_l, P->d_inv_r, b, x, ycb, nrhs, nc,
                  mmax, cld, ldsw);
+        else if (D.n_wup == 0)
+          return;                               // no front of the class has pivots
         else if (trans)
-          LAUNCH(K_UP_WAVE, c, mf::k_solve_up_wave<true>, dim3(grid), dim3(256), lds, s, rec,
-                 n, P->d_store, P->d_front_idx, x, nrhs, nc, mmax, cld, ldsw);
+          LAUNCH(K_UP_WAVE, c, mf::k_solve_up_wave<true>, dim3(grid_up), dim3(256), lds, s,
+                 rec_up, (int)D.n_wup, P->d_store, P->d_front_idx, x, nrhs, nc, mmax, cld, ldsw);
         else
-          LAUNCH(K_UP_WAVE, c, mf::k_solve_up_wave<false>, dim3(grid), dim3(256), lds, s, rec,
-                 n, P->d_store, P->d_front_idx, x, nrhs, nc, mmax, cld, ldsw);
+          LAUNCH(K_UP_WAVE, c, mf::k_solve_up_wave<false>, dim3(grid_up), dim3(256), lds, s,
+                 rec_up, (int)D.n_wup, P->d_store, P->d_front_idx, x, nrhs, nc, mmax, cld, ldsw);
       } else {
         // the pivot block (one workgroup per front, blocks of NBS in sequence) and the
         // rectangular part (many workgroups): down triangle then rect, up rect then triangle
@@ -1157,10 +1174,10 @@ constexpr int kSideStride = 0;
 constexpr bool kSideInterleave = false;
 
 int launch_factor_solve(mf_plan *P, const double *K, int prec, const double *b, double *x,
-                        int32_t nrhs, hipStream_t s) {
+                        int32_t nrhs, hipStream_t s, bool cleared = false) {
   hipStream_t side = P->side_stream;
   const size_t L = P->lv.size();
-  clear_status(P, s);
+  if (!cleared) clear_status(P, s);
   int rc;
   // The second stream's class l needs the factorization of classes <= l.  It joins the
   // caller's stream at "sync" classes: every class from the first one with tiled fronts (from
@@ -1885,17 +1902,19 @@ int mf_factor_refine(mf_plan *P, const double *elem_mats, int32_t precision, con
   // on this platform -- measured: no overlap, 3 % slower than the sequential calls)
   {
     // the norms of b do not depend on the factorization: their partial sums run first, on the
-    // caller's stream (the first launches of a step find the device idle while the host issues
-    // them; a second stream would need an event and a wait, two more host calls)
+    // caller's stream, in the launch that also clears the status words and counters (the first
+    // launches of a step find the device idle while the host issues them; a second stream
+    // would need an event and a wait, two more host calls)
     const int64_t n = P->hp.n;
     const size_t nn = (size_t)n * nrhs;
     const NormLayout NL = norm_layout(n, nrhs);
     if ((rc = grow(P, P->d_work, P->work_cap, 2 * nn + NL.r_parts + NL.b_parts))) return rc;
-    hipLaunchKernelGGL(mf::k_colsq_partial, dim3((unsigned)NL.b_blocks), dim3(256), 0, s, b, n,
-                       nrhs, kNormRows, P->d_work + 2 * nn + NL.r_parts);
+    hipLaunchKernelGGL(mf::k_refine_prologue, dim3((unsigned)NL.b_blocks), dim3(256), 0, s, b, n,
+                       nrhs, kNormRows, P->d_work + 2 * nn + NL.r_parts, P->d_status, P->d_ccnt,
+                       P->n_ccnt);
     HIPCHK(hipGetLastError());
   }
-  if ((rc = launch_factor_solve(P, elem_mats, precision, b, x, nrhs, s))) return rc;
+  if ((rc = launch_factor_solve(P, elem_mats, precision, b, x, nrhs, s, true))) return rc;
   // the pivot status travels with the first residual's norms (k_norm_publish): one
   // synchronization for both
   P->factored = true;     // withdrawn by refine_loop if the status reports a bad pivot

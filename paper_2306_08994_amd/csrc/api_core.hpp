@@ -81,6 +81,7 @@ struct LevelDev {
   int32_t fused_max_m = 0;
   int64_t all = 0, n_all = 0;
   int64_t rall = 0;            // first wave record of the class (records follow `all`)
+  int64_t rwup = 0, n_wup = 0; // the class's fronts with pivots in the up sweep's wave records
   int32_t max_m = 0, max_k = 0;
   std::vector<StepDev> steps;
   int64_t schur = 0, n_schur = 0;
@@ -174,6 +175,7 @@ struct mf_plan {
   int4 *d_rect = nullptr;
   mf::PanelRec *d_panel = nullptr;   // panel records of every step, class after class
   mf::WaveRec *d_wrec = nullptr;   // wave records of every class's front list, class after class
+  mf::WaveRec *d_wrec_up = nullptr;   // the same without fronts that have no pivots (up sweep)
   double *d_store = nullptr;
   // inverses of the diagonal blocks of the fronts the block solves handle (see k_diag_inverse)
   double *d_dinv = nullptr;
@@ -253,6 +255,7 @@ struct mf_plan {
     mfapi::dfree(d_tasks);
     mfapi::dfree(d_rect);
     mfapi::dfree(d_wrec);
+    mfapi::dfree(d_wrec_up);
     mfapi::dfree(sub_f.d_rec);
     mfapi::dfree(sub_f.d_ptr);
     mfapi::dfree(sub_s.d_rec);

@@ -944,10 +944,9 @@ k_norm_publish(const double *__restrict__ rpart, int64_t rblocks,
 // round: every thread keeps one column (its index mod nrhs) and all loads are contiguous; the
 // per-thread sums of a column are then added in a fixed order, so the result is deterministic.
 // Otherwise one column after another.
-__global__ void __launch_bounds__(256)
-k_colsq_partial(const double *__restrict__ a, int64_t n, int nrhs, int64_t rows_per,
-                double *__restrict__ part) {
-  __shared__ double red[256];
+__device__ __forceinline__ void colsq_block(const double *__restrict__ a, int64_t n, int nrhs,
+                                            int64_t rows_per, double *__restrict__ part,
+                                            double *red) {
   const int64_t r0 = (int64_t)blockIdx.x * rows_per;
   const int64_t r1 = min(n, r0 + rows_per);
   if (256 % nrhs == 0) {
@@ -980,6 +979,27 @@ k_colsq_partial(const double *__restrict__ a, int64_t n, int nrhs, int64_t rows_
     if (threadIdx.x == 0) part[(int64_t)blockIdx.x * nrhs + c] = red[0];
     __syncthreads();
   }
+}
+
+__global__ void __launch_bounds__(256)
+k_colsq_partial(const double *__restrict__ a, int64_t n, int nrhs, int64_t rows_per,
+                double *__restrict__ part) {
+  __shared__ double red[256];
+  colsq_block(a, n, nrhs, rows_per, part, red);
+}
+
+// The first launch of a combined factorization and solve: b's partial column sums of squares
+// (as k_colsq_partial) and the clearing of the status words and of the persistent class
+// launches' counters (as k_clear_status_counters), in one launch instead of two.
+__global__ void __launch_bounds__(256)
+k_refine_prologue(const double *__restrict__ b, int64_t n, int nrhs, int64_t rows_per,
+                  double *__restrict__ part, int *__restrict__ st, int *__restrict__ cnt,
+                  int64_t ncnt) {
+  __shared__ double red[256];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < kStatusWords) st[i] = 0;
+  for (int64_t j = i; j < ncnt; j += (int64_t)gridDim.x * 256) cnt[j] = 0;
+  colsq_block(b, n, nrhs, rows_per, part, red);
 }
 
 __global__ void __launch_bounds__(256)
