@@ -69,7 +69,8 @@ KIND_SOURCE = {
     "solve_up_block": "solve_kernels.hpp", "diag_block_inverse": "solve_kernels.hpp",
     "panel_lookahead": "factor_kernels.hpp", "class_tiled": "class_kernels.hpp",
     "factor_subtree": "factor_kernels.hpp", "solve_down_subtree": "solve_kernels.hpp",
-    "solve_up_subtree": "solve_kernels.hpp",
+    "solve_up_subtree": "solve_kernels.hpp", "solve_chunk": "solve_kernels.hpp",
+    "solve_chunk_stage": "solve_kernels.hpp",
 }
 TRAFFIC_TAG = re.compile(r"<!-- traffic kind=(\S+) source=(\S+) sha256=([0-9a-f]{64}) "
                          r"bytes_per_launch=([0-9.eE+]+) -->")
@@ -329,6 +330,7 @@ def schedule(plan, K, prec, tuning):
 
 
 SUBTREE = None     # --subtree: (max_classes, min_units) of the bottom-subtree launches
+CHUNKED = None     # --chunked: min_pivots of the chunked triangle solves
 
 
 def new_plan(meshes):
@@ -337,6 +339,8 @@ def new_plan(meshes):
     plan = Plan(meshes)
     if SUBTREE is not None:
         plan.set_subtree_launch(*SUBTREE)
+    if CHUNKED is not None:
+        plan.set_chunked_solve(CHUNKED)
     return plan
 
 
@@ -611,6 +615,9 @@ def main():
     ap.add_argument("--subtree", default=None,
                     help="max_classes[,min_units] of the bottom-subtree launches (0: per-class "
                          "launches; default: the library's choice)")
+    ap.add_argument("--chunked", type=int, default=None,
+                    help="min_pivots of the chunked triangle solves (0: off; default: the "
+                         "library's choice)")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="run a few steps and a 1 GiB device copy (HBM counter calibration) only")
     args = ap.parse_args()
@@ -622,7 +629,8 @@ def main():
     import torch
 
     from fixtures import config_problem
-    global SUBTREE
+    global SUBTREE, CHUNKED
+    CHUNKED = args.chunked
     if args.subtree:
         v = [int(x) for x in args.subtree.split(",")]
         SUBTREE = (v[0], v[1] if len(v) > 1 else 2048)

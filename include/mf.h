@@ -171,6 +171,15 @@ int mf_set_subtree_launch(mf_plan *plan, int32_t max_classes, int64_t min_units)
  * (0 classes: per-class launches).  Errors: MF_EINVAL, MF_EHIP. */
 int mf_subtree_launch_info(mf_plan *plan, int64_t *out);
 
+/* Chunked triangle solves (no transposition): a class whose widest front has at least
+ * min_pivots pivots solves its fronts' pivot triangles in launches of 128 pivots, one workgroup
+ * per 128-row tile of the rows each chunk updates (every workgroup solving the chunk's own
+ * triangle from its diagonal-block inverses), instead of one workgroup walking each front's
+ * whole triangle; its contribution rows take the rectangular launches.  The same solution up to
+ * rounding.  min_pivots: 0 = off; default 512.  Takes effect at the next device call (the
+ * factorization is kept).  Errors: MF_EINVAL. */
+int mf_set_chunked_solve(mf_plan *plan, int32_t min_pivots);
+
 /* Autotuner: factors elem_mats (device, as in mf_factor) under each candidate schedule that the
  * workload's front widths make relevant -- persistent class launches on/off, GEMM tile 64/32,
  * fused route on/off, panel width 32/64, LDS limit 128/64 -- timing `reps` factorizations of
@@ -203,14 +212,16 @@ int mf_solve(mf_plan *plan, const double *b, double *x, int32_t nrhs, int32_t tr
              void *hip_stream);
 
 /* Largest scratch of mf_solve_noalloc, in doubles (64 MiB): the sum of contribution-block
- * widths of the plan times nrhs must not exceed it (the 256 x 256 Q1 grid: 901,042 x 8 RHS). */
+ * widths of the plan (plus the chunked triangle solves' rows) times nrhs must not exceed it (the
+ * 256 x 256 Q1 grid: 901,042 x 8 RHS). */
 #define MF_NOALLOC_SCRATCH_DOUBLES 8388608
 
 /* mf_solve for callers that cannot allocate device memory (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): the same kernels and results as mf_solve,
  * launched eagerly on hip_stream, with no hipMalloc, hipFree or other allocation in the call.
- * Its only workspace, the per-front contribution blocks of the right-hand sides (sum of CB
- * widths x nrhs doubles), lives in a static device array of MF_NOALLOC_SCRATCH_DOUBLES doubles
+ * Its only workspace, the per-front contribution blocks of the right-hand sides and the pivot
+ * rows of the chunked triangle solves ((sum of CB widths + the widest chunked class's pivots)
+ * x nrhs doubles), lives in a static device array of MF_NOALLOC_SCRATCH_DOUBLES doubles
  * that each GPU holds until the process ends; its device address is looked up once per device
  * (on the first call with that device current).  Every call on one GPU shares that array, so
  * calls that overlap on one GPU (two streams, two threads, two plans) race: order them.  The

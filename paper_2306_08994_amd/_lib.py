@@ -15,7 +15,7 @@ ERROR_NAMES = {MF_EINVAL: "MF_EINVAL", MF_ENOMEM: "MF_ENOMEM", MF_EZERO_PIVOT: "
                MF_EHIP: "MF_EHIP", MF_ENOCONV: "MF_ENOCONV", MF_ESTATE: "MF_ESTATE"}
 
 EXPORTED = ["mf_analyse", "mf_plan_info", "mf_plan_export_tree", "mf_task_trace", "mf_set_tuning",
-            "mf_set_class_tuning", "mf_set_subtree_launch", "mf_subtree_launch_info",
+            "mf_set_class_tuning", "mf_set_subtree_launch", "mf_subtree_launch_info", "mf_set_chunked_solve",
             "mf_autotune",
             "mf_factor", "mf_solve", "mf_solve_noalloc",
             "mf_residual", "mf_refine", "mf_refine_gmres", "mf_factor_refine", "mf_elem_grad", "mf_export_factors", "mf_profile",
@@ -69,6 +69,7 @@ def load():
         "mf_set_class_tuning": (c_int32, [P, c_int32, c_void_p]),
         "mf_set_subtree_launch": (c_int32, [P, c_int32, c_int64]),
         "mf_subtree_launch_info": (c_int32, [P, POINTER(c_int64)]),
+        "mf_set_chunked_solve": (c_int32, [P, c_int32]),
         "mf_autotune": (c_int32, [P, c_void_p, c_int32, c_int32, c_void_p, c_char_p, c_int64,
                                   POINTER(c_int64)]),
         "mf_factor": (c_int32, [P, c_void_p, c_int32, c_void_p]),

@@ -414,7 +414,8 @@ int ensure_uploaded(mf_plan *P) {
     }
   }
   // rectangular-part tasks of the classes the block solves handle (x: the front's wave record)
-  std::vector<int4> rect;
+  std::vector<int4> rect, chunk;
+  P->chunk_ws_rows = 0;
   for (size_t l = 0; l < H.levels.size(); ++l) {
     const mf::LevelSchedule &S = H.levels[l];
     LevelDev &D = P->lv[l];
@@ -431,6 +432,10 @@ int ensure_uploaded(mf_plan *P) {
     // rectangular part is large (measured on the 256 x 256 grid: from c k = 16K down, 8K up)
     D.split_down = ckmax >= kSplitDownCK;
     D.split_up = ckmax >= kSplitUpCK;
+    // chunked triangle solves (k_solve_chunk) for classes with many pivots; their contribution
+    // rows then always take the rectangular launches
+    D.chunked = P->chunk_min_k > 0 && kmax >= P->chunk_min_k;
+    if (D.chunked) D.split_down = D.split_up = ckmax > 0;
     // slabs of 64 rows, or of 16 (the quarter form) where a class has too few slabs of 64 to
     // occupy the chip
     int64_t n64_down = 0, n64_up = 0;
@@ -460,6 +465,47 @@ int ensure_uploaded(mf_plan *P) {
         for (int32_t r = 0; r < d.k; r += su) rect.push_back(make_int4(ri, r, std::min(su, d.k - r), 0));
       }
     D.n_rup = (int64_t)rect.size() - D.rup;
+    if (D.chunked) {
+      // per front: its pivot rows in the workspace; stage strips; per launch of each sweep the
+      // chunk's writer and its tiles (down: rows below the chunk, up: rows above it)
+      int32_t wrow = 0, nch = 0;
+      std::vector<int32_t> wr(S.all.size());
+      std::vector<std::vector<int32_t>> starts(S.all.size());   // first pivot of each chunk
+      for (size_t i = 0; i < S.all.size(); ++i) {
+        const mf::FrontDesc &d = H.desc[S.all[i]];
+        wr[i] = wrow;
+        wrow += d.k;
+        for (int32_t p0 = 0; p0 < d.k; p0 += mf::chunk_pivots(d.k, p0)) starts[i].push_back(p0);
+        nch = std::max(nch, (int32_t)starts[i].size());
+      }
+      P->chunk_ws_rows = std::max<int64_t>(P->chunk_ws_rows, wrow);
+      D.cstage = (int64_t)chunk.size();
+      for (size_t i = 0; i < S.all.size(); ++i) {
+        const mf::FrontDesc &d = H.desc[S.all[i]];
+        const int32_t ri = (int32_t)(D.rall + (int64_t)i);
+        for (int32_t r = 0; r < d.k; r += 256) chunk.push_back(make_int4(ri, r, std::min(256, d.k - r), wr[i]));
+      }
+      D.n_cstage = (int64_t)chunk.size() - D.cstage;
+      for (int up = 0; up < 2; ++up) {
+        std::vector<std::pair<int64_t, int64_t>> &steps = up ? D.csteps_up : D.csteps_down;
+        steps.clear();
+        for (int32_t st = 0; st < nch; ++st) {
+          const int64_t first = (int64_t)chunk.size();
+          for (size_t i = 0; i < S.all.size(); ++i) {
+            const mf::FrontDesc &d = H.desc[S.all[i]];
+            const int32_t ri = (int32_t)(D.rall + (int64_t)i);
+            const int32_t nf = (int32_t)starts[i].size();
+            if (st >= nf) continue;
+            const int32_t c = up ? nf - 1 - st : st, p0 = starts[i][c];
+            const int32_t p1 = p0 + mf::chunk_pivots(d.k, p0);
+            chunk.push_back(make_int4(ri, p0, -1, wr[i]));
+            const int32_t lo = up ? 0 : p1, hi = up ? p0 : d.k;
+            for (int32_t r = lo; r < hi; r += mf::kTileRows) chunk.push_back(make_int4(ri, p0, r, wr[i]));
+          }
+          steps.emplace_back(first, (int64_t)chunk.size() - first);
+        }
+      }
+    }
   }
   // persistent class launches: per class with tiled fronts, its task list in phase order
   // (extend-add strips, then per panel step the chunks and the update tiles, then the Schur
@@ -566,7 +612,8 @@ int ensure_uploaded(mf_plan *P) {
   }
   int rc;
   if ((rc = upload(P->d_lists, lists)) || (rc = upload(P->d_tasks, tasks)) ||
-      (rc = upload(P->d_rect, rect)) || (rc = upload(P->d_panel, panel)) ||
+      (rc = upload(P->d_rect, rect)) || (rc = upload(P->d_chunk, chunk)) ||
+      (rc = upload(P->d_panel, panel)) ||
       (rc = upload(P->d_ctasks, ctasks)))
     return rc;
   {
@@ -734,7 +781,8 @@ int ensure_uploaded(mf_plan *P) {
                        (const void *)mf::k_solve_down_subtree<false>,
                        (const void *)mf::k_solve_down_subtree<true>,
                        (const void *)mf::k_solve_up_subtree<false>,
-                       (const void *)mf::k_solve_up_subtree<true>};
+                       (const void *)mf::k_solve_up_subtree<true>,
+                       (const void *)mf::k_solve_chunk<false>, (const void *)mf::k_solve_chunk<true>};
   for (const void *fn : dyn)
     (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, P->max_shared);
   (void)hipGetLastError();
@@ -772,6 +820,12 @@ std::string pivot_message(const mf_plan *P, int32_t f, int32_t p) {
            " of that mesh";
   }
   return msg + ")";
+}
+
+// Doubles of a solve's contribution-block buffer: the per-front contribution blocks (sum_c rows)
+// and the chunked triangle solves' workspace rows, nrhs values per row.
+size_t ycb_doubles(const mf_plan *P, int32_t nrhs) {
+  return (size_t)std::max<int64_t>(1, P->hp.sum_c + P->chunk_ws_rows) * nrhs;
 }
 
 int grow(mf_plan *P, double *&buf, size_t &cap, size_t doubles) {
@@ -1122,7 +1176,39 @@ void solve_level(mf_plan *P, const double *b, double *x, int32_t nrhs, bool tran
     if (rq) MF_RECT_Q(KIND, TR, UP, true);                                                      \
     else MF_RECT_Q(KIND, TR, UP, false);                                                        \
   } while (0)
-        if (down) {
+        if (!trans && D.chunked) {
+          // chunked triangle: stage the pivot rows, one launch per chunk; the contribution rows
+          // by the rectangular launches (after the triangle going down, before it going up)
+          double *wsp = ycb + P->hp.sum_c * (int64_t)nrhs;
+          const int ncc = chunk(P, nrhs, mf::chunk_solve_fixed_doubles(), mf::chunk_solve_col_doubles());
+          const size_t clds =
+              (size_t)(mf::chunk_solve_fixed_doubles() + (int64_t)mf::chunk_solve_col_doubles() * ncc) * 8;
+          const int4 *stk = P->d_chunk + D.cstage;
+          const unsigned nst = (unsigned)D.n_cstage;
+          Cost cst, cc = ct;
+          const double sum_k = D.tri_down_rhs_bytes / 24.0;    // pivots of the class
+          cst.bytes = 16.0 * nrhs * sum_k;                      // pivot rows in and out
+          const double nsteps = (double)std::max<size_t>(1, D.csteps_down.size());
+          cc.bytes /= nsteps;                                   // the triangle's cost per launch
+          cc.flops /= nsteps;
+          if (down) {
+            LAUNCH(K_CHUNK_STAGE, cst, mf::k_solve_chunk_stage<false>, dim3(nst), dim3(256), 0, s,
+                   P->d_wrec, stk, P->d_front_idx, P->d_inv_l, P->d_inv_r, b, x, ycb, wsp, nrhs);
+            for (const auto &st : D.csteps_down)
+              LAUNCH(K_CHUNK, cc, mf::k_solve_chunk<false>, dim3((unsigned)st.second), dim3(256), clds,
+                     s, P->d_wrec, P->d_chunk + st.first, P->d_store, P->d_front_idx, x, wsp, nrhs,
+                     ncc, P->d_dinv);
+            if (nt) MF_RECT(K_DOWN_RECT, false, false);
+          } else {
+            if (nt) MF_RECT(K_UP_RECT, false, true);
+            LAUNCH(K_CHUNK_STAGE, cst, mf::k_solve_chunk_stage<true>, dim3(nst), dim3(256), 0, s,
+                   P->d_wrec, stk, P->d_front_idx, P->d_inv_l, P->d_inv_r, b, x, ycb, wsp, nrhs);
+            for (const auto &st : D.csteps_up)
+              LAUNCH(K_CHUNK, cc, mf::k_solve_chunk<true>, dim3((unsigned)st.second), dim3(256), clds,
+                     s, P->d_wrec, P->d_chunk + st.first, P->d_store, P->d_front_idx, x, wsp, nrhs,
+                     ncc, P->d_dinv);
+          }
+        } else if (down) {
           if (split) {
             if (trans) MF_DOWN_BLOCK(true, false); else MF_DOWN_BLOCK(false, false);
             if (nt) {
@@ -1517,6 +1603,15 @@ int mf_set_subtree_launch(mf_plan *P, int32_t max_classes, int64_t min_units) {
   return MF_OK;
 }
 
+int mf_set_chunked_solve(mf_plan *P, int32_t min_pivots) {
+  if (!P) return fail(MF_EINVAL, "null plan");
+  if (min_pivots < 0) return fail(MF_EINVAL, "min_pivots must be >= 0");
+  P->chunk_min_k = min_pivots;
+  P->uploaded = false;      // the solve schedule is rebuilt at the next device call
+  P->drop_graphs();
+  return MF_OK;
+}
+
 int mf_subtree_launch_info(mf_plan *P, int64_t *out) {
   if (!P || !out) return fail(MF_EINVAL, "null argument");
   const int rc = ensure_uploaded(P);
@@ -1591,7 +1686,7 @@ int mf_solve(mf_plan *P, const double *b, double *x, int32_t nrhs, int32_t trans
   if (transpose != 0 && transpose != 1) return fail(MF_EINVAL, "transpose must be 0 or 1");
   if (!P->factored) return fail(MF_ESTATE, "no valid factorization: call mf_factor first");
   int rc;
-  if ((rc = grow(P, P->d_ycb, P->ycb_cap, (size_t)std::max<int64_t>(1, P->hp.sum_c) * nrhs)))
+  if ((rc = grow(P, P->d_ycb, P->ycb_cap, ycb_doubles(P, nrhs))))
     return rc;
   GraphKey key;
   key.p0 = b;
@@ -1608,12 +1703,13 @@ int mf_solve_noalloc(mf_plan *P, const double *b, double *x, int32_t nrhs, int32
   if (nrhs < 1) return fail(MF_EINVAL, "nrhs must be >= 1");
   if (transpose != 0 && transpose != 1) return fail(MF_EINVAL, "transpose must be 0 or 1");
   if (!P->factored) return fail(MF_ESTATE, "no valid factorization: call mf_factor first");
-  const int64_t need = std::max<int64_t>(1, P->hp.sum_c) * (int64_t)nrhs;
+  const int64_t need = (int64_t)ycb_doubles(P, nrhs);
   if (need > (int64_t)MF_NOALLOC_SCRATCH_DOUBLES)
     return fail(MF_EINVAL, "mf_solve_noalloc needs " + std::to_string(need) +
-                               " doubles of scratch (sum of contribution-block widths " +
-                               std::to_string(P->hp.sum_c) + " x nrhs " + std::to_string(nrhs) +
-                               "), above its limit of " +
+                               " doubles of scratch ((sum of contribution-block widths " +
+                               std::to_string(P->hp.sum_c) + " + chunked-solve rows " +
+                               std::to_string(P->chunk_ws_rows) + ") x nrhs " +
+                               std::to_string(nrhs) + "), above its limit of " +
                                std::to_string((int64_t)MF_NOALLOC_SCRATCH_DOUBLES));
   double *ycb = nullptr;
   int rc;
@@ -1730,7 +1826,7 @@ int mf_refine_gmres(mf_plan *P, const double *elem_mats, const double *b, double
   const size_t total = (size_t)(2 * m + 3) * nn + ndots + NL.r_parts + NL.b_parts + (size_t)(m + 1) * nrhs;
   int rc;
   if ((rc = grow(P, P->d_kry, P->kry_cap, total))) return rc;
-  if ((rc = grow(P, P->d_ycb, P->ycb_cap, (size_t)std::max<int64_t>(1, H.sum_c) * nrhs))) return rc;
+  if ((rc = grow(P, P->d_ycb, P->ycb_cap, ycb_doubles(P, nrhs)))) return rc;
   const size_t hneed = std::max(ndots, (size_t)(m + 1) * nrhs) + (size_t)(m + 1) * nrhs;
   if (P->hkry_cap < hneed) {
     if (P->h_kry) (void)hipHostFree(P->h_kry);
@@ -1893,7 +1989,7 @@ int mf_factor_refine(mf_plan *P, const double *elem_mats, int32_t precision, con
   if (nrhs < 1 || max_it < 0 || !(tol >= 0)) return fail(MF_EINVAL, "bad nrhs, max_it or tol");
   int rc = ensure_uploaded(P);
   if (rc) return rc;
-  if ((rc = grow(P, P->d_ycb, P->ycb_cap, (size_t)std::max<int64_t>(1, P->hp.sum_c) * nrhs)))
+  if ((rc = grow(P, P->d_ycb, P->ycb_cap, ycb_doubles(P, nrhs))))
     return rc;
   hipStream_t s = (hipStream_t)hip_stream;
   P->factored = false;

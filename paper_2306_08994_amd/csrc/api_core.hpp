@@ -45,13 +45,15 @@ inline int fail(int code, const std::string &msg) {
 enum Kind {
   K_TINY, K_SMALL, K_ASSEMBLE, K_FUSED, K_TRSM, K_GEMM_PANEL, K_GEMM_SCHUR,
   K_DOWN_WAVE, K_DOWN_BLOCK, K_UP_WAVE, K_UP_BLOCK, K_DOWN_RECT, K_UP_RECT, K_RESIDUAL,
-  K_DIAG_INV, K_CLASS, K_PANEL_LA, K_SUB_FACTOR, K_SUB_DOWN, K_SUB_UP, K_OTHER, K_COUNT
+  K_DIAG_INV, K_CLASS, K_PANEL_LA, K_SUB_FACTOR, K_SUB_DOWN, K_SUB_UP, K_CHUNK_STAGE, K_CHUNK,
+  K_OTHER, K_COUNT
 };
 static const char *const kKindName[K_COUNT] = {
     "factor_tiny", "factor_small", "assemble", "front_panels", "panel_lu_trsm", "gemm_panel",
     "gemm_schur", "solve_down_wave", "solve_down_block", "solve_up_wave", "solve_up_block",
     "solve_down_rect", "solve_up_rect", "residual", "diag_block_inverse", "class_tiled",
-    "panel_lookahead", "factor_subtree", "solve_down_subtree", "solve_up_subtree", "other"};
+    "panel_lookahead", "factor_subtree", "solve_down_subtree", "solve_up_subtree",
+    "solve_chunk_stage", "solve_chunk", "other"};
 
 // Algorithmic traffic and work of one launch (bytes that must cross HBM at least once, flops
 // of the method's own operation count).
@@ -101,6 +103,11 @@ struct LevelDev {
   // rectangular-part tasks (int4: the front's wave record, first row, rows, 0)
   int64_t rdown = 0, n_rdown = 0, rup = 0, n_rup = 0;
   bool split_down = false, split_up = false;   // rectangular part in its own launch
+  // chunked triangle solves (no transposition): stage tasks and, per launch of each sweep,
+  // (first, count) of its tasks in d_chunk
+  bool chunked = false;
+  int64_t cstage = 0, n_cstage = 0;
+  std::vector<std::pair<int64_t, int64_t>> csteps_down, csteps_up;
   bool rect_q_down = false, rect_q_up = false; // ... in slabs of 16 rows (quarter form)
 };
 
@@ -173,6 +180,9 @@ struct mf_plan {
   int32_t *d_lists = nullptr;
   mf::GemmTask *d_tasks = nullptr;
   int4 *d_rect = nullptr;
+  int4 *d_chunk = nullptr;    // tasks of the chunked triangle solves
+  int32_t chunk_min_k = 512;  // classes with a front of at least this many pivots are chunked
+  int64_t chunk_ws_rows = 0;  // workspace rows (after the contribution blocks' sum_c rows)
   mf::PanelRec *d_panel = nullptr;   // panel records of every step, class after class
   mf::WaveRec *d_wrec = nullptr;   // wave records of every class's front list, class after class
   mf::WaveRec *d_wrec_up = nullptr;   // the same without fronts that have no pivots (up sweep)
@@ -254,6 +264,7 @@ struct mf_plan {
     mfapi::dfree(d_lists);
     mfapi::dfree(d_tasks);
     mfapi::dfree(d_rect);
+    mfapi::dfree(d_chunk);
     mfapi::dfree(d_wrec);
     mfapi::dfree(d_wrec_up);
     mfapi::dfree(sub_f.d_rec);

@@ -118,6 +118,11 @@ k_class_tiled(const ClassTask *__restrict__ tasks, int ntasks, int *__restrict__
     __syncthreads();
     if (tid == 0) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      // the L2 write-back the release issues must be complete before the count is raised: the
+      // wait the fence carries is dropped by the compiler when no other memory operation is
+      // outstanding here (every store was waited for above), which let a consumer on another
+      // XCD see the count before the producer's results reached memory
+      __builtin_amdgcn_s_waitcnt(0);
       s_prev = __hip_atomic_fetch_add(cnt + tk.ci, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();

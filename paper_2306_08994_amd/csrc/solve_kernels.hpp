@@ -716,6 +716,187 @@ k_solve_up_block(const WaveRec *__restrict__ recs, int nrec,
 }
 
 // ---------------------------------------------------------------------------------------------
+// Chunked triangle solves (no transposition) of fronts with many pivots.  The one-workgroup
+// block solve walks a front's whole triangle of L or U, k^2/2 coefficients through one CU (the
+// 1,089-pivot root of the 3D workload: 4.7 MB, over 300 us per sweep).  Here the triangle is
+// cut into chunks of kChunkPiv pivots (see chunk_pivots), one launch per chunk, one workgroup per 128-row tile of
+// the pivot rows the chunk updates (below it in the down sweep, above it in the up sweep) and
+// one "writer" workgroup per front: every workgroup solves the chunk's own small triangle
+// redundantly from its diagonal-block inverses, then the tile workgroups apply the chunk's
+// columns to their rows.  The pivot rows' right-hand sides live between launches in a
+// workspace (row wrow + i of the front's pivot i, nrhs values per row), staged by
+// k_solve_chunk_stage from b and the children's contribution blocks (down) or from x (up); a
+// launch reads chunk and tile rows of the workspace and writes only its tile rows there and
+// the chunk's solution into x, so no workgroup reads what another writes in the same launch.
+// Task (int4): wave record, first pivot of the chunk, first row of the tile (-1: the writer),
+// the front's first workspace row.
+// ---------------------------------------------------------------------------------------------
+constexpr int kChunkPiv = 4 * NBS;
+constexpr int kChunkMax = kChunkPiv + NBS;       // a remainder of up to NBS joins the last chunk
+constexpr int kChunkRows = kChunkMax + kTileRows + NBS;     // LDS rows: chunk, tile, zero rows
+constexpr int kChunkLd = kChunkRows | 1;
+// Pivots of the chunk starting at p0 of a front with k pivots (chunks of kChunkPiv from 0, the
+// last one taking a remainder of up to NBS more).
+__host__ __device__ inline int chunk_pivots(int k, int p0) {
+  return k - p0 <= kChunkMax ? k - p0 : kChunkPiv;
+}
+__host__ __device__ constexpr int chunk_solve_fixed_doubles() {
+  return NBS * (NBS + 1) + 2 * kTileRows * (NBS + 1);
+}
+__host__ __device__ constexpr int chunk_solve_col_doubles() { return kChunkLd + NBS; }
+
+// F[row][col] for rows rb.. (clamped below r_hi) and the NBS columns c0.. (clamped below c_hi),
+// in the layout of tile_load<false>.
+__device__ inline void ctile_load(const double *F, int m, int rb, int r_hi, int c0, int c_hi,
+                                  int tid, double *v) {
+#pragma unroll
+  for (int u = 0; u < kTileLoads; ++u) {
+    int i, p;
+    tile_pos<false>(tid, u, i, p);
+    const int row = min(rb + i, r_hi - 1), col = min(c0 + p, c_hi - 1);
+    v[u] = F[(int64_t)row * m + col];
+  }
+}
+
+// Stage the pivot rows [row0, row0 + rows) of a front into the workspace: down, b plus the
+// children's contribution blocks; up, x.  Task (int4): wave record, row0, rows (<= 256), wrow.
+template <bool UP>
+__global__ void __launch_bounds__(256)
+k_solve_chunk_stage(const WaveRec *__restrict__ recs, const int4 *__restrict__ tasks,
+                    const int32_t *__restrict__ front_idx, const int32_t *__restrict__ inv_l,
+                    const int32_t *__restrict__ inv_r, const double *b, const double *x,
+                    const double *ycb, double *wsp, int nrhs) {
+  const int4 tk = tasks[blockIdx.x];
+  const WaveRec d = recs[tk.x];
+  const int i = tk.y + (int)threadIdx.x;
+  if ((int)threadIdx.x >= tk.z) return;
+  const int64_t gi = front_idx[d.idx + i];
+  const int xa = !UP && d.ycb[0] >= 0 ? inv_l[d.idx + i] : -1;
+  const int xc = !UP && d.ycb[1] >= 0 ? inv_r[d.idx + i] : -1;
+  double *out = wsp + ((int64_t)tk.w + i) * nrhs;
+  for (int rb = 0; rb < nrhs; rb += kRhsBatch) {       // loads of a batch in flight together
+    double v[kRhsBatch];
+#pragma unroll
+    for (int u = 0; u < kRhsBatch; ++u) {
+      const int r = rb + u;
+      v[u] = 0.0;
+      if (r < nrhs) {
+        if (UP) {
+          v[u] = x[gi * nrhs + r];
+        } else {
+          v[u] = b[gi * nrhs + r];
+          if (xa >= 0) v[u] += ycb[(d.ycb[0] + xa) * nrhs + r];
+          if (xc >= 0) v[u] += ycb[(d.ycb[1] + xc) * nrhs + r];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kRhsBatch; ++u)
+      if (rb + u < nrhs) out[rb + u] = v[u];
+  }
+}
+
+// One chunk of a front (see above): W in LDS holds the chunk's rows [0, kChunkPiv), the tile's
+// rows [kChunkPiv, kChunkPiv + kTileRows) and NBS zero rows, for nr right-hand sides.
+template <bool UP>
+__global__ void __launch_bounds__(256)
+k_solve_chunk(const WaveRec *__restrict__ recs, const int4 *__restrict__ tasks,
+              const double *__restrict__ store, const int32_t *__restrict__ front_idx, double *x,
+              double *wsp, int nrhs, int nc, const double *__restrict__ dinv) {
+  extern __shared__ double sm[];
+  constexpr int PC = kChunkMax, ld = kChunkLd;
+  double *W = sm;
+  double *Ms = W + ld * nc;
+  double *T1 = Ms + NBS * (NBS + 1);            // coefficients of the chunk rows a block updates
+  double *T2 = T1 + kTileRows * (NBS + 1);      // ... and of the tile rows
+  double *Y = T2 + kTileRows * (NBS + 1);
+  const int tid = threadIdx.x;
+  const int4 tk = tasks[blockIdx.x];
+  const WaveRec d = recs[tk.x];
+  const int m = d.m, k = d.k, p0 = tk.y, rt0 = tk.z;
+  const int64_t wrow = tk.w;
+  const int pc = chunk_pivots(k, p0);                    // the chunk's pivots
+  const int tr = rt0 < 0 ? 0 : (UP ? min(kTileRows, p0 - rt0) : min(kTileRows, k - rt0));
+  const double *F = store + d.store;
+  const double *dv = dinv + d.dinv;
+  const int nblk = (pc + NBS - 1) / NBS;
+  // block bi of the chunk in processing order: first pivot (in the chunk), pivots, and the
+  // chunk rows it updates (down: below it, up: above it)
+  auto blk = [&](int bi, int &qb, int &pb, int &ulo, int &uhi) {
+    qb = UP ? (nblk - 1 - bi) * NBS : bi * NBS;
+    pb = min(NBS, pc - qb);
+    ulo = UP ? 0 : qb + pb;
+    uhi = UP ? qb : pc;
+  };
+  // the coefficients of a block (its inverse, its chunk-row and tile-row tiles) do not depend on
+  // the values: block bi + 1's are loaded while block bi is applied
+  double mv[kInvPerThread], cv[kTileLoads], tv[kTileLoads];
+  auto load_blk = [&](int bi) {
+    int qb, pb, ulo, uhi;
+    blk(bi, qb, pb, ulo, uhi);
+    load_block_inverse<false, UP>(dv, p0 + qb, tid, mv);
+    if (uhi > ulo) ctile_load(F, m, p0 + ulo, p0 + uhi, p0 + qb, p0 + qb + pb, tid, cv);
+    if (tr > 0) ctile_load(F, m, rt0, rt0 + tr, p0 + qb, p0 + qb + pb, tid, tv);
+  };
+  for (int r0 = 0; r0 < nrhs; r0 += nc) {
+    const int nr = min(nc, nrhs - r0);
+    load_blk(0);
+    // chunk rows, tile rows, zeros (row index fastest: a constant divisor)
+    for (int t0 = tid; t0 < kChunkRows * nr; t0 += 256 * kRhsBatch) {
+      double v[kRhsBatch];
+#pragma unroll
+      for (int u = 0; u < kRhsBatch; ++u) {
+        const int t = t0 + 256 * u, r = t / kChunkRows, i = t - r * kChunkRows;
+        v[u] = 0.0;
+        if (r < nr) {
+          if (i < pc)
+            v[u] = wsp[(wrow + p0 + i) * nrhs + r0 + r];
+          else if (i >= PC && i < PC + tr)
+            v[u] = wsp[(wrow + rt0 + i - PC) * nrhs + r0 + r];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kRhsBatch; ++u) {
+        const int t = t0 + 256 * u, r = t / kChunkRows, i = t - r * kChunkRows;
+        if (r < nr) W[r * ld + i] = v[u];
+      }
+    }
+    // the chunk's triangle block by block, each block's columns applied to the chunk rows and
+    // the tile rows it updates right away
+    for (int bi = 0; bi < nblk; ++bi) {
+      int qb, pb, ulo, uhi;
+      blk(bi, qb, pb, ulo, uhi);
+      __syncthreads();            // W's rows of this block final; Ms, T1, T2, Y free
+      store_block_inverse<false>(mv, tid, Ms);
+      if (uhi > ulo) tile_store<false>(cv, tid, T1);
+      if (tr > 0) tile_store<false>(tv, tid, T2);
+      if (bi + 1 < nblk) load_blk(bi + 1);
+      __syncthreads();
+      block_matvec(Ms, W, ld, Y, qb, pb, nr, tid);
+      __syncthreads();            // Y complete
+      for (int t = tid; t < NBS * nr; t += 256) {
+        const int r = t / NBS, q = t - (t / NBS) * NBS;
+        W[r * ld + qb + q] = Y[r * NBS + q];                // zero beyond pb
+      }
+      if (uhi > ulo) tile_apply_mfma(T1, Y, NBS, W, ld, ulo, uhi, nr, tid);
+      if (tr > 0) tile_apply_mfma(T2, Y, NBS, W, ld, PC, PC + tr, nr, tid);
+    }
+    __syncthreads();
+    if (rt0 < 0) {
+      const int32_t *idx = front_idx + d.idx + p0;
+      for (int i = tid; i < pc; i += 256) {
+        const int64_t gi = idx[i];
+        for (int r = 0; r < nr; ++r) x[gi * nrhs + r0 + r] = W[r * ld + i];
+      }
+    } else {
+      for (int i = tid; i < tr; i += 256)
+        for (int r = 0; r < nr; ++r) wsp[(wrow + rt0 + i) * nrhs + r0 + r] = W[r * ld + PC + i];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
 // The rectangular part of a wide front's sweep, off the front's sequential block path and
 // spread over many workgroups:
 //   down: the contribution-block rows i in [k, m):  ycb_i = w_i - sum_{p < k} cd(i, p) y_p
@@ -931,9 +1112,11 @@ k_norm_publish(const double *__restrict__ rpart, int64_t rblocks,
     if (blockIdx.x == 0 && status)
       for (int w = 0; w < kStatusWords; ++w) out_status[w] = status[w];
     __threadfence_system();
+    __builtin_amdgcn_s_waitcnt(0);       // this block's values in memory before it is counted
     if (atomicAdd(count, 1) == (int)gridDim.x - 1) {
       *count = 0;
       __threadfence_system();
+      __builtin_amdgcn_s_waitcnt(0);     // the write-back complete before the sequence number
       __hip_atomic_store(seq_out, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
   }

@@ -146,6 +146,11 @@ class Plan:
         return {"factor_classes": out[0], "factor_units": out[1], "solve_classes": out[2],
                 "solve_units": out[3]}
 
+    def set_chunked_solve(self, min_pivots: int = 512):
+        """Chunked triangle solves for classes whose widest front has >= min_pivots pivots
+        (see mf_set_chunked_solve; 0 = off)."""
+        check(_lib.load().mf_set_chunked_solve(self._h, int(min_pivots)))
+
     def autotune(self, K, precision: str = "fp64", reps: int = 3) -> dict:
         """Times the relevant schedule candidates on K, keeps the fastest (see mf_autotune)."""
         import json
