@@ -46,9 +46,23 @@ __device__ __forceinline__ bool wave_diag_lu(double *F, int64_t m, int pb, doubl
     const bool act = lane > p;
     const double u = act ? col[p] / piv : col[p];
     col[p] = u;
+    // the select is made here: left to the compiler it is sunk to the final stores, which keeps
+    // every pivot's lane mask alive in scalar registers and leaves one scalar pair for all the
+    // broadcasts below (each broadcast then waits for the previous multiply-add)
+    asm volatile("" : "+v"(col[p]));
     const double ua = act ? u : 0.0;
+    // the multipliers four at a time, all four live at once (distinct scalar pairs), so that
+    // each multiply-add does not wait for the broadcast just before it
 #pragma unroll
-    for (int i = p + 1; i < NB; ++i) col[i] -= readlane(col[i], p) * ua;
+    for (int i0 = p + 1; i0 < NB; i0 += 4) {
+      double mu[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) mu[t] = i0 + t < NB ? readlane(col[i0 + t], p) : 0.0;
+      asm volatile("" ::"s"(mu[0]), "s"(mu[1]), "s"(mu[2]), "s"(mu[3]));
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (i0 + t < NB) col[i0 + t] -= mu[t] * ua;
+    }
   }
   if (bad < pb && lane == 0) record_bad_pivot(status, f, p0 + bad);
   if (lane < NB) {
