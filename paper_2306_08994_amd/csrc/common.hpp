@@ -23,6 +23,9 @@ namespace mf {
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+// two consecutive doubles at any 8-byte-aligned address: one 16-byte access (the memory
+// system takes accesses that are not naturally aligned)
+typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
 
 constexpr int kStatusWords = 4;   // [0] bad-pivot flag, [1] front, [2] pivot, [3] wait abort
 

@@ -593,7 +593,6 @@ k_panel_lookahead(const PanelRec *__restrict__ recs, int nrec, int cmax,
   const int item = chunk * LA_ITEMS + tid - 64;
   const bool colitem = wv > 0 && item < rest;
   const bool has = colitem || (wv > 0 && item >= rpad && item < rpad + rest);
-  const int st = colitem ? m : 1;
   const uint32_t io = colitem ? p0 * m + pe + item : (pe + item - rpad) * m + p0;
   double v[NB];
   // the diagonal block and the previous panel's blocks of this panel, staged in LDS by waves
@@ -701,7 +700,8 @@ k_panel_lookahead(const PanelRec *__restrict__ recs, int nrec, int cmax,
     // substitution against the factored block: a column solves L11 u = v (pivots on the
     // diagonal: v[q] = (v[q] - sum_{r<q} D[q][r] v[r]) / D[q][q]), a row solves l U11 = v (unit
     // diagonal: v[q] -= sum_{r<q} v[r] D[r][q]); each step reads its entries of D into
-    // registers first, the reads issued together
+    // registers first, the reads issued together, and stores its result at once, so that the
+    // stores drain while the later steps compute
     double dr[NB];
     if (colitem) {
 #pragma unroll
@@ -718,6 +718,7 @@ k_panel_lookahead(const PanelRec *__restrict__ recs, int nrec, int cmax,
         }
         if (q & 1) s0 -= dr[q - 1] * v[q - 1];
         v[q] = (s0 + s1) * rq;
+        if (q < pb) F[io + (uint32_t)(q * m)] = v[q];
       }
     } else {
 #pragma unroll
@@ -733,11 +734,17 @@ k_panel_lookahead(const PanelRec *__restrict__ recs, int nrec, int cmax,
         }
         if (q & 1) s0 -= dr[q - 1] * v[q - 1];
         v[q] = s0 + s1;
+        // a row's entries are contiguous: a full panel's in 16-byte pairs
+        if (q & 1) {
+          if (pb == NB) {
+            *reinterpret_cast<d2u *>(F + io + q - 1) = d2u{v[q - 1], v[q]};
+          } else {
+            if (q - 1 < pb) F[io + (uint32_t)(q - 1)] = v[q - 1];
+            if (q < pb) F[io + (uint32_t)q] = v[q];
+          }
+        }
       }
     }
-#pragma unroll
-    for (int q = 0; q < NB; ++q)
-      if (q < pb) F[io + (uint32_t)(q * st)] = v[q];
   } else if (wv == 0) {
     // the factored diagonal block: by the only workgroup of the front, or by the one that
     // arrived last (every other one has staged the block by now)
