@@ -91,7 +91,10 @@ typedef struct {
  * Errors: MF_EINVAL (bad sizes, ids out of range, duplicate elem_ijk, unused node), MF_ENOMEM. */
 int mf_analyse(int32_t n_mesh, const mf_mesh *meshes, mf_plan **out);
 
-/* Sizes and operation counts of an analysed plan. */
+/* Sizes and operation counts of an analysed plan: fronts, Foata classes (Sec. 3.3) and the
+ * flop counts of the task alphabet of Sec. 3 (per pivot of a front, Table 2's division,
+ * multiplication and subtraction tasks; per pivot and right-hand side, the solve's).
+ * out: host, filled on success.  Errors: MF_EINVAL (null argument). */
 int mf_plan_info(const mf_plan *plan, mf_info *out);
 
 /* Copies the tree to host buffers sized from mf_info (any pointer may be NULL to skip it):
@@ -232,12 +235,16 @@ int mf_solve(mf_plan *plan, const double *b, double *x, int32_t nrhs, int32_t tr
 int mf_solve_noalloc(mf_plan *plan, const double *b, double *x, int32_t nrhs, int32_t transpose,
                      void *hip_stream);
 
-/* r = b - A x with A applied element by element (A = sum_e P_e^T K_e P_e), FP64.
+/* r = b - A x with A applied element by element (A = sum_e P_e^T K_e P_e, the FEM operator
+ * whose element matrices are the leaves of Sec. 2.4), FP64.  Not a step of the paper's method:
+ * the check of the solve that the refinement below uses.
  * elem_mats device [n_elem][npe][npe]; x, b, r device [n][nrhs].  Asynchronous. */
 int mf_residual(mf_plan *plan, const double *elem_mats, const double *x, const double *b,
                 double *r, int32_t nrhs, void *hip_stream);
 
-/* Iterative refinement in FP64: x = solve(b); repeat r = b - A x, x += solve(r) until
+/* Iterative refinement in FP64 around the solve of Sec. 1.1 (not in the paper; it restores
+ * FP64 accuracy when the Schur updates of Sec. 2.2 ran in FP32 or BF16, MF_SCHUR_*):
+ * x = solve(b); repeat r = b - A x, x += solve(r) until
  * max_r ||r_r||_2 / ||b_r||_2 <= tol or max_it corrections were applied.
  * elem_mats, b, x as above; its (host, may be NULL) receives the number of corrections and
  * relres (host, may be NULL) the final relative residual.  Synchronizes hip_stream once per
@@ -282,7 +289,9 @@ int mf_factor_refine(mf_plan *plan, const double *elem_mats, int32_t precision, 
 int mf_elem_grad(mf_plan *plan, const double *lam, const double *u, int32_t nrhs,
                  double *gK, void *hip_stream);
 
-/* Copies the factors to host buffers sized from mf_info, front after front in id order:
+/* Copies the factors of every front (Table 2's compute_front: the division tasks scale the
+ * pivot row, so U is unit upper and L carries the pivots, Sec. 3) to host buffers sized from
+ * mf_info, front after front in id order:
  *   L: for each front an m x k row-major block, L[i][p] for i >= p (pivots on the diagonal),
  *      zeros above;
  *   U: for each front a k x m row-major block, U[p][p] = 1, U[p][j] for j > p, zeros left.
