@@ -2,8 +2,9 @@
 and of even width with at least two full panels: a full panel stores its L21 rows in 16-byte
 pairs, which start 8 bytes past a 16-byte boundary on every other row of an odd-width front,
 and each substitution result is stored as soon as it is final.  Factors and solves against the
-oracle, for both GEMM tiles of the launch (32 and 64); and a non-finite pivot inside the root's
-second panel, which the diagonal-block LU of that panel's launch must report by front and pivot."""
+oracle, for both GEMM tiles of the launch (32 and 64); and a non-finite pivot inside a later
+panel of the root, which every panel route (look-ahead, two-launch, fused, persistent class
+launch) must report by front and pivot."""
 import numpy as np
 import pytest
 
@@ -37,7 +38,11 @@ def test_lookahead_full_panels(shape, parity, tile):
     b = torch.from_numpy(np.ascontiguousarray(p.b)).to(dev)
     plan = Plan(p.meshes)
     plan.set_tuning(SMAX, NB, FUSED_OFF, tile, PERSISTENT_OFF)
+    plan.profile(True)
     plan.factor(K)
+    kinds = {k["name"] for k in plan.profile_report()["kernels"] if k["launches"] > 0}
+    plan.profile(False)
+    assert "panel_lookahead" in kinds and "panel_lu_trsm" not in kinds, kinds
     Ls, Us = plan.export_factors()
     assert G.factor_violation(Ls, Us, fac) <= G.TOL_FACTOR
     for trans in (False, True):
@@ -45,11 +50,22 @@ def test_lookahead_full_panels(shape, parity, tile):
         assert G.rel_err(x, G.oracle_solve(tree, fac, p.b, trans)) <= G.TOL_SOLVE, trans
 
 
-def test_lookahead_bad_pivot_in_second_panel():
+# (panel width, fused-route limit, GEMM tile, persistent) of each route the root can take, and
+# the kernel kind (profile report) that factors the panels on it
+ROUTES = {"lookahead_t32": (32, FUSED_OFF, 32, PERSISTENT_OFF, "panel_lookahead"),
+          "lookahead_t64": (32, FUSED_OFF, 64, PERSISTENT_OFF, "panel_lookahead"),
+          "two_launch_nb16": (16, FUSED_OFF, 32, PERSISTENT_OFF, "panel_lu_trsm"),
+          "two_launch_nb64": (64, FUSED_OFF, 32, PERSISTENT_OFF, "panel_lu_trsm"),
+          "fused": (32, 128, 32, PERSISTENT_OFF, "front_panels"),
+          "persistent": (32, FUSED_OFF, 32, 1, "class_tiled")}
+
+
+@pytest.mark.parametrize("route", sorted(ROUTES))
+def test_bad_pivot_inside_a_later_panel(route):
     """A NaN on the diagonal of a root pivot's element row reaches no pivot below the root (the
-    node is a contribution-block entry there) and becomes the root's pivot 40, inside its second
-    panel (pivots 32..63); the factorization reports that front and pivot, and the plan then
-    factors the intact matrix."""
+    node is a contribution-block entry there) and becomes the root's pivot 40 (the second panel
+    at widths 16 and 32, inside the first at 64); each panel route reports that front and pivot,
+    and the plan then factors the intact matrix."""
     import torch
     from paper_2306_08994_amd import MFError, Plan
     from paper_2306_08994_amd import _lib
@@ -66,9 +82,14 @@ def test_lookahead_bad_pivot_in_second_panel():
     K = torch.from_numpy(p.K).to(dev)
     Kbad = K.clone()
     Kbad[e, a, a] = float("nan")
-    plan.set_tuning(SMAX, NB, FUSED_OFF, 32, PERSISTENT_OFF)
+    nb, fused, tile, persistent, kind = ROUTES[route]
+    plan.set_tuning(SMAX, nb, fused, tile, persistent)
+    plan.profile(True)
     with pytest.raises(MFError) as ei:
         plan.factor(Kbad)
+    kinds = {k["name"] for k in plan.profile_report()["kernels"] if k["launches"] > 0}
+    plan.profile(False)
+    assert kind in kinds, kinds
     assert ei.value.code == _lib.MF_EZERO_PIVOT
     msg = str(ei.value)
     assert f"front {root}, pivot 40 " in msg and f"node {node} " in msg, msg
