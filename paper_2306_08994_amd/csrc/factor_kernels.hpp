@@ -543,7 +543,11 @@ k_gemm_update(const GemmTask *__restrict__ tasks, double *__restrict__ store) {
 // inter-kernel gaps less per step on the dependency chain of a front.
 // An A chunk is 256 threads: wave 0 stages and factors the diagonal block, waves 1-3 hold 192
 // items (item t < rest a U12 column, t in [R, R + rest) an L21 row, R = rest rounded up to 64,
-// so that no wave holds both kinds).
+// so that no wave holds both kinds).  Each item wave applies the previous panel's update to its
+// 64 items as one small product on MFMA while wave 0 factors: done per item against the staged
+// 32 x 32 block, every lane would read all 1024 entries (LDS broadcasts, whose return traffic
+// kept that phase longer than the factorization it overlaps).  Two waves per SIMD (the
+// launch bound), so that the B tiles keep their occupancy.
 // ---------------------------------------------------------------------------------------------
 constexpr int LA_NB = 32;
 constexpr int LA_ITEMS = 192;
@@ -562,12 +566,15 @@ union LookaheadLds {
     double Dg[LA_NB][LA_NB + 1];    // the diagonal block as loaded, then updated
     double Lp[LA_NB][LA_NB + 1];    // Lp[i][q] = F[p0 + i][p0 - 32 + q]: previous panel's L rows
     double UpT[LA_NB][LA_NB + 1];   // UpT[j][q] = F[p0 - 32 + q][p0 + j]: its U columns
+    // per item wave: half of its items' previous-panel entries (64 x 16, padded), then half of
+    // the products, on their way between the item layout and the MFMA layout
+    double Ws[LA_ITEMS / 64][64 * 17];
   } a;
   GemmLds<0, TILE> g;
 };
 
 template <int TILE>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 2)
 k_panel_lookahead(const PanelRec *__restrict__ recs, int nrec, int cmax,
                   const GemmTask *__restrict__ tiles, double *__restrict__ store,
                   int *__restrict__ status, int *__restrict__ arrive) {
@@ -587,6 +594,7 @@ k_panel_lookahead(const PanelRec *__restrict__ recs, int nrec, int cmax,
   if (chunk >= nact) return;                             // idle chunk of a narrower front
   const bool prev = p0 > 0;                              // every panel but the last is NB wide
   const int rest = m - pe, rpad = (rest + 63) & ~63;
+  const int i0w = chunk * LA_ITEMS + (wv - 1) * 64;      // first item of this wave (waves 1-3)
   double *F = store + d.store;
   // this thread's item: a U12 column (entries F[p0 + q][j], stride m) or an L21 row (entries
   // F[i][p0 + q], stride 1), at 32-bit element offset io from the front's (uniform) base
@@ -650,11 +658,12 @@ k_panel_lookahead(const PanelRec *__restrict__ recs, int nrec, int cmax,
   }
   if (wv == 0) {
     wave_diag_lu<NB>(&sm.a.Dg[0][0], NB + 1, pb, sm.a.D, sm.a.rd, lane, d.f, p0, status, false);
-  } else if (has) {
+  } else if (wv > 0 && (i0w < rest || (i0w >= rpad && i0w < rpad + rest))) {
     // while wave 0 factors the block: this item's entries in this panel (v) and in the
     // previous one (w) -- loaded here, after the barriers, which wait for every outstanding
     // load -- and the previous panel's update of them, v[q] -= sum_r Lp[q][r] w[r] for a
-    // column, v[q] -= sum_r w[r] U[r][q] for a row
+    // column, v[q] -= sum_r w[r] U[r][q] for a row.  The wave holds only columns or only rows
+    // (i0w: its first item); lanes without an item take part with zeros.
     double w[NB];
     if (colitem) {
 #pragma unroll
@@ -663,35 +672,66 @@ k_panel_lookahead(const PanelRec *__restrict__ recs, int nrec, int cmax,
 #pragma unroll
         for (int q = 0; q < NB; ++q) w[q] = F[io + (uint32_t)((q - NB) * m)];
       }
-    } else {
+    } else if (has) {
 #pragma unroll
       for (int q = 0; q < NB; ++q) v[q] = F[io + (uint32_t)min(q, pb - 1)];
       if (prev) {
 #pragma unroll
         for (int q = 0; q < NB; ++q) w[q] = F[io + (uint32_t)(q - NB)];
       }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NB; ++q) v[q] = w[q] = 0.0;
     }
-    if (prev && colitem) {
+    if (prev) {
+      // the wave's 64 items at once, P = W M^T (W: items x 32 previous-panel entries; M = Lp
+      // for columns, UpT for rows, M[q][r]) on MFMA: each lane reads distinct entries of M
+      // instead of every lane all 1024 (LDS broadcasts, which bound the product otherwise).
+      // A operand lane l = W[16 rb + l%16][4 s + l/16] (staged through Ws, 16 entries of each
+      // item at a time), B operand lane l = M[16 cb + l%16][4 s + l/16]; result lane l register
+      // t = P[16 rb + 4 t + l/16][16 cb + l%16], staged back through Ws per 16 columns.
+      const double(*M)[NB + 1] = i0w < rest ? sm.a.Lp : sm.a.UpT;
+      double *Ws = sm.a.Ws[wv - 1];
+      const int li = lane & 15, lk = lane >> 4;
+      v4d acc[4][2];
 #pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        double s0 = v[q], s1 = 0.0;
+      for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-        for (int r = 0; r < NB; r += 2) {
-          s0 -= sm.a.Lp[q][r] * w[r];
-          s1 -= sm.a.Lp[q][r + 1] * w[r + 1];
-        }
-        v[q] = s0 + s1;
+        for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int t = 0; t < 16; ++t) Ws[lane * 17 + t] = w[16 * h + t];
+        wave_sync();
+        double aop[4][4], bop[2][4];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+          for (int ss = 0; ss < 4; ++ss) aop[rb][ss] = Ws[(16 * rb + li) * 17 + 4 * ss + lk];
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+          for (int ss = 0; ss < 4; ++ss) bop[cb][ss] = M[16 * cb + li][16 * h + 4 * ss + lk];
+        wave_sync();                                 // read before the next half overwrites
+#pragma unroll
+        for (int ss = 0; ss < 4; ++ss)
+#pragma unroll
+          for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb)
+              acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[rb][ss], bop[cb][ss],
+                                                                 acc[rb][cb], 0, 0, 0);
       }
-    } else if (prev) {
 #pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        double s0 = v[q], s1 = 0.0;
+      for (int cb = 0; cb < 2; ++cb) {
 #pragma unroll
-        for (int r = 0; r < NB; r += 2) {
-          s0 -= sm.a.UpT[q][r] * w[r];
-          s1 -= sm.a.UpT[q][r + 1] * w[r + 1];
-        }
-        v[q] = s0 + s1;
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+          for (int t = 0; t < 4; ++t) Ws[(16 * rb + 4 * t + lk) * 17 + li] = acc[rb][cb][t];
+        wave_sync();
+#pragma unroll
+        for (int t = 0; t < 16; ++t) v[16 * cb + t] -= Ws[lane * 17 + t];
+        wave_sync();
       }
     }
   }
