@@ -736,16 +736,19 @@ k_panel_lookahead(const PanelRec *__restrict__ recs, int nrec, int cmax,
     }
   }
   __syncthreads();
-  if (has) {
+  if (wv > 0 && (i0w < rest || (i0w >= rpad && i0w < rpad + rest))) {
     // substitution against the factored block: a column solves L11 u = v (pivots on the
     // diagonal: v[q] = (v[q] - sum_{r<q} D[q][r] v[r]) / D[q][q]), a row solves l U11 = v (unit
-    // diagonal: v[q] -= sum_{r<q} v[r] D[r][q]); each step reads its entries of D into
-    // registers first, the reads issued together, and stores its result at once, so that the
-    // stores drain while the later steps compute
+    // diagonal: v[q] -= sum_{r<q} v[r] D[r][q]); in two halves of 16, the contribution of the
+    // first half to the second taken for the wave's 64 items at once on MFMA (as the previous
+    // panel's update above), so that the per-item steps read 240 entries of D instead of 496.
+    // Each step reads its entries of D into registers first, the reads issued together, and
+    // stores its result at once, so that the stores drain while the later steps compute.
+    const bool colw = i0w < rest;
     double dr[NB];
-    if (colitem) {
+    if (colw) {
 #pragma unroll
-      for (int q = 0; q < NB; ++q) {
+      for (int q = 0; q < 16; ++q) {
 #pragma unroll
         for (int r = 0; r < q; ++r) dr[r] = sm.a.D[q][r];
         const double rq = sm.a.rd[q];
@@ -756,13 +759,13 @@ k_panel_lookahead(const PanelRec *__restrict__ recs, int nrec, int cmax,
           s0 -= dr[r] * v[r];
           s1 -= dr[r + 1] * v[r + 1];
         }
-        if (q & 1) s0 -= dr[q - 1] * v[q - 1];
+        if ((q - 0) & 1) s0 -= dr[q - 1] * v[q - 1];
         v[q] = (s0 + s1) * rq;
-        if (q < pb) F[io + (uint32_t)(q * m)] = v[q];
+        if (has && q < pb) F[io + (uint32_t)(q * m)] = v[q];
       }
     } else {
 #pragma unroll
-      for (int q = 0; q < NB; ++q) {
+      for (int q = 0; q < 16; ++q) {
 #pragma unroll
         for (int r = 0; r < q; ++r) dr[r] = sm.a.D[r][q];
         __builtin_amdgcn_sched_barrier(0);
@@ -772,10 +775,87 @@ k_panel_lookahead(const PanelRec *__restrict__ recs, int nrec, int cmax,
           s0 -= dr[r] * v[r];
           s1 -= dr[r + 1] * v[r + 1];
         }
-        if (q & 1) s0 -= dr[q - 1] * v[q - 1];
+        if ((q - 0) & 1) s0 -= dr[q - 1] * v[q - 1];
         v[q] = s0 + s1;
         // a row's entries are contiguous: a full panel's in 16-byte pairs
-        if (q & 1) {
+        if (has && (q & 1)) {
+          if (pb == NB) {
+            *reinterpret_cast<d2u *>(F + io + q - 1) = d2u{v[q - 1], v[q]};
+          } else {
+            if (q - 1 < pb) F[io + (uint32_t)(q - 1)] = v[q - 1];
+            if (q < pb) F[io + (uint32_t)q] = v[q];
+          }
+        }
+      }
+    }
+    {
+      // v[16 + j] -= sum_{r<16} M[j][r] v[r], M[j][r] = D[16 + j][r] (columns) or D[r][16 + j]
+      // (rows): A operand lane l = v[r = 4 s + l/16] of item 16 rb + l%16 (staged through Ws),
+      // B operand lane l = M[l%16][4 s + l/16]; result lane l register t = item 16 rb + 4 t +
+      // l/16, j = l%16
+      double *Ws = sm.a.Ws[wv - 1];
+      const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+      for (int t = 0; t < 16; ++t) Ws[lane * 17 + t] = v[t];
+      wave_sync();
+      double aop[4][4], bop[4];
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int ss = 0; ss < 4; ++ss) aop[rb][ss] = Ws[(16 * rb + li) * 17 + 4 * ss + lk];
+#pragma unroll
+      for (int ss = 0; ss < 4; ++ss)
+        bop[ss] = colw ? sm.a.D[16 + li][4 * ss + lk] : sm.a.D[4 * ss + lk][16 + li];
+      wave_sync();                                   // read before the products overwrite
+      v4d acc[4];
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) acc[rb] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ss = 0; ss < 4; ++ss)
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+          acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[rb][ss], bop[ss], acc[rb], 0, 0, 0);
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) Ws[(16 * rb + 4 * t + lk) * 17 + li] = acc[rb][t];
+      wave_sync();
+#pragma unroll
+      for (int t = 0; t < 16; ++t) v[16 + t] -= Ws[lane * 17 + t];
+    }
+    if (colw) {
+#pragma unroll
+      for (int q = 16; q < 32; ++q) {
+#pragma unroll
+        for (int r = 16; r < q; ++r) dr[r] = sm.a.D[q][r];
+        const double rq = sm.a.rd[q];
+        __builtin_amdgcn_sched_barrier(0);
+        double s0 = v[q], s1 = 0.0;
+#pragma unroll
+        for (int r = 16; r + 1 < q; r += 2) {
+          s0 -= dr[r] * v[r];
+          s1 -= dr[r + 1] * v[r + 1];
+        }
+        if ((q - 16) & 1) s0 -= dr[q - 1] * v[q - 1];
+        v[q] = (s0 + s1) * rq;
+        if (has && q < pb) F[io + (uint32_t)(q * m)] = v[q];
+      }
+    } else {
+#pragma unroll
+      for (int q = 16; q < 32; ++q) {
+#pragma unroll
+        for (int r = 16; r < q; ++r) dr[r] = sm.a.D[r][q];
+        __builtin_amdgcn_sched_barrier(0);
+        double s0 = v[q], s1 = 0.0;
+#pragma unroll
+        for (int r = 16; r + 1 < q; r += 2) {
+          s0 -= dr[r] * v[r];
+          s1 -= dr[r + 1] * v[r + 1];
+        }
+        if ((q - 16) & 1) s0 -= dr[q - 1] * v[q - 1];
+        v[q] = s0 + s1;
+        // a row's entries are contiguous: a full panel's in 16-byte pairs
+        if (has && (q & 1)) {
           if (pb == NB) {
             *reinterpret_cast<d2u *>(F + io + q - 1) = d2u{v[q - 1], v[q]};
           } else {
